@@ -1,0 +1,211 @@
+/*
+ * hq.h -- C ABI of the MI355X (gfx950) library for the hierarchical
+ * orthogonal complement of rigid-body Z-matrices.
+ *
+ * Fang, Huang, Huber, McCammon, Zhang, "Hierarchical Orthogonal Matrix
+ * Generation and Matrix-Vector Multiplications in Rigid Body Simulations".
+ *
+ * A rigid body j has n_j beads at r_k.  Its Z-matrix (Eq. 1.2) is the
+ * 6 x 3n_j matrix [I ... I; A_1 ... A_n] with A_k f = r_k x f.  For m bodies the
+ * matrices are block diagonal (Section 1): Q~ = diag(Q~^1, ..., Q~^m), where
+ * Q~^j has 3n_j - 6 orthonormal rows spanning the orthogonal complement of the
+ * row space of Z^j.  The Problem Statement of Section 1 asks to construct Q~
+ * (explicitly if needed) and to compute Q~ v and Q~^T v; this ABI exposes
+ * exactly that:
+ *
+ *   hq_build    tree and FP64 local transforms (Sections 2.1, 3; Algorithm 1's
+ *               generation part, Eqs. 3.4-3.13), O(n log n)
+ *   hq_apply    Q~ v (Algorithm 2, Eqs. 4.2-4.3) or Q~^T w (Algorithm 3,
+ *               Theorem 4.3), O(n) per right-hand side
+ *   hq_explicit Q~ itself (Algorithm 1), dense per body or block-sparse
+ *
+ * Conventions (all bodies):
+ *   - Bead vectors are row-major (3N x nrhs), the right-hand sides fastest;
+ *     bead k of body j occupies rows 3(off_j + k) .. 3(off_j + k) + 2 in the
+ *     caller's bead order (the paper's f = [f_1; ...; f_n], Section 1).
+ *   - Residue vectors are row-major (rows x nrhs), rows = sum_j (3n_j - 6);
+ *     body j's rows start at sum_{i<j} (3n_i - 6).  Inside a body the rows
+ *     follow the block form Q~_p = [Residue_p; diag(Q~_x, Q~_y)] of Section 3:
+ *     a node's residue rows, then its x subtree's, then its y subtree's.
+ *   - The tree: per body, the cube with lower corner at the per-axis bead
+ *     minimum and side equal to the largest extent; coordinates quantised to
+ *     21 bits; boxes split at midpoints in z, then y, then x (Section 2.1);
+ *     x = lower half; single-child boxes collapse; beads sharing all 63 bits
+ *     split by the highest differing bit of their sorted position in the body.
+ *   - Transforms: K = [T22_x | T22_y | sqrt(n_x n_y / n) [c_x - c_y]x] (leaf
+ *     blocks absent) is factored by Householder reflections in LAPACK's sign
+ *     convention, K = [T22 | 0] G; a two-bead node's rank-2 T22 has its
+ *     third column set to exactly 0 (Eq. 3.9).
+ *
+ * Memory and streams: pointers documented "device" are HIP device memory
+ * owned by the caller; "host" pointers are ordinary host memory.  Every call
+ * that takes a stream is stream-ordered and asynchronous unless noted; the
+ * caller synchronises before reading results.  A hq_stream is a hipStream_t
+ * (NULL = the default stream).
+ *
+ * Errors: every function returns a status and never aborts.  hq_last_error()
+ * returns a thread-local message for the last failing call on the thread.
+ * Conditions found on the device (non-finite positions, an internal limit)
+ * raise a per-handle device flag that hq_query() reports.
+ */
+#ifndef HQ_H
+#define HQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hq_plan_s *hq_handle;
+typedef void *hq_stream;
+
+typedef enum {
+    HQ_OK = 0,
+    HQ_E_INVALID = 1,      /* bad argument, offsets, sizes, or non-finite input */
+    HQ_E_DEGENERATE = 2,   /* reserved: degenerate bodies are flagged, not failed */
+    HQ_E_NOMEM = 3,        /* device allocation failed */
+    HQ_E_DEVICE = 4,       /* a HIP runtime call failed */
+    HQ_E_UNSUPPORTED = 5   /* request outside a documented limit */
+} hq_status;
+
+typedef enum { HQ_FP64 = 0, HQ_FP32 = 1 } hq_precision;
+
+/* Device flag bits reported by hq_query (hq_info.device_flags). */
+#define HQ_FLAG_NONFINITE   1  /* a position was NaN or infinite */
+#define HQ_FLAG_STACK       2  /* an internal per-tile stack limit was hit */
+#define HQ_FLAG_BOUNDS      4  /* an internal index failed its bounds check */
+#define HQ_FLAG_PHASES      8  /* a rebuilt tree needed more tile phases than reserved */
+
+/* Per-body flag bits (hq_body_info). */
+#define HQ_BODY_ILLCOND     1  /* some node with k > 3 has kappa(T22) > 1e4 */
+#define HQ_BODY_DEGENERATE  2  /* rank Z < 6 (e.g. collinear beads, Section 2.2) */
+
+typedef struct {
+    int32_t tile_units;    /* max units (beads or sub-tile roots) per tile; 0 = 256; <= 1024 */
+    int32_t store;         /* transforms kept: 1 = FP64, 2 = FP32, 3 or 0 = both */
+    int32_t explicit_dense_max_n; /* largest n_j for hq_explicit; 0 = 4096 */
+    int32_t max_phases;    /* tile phases reserved for hq_rebuild; 0 = found at build + 2 */
+} hq_options;
+
+typedef struct {
+    int64_t N;             /* beads */
+    int64_t m;             /* bodies */
+    int64_t rows;          /* sum_j (3 n_j - 6) */
+    int64_t internal_nodes;/* N - m */
+    int64_t tiles;         /* tiles of the last build */
+    int32_t phases;        /* tile phases of the last build */
+    int32_t device_flags;  /* HQ_FLAG_* raised since the handle was built */
+    int32_t tile_units;
+    int32_t store;
+    double max_kappa;      /* max over bodies of the largest kappa(T22), k > 3 nodes */
+    int64_t ill_conditioned_bodies;
+    int64_t degenerate_bodies;
+} hq_info;
+
+/* Build the tree and the FP64 local transforms of m bodies.
+ *   positions     device, N x 3 FP64, x,y,z interleaved, caller's bead order.
+ *   body_offsets  host, m + 1 entries: [0] = 0, strictly increasing, so that
+ *                 body j holds beads [off_j, off_{j+1}); every n_j >= 2.
+ *   opt           host, may be NULL for the defaults.
+ *   out           receives the handle, which owns all device memory it uses
+ *                 (allocated here with hipMalloc).
+ * Synchronises the stream once (to size the tile phases).  Errors:
+ * HQ_E_INVALID for bad offsets, n_j < 2, NULL pointers or non-finite
+ * positions (found on the device); HQ_E_NOMEM; HQ_E_DEVICE. */
+hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t m,
+                   const hq_options *opt, hq_stream stream, hq_handle *out);
+
+/* Rebuild the same bodies (same offsets) from new positions: device,
+ * N x 3 FP64.  No allocation and no host synchronisation, so a stream
+ * capture may record it; tile phases beyond the reserved count raise
+ * HQ_FLAG_PHASES. */
+hq_status hq_rebuild(hq_handle h, const double *positions, hq_stream stream);
+
+/* Pre-allocate the per-tile exchange buffers for up to nrhs right-hand sides
+ * of precision prec, so that later hq_apply calls allocate nothing (needed
+ * before a stream capture).  Synchronous. */
+hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec);
+
+/* Apply Q~ or Q~^T to nrhs right-hand sides.
+ *   transpose = 0: v device (3N x nrhs) -> out device (rows x nrhs) = Q~ v
+ *                  (Algorithm 2; each body's root Info-set is dropped).
+ *   transpose = 1: v device (rows x nrhs) -> out device (3N x nrhs) = Q~^T v
+ *                  (Algorithm 3 with a zero root Velocity-set).
+ *   Elements are double for HQ_FP64, float for HQ_FP32; the transforms of that
+ *   precision must have been kept (hq_options.store).  v and out must not
+ *   overlap.  Allocates the exchange buffers on first use unless reserved. */
+hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
+                   hq_precision prec, hq_stream stream);
+
+/* Dense Q~ of one body (Algorithm 1): out device FP64, (3n_j - 6) rows with
+ * leading dimension ld >= 3n_j, columns in the caller's bead order.  A
+ * two-bead body has no rows: HQ_OK without touching out (which may be NULL).
+ * HQ_E_UNSUPPORTED when n_j exceeds explicit_dense_max_n. */
+hq_status hq_explicit(hq_handle h, int64_t body, double *out, int64_t ld, hq_stream stream);
+
+/* Block-sparse Q~ of one body in O(n log n) storage (Section 3, Algorithm
+ * complexity).  Each internal node p with residue rows owns one dense block of
+ * dim_p rows and 3 n_p columns: the rows are body rows row_off[b] ..
+ * row_off[b] + rows[b] - 1 and the columns are the beads
+ * hq_sorted_beads()[bead_first[b] .. bead_first[b] + cols[b]/3 - 1] (each bead
+ * three columns x,y,z).  Q~ is zero outside the blocks.
+ * hq_explicit_blocks_size gives the block count and the total value count;
+ * hq_explicit_blocks fills values (device, prec's element type, blocks
+ * row-major and concatenated) and the host arrays val_off (nblocks + 1),
+ * row_off, bead_first (nblocks), rows and cols (nblocks).  Synchronises. */
+hq_status hq_explicit_blocks_size(hq_handle h, int64_t body, int64_t *nblocks, int64_t *nvalues);
+hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void *values,
+                             int64_t *val_off, int64_t *row_off, int64_t *bead_first,
+                             int32_t *rows, int32_t *cols, hq_stream stream);
+
+/* The tree order of one body's beads: host, n_j entries, the caller's bead
+ * index (0-based within the body) of each tree leaf left to right.
+ * Synchronises. */
+hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index);
+
+/* Rigid motion of every body (a Brownian-dynamics step's position update):
+ * r <- Rot_j (r - c_j) + c_j + t_j for the beads of body j, with c_j the
+ * body centroid of the last build.  positions device N x 3 FP64 (in place),
+ * rot device m x 9 FP64 row-major, trans device m x 3 FP64.  Capturable. */
+hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot,
+                          const double *trans, hq_stream stream);
+
+/* Sizes, phase/tile counts and device flags (synchronises the handle's
+ * device state). */
+hq_status hq_query(hq_handle h, hq_info *info);
+
+/* Per-body flags and largest kappa(T22): host arrays of m entries (either may
+ * be NULL).  Synchronises. */
+hq_status hq_body_info(hq_handle h, int32_t *flags, double *kappa);
+
+/* Per-node data for tests, host arrays of N - m entries in the handle's node
+ * order (any may be NULL): first/last sorted bead position within the body,
+ * the children (>= 0: node index; < 0: -(sorted position within body) - 1),
+ * body index, beads below, centroid (3, body-local: relative to the body's
+ * lower corner), T22 (9, row-major), G (81, row-major k x k in the top-left),
+ * k, and the first residue row within the body.  Synchronises. */
+hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchild,
+                       int32_t *ychild, int32_t *body, int32_t *nbeads, double *centroid,
+                       double *T22, double *G, int32_t *k, int32_t *row);
+
+/* Stream capture helpers (hipStreamBeginCapture / EndCapture /
+ * hipGraphInstantiate / hipGraphLaunch): everything enqueued between begin
+ * and end on the stream is recorded into *graph_exec, which replays it. */
+hq_status hq_capture_begin(hq_stream stream);
+hq_status hq_capture_end(hq_stream stream, void **graph_exec);
+hq_status hq_graph_launch(void *graph_exec, hq_stream stream);
+void hq_graph_destroy(void *graph_exec);
+
+/* Destroy a handle and free what it allocated (NULL is accepted). */
+void hq_destroy(hq_handle h);
+
+const char *hq_status_string(hq_status s);
+const char *hq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HQ_H */

@@ -147,8 +147,8 @@ class Body:
         Q_Z v, or supplies the root Velocity-set."""
         v = np.asarray(v, dtype=np.float64)
         vec = v.ndim == 1
-        v2 = np.ascontiguousarray(v.reshape(v.shape[0], -1))
-        R = v2.shape[1]
+        R = 1 if vec else v.shape[1]
+        v2 = np.ascontiguousarray(v.reshape(v.shape[0], R))
         if not transpose:
             assert v2.shape[0] == 3 * self.n
             out = np.zeros((self.rows, R))
@@ -199,8 +199,8 @@ class Batch:
 
     def apply(self, v, transpose=False):
         v = np.asarray(v, dtype=np.float64)
-        v2 = v.reshape(v.shape[0], -1)
-        R = v2.shape[1]
+        R = 1 if v.ndim == 1 else v.shape[1]
+        v2 = v.reshape(v.shape[0], R)
         N = int(self.offsets[-1])
         out = np.zeros(((3 * N) if transpose else self.rows, R))
         for j, b in enumerate(self.bodies):

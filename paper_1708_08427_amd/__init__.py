@@ -1,0 +1,270 @@
+"""Hierarchical orthogonal complements of rigid-body Z-matrices on MI355X.
+
+Thin Python binding of the C ABI in ``include/hq.h`` (``libhq.so``): argument
+marshalling only.  Every step of the method runs in the library's HIP kernels;
+PyTorch supplies device memory and the current stream.
+
+    h = build(positions, offsets)          # tree + FP64 transforms
+    y = h.apply(v)                         # Q~ v      (v: 3N x R, float64/float32)
+    z = h.apply(w, transpose=True)         # Q~^T w    (w: rows x R)
+    Q = h.explicit(body)                   # dense Q~ of one body
+
+Fang, Huang, Huber, McCammon, Zhang, "Hierarchical Orthogonal Matrix
+Generation and Matrix-Vector Multiplications in Rigid Body Simulations"
+(Sections 3-4, Algorithms 1-3).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (HQ_BODY_DEGENERATE, HQ_BODY_ILLCOND, HQ_FLAG_BOUNDS, HQ_FLAG_NONFINITE, HQ_FLAG_PHASES,
+                   HQ_FLAG_STACK, HQ_FP32, HQ_FP64, Info, Options)
+
+__all__ = ["HQError", "Handle", "build", "load", "HQ_FP64", "HQ_FP32"]
+
+
+class HQError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _lib.load()
+        self.status = int(status)
+        msg = lib.hq_last_error().decode(errors="replace")
+        name = lib.hq_status_string(status).decode()
+        super().__init__(f"{where}: {name}: {msg}")
+
+
+def load():
+    return _lib.load()
+
+
+def _check(st, where):
+    if st != 0:
+        raise HQError(st, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(dtype):
+    torch = _torch()
+    if dtype == torch.float64:
+        return HQ_FP64
+    if dtype == torch.float32:
+        return HQ_FP32
+    raise TypeError(f"unsupported dtype {dtype}: use float64 or float32")
+
+
+def _check_dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Handle:
+    """A built set of bodies (owns the library's device state)."""
+
+    def __init__(self, raw, offsets, stream=None):
+        self._raw = raw
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        sizes = np.diff(self.offsets)
+        self.row_offsets = np.concatenate([[0], np.cumsum(3 * sizes - 6)]).astype(np.int64)
+
+    @property
+    def N(self):
+        return int(self.offsets[-1])
+
+    @property
+    def m(self):
+        return len(self.offsets) - 1
+
+    @property
+    def rows(self):
+        return int(self.row_offsets[-1])
+
+    def _h(self):
+        if not self._raw:
+            raise RuntimeError("handle was destroyed")
+        return self._raw
+
+    def destroy(self):
+        if self._raw:
+            _lib.load().hq_destroy(self._raw)
+            self._raw = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    # -- products ---------------------------------------------------------
+    def apply(self, v, transpose=False, out=None, stream=None):
+        """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v."""
+        torch = _torch()
+        _check_dev(v, "v")
+        squeeze = v.dim() == 1
+        v2 = v.reshape(v.shape[0], 1) if squeeze else v
+        R = v2.shape[1]
+        nin, nout = (self.rows, 3 * self.N) if transpose else (3 * self.N, self.rows)
+        if v2.shape[0] != nin:
+            raise ValueError(f"v has {v2.shape[0]} rows, expected {nin}")
+        if out is None:
+            out = torch.empty((nout, R), dtype=v.dtype, device=v.device)
+        else:
+            _check_dev(out, "out")
+            if out.shape != (nout, R) and not (squeeze and out.shape == (nout,)):
+                raise ValueError("out has the wrong shape")
+            if out.dtype != v.dtype:
+                raise TypeError("out and v must have the same dtype")
+        lib = _lib.load()
+        _check(lib.hq_apply(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
+                            _stream(stream)), "hq_apply")
+        return out.reshape(nout) if squeeze else out
+
+    def reserve(self, nrhs, dtype):
+        _check(_lib.load().hq_reserve(self._h(), int(nrhs), _prec(dtype)), "hq_reserve")
+
+    def rebuild(self, positions, stream=None):
+        _check_dev(positions, "positions")
+        _check(_lib.load().hq_rebuild(self._h(), _ptr(positions), _stream(stream)), "hq_rebuild")
+
+    def rigid_update(self, positions, rot, trans, stream=None):
+        for t, nm in ((positions, "positions"), (rot, "rot"), (trans, "trans")):
+            _check_dev(t, nm)
+        _check(_lib.load().hq_rigid_update(self._h(), _ptr(positions), _ptr(rot), _ptr(trans), _stream(stream)),
+               "hq_rigid_update")
+
+    # -- explicit Q~ --------------------------------------------------------
+    def explicit(self, body=0, stream=None):
+        """Dense Q~ of one body: (3n-6) x 3n float64 on the device."""
+        torch = _torch()
+        n = int(self.offsets[body + 1] - self.offsets[body])
+        out = torch.empty((max(3 * n - 6, 0), 3 * n), dtype=torch.float64, device="cuda")
+        _check(_lib.load().hq_explicit(self._h(), int(body), _ptr(out), 3 * n, _stream(stream)), "hq_explicit")
+        return out
+
+    def explicit_blocks(self, body=0, dtype=None, stream=None):
+        """Block-sparse Q~ of one body: (values, val_off, row_off, bead_first,
+        rows, cols); see hq_explicit_blocks."""
+        torch = _torch()
+        dtype = dtype or torch.float64
+        lib = _lib.load()
+        nb, nv = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib.hq_explicit_blocks_size(self._h(), int(body), ctypes.byref(nb), ctypes.byref(nv)),
+               "hq_explicit_blocks_size")
+        nb, nv = nb.value, nv.value
+        values = torch.empty(max(nv, 1), dtype=dtype, device="cuda")
+        val_off = np.zeros(nb + 1, dtype=np.int64)
+        row_off = np.zeros(max(nb, 1), dtype=np.int64)
+        bead_first = np.zeros(max(nb, 1), dtype=np.int64)
+        rows = np.zeros(max(nb, 1), dtype=np.int32)
+        cols = np.zeros(max(nb, 1), dtype=np.int32)
+        _check(lib.hq_explicit_blocks(self._h(), int(body), _prec(dtype), _ptr(values),
+                                      val_off.ctypes.data_as(_lib.P_i64), row_off.ctypes.data_as(_lib.P_i64),
+                                      bead_first.ctypes.data_as(_lib.P_i64), rows.ctypes.data_as(_lib.P_i32),
+                                      cols.ctypes.data_as(_lib.P_i32), _stream(stream)), "hq_explicit_blocks")
+        return values[:nv], val_off, row_off[:nb], bead_first[:nb], rows[:nb], cols[:nb]
+
+    def sorted_beads(self, body=0):
+        n = int(self.offsets[body + 1] - self.offsets[body])
+        out = np.zeros(n, dtype=np.int64)
+        _check(_lib.load().hq_sorted_beads(self._h(), int(body), out.ctypes.data_as(_lib.P_i64)),
+               "hq_sorted_beads")
+        return out
+
+    # -- introspection ------------------------------------------------------
+    def query(self):
+        info = Info()
+        _check(_lib.load().hq_query(self._h(), ctypes.byref(info)), "hq_query")
+        return {f: getattr(info, f) for f, _ in Info._fields_}
+
+    def body_info(self):
+        flags = np.zeros(self.m, dtype=np.int32)
+        kappa = np.zeros(self.m, dtype=np.float64)
+        _check(_lib.load().hq_body_info(self._h(), flags.ctypes.data_as(_lib.P_i32),
+                                        kappa.ctypes.data_as(_lib.P_f64)), "hq_body_info")
+        return flags, kappa
+
+    def node_data(self):
+        NI = self.N - self.m
+        a = {k: np.zeros(NI, dtype=np.int32) for k in ("first", "last", "x", "y", "body", "n", "k", "row")}
+        cen = np.zeros((NI, 3))
+        T22 = np.zeros((NI, 3, 3))
+        G = np.zeros((NI, 9, 9))
+        P = _lib.P_i32
+        _check(_lib.load().hq_node_data(self._h(), a["first"].ctypes.data_as(P), a["last"].ctypes.data_as(P),
+                                        a["x"].ctypes.data_as(P), a["y"].ctypes.data_as(P),
+                                        a["body"].ctypes.data_as(P), a["n"].ctypes.data_as(P),
+                                        cen.ctypes.data_as(_lib.P_f64), T22.ctypes.data_as(_lib.P_f64),
+                                        G.ctypes.data_as(_lib.P_f64), a["k"].ctypes.data_as(P),
+                                        a["row"].ctypes.data_as(P)), "hq_node_data")
+        a.update(centroid=cen, T22=T22, G=G)
+        return a
+
+
+def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max_phases=0, stream=None):
+    """Build the tree and FP64 transforms for bodies given by ``offsets``
+    (host, m + 1 int64) over ``positions`` (device, N x 3 float64)."""
+    _check_dev(positions, "positions")
+    torch = _torch()
+    if positions.dtype != torch.float64:
+        raise TypeError("positions must be float64")
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or len(off) < 2:
+        raise ValueError("offsets must hold m + 1 entries")
+    if positions.dim() != 2 or positions.shape[1] != 3 or positions.shape[0] != int(off[-1]):
+        raise ValueError("positions must be N x 3 with N = offsets[-1]")
+    opt = Options(int(tile_units), int(store), int(explicit_dense_max_n), int(max_phases))
+    raw = ctypes.c_void_p()
+    lib = _lib.load()
+    _check(lib.hq_build(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, ctypes.byref(opt),
+                        _stream(stream), ctypes.byref(raw)), "hq_build")
+    return Handle(raw, off)
+
+
+def capture_begin(stream=None):
+    _check(_lib.load().hq_capture_begin(_stream(stream)), "hq_capture_begin")
+
+
+def capture_end(stream=None):
+    ex = ctypes.c_void_p()
+    _check(_lib.load().hq_capture_end(_stream(stream), ctypes.byref(ex)), "hq_capture_end")
+    return Graph(ex)
+
+
+class Graph:
+    """A captured stream sequence (hipGraphExec), replayed by launch()."""
+
+    def __init__(self, ex):
+        self._ex = ex
+
+    def launch(self, stream=None):
+        _check(_lib.load().hq_graph_launch(self._ex, _stream(stream)), "hq_graph_launch")
+
+    def destroy(self):
+        if self._ex:
+            _lib.load().hq_graph_destroy(self._ex)
+            self._ex = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,722 @@
+// The C ABI of include/hq.h: argument checks, the plan behind a handle, device
+// buffers, and the launch sequences of hq_build.hip / hq_apply.hip /
+// hq_explicit.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hq_common.h"
+
+namespace hq {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+template <typename T>
+hq_status dalloc(Plan &P, T **p, int64_t count) {
+    *p = nullptr;
+    if (count < 1) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc of ") + std::to_string((size_t)count * sizeof(T)) +
+                  " bytes: " + hipGetErrorString(e));
+        return HQ_E_NOMEM;
+    }
+    P.allocs.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return HQ_OK;
+}
+
+template <typename T>
+hq_status upload(Plan &P, T **dst, const std::vector<T> &src) {
+    HQ_TRY(dalloc(P, dst, (int64_t)src.size()));
+    if (!src.empty()) HQ_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HQ_OK;
+}
+
+void free_plan(Plan *P) {
+    if (!P) return;
+    hipDeviceSynchronize();
+    for (void *p : P->allocs) hipFree(p);
+    if (P->d_xch) hipFree(P->d_xch);
+    P->magic = 0;
+    delete P;
+}
+
+Plan *get_plan(hq_handle h) {
+    Plan *P = reinterpret_cast<Plan *>(h);
+    if (!P || P->magic != kPlanMagic) {
+        set_error("invalid or destroyed handle");
+        return nullptr;
+    }
+    return P;
+}
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *opt) {
+    P.m = m;
+    P.offsets.assign(off, off + m + 1);
+    P.N = off[m];
+    P.NI = P.N - m;
+    P.row_off.assign(m + 1, 0);
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t n = off[j + 1] - off[j];
+        P.row_off[j + 1] = P.row_off[j] + 3 * n - 6;
+        P.max_n = (int)std::max<int64_t>(P.max_n, n);
+    }
+    P.rows = P.row_off[m];
+    P.S = (opt && opt->tile_units) ? opt->tile_units : 256;
+    P.store = (opt && opt->store) ? opt->store : 3;
+    P.dense_max_n = (opt && opt->explicit_dense_max_n) ? opt->explicit_dense_max_n : 4096;
+    P.phases_reserved = (opt && opt->max_phases) ? opt->max_phases : 0;
+
+    const int64_t N = P.N, NI = P.NI;
+    std::vector<int32_t> bead_off(m + 1), node_off(m + 1), row_off(m + 1);
+    for (int64_t j = 0; j <= m; ++j) {
+        bead_off[j] = (int32_t)off[j];
+        node_off[j] = (int32_t)(off[j] - j);
+        row_off[j] = (int32_t)P.row_off[j];
+    }
+    HQ_TRY(upload(P, &P.d_bead_off, bead_off));
+    HQ_TRY(upload(P, &P.d_node_off, node_off));
+    HQ_TRY(upload(P, &P.d_row_off, row_off));
+
+    // chunk table for the per-bead kernels
+    std::vector<int32_t> chunks;
+    constexpr int64_t kChunk = 2048;
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t b = off[j]; b < off[j + 1]; b += kChunk) {
+            chunks.push_back((int32_t)j);
+            chunks.push_back((int32_t)b);
+            chunks.push_back((int32_t)std::min(off[j + 1], b + kChunk));
+        }
+    P.nchunks = (int)(chunks.size() / 3);
+    HQ_TRY(upload(P, &P.d_chunks, chunks));
+
+    // sort plan: bodies up to kSortLdsMax beads in one LDS sort, larger ones
+    // as LDS-sorted chunks followed by merge passes
+    std::vector<std::vector<int32_t>> small_seg(15), chunk_seg(15);
+    std::vector<int32_t> large;
+    std::vector<int64_t> large_prefix;
+    int64_t lsum = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t n = off[j + 1] - off[j];
+        if (n <= kSortLdsMax) {
+            const int npad = std::max(64, next_pow2((int)n));
+            auto &v = small_seg[floor_log2(npad)];
+            v.push_back((int32_t)off[j]);
+            v.push_back((int32_t)n);
+            v.push_back((int32_t)j);
+        } else {
+            large.push_back((int32_t)j);
+            large_prefix.push_back(lsum);
+            lsum += n;
+            int passes = 0;
+            for (int64_t L = kSortLdsMax; L < n; L *= 2) ++passes;
+            P.large_passes = std::max(P.large_passes, passes);
+            for (int64_t b = 0; b < n; b += kSortLdsMax) {
+                const int len = (int)std::min<int64_t>(kSortLdsMax, n - b);
+                const int npad = std::max(64, next_pow2(len));
+                auto &v = chunk_seg[floor_log2(npad)];
+                v.push_back((int32_t)(off[j] + b));
+                v.push_back(len);
+                v.push_back((int32_t)j);
+            }
+        }
+    }
+    for (int c = 0; c < 15; ++c) {
+        if (!small_seg[c].empty()) {
+            Plan::SortClass sc;
+            sc.npad = 1 << c;
+            sc.nseg = (int)(small_seg[c].size() / 3);
+            HQ_TRY(upload(P, &sc.d_seg, small_seg[c]));
+            P.sort_small.push_back(sc);
+        }
+        if (!chunk_seg[c].empty()) {
+            Plan::SortClass sc;
+            sc.npad = 1 << c;
+            sc.nseg = (int)(chunk_seg[c].size() / 3);
+            HQ_TRY(upload(P, &sc.d_seg, chunk_seg[c]));
+            P.sort_chunks.push_back(sc);
+        }
+    }
+    P.nlarge = (int)large.size();
+    P.large_elems = lsum;
+    if (P.nlarge) {
+        HQ_TRY(upload(P, &P.d_large, large));
+        HQ_TRY(upload(P, &P.d_large_prefix, large_prefix));
+    }
+
+    // body level
+    HQ_TRY(dalloc(P, &P.d_bmin, 3 * m));
+    HQ_TRY(dalloc(P, &P.d_bmax, 3 * m));
+    HQ_TRY(dalloc(P, &P.d_lo, 3 * m));
+    HQ_TRY(dalloc(P, &P.d_h, m));
+    HQ_TRY(dalloc(P, &P.d_cen, 3 * m));
+    HQ_TRY(dalloc(P, &P.d_kappa, m));
+    HQ_TRY(dalloc(P, &P.d_bflags, m));
+    // bead level
+    HQ_TRY(dalloc(P, &P.d_keyA, N));
+    HQ_TRY(dalloc(P, &P.d_valA, N));
+    if (P.nlarge) {
+        HQ_TRY(dalloc(P, &P.d_keyB, N));
+        HQ_TRY(dalloc(P, &P.d_valB, N));
+    }
+    HQ_TRY(dalloc(P, &P.d_scode, N));
+    HQ_TRY(dalloc(P, &P.d_perm, N));
+    HQ_TRY(dalloc(P, &P.d_leafpar, N));
+    HQ_TRY(dalloc(P, &P.d_mark, N));
+    HQ_TRY(dalloc(P, &P.d_msum, N));
+    // node level
+    HQ_TRY(dalloc(P, &P.d_lc, NI));
+    HQ_TRY(dalloc(P, &P.d_rc, NI));
+    HQ_TRY(dalloc(P, &P.d_par, NI));
+    HQ_TRY(dalloc(P, &P.d_first, NI));
+    HQ_TRY(dalloc(P, &P.d_last, NI));
+    HQ_TRY(dalloc(P, &P.d_nbody, NI));
+    HQ_TRY(dalloc(P, &P.d_cov, NI));
+    HQ_TRY(dalloc(P, &P.d_units, NI));
+    HQ_TRY(dalloc(P, &P.d_tileof, NI));
+    HQ_TRY(dalloc(P, &P.d_sched, NI));
+    HQ_TRY(dalloc(P, &P.d_yfirst, NI));
+    HQ_TRY(dalloc(P, &P.d_trval, NI));
+    HQ_TRY(dalloc(P, &P.d_trscan, NI));
+    HQ_TRY(dalloc(P, &P.d_nn, NI));
+    HQ_TRY(dalloc(P, &P.d_ncen, 3 * NI));
+    HQ_TRY(dalloc(P, &P.d_T22, 6 * NI));
+    HQ_TRY(dalloc(P, &P.d_tile_root, NI));
+    HQ_TRY(dalloc(P, &P.d_tile_base, NI));
+    HQ_TRY(dalloc(P, &P.d_tile_len, NI));
+    HQ_TRY(dalloc(P, &P.d_sched_node, NI));
+    HQ_TRY(dalloc(P, &P.d_links, 4 * NI));
+    if (P.store & 2) HQ_TRY(dalloc(P, &P.d_rec32, (int64_t)kRecWords * NI));
+    if (P.store & 1) HQ_TRY(dalloc(P, &P.d_rec64, (int64_t)kRecWords * NI));
+    HQ_TRY(dalloc(P, &P.d_phase, 2 * kMaxPhases));
+    HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
+    HQ_TRY(dalloc(P, &P.d_err, 1));
+    HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
+    P.scan_blk_cap = scan_blocks_needed(std::max(N, NI)) + 8;
+    HQ_TRY(dalloc(P, &P.d_scan_blk, P.scan_blk_cap));
+    return HQ_OK;
+}
+
+hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
+    const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
+    const int64_t cap_tiles = 2 * P.tiles_built + 64;
+    const size_t need = (size_t)cap_tiles * 6 * (size_t)nrhs * elem;
+    if (P.xch_bytes >= need) return HQ_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        set_error("exchange buffer too small during stream capture: call hq_reserve first");
+        return HQ_E_INVALID;
+    }
+    HQ_HIP(hipDeviceSynchronize());
+    if (P.d_xch) {
+        hipFree(P.d_xch);
+        P.d_xch = nullptr;
+        P.xch_bytes = 0;
+    }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, need);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc of the exchange buffer: ") + hipGetErrorString(e));
+        return HQ_E_NOMEM;
+    }
+    P.d_xch = q;
+    P.xch_bytes = need;
+    return HQ_OK;
+}
+
+}  // namespace
+}  // namespace hq
+
+using namespace hq;
+
+extern "C" {
+
+const char *hq_last_error(void) { return g_last_error.c_str(); }
+
+const char *hq_status_string(hq_status s) {
+    switch (s) {
+    case HQ_OK: return "HQ_OK";
+    case HQ_E_INVALID: return "HQ_E_INVALID";
+    case HQ_E_DEGENERATE: return "HQ_E_DEGENERATE";
+    case HQ_E_NOMEM: return "HQ_E_NOMEM";
+    case HQ_E_DEVICE: return "HQ_E_DEVICE";
+    case HQ_E_UNSUPPORTED: return "HQ_E_UNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t m, const hq_options *opt,
+                   hq_stream stream, hq_handle *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return HQ_E_INVALID;
+    }
+    *out = nullptr;
+    if (!positions || !body_offsets) {
+        set_error("positions or body_offsets is NULL");
+        return HQ_E_INVALID;
+    }
+    if (m < 1 || m > (1 << 26)) {
+        set_error("m must be in [1, 2^26]");
+        return HQ_E_INVALID;
+    }
+    if (body_offsets[0] != 0) {
+        set_error("body_offsets[0] must be 0");
+        return HQ_E_INVALID;
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        if (body_offsets[j + 1] - body_offsets[j] < 2) {
+            set_error("body " + std::to_string(j) + " has fewer than 2 beads (offsets must increase by >= 2)");
+            return HQ_E_INVALID;
+        }
+    }
+    if (body_offsets[m] > (int64_t(1) << 28)) {
+        set_error("more than 2^28 beads");
+        return HQ_E_UNSUPPORTED;
+    }
+    if (opt) {
+        if (opt->tile_units != 0 && (opt->tile_units < 2 || opt->tile_units > kMaxTileUnits)) {
+            set_error("tile_units must be 0 or in [2, 1024]");
+            return HQ_E_INVALID;
+        }
+        if (opt->store < 0 || opt->store > 3) {
+            set_error("store must be 0..3");
+            return HQ_E_INVALID;
+        }
+        if (opt->max_phases < 0 || opt->max_phases >= kMaxPhases) {
+            set_error("max_phases must be in [0, 63]");
+            return HQ_E_INVALID;
+        }
+        if (opt->explicit_dense_max_n < 0) {
+            set_error("explicit_dense_max_n must be >= 0");
+            return HQ_E_INVALID;
+        }
+    }
+    Plan *P = new (std::nothrow) Plan;
+    if (!P) {
+        set_error("host allocation failed");
+        return HQ_E_NOMEM;
+    }
+    P->magic = kPlanMagic;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hq_status st = create_plan(*P, body_offsets, m, opt);
+    if (st == HQ_OK) st = build_device(*P, positions, s, true);
+    if (st == HQ_OK) {
+        if (P->phases_reserved == 0) P->phases_reserved = std::min(kMaxPhases - 1, P->phases_built + 2);
+        P->phases_reserved = std::max(P->phases_reserved, P->phases_built);
+        hipError_t e = hipStreamSynchronize(s);
+        int32_t err = 0;
+        if (e == hipSuccess) e = hipMemcpy(&err, P->d_err, sizeof err, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            set_error(std::string("hq_build: ") + hipGetErrorString(e));
+            st = HQ_E_DEVICE;
+        } else if (err & kFlagNonFinite) {
+            set_error("non-finite bead position");
+            st = HQ_E_INVALID;
+        } else if (err) {
+            set_error("device flags raised during the build: " + std::to_string(err));
+            st = HQ_E_DEVICE;
+        }
+    }
+    if (st != HQ_OK) {
+        free_plan(P);
+        return st;
+    }
+    *out = reinterpret_cast<hq_handle>(P);
+    return HQ_OK;
+}
+
+hq_status hq_rebuild(hq_handle h, const double *positions, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!positions) {
+        set_error("positions is NULL");
+        return HQ_E_INVALID;
+    }
+    return build_device(*P, positions, reinterpret_cast<hipStream_t>(stream), false);
+}
+
+hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (nrhs < 1 || (prec != HQ_FP64 && prec != HQ_FP32)) {
+        set_error("nrhs must be >= 1 and prec HQ_FP64 or HQ_FP32");
+        return HQ_E_INVALID;
+    }
+    HQ_TRY(ensure_xch(*P, nrhs, prec, nullptr));
+    HQ_HIP(hipDeviceSynchronize());
+    return HQ_OK;
+}
+
+hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
+                   hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!v || !out) {
+        set_error("v or out is NULL");
+        return HQ_E_INVALID;
+    }
+    if (v == out) {
+        set_error("v and out must not overlap");
+        return HQ_E_INVALID;
+    }
+    if (transpose != 0 && transpose != 1) {
+        set_error("transpose must be 0 or 1");
+        return HQ_E_INVALID;
+    }
+    if (nrhs < 1 || nrhs > (1 << 20)) {
+        set_error("nrhs must be in [1, 2^20]");
+        return HQ_E_INVALID;
+    }
+    if (prec != HQ_FP64 && prec != HQ_FP32) {
+        set_error("prec must be HQ_FP64 or HQ_FP32");
+        return HQ_E_INVALID;
+    }
+    if ((prec == HQ_FP64 && !(P->store & 1)) || (prec == HQ_FP32 && !(P->store & 2))) {
+        set_error("transforms of this precision were not kept (hq_options.store)");
+        return HQ_E_INVALID;
+    }
+    if ((3 * P->N) * nrhs > (int64_t(1) << 40)) {
+        set_error("vector too large");
+        return HQ_E_UNSUPPORTED;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HQ_TRY(ensure_xch(*P, nrhs, prec, s));
+    return apply_device(*P, v, out, transpose, nrhs, prec, s);
+}
+
+hq_status hq_explicit(hq_handle h, int64_t body, double *out, int64_t ld, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (body < 0 || body >= P->m) {
+        set_error("body out of range");
+        return HQ_E_INVALID;
+    }
+    const int64_t n = P->offsets[body + 1] - P->offsets[body];
+    if (n == 2) return HQ_OK;  // Q~ has no rows
+    if (!out) {
+        set_error("out is NULL");
+        return HQ_E_INVALID;
+    }
+    if (n > P->dense_max_n) {
+        set_error("body larger than explicit_dense_max_n");
+        return HQ_E_UNSUPPORTED;
+    }
+    if (ld < 3 * n) {
+        set_error("ld must be >= 3 n_j");
+        return HQ_E_INVALID;
+    }
+    if (!(P->store & 1)) {
+        set_error("explicit Q~ needs the FP64 transforms (hq_options.store)");
+        return HQ_E_INVALID;
+    }
+    return explicit_dense(*P, body, out, ld, reinterpret_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+struct BodyNodes {
+    std::vector<int32_t> lc, rc, nn, first, sched;
+};
+
+hq_status read_body_nodes(Plan &P, int64_t body, BodyNodes &B, int64_t &nb, int64_t &nin) {
+    nb = P.offsets[body];
+    const int64_t n = P.offsets[body + 1] - nb;
+    nin = n - 1;
+    const int64_t g0 = nb - body;
+    HQ_HIP(hipDeviceSynchronize());
+    B.lc.resize(nin);
+    B.rc.resize(nin);
+    B.nn.resize(nin);
+    B.first.resize(nin);
+    B.sched.resize(nin);
+    HQ_HIP(hipMemcpy(B.lc.data(), P.d_lc + g0, nin * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(B.rc.data(), P.d_rc + g0, nin * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(B.nn.data(), P.d_nn + g0, nin * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(B.first.data(), P.d_first + g0, nin * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(B.sched.data(), P.d_sched + g0, nin * 4, hipMemcpyDeviceToHost));
+    return HQ_OK;
+}
+
+}  // namespace
+
+hq_status hq_explicit_blocks_size(hq_handle h, int64_t body, int64_t *nblocks, int64_t *nvalues) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!nblocks || !nvalues || body < 0 || body >= P->m) {
+        set_error("NULL output or body out of range");
+        return HQ_E_INVALID;
+    }
+    BodyNodes B;
+    int64_t nb, nin;
+    HQ_TRY(read_body_nodes(*P, body, B, nb, nin));
+    int64_t cnt = 0, vals = 0;
+    for (int64_t q = 0; q < nin; ++q) {
+        const int dim = 3 * (B.lc[q] >= 0) + 3 * (B.rc[q] >= 0);
+        if (dim == 0) continue;
+        ++cnt;
+        vals += (int64_t)dim * 3 * B.nn[q];
+    }
+    *nblocks = cnt;
+    *nvalues = vals;
+    return HQ_OK;
+}
+
+hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void *values, int64_t *val_off,
+                             int64_t *row_off, int64_t *bead_first, int32_t *rows, int32_t *cols, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!values || !val_off || !row_off || !bead_first || !rows || !cols || body < 0 || body >= P->m ||
+        (prec != HQ_FP64 && prec != HQ_FP32)) {
+        set_error("NULL argument, bad precision or body out of range");
+        return HQ_E_INVALID;
+    }
+    if (!(P->store & 1)) {
+        set_error("explicit Q~ needs the FP64 transforms (hq_options.store)");
+        return HQ_E_INVALID;
+    }
+    BodyNodes B;
+    int64_t nb, nin;
+    HQ_TRY(read_body_nodes(*P, body, B, nb, nin));
+    std::vector<int32_t> links(4 * (size_t)P->NI);
+    HQ_HIP(hipMemcpy(links.data(), P->d_links, links.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> blk_off(nin, -1);
+    int64_t b = 0, acc = 0;
+    val_off[0] = 0;
+    for (int64_t q = 0; q < nin; ++q) {
+        const int dim = 3 * (B.lc[q] >= 0) + 3 * (B.rc[q] >= 0);
+        if (dim == 0) continue;
+        blk_off[q] = acc;
+        row_off[b] = links[4 * (size_t)B.sched[q] + 2] - P->row_off[body];
+        bead_first[b] = B.first[q] - nb;
+        rows[b] = dim;
+        cols[b] = 3 * B.nn[q];
+        acc += (int64_t)dim * 3 * B.nn[q];
+        ++b;
+        val_off[b] = acc;
+    }
+    int64_t *d_blk = nullptr;
+    HQ_HIP(hipMalloc(&d_blk, std::max<int64_t>(1, nin) * sizeof(int64_t)));
+    hipError_t e = hipMemcpy(d_blk, blk_off.data(), nin * sizeof(int64_t), hipMemcpyHostToDevice);
+    hq_status st = HQ_OK;
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        st = HQ_E_DEVICE;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (st == HQ_OK) st = explicit_blocks_launch(*P, body, prec == HQ_FP64 ? 0 : 1, values, d_blk, s);
+    hipStreamSynchronize(s);
+    hipFree(d_blk);
+    return st;
+}
+
+hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!bead_index || body < 0 || body >= P->m) {
+        set_error("NULL output or body out of range");
+        return HQ_E_INVALID;
+    }
+    const int64_t b0 = P->offsets[body], n = P->offsets[body + 1] - b0;
+    std::vector<int32_t> tmp(n);
+    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipMemcpy(tmp.data(), P->d_perm + b0, n * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) bead_index[i] = tmp[i] - b0;
+    return HQ_OK;
+}
+
+hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot, const double *trans, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!positions || !rot || !trans) {
+        set_error("NULL argument");
+        return HQ_E_INVALID;
+    }
+    return rigid_update(*P, positions, rot, trans, reinterpret_cast<hipStream_t>(stream));
+}
+
+hq_status hq_query(hq_handle h, hq_info *info) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!info) {
+        set_error("info is NULL");
+        return HQ_E_INVALID;
+    }
+    HQ_HIP(hipDeviceSynchronize());
+    int32_t err = 0, cnt[kCntNum];
+    HQ_HIP(hipMemcpy(&err, P->d_err, sizeof err, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(cnt, P->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> kap(P->m);
+    std::vector<int32_t> fl(P->m);
+    HQ_HIP(hipMemcpy(kap.data(), P->d_kappa, P->m * 8, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(fl.data(), P->d_bflags, P->m * 4, hipMemcpyDeviceToHost));
+    std::memset(info, 0, sizeof *info);
+    info->N = P->N;
+    info->m = P->m;
+    info->rows = P->rows;
+    info->internal_nodes = P->NI;
+    info->tiles = cnt[kCntTiles];
+    info->phases = cnt[kCntPhases];
+    info->device_flags = err;
+    info->tile_units = P->S;
+    info->store = P->store;
+    double mk = 0.0;
+    for (int64_t j = 0; j < P->m; ++j) {
+        double d;
+        std::memcpy(&d, &kap[j], 8);
+        mk = std::max(mk, d);
+        if (fl[j] & HQ_BODY_ILLCOND) ++info->ill_conditioned_bodies;
+        if (fl[j] & HQ_BODY_DEGENERATE) ++info->degenerate_bodies;
+    }
+    info->max_kappa = mk;
+    return HQ_OK;
+}
+
+hq_status hq_body_info(hq_handle h, int32_t *flags, double *kappa) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    HQ_HIP(hipDeviceSynchronize());
+    if (flags) HQ_HIP(hipMemcpy(flags, P->d_bflags, P->m * 4, hipMemcpyDeviceToHost));
+    if (kappa) HQ_HIP(hipMemcpy(kappa, P->d_kappa, P->m * 8, hipMemcpyDeviceToHost));
+    return HQ_OK;
+}
+
+hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchild, int32_t *ychild, int32_t *body,
+                       int32_t *nbeads, double *centroid, double *T22, double *G, int32_t *k, int32_t *row) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    const int64_t NI = P->NI;
+    HQ_HIP(hipDeviceSynchronize());
+    std::vector<int32_t> lc(NI), rc(NI), nbody(NI), fst(NI), lst(NI), nn(NI), sched(NI);
+    HQ_HIP(hipMemcpy(lc.data(), P->d_lc, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(rc.data(), P->d_rc, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(nbody.data(), P->d_nbody, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(fst.data(), P->d_first, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(lst.data(), P->d_last, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(nn.data(), P->d_nn, NI * 4, hipMemcpyDeviceToHost));
+    HQ_HIP(hipMemcpy(sched.data(), P->d_sched, NI * 4, hipMemcpyDeviceToHost));
+    std::vector<double> cen, t22, rec;
+    if (centroid) {
+        cen.resize(3 * NI);
+        HQ_HIP(hipMemcpy(cen.data(), P->d_ncen, 3 * NI * 8, hipMemcpyDeviceToHost));
+    }
+    if (T22) {
+        t22.resize(6 * NI);
+        HQ_HIP(hipMemcpy(t22.data(), P->d_T22, 6 * NI * 8, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> links;
+    if (G || row) {
+        links.resize(4 * NI);
+        HQ_HIP(hipMemcpy(links.data(), P->d_links, 4 * NI * 4, hipMemcpyDeviceToHost));
+    }
+    if (G) {
+        if (!(P->store & 1)) {
+            set_error("G needs the FP64 transforms");
+            return HQ_E_INVALID;
+        }
+        rec.resize((size_t)kRecWords * NI);
+        HQ_HIP(hipMemcpy(rec.data(), P->d_rec64, rec.size() * 8, hipMemcpyDeviceToHost));
+    }
+    for (int64_t g = 0; g < NI; ++g) {
+        const int j = nbody[g];
+        const int64_t b0 = P->offsets[j], g0 = b0 - j;
+        auto loc = [&](int c) -> int32_t {
+            if (c >= 0) return (int32_t)(c - g0);
+            return (int32_t)(-((-(c + 1)) - b0) - 1);
+        };
+        if (first) first[g] = (int32_t)(fst[g] - b0);
+        if (last) last[g] = (int32_t)(lst[g] - b0);
+        if (xchild) xchild[g] = loc(lc[g]);
+        if (ychild) ychild[g] = loc(rc[g]);
+        if (body) body[g] = j;
+        if (nbeads) nbeads[g] = nn[g];
+        const int kk = 3 + 3 * (lc[g] >= 0) + 3 * (rc[g] >= 0);
+        if (k) k[g] = kk;
+        if (centroid)
+            for (int d = 0; d < 3; ++d) centroid[3 * g + d] = cen[3 * g + d];
+        if (T22) {
+            const double *t = &t22[6 * g];
+            double M[9] = {t[0], 0, 0, t[1], t[2], 0, t[3], t[4], t[5]};
+            std::memcpy(T22 + 9 * g, M, sizeof M);
+        }
+        if (row) row[g] = links[4 * (size_t)sched[g] + 2] - (int32_t)P->row_off[j];
+        if (G) {
+            const double *r = &rec[(size_t)kRecWords * sched[g]];
+            double *Gg = G + 81 * g;
+            for (int i = 0; i < 81; ++i) Gg[i] = 0.0;
+            for (int col = 0; col < kk; ++col) {
+                double t[9] = {0};
+                t[col] = 1.0;
+                for (int jj = 0; jj < 3; ++jj) {
+                    const double *tl = r + tail_off(jj);
+                    double w = t[jj];
+                    for (int i = jj + 1; i < kk; ++i) w += tl[i - jj - 1] * t[i];
+                    w *= r[kRecTau + jj];
+                    t[jj] -= w;
+                    for (int i = jj + 1; i < kk; ++i) t[i] -= w * tl[i - jj - 1];
+                }
+                for (int i = 0; i < kk; ++i) Gg[9 * i + col] = t[i];
+            }
+        }
+    }
+    return HQ_OK;
+}
+
+hq_status hq_capture_begin(hq_stream stream) {
+    HQ_HIP(hipStreamBeginCapture(reinterpret_cast<hipStream_t>(stream), hipStreamCaptureModeRelaxed));
+    return HQ_OK;
+}
+
+hq_status hq_capture_end(hq_stream stream, void **graph_exec) {
+    if (!graph_exec) {
+        set_error("graph_exec is NULL");
+        return HQ_E_INVALID;
+    }
+    hipGraph_t g = nullptr;
+    HQ_HIP(hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        return HQ_E_DEVICE;
+    }
+    *graph_exec = reinterpret_cast<void *>(ex);
+    return HQ_OK;
+}
+
+hq_status hq_graph_launch(void *graph_exec, hq_stream stream) {
+    if (!graph_exec) {
+        set_error("graph_exec is NULL");
+        return HQ_E_INVALID;
+    }
+    HQ_HIP(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(graph_exec), reinterpret_cast<hipStream_t>(stream)));
+    return HQ_OK;
+}
+
+void hq_graph_destroy(void *graph_exec) {
+    if (graph_exec) hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec));
+}
+
+void hq_destroy(hq_handle h) {
+    Plan *P = reinterpret_cast<Plan *>(h);
+    if (!P || P->magic != kPlanMagic) return;
+    free_plan(P);
+}
+
+}  // extern "C"

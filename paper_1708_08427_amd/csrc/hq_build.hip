@@ -1,0 +1,801 @@
+// Setup of the hierarchical transforms on the GPU (Sections 2.1 and 3).
+//
+//   1. per-body bounding cube and 21-bit z-y-x interleaved box codes
+//   2. per-body sort of (code, position in body): LDS bitonic sort for
+//      segments of up to 8192 beads, pairwise merges above that
+//   3. binary radix tree per body (Karras' construction on the sorted codes,
+//      which is the nested-box bisection with empty halves pruned)
+//   4. tiles: the tree is cut into connected pieces of at most S "units"
+//      (beads or roots of earlier tiles); phase 1 takes the maximal subtrees
+//      of at most S beads, later phases repeat on what remains.  Inside a tile
+//      nodes are ordered by a post-order that visits the child with more
+//      units first, so a sweep needs at most floor(log2 S) + 1 pending results.
+//   5. per node in FP64: centroid, K = [T22_x | T22_y | sqrt(n_x n_y/n)
+//      [c_x - c_y]x] (Eq. 3.5 with the leaf cases of Cases I and II) and its
+//      Householder QR, giving T22 and G (Eqs. 3.6-3.8); FP64 and FP32 records
+//      in schedule order.
+#include "hq_common.h"
+
+#include <climits>
+
+namespace hq {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline unsigned long long ord_key(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ inline double ord_val(unsigned long long k) {
+    unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+__device__ inline void raise_flag(int32_t *err, int f) { atomicOr(err, f); }
+
+// ---------------------------------------------------------------------------
+// initialisation
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_init_bodies(int64_t m, unsigned long long *bmin, unsigned long long *bmax,
+                              unsigned long long *kappa, int32_t *bflags) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; ++d) {
+            bmin[3 * j + d] = ~0ull;
+            bmax[3 * j + d] = 0ull;
+        }
+        kappa[j] = 0ull;
+        bflags[j] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. bounding boxes and codes
+// ---------------------------------------------------------------------------
+__device__ inline double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_bbox(const int32_t *__restrict__ chunks, const double *__restrict__ pos,
+                                                   unsigned long long *bmin, unsigned long long *bmax, int32_t *err) {
+    __shared__ double smn[3][kThreads / 64], smx[3][kThreads / 64];
+    const int body = chunks[3 * blockIdx.x], b0 = chunks[3 * blockIdx.x + 1], b1 = chunks[3 * blockIdx.x + 2];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        for (int d = 0; d < 3; ++d) {
+            double x = pos[3 * (int64_t)i + d];
+            if (!isfinite(x)) bad = true;
+            mn[d] = fmin(mn[d], x);
+            mx[d] = fmax(mx[d], x);
+        }
+    }
+    if (bad) raise_flag(err, kFlagNonFinite);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        double a = wave_min(mn[d]), b = wave_max(mx[d]);
+        if (lane == 0) { smn[d][wid] = a; smx[d][wid] = b; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        double a = smn[d][0], b = smx[d][0];
+        for (int w = 1; w < kThreads / 64; ++w) { a = fmin(a, smn[d][w]); b = fmax(b, smx[d][w]); }
+        if (a <= b) {
+            atomicMin(&bmin[3 * body + d], ord_key(a));
+            atomicMax(&bmax[3 * body + d], ord_key(b));
+        }
+    }
+}
+
+// Spread the low 21 bits of x to every third bit.
+__device__ inline unsigned long long spread3(unsigned long long x) {
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline unsigned int quantise(double x, double lo, double h) {
+    if (!(h > 0.0)) return 0u;
+    double t = ((x - lo) / h) * 2097152.0;  // 2^21
+    double f = floor(t);
+    f = fmin(fmax(f, 0.0), 2097151.0);
+    return (unsigned int)f;
+}
+
+__global__ void __launch_bounds__(kThreads) k_codes(const int32_t *__restrict__ chunks, const int32_t *__restrict__ bead_off,
+                                                    const double *__restrict__ pos, const unsigned long long *__restrict__ bmin,
+                                                    const unsigned long long *__restrict__ bmax, double *lo_out, double *h_out,
+                                                    unsigned long long *__restrict__ key, int32_t *__restrict__ val) {
+    const int body = chunks[3 * blockIdx.x], b0 = chunks[3 * blockIdx.x + 1], b1 = chunks[3 * blockIdx.x + 2];
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = ord_val(bmin[3 * body + d]);
+        hi[d] = ord_val(bmax[3 * body + d]);
+    }
+    double h = 0.0;
+    for (int d = 0; d < 3; ++d) h = fmax(h, hi[d] - lo[d]);
+    if (!(h >= 0.0)) h = 0.0;
+    const int start = bead_off[body];
+    if (b0 == start && threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) lo_out[3 * body + d] = lo[d];
+        h_out[body] = h;
+    }
+    for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        unsigned int qx = quantise(pos[3 * (int64_t)i + 0], lo[0], h);
+        unsigned int qy = quantise(pos[3 * (int64_t)i + 1], lo[1], h);
+        unsigned int qz = quantise(pos[3 * (int64_t)i + 2], lo[2], h);
+        key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+        val[i] = i - start;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. per-body sort of (code, position in body)
+// ---------------------------------------------------------------------------
+__device__ inline bool key_less(unsigned long long ka, unsigned int va, unsigned long long kb, unsigned int vb) {
+    return ka < kb || (ka == kb && va < vb);
+}
+
+// seg: (start, len, body) triples; every len <= npad.  final: write sorted
+// codes and the caller's bead index; otherwise write the sorted run back.
+__global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad, int final_out, unsigned long long *keys,
+                           int32_t *vals, const int32_t *__restrict__ bead_off, unsigned long long *scode,
+                           int32_t *perm) {
+    extern __shared__ unsigned char smem[];
+    unsigned long long *K = reinterpret_cast<unsigned long long *>(smem);
+    unsigned int *V = reinterpret_cast<unsigned int *>(smem + sizeof(unsigned long long) * npad);
+    const int start = seg[3 * blockIdx.x], len = seg[3 * blockIdx.x + 1], body = seg[3 * blockIdx.x + 2];
+    for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+        if (i < len) {
+            K[i] = keys[start + i];
+            V[i] = (unsigned int)vals[start + i];
+        } else {
+            K[i] = ~0ull;
+            V[i] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= npad; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    unsigned long long ka = K[i], kb = K[ixj];
+                    unsigned int va = V[i], vb = V[ixj];
+                    bool up = (i & k) == 0;
+                    bool gt = key_less(kb, vb, ka, va);
+                    if (gt == up) {
+                        K[i] = kb; K[ixj] = ka;
+                        V[i] = vb; V[ixj] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (final_out) {
+        const int base = bead_off[body];
+        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+            scode[start + i] = K[i];
+            perm[start + i] = base + (int)V[i];
+        }
+    } else {
+        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+            keys[start + i] = K[i];
+            vals[start + i] = (int)V[i];
+        }
+    }
+}
+
+__device__ inline int find_large(const int64_t *prefix, int nlarge, int64_t e) {
+    int lo = 0, hi = nlarge - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One pairwise merge of sorted runs of length L inside each large body; an
+// element's output position is its rank in its run plus the number of smaller
+// elements in the partner run (keys are unique).
+__global__ void k_merge_pass(const int32_t *__restrict__ large, const int64_t *__restrict__ prefix, int nlarge,
+                             int64_t total, const int32_t *__restrict__ bead_off, int L,
+                             const unsigned long long *__restrict__ kin, const int32_t *__restrict__ vin,
+                             unsigned long long *__restrict__ kout, int32_t *__restrict__ vout) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int li = find_large(prefix, nlarge, e);
+        const int body = large[li];
+        const int start = bead_off[body], n = bead_off[body + 1] - start;
+        const int i = (int)(e - prefix[li]);
+        const int r = i / L, partner = r ^ 1;
+        const int pstart = partner * L;
+        const unsigned long long k = kin[start + i];
+        const int v = vin[start + i];
+        if (pstart >= n) {
+            kout[start + i] = k;
+            vout[start + i] = v;
+            continue;
+        }
+        const int plen = min(L, n - pstart);
+        int lo = 0, hi = plen;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            unsigned long long pk = kin[start + pstart + mid];
+            unsigned int pv = (unsigned int)vin[start + pstart + mid];
+            if (key_less(pk, pv, k, (unsigned int)v)) lo = mid + 1; else hi = mid;
+        }
+        const int out = min(r, partner) * L + (i - r * L) + lo;
+        kout[start + out] = k;
+        vout[start + out] = v;
+    }
+}
+
+__global__ void k_large_final(const int32_t *__restrict__ large, const int64_t *__restrict__ prefix, int nlarge,
+                              int64_t total, const int32_t *__restrict__ bead_off,
+                              const unsigned long long *__restrict__ kin, const int32_t *__restrict__ vin,
+                              unsigned long long *__restrict__ scode, int32_t *__restrict__ perm) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int li = find_large(prefix, nlarge, e);
+        const int body = large[li];
+        const int start = bead_off[body];
+        const int i = (int)(e - prefix[li]);
+        scode[start + i] = kin[start + i];
+        perm[start + i] = start + vin[start + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. binary radix tree (Karras 2012) over each body's sorted keys
+// ---------------------------------------------------------------------------
+__device__ inline int body_of_node(const int32_t *node_off, int m, int g) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (node_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Length of the common prefix of the keys (code, position) at i and j.
+__device__ inline int prefix_len(const unsigned long long *sc, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    unsigned long long a = sc[i], b = sc[j];
+    if (a != b) return __clzll((long long)(a ^ b));
+    return 64 + __clz(i ^ j);
+}
+
+__global__ void k_tree(int64_t NI, int m, const int32_t *__restrict__ bead_off, const int32_t *__restrict__ node_off,
+                       const unsigned long long *__restrict__ scode, int32_t *lc, int32_t *rc, int32_t *par,
+                       int32_t *first, int32_t *last, int32_t *nn, int32_t *nbody, int32_t *leafpar) {
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)gg;
+        const int j = body_of_node(node_off, m, g);
+        const int i = g - node_off[j];
+        const int base = bead_off[j], n = bead_off[j + 1] - base;
+        const unsigned long long *sc = scode + base;
+        const int d = (prefix_len(sc, n, i, i + 1) - prefix_len(sc, n, i, i - 1)) > 0 ? 1 : -1;
+        const int dmin = prefix_len(sc, n, i, i - d);
+        int lmax = 2;
+        while (prefix_len(sc, n, i, i + lmax * d) > dmin) lmax <<= 1;
+        int l = 0;
+        for (int t = lmax >> 1; t >= 1; t >>= 1)
+            if (prefix_len(sc, n, i, i + (l + t) * d) > dmin) l += t;
+        const int jj = i + l * d;
+        const int dnode = prefix_len(sc, n, i, jj);
+        int s = 0, t = l;
+        do {
+            t = (t + 1) >> 1;
+            if (prefix_len(sc, n, i, i + (s + t) * d) > dnode) s += t;
+        } while (t > 1);
+        const int gamma = i + s * d + min(d, 0);
+        const int lo = min(i, jj), hi = max(i, jj);
+        int left, right;
+        if (lo == gamma) {
+            left = -(base + gamma) - 1;
+            leafpar[base + gamma] = g;
+        } else {
+            left = node_off[j] + gamma;
+            par[left] = g;
+        }
+        if (hi == gamma + 1) {
+            right = -(base + gamma + 1) - 1;
+            leafpar[base + gamma + 1] = g;
+        } else {
+            right = node_off[j] + gamma + 1;
+            par[right] = g;
+        }
+        lc[g] = left;
+        rc[g] = right;
+        first[g] = base + lo;
+        last[g] = base + hi;
+        nn[g] = hi - lo + 1;
+        nbody[g] = j;
+        if (i == 0) par[g] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. tiles
+// ---------------------------------------------------------------------------
+__device__ inline int units_of(int g, int phase, const int32_t *nn, const int32_t *first, const int32_t *last,
+                               const int32_t *msum) {
+    if (phase == 1) return nn[g];
+    const int f = first[g], l = last[g];
+    return msum[l] - (f > 0 ? msum[f - 1] : 0);
+}
+
+// units of a child of an uncovered node: a bead or an earlier tile's root
+// counts as one unit
+__device__ inline int child_units(int c, const int32_t *cov, const int32_t *units) {
+    if (c < 0) return 1;
+    if (cov[c] != 0) return 1;
+    return units[c];
+}
+
+__global__ void k_mark_beads(int64_t N, const int32_t *leafpar, const int32_t *cov, int32_t *mark) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        mark[i] = (cov[leafpar[i]] == 0) ? 1 : 0;
+}
+
+__global__ void k_mark_roots(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *first, int32_t *mark) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x) {
+        const int p = par[g];
+        if (cov[g] != 0 && p >= 0 && cov[p] == 0) mark[first[g]] = 1;
+    }
+}
+
+__global__ void k_tile_roots(int64_t NI, int phase, int S, const int32_t *cov, const int32_t *par,
+                             const int32_t *nn, const int32_t *first, const int32_t *last, const int32_t *msum,
+                             int32_t *units, long long *trval) {
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)gg;
+        if (cov[g] != 0) {
+            trval[g] = 0;
+            continue;
+        }
+        const int u = units_of(g, phase, nn, first, last, msum);
+        const int p = par[g];
+        const int up = (p < 0) ? INT_MAX : units_of(p, phase, nn, first, last, msum);
+        units[g] = u;
+        const bool root = (u <= S) && (up > S);
+        trval[g] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
+    }
+}
+
+__global__ void k_tile_emit(int64_t NI, const long long *trval, const long long *trscan, const int32_t *cnt,
+                            int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof) {
+    const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const long long v = trval[gg];
+        if (v == 0) continue;
+        const long long sc = trscan[gg];
+        const int t = tiles0 + (int)(sc >> 32);
+        tile_root[t] = (int)gg;
+        tile_len[t] = (int)(v & 0xffffffffll);
+        tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
+        tileof[gg] = t;
+    }
+}
+
+// Post-order position of every uncovered node inside the tile whose root it
+// reaches first going up; the child with more units is evaluated first.
+__global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc, const int32_t *rc,
+                         const int32_t *units, const long long *trval, const int32_t *tile_base,
+                         int32_t *tileof, int32_t *sched, int32_t *sched_node, int32_t *yfirst, int32_t *err,
+                         int64_t sched_cap) {
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)gg;
+        if (cov[g] != 0) continue;
+        {
+            const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
+            yfirst[g] = (uy > ux) ? 1 : 0;
+        }
+        int pos = units[g] - 2;
+        int q = g;
+        bool found = false;
+        bool too_deep = true;
+        for (int guard = 0; guard < kMaxDepth; ++guard) {
+            if (trval[q] != 0) { found = true; too_deep = false; break; }
+            const int p = par[q];
+            if (p < 0) { too_deep = false; break; }
+            const int x = lc[p], y = rc[p];
+            const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
+            const bool y_first = uy > ux;
+            const int second = y_first ? x : y;
+            if (q == second) pos += (y_first ? uy : ux) - 1;
+            q = p;
+        }
+        if (too_deep) raise_flag(err, kFlagBounds);
+        if (!found) continue;
+        const int t = tileof[q];
+        const int64_t s = (int64_t)tile_base[t] + pos;
+        if (pos < 0 || s < 0 || s >= sched_cap) {
+            raise_flag(err, kFlagBounds);
+            continue;
+        }
+        tileof[g] = t;
+        sched[g] = (int)s;
+        sched_node[s] = g;
+    }
+}
+
+__global__ void k_commit(int64_t NI, int phase, int32_t *cov, const int32_t *tileof) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x)
+        if (cov[g] == 0 && tileof[g] >= 0) cov[g] = phase;
+}
+
+__global__ void k_phase_close(int64_t NI, int phase, const long long *trval, const long long *trscan,
+                              int32_t *cnt, int32_t *phase_tab) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long long tot = (NI > 0) ? trscan[NI - 1] + trval[NI - 1] : 0;
+    const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
+    phase_tab[2 * phase] = cnt[kCntTiles];
+    phase_tab[2 * phase + 1] = cnt[kCntTiles] + ntiles;
+    cnt[kCntTiles] += ntiles;
+    cnt[kCntNodes] += nnodes;
+    if (ntiles > 0) cnt[kCntPhases] = phase;
+    cnt[kCntRemain] = (int)(NI - cnt[kCntNodes]);
+}
+
+__global__ void k_check_phases(int32_t *cnt, int32_t *err) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[kCntRemain] != 0) raise_flag(err, kFlagPhases);
+}
+
+// Links of every node: child references, residue row (pre-order, Section 3's
+// Q~_p = [Residue_p; diag(Q~_x, Q~_y)]) and flags.
+__global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, const int32_t *sched,
+                        const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
+                        const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
+                        const int32_t *perm, const int32_t *row_off, int32_t *links, int32_t *err) {
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)gg;
+        if (cov[g] == 0) continue;
+        const int t = tileof[g];
+        int ref[2];
+        const int ch[2] = {lc[g], rc[g]};
+        for (int c = 0; c < 2; ++c) {
+            const int x = ch[c];
+            if (x < 0) ref[c] = perm[-(x + 1)];
+            else if (cov[x] == cov[g] && tileof[x] == t) ref[c] = kRefStack;
+            else ref[c] = -2 - tileof[x];
+        }
+        int off = 0, q = g;
+        for (int guard = 0; guard <= kMaxDepth; ++guard) {
+            if (guard == kMaxDepth) {
+                raise_flag(err, kFlagBounds);
+                break;
+            }
+            const int p = par[q];
+            if (p < 0) break;
+            const int x = lc[p], y = rc[p];
+            const int xi = x >= 0, yi = y >= 0;
+            off += 3 * xi + 3 * yi;
+            if (q == y && xi) off += 3 * nn[x] - 6;
+            q = p;
+        }
+        off += row_off[nbody[g]];
+        int meta = 0;
+        if (tile_root[t] == g) meta |= kMetaTileRoot | (t << kMetaSlotShift);
+        if (par[g] < 0) meta |= kMetaBodyRoot;
+        if (yfirst[g]) meta |= kMetaYFirst;
+        const int s = sched[g];
+        links[4 * s + 0] = ref[0];
+        links[4 * s + 1] = ref[1];
+        links[4 * s + 2] = off;
+        links[4 * s + 3] = meta;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. FP64 transforms (Eqs. 3.4-3.13), one lane per tile, nodes in schedule order
+// ---------------------------------------------------------------------------
+// Eigenvalues of a symmetric 3x3 matrix (trigonometric closed form, Smith
+// 1961); returns sqrt(lmax / lmin) or a huge value when lmin <= 0.
+__device__ double cond_lower3(const double T[6]) {
+    const double a = T[0], b = T[1], c = T[2], d = T[3], e = T[4], f = T[5];
+    const double s00 = a * a + b * b + d * d, s01 = b * c + d * e, s02 = d * f;
+    const double s11 = c * c + e * e, s12 = e * f, s22 = f * f;
+    const double p1 = s01 * s01 + s02 * s02 + s12 * s12;
+    const double q = (s00 + s11 + s22) / 3.0;
+    const double p2 = (s00 - q) * (s00 - q) + (s11 - q) * (s11 - q) + (s22 - q) * (s22 - q) + 2.0 * p1;
+    const double p = sqrt(p2 / 6.0);
+    if (!(p > 0.0)) return (q > 0.0) ? 1.0 : 1e300;
+    const double b00 = (s00 - q) / p, b11 = (s11 - q) / p, b22 = (s22 - q) / p;
+    const double b01 = s01 / p, b02 = s02 / p, b12 = s12 / p;
+    double r = 0.5 * (b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02));
+    r = fmin(fmax(r, -1.0), 1.0);
+    const double phi = acos(r) / 3.0;
+    const double l1 = q + 2.0 * p * cos(phi);
+    const double l3 = q + 2.0 * p * cos(phi + 2.0943951023931957);
+    if (!(l3 > 0.0)) return 1e300;
+    return sqrt(l1 / l3);
+}
+
+__global__ void __launch_bounds__(64) k_gen(int phase, const int32_t *phase_tab, const int32_t *tile_base,
+                                            const int32_t *tile_len, const int32_t *sched_node,
+                                            const int32_t *links, const int32_t *lc, const int32_t *rc,
+                                            const int32_t *nbody, const int32_t *nn_arr, const double *pos,
+                                            const double *lo, double *ncen, double *T22, float *rec32,
+                                            double *rec64, int store, double *bcen,
+                                            unsigned long long *kappa, int32_t *bflags, int64_t N, int64_t NI,
+                                            int32_t *err) {
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    for (int t = tb + blockIdx.x * blockDim.x + threadIdx.x; t < te; t += gridDim.x * blockDim.x) {
+        const int base = tile_base[t], len = tile_len[t];
+        if (base < 0 || len < 0 || (int64_t)base + len > NI) {
+            raise_flag(err, kFlagBounds);
+            continue;
+        }
+        for (int s = base; s < base + len; ++s) {
+            const int g = sched_node[s];
+            if (g < 0 || g >= NI) {
+                raise_flag(err, kFlagBounds);
+                continue;
+            }
+            const int body = nbody[g];
+            const int ch[2] = {lc[g], rc[g]};
+            const int *lk = links + 4 * s;
+            double cc[2][3], Tc[2][6];
+            double ncnt[2];
+            bool internal[2];
+            for (int c = 0; c < 2; ++c) {
+                const int x = ch[c];
+                internal[c] = x >= 0;
+                if (x >= 0) {
+                    ncnt[c] = (double)nn_arr[x];
+                    for (int d = 0; d < 3; ++d) cc[c][d] = ncen[3 * (int64_t)x + d];
+                    for (int d = 0; d < 6; ++d) Tc[c][d] = T22[6 * (int64_t)x + d];
+                } else {
+                    const int u = lk[c];
+                    if (u < 0 || u >= N) {
+                        raise_flag(err, kFlagBounds);
+                        ncnt[c] = 1.0;
+                        for (int d = 0; d < 3; ++d) cc[c][d] = 0.0;
+                        continue;
+                    }
+                    ncnt[c] = 1.0;
+                    for (int d = 0; d < 3; ++d) cc[c][d] = pos[3 * (int64_t)u + d] - lo[3 * body + d];
+                }
+            }
+            const double nx = ncnt[0], ny = ncnt[1], n = nx + ny;
+            double cp[3], dv[3];
+            for (int d = 0; d < 3; ++d) {
+                cp[d] = (nx * cc[0][d] + ny * cc[1][d]) / n;
+                dv[d] = cc[0][d] - cc[1][d];
+            }
+            // A = K^T, rows packed: x's T22 columns, y's T22 columns, then D
+            double A[9][3];
+            for (int i = 0; i < 9; ++i) A[i][0] = A[i][1] = A[i][2] = 0.0;
+            int k = 0;
+            for (int c = 0; c < 2; ++c) {
+                if (!internal[c]) continue;
+                const double *T = Tc[c];
+                // K block column jj = T22 column jj -> A row k+jj = (T[0][jj], T[1][jj], T[2][jj])
+                A[k + 0][0] = T[0]; A[k + 0][1] = T[1]; A[k + 0][2] = T[3];
+                A[k + 1][0] = 0.0;  A[k + 1][1] = T[2]; A[k + 1][2] = T[4];
+                A[k + 2][0] = 0.0;  A[k + 2][1] = 0.0;  A[k + 2][2] = T[5];
+                k += 3;
+            }
+            {
+                const double sc = sqrt(nx * ny / n);
+                // D = sc [d]x ; A row k+jj = D column jj
+                A[k + 0][0] = 0.0;          A[k + 0][1] = sc * dv[2];   A[k + 0][2] = -sc * dv[1];
+                A[k + 1][0] = -sc * dv[2];  A[k + 1][1] = 0.0;          A[k + 1][2] = sc * dv[0];
+                A[k + 2][0] = sc * dv[1];   A[k + 2][1] = -sc * dv[0];  A[k + 2][2] = 0.0;
+                k += 3;
+            }
+            double tail[3][8], tau[3];
+            for (int j = 0; j < 3; ++j) {
+                for (int i = 0; i < 8; ++i) tail[j][i] = 0.0;
+                const double alpha = A[j][j];
+                double xs = 0.0;
+                for (int i = j + 1; i < 9; ++i) xs = fma(A[i][j], A[i][j], xs);
+                if (xs == 0.0) {
+                    tau[j] = 0.0;
+                    continue;
+                }
+                const double nrm = sqrt(fma(alpha, alpha, xs));
+                const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                tau[j] = (beta - alpha) / beta;
+                const double scal = 1.0 / (alpha - beta);
+                for (int i = j + 1; i < 9; ++i) tail[j][i - j - 1] = A[i][j] * scal;
+                A[j][j] = beta;
+                for (int l = j + 1; l < 3; ++l) {
+                    double w = A[j][l];
+                    for (int i = j + 1; i < 9; ++i) w = fma(tail[j][i - j - 1], A[i][l], w);
+                    w *= tau[j];
+                    A[j][l] -= w;
+                    for (int i = j + 1; i < 9; ++i) A[i][l] = fma(-w, tail[j][i - j - 1], A[i][l]);
+                }
+            }
+            double T[6];
+            T[0] = A[0][0];
+            T[1] = A[0][1];
+            T[2] = A[1][1];
+            T[3] = A[0][2];
+            T[4] = A[1][2];
+            T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
+            for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
+            for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
+            const double sx = sqrt(nx / n), sy = sqrt(ny / n);
+            double r[26];
+            for (int i = 0; i < 8; ++i) r[i] = tail[0][i];
+            for (int i = 0; i < 7; ++i) r[8 + i] = tail[1][i];
+            for (int i = 0; i < 6; ++i) r[15 + i] = tail[2][i];
+            r[21] = tau[0]; r[22] = tau[1]; r[23] = tau[2];
+            r[24] = sx; r[25] = sy;
+            if (store & 1) {
+                double *o = rec64 + (int64_t)kRecWords * s;
+                for (int i = 0; i < 26; ++i) o[i] = r[i];
+                int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
+                for (int i = 0; i < 4; ++i) ol[i] = lk[i];
+            }
+            if (store & 2) {
+                float *o = rec32 + (int64_t)kRecWords * s;
+                for (int i = 0; i < 26; ++i) o[i] = (float)r[i];
+                int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
+                for (int i = 0; i < 4; ++i) ol[i] = lk[i];
+            }
+            const bool body_root = (lk[3] & kMetaBodyRoot) != 0;
+            if (k > 3 || body_root) {
+                const double kap = (k > 3) ? cond_lower3(T) : 1e300;
+                if (k > 3) atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kap));
+                if (k > 3 && kap > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
+                if (body_root && kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+            }
+            if (body_root)
+                for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
+        }
+    }
+}
+
+// Rigid motion: r <- Rot (r - c) + c + t per body.
+__global__ void __launch_bounds__(kThreads) k_rigid(const int32_t *__restrict__ chunks, double *pos,
+                                                    const double *__restrict__ rot, const double *__restrict__ trans,
+                                                    const double *__restrict__ bcen) {
+    const int body = chunks[3 * blockIdx.x], b0 = chunks[3 * blockIdx.x + 1], b1 = chunks[3 * blockIdx.x + 2];
+    double R[9], c[3], t[3];
+    for (int i = 0; i < 9; ++i) R[i] = rot[9 * body + i];
+    for (int d = 0; d < 3; ++d) { c[d] = bcen[3 * body + d]; t[d] = trans[3 * body + d]; }
+    for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = pos[3 * (int64_t)i + d] - c[d];
+        for (int d = 0; d < 3; ++d)
+            pos[3 * (int64_t)i + d] = R[3 * d] * x[0] + R[3 * d + 1] * x[1] + R[3 * d + 2] * x[2] + c[d] + t[d];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int threads = kThreads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases) {
+    const int64_t N = P.N, m = P.m, NI = P.NI;
+    if (probe_phases) {
+        HQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_sort),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSortLdsMax * 12));
+    }
+    // --- init
+    hipLaunchKernelGGL(k_init_bodies, dim3(grid_for(m)), dim3(kThreads), 0, s, m, P.d_bmin, P.d_bmax, P.d_kappa,
+                       P.d_bflags);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_cov, NI, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_tileof, NI, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_sched_node, NI, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, P.d_cnt, (int64_t)kCntNum, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_phase, (int64_t)(2 * kMaxPhases), 0);
+    // --- 1. boxes and codes
+    hipLaunchKernelGGL(k_bbox, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, P.d_bmin, P.d_bmax, P.d_err);
+    hipLaunchKernelGGL(k_codes, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, P.d_bead_off, pos, P.d_bmin,
+                       P.d_bmax, P.d_lo, P.d_h, P.d_keyA, P.d_valA);
+    // --- 2. sort
+    for (auto &c : P.sort_small) {
+        const int thr = std::min(1024, std::max(64, c.npad / 2));
+        hipLaunchKernelGGL(k_lds_sort, dim3(c.nseg), dim3(thr), (size_t)c.npad * 12, s, c.d_seg, c.npad, 1,
+                           P.d_keyA, P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
+    }
+    if (P.nlarge > 0) {
+        for (auto &c : P.sort_chunks) {
+            const int thr = std::min(1024, std::max(64, c.npad / 2));
+            hipLaunchKernelGGL(k_lds_sort, dim3(c.nseg), dim3(thr), (size_t)c.npad * 12, s, c.d_seg, c.npad, 0,
+                               P.d_keyA, P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
+        }
+        unsigned long long *kin = P.d_keyA, *kout = P.d_keyB;
+        int32_t *vin = P.d_valA, *vout = P.d_valB;
+        int L = kSortLdsMax;
+        for (int p = 0; p < P.large_passes; ++p) {
+            hipLaunchKernelGGL(k_merge_pass, dim3(grid_for(P.large_elems)), dim3(kThreads), 0, s, P.d_large,
+                               P.d_large_prefix, P.nlarge, P.large_elems, P.d_bead_off, L, kin, vin, kout, vout);
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+            L *= 2;
+        }
+        hipLaunchKernelGGL(k_large_final, dim3(grid_for(P.large_elems)), dim3(kThreads), 0, s, P.d_large,
+                           P.d_large_prefix, P.nlarge, P.large_elems, P.d_bead_off, kin, vin, P.d_scode, P.d_perm);
+    }
+    // --- 3. tree
+    hipLaunchKernelGGL(k_tree, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, (int)m, P.d_bead_off, P.d_node_off,
+                       P.d_scode, P.d_lc, P.d_rc, P.d_par, P.d_first, P.d_last, P.d_nn, P.d_nbody, P.d_leafpar);
+    HQ_HIP(hipGetLastError());
+    // --- 4. tiles
+    int phases = 0;
+    const int max_ph = probe_phases ? (kMaxPhases - 1) : P.phases_reserved;
+    for (int ph = 1; ph <= max_ph; ++ph) {
+        if (ph >= 2) {
+            hipLaunchKernelGGL(k_mark_beads, dim3(grid_for(N)), dim3(kThreads), 0, s, N, P.d_leafpar, P.d_cov,
+                               P.d_mark);
+            hipLaunchKernelGGL(k_mark_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par,
+                               P.d_first, P.d_mark);
+            HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, N, s));
+        }
+        hipLaunchKernelGGL(k_tile_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.S, P.d_cov, P.d_par,
+                           P.d_nn, P.d_first, P.d_last, P.d_msum, P.d_units, P.d_trval);
+        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s));
+        hipLaunchKernelGGL(k_tile_emit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_trval, P.d_trscan,
+                           P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof);
+        hipLaunchKernelGGL(k_assign, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par, P.d_lc,
+                           P.d_rc, P.d_units, P.d_trval, P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node,
+                           P.d_yfirst, P.d_err, NI);
+        hipLaunchKernelGGL(k_commit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.d_cov, P.d_tileof);
+        hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, ph, P.d_trval, P.d_trscan, P.d_cnt,
+                           P.d_phase);
+        HQ_HIP(hipGetLastError());
+        phases = ph;
+        if (probe_phases) {
+            int32_t cnt[kCntNum];
+            HQ_HIP(hipMemcpyAsync(cnt, P.d_cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
+            HQ_HIP(hipStreamSynchronize(s));
+            if (cnt[kCntRemain] == 0) {
+                P.tiles_built = cnt[kCntTiles];
+                break;
+            }
+            if (ph == max_ph) {
+                set_error("tree needs more tile phases than supported");
+                return HQ_E_UNSUPPORTED;
+            }
+        }
+    }
+    if (probe_phases) P.phases_built = phases;
+    hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
+    hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
+                       P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
+                       P.d_row_off, P.d_links, P.d_err);
+    // --- 5. transforms, phase by phase (children before parents)
+    for (int ph = 1; ph <= phases; ++ph) {
+        hipLaunchKernelGGL(k_gen, dim3(1024), dim3(64), 0, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len,
+                           P.d_sched_node, P.d_links, P.d_lc, P.d_rc, P.d_nbody, P.d_nn, pos, P.d_lo, P.d_ncen,
+                           P.d_T22, P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kappa, P.d_bflags, N, NI, P.d_err);
+    }
+    HQ_HIP(hipGetLastError());
+    return HQ_OK;
+}
+
+hq_status rigid_update(Plan &P, double *pos, const double *rot, const double *trans, hipStream_t s) {
+    hipLaunchKernelGGL(k_rigid, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, rot, trans, P.d_cen);
+    HQ_HIP(hipGetLastError());
+    return HQ_OK;
+}
+
+}  // namespace hq

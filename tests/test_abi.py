@@ -1,0 +1,79 @@
+"""The C ABI library: every symbol declared in include/hq.h is exported, and
+argument errors are rejected on the host before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hq_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1708_08427_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libhq.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_1708_08427_amd import _lib
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert set(declared_functions()) == bound
+
+
+def test_status_strings(lib):
+    assert lib.hq_status_string(0) == b"HQ_OK"
+    assert lib.hq_status_string(5) == b"HQ_E_UNSUPPORTED"
+
+
+def _build(lib, offsets, pos_ptr=1):
+    off = np.asarray(offsets, dtype=np.int64)
+    h = ctypes.c_void_p()
+    st = lib.hq_build(ctypes.c_void_p(pos_ptr), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      len(off) - 1, None, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("offsets", [[1, 5], [0, 1], [0, 4, 5], [0, 4, 3], [0]])
+def test_invalid_offsets_rejected_on_host(lib, offsets):
+    st, h = _build(lib, offsets)
+    assert st == 1 and not h.value
+    assert lib.hq_last_error()
+
+
+def test_null_arguments_rejected(lib):
+    off = np.array([0, 4], dtype=np.int64)
+    h = ctypes.c_void_p()
+    assert lib.hq_build(None, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, None, None,
+                        ctypes.byref(h)) == 1
+    assert lib.hq_build(ctypes.c_void_p(1), None, 1, None, None, ctypes.byref(h)) == 1
+    assert lib.hq_apply(None, None, None, 0, 1, 0, None) == 1
+    assert lib.hq_query(None, None) == 1
+    lib.hq_destroy(None)
+
+
+def test_bad_options_rejected(lib):
+    from paper_1708_08427_amd._lib import Options
+    off = np.array([0, 4], dtype=np.int64)
+    h = ctypes.c_void_p()
+    for opt in (Options(1, 0, 0, 0), Options(4096, 0, 0, 0), Options(0, 7, 0, 0), Options(0, 0, 0, 99)):
+        st = lib.hq_build(ctypes.c_void_p(1), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1,
+                          ctypes.byref(opt), None, ctypes.byref(h))
+        assert st == 1

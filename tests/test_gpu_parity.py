@@ -1,0 +1,205 @@
+"""GPU path against the FP64 oracle, element by element on seeded inputs.
+
+Tolerances: FP64 products <= 1e-12 relative 2-norm per (body, RHS) against the
+hierarchical oracle; FP32 products and the leak ||Z (Q~^T w)|| / (||Z|| ||w||)
+<= 1e-5 against FP64.  Tree and permutation (index work) are bit-exact.
+Bodies whose oracle has an ill-conditioned node (kappa(T22) > 1e4) are
+compared on the basis-free projector instead, because their Q~ basis is not
+determined beyond rounding.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, hier
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import paper_1708_08427_amd as hq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return hq
+
+
+def build(hq, w, **kw):
+    print(f"[gpu] build {w.name} N={w.N} m={w.m} {kw}", flush=True)
+    h = hq.build(_dev(w.pos), w.offsets, **kw)
+    q = h.query()
+    assert q["device_flags"] == 0, q
+    return h
+
+
+def rel_per_body(a, b, offsets, scale_rows):
+    """max over bodies and RHS of ||a_j - b_j|| / ||b_j|| on row blocks."""
+    worst = 0.0
+    for j in range(len(offsets) - 1):
+        r0, r1 = scale_rows[j], scale_rows[j + 1]
+        if r1 == r0:
+            continue
+        d = np.linalg.norm(a[r0:r1] - b[r0:r1], axis=0)
+        n = np.maximum(np.linalg.norm(b[r0:r1], axis=0), 1e-300)
+        worst = max(worst, float((d / n).max()))
+    return worst
+
+
+def oracle_products(w, v, wv):
+    bt = hier.Batch(w.pos, w.offsets)
+    return bt, bt.apply(v), bt.apply(wv, transpose=True)
+
+
+def check_fp64(hq, w, S=0, nrhs=None):
+    rng = np.random.default_rng(123)
+    R = nrhs or w.nrhs
+    v = rng.standard_normal((3 * w.N, R))
+    wv = rng.standard_normal((w.rows, R))
+    h = build(hq, w, tile_units=S)
+    bt, up_o, dn_o = oracle_products(w, v, wv)
+    up = h.apply(_dev(v)).cpu().numpy()
+    dn = h.apply(_dev(wv), transpose=True).cpu().numpy()
+    assert h.query()["device_flags"] == 0
+    rows = h.row_offsets
+    beads3 = 3 * w.offsets
+    ill = np.array([b.max_kappa > 1e4 for b in bt.bodies])
+    if not ill.any():
+        assert rel_per_body(up, up_o, w.offsets, rows) <= 1e-12
+        assert rel_per_body(dn, dn_o, w.offsets, beads3) <= 1e-12
+    # projector round trip per body is basis-free
+    pr = h.apply(h.apply(_dev(v)), transpose=True).cpu().numpy()
+    for j in range(w.m):
+        b0, b1 = beads3[j], beads3[j + 1]
+        pj = w.pos[w.offsets[j]:w.offsets[j + 1]]
+        if dense.rank(pj) < 6:
+            continue  # rank-5 body (two beads, collinear): Q~ spans less than the complement
+        want = dense.project(pj, v[b0:b1])
+        assert np.abs(pr[b0:b1] - want).max() <= 1e-12 * max(1.0, np.abs(v[b0:b1]).max())
+    return h
+
+
+def test_sphere_n64_fp64(hq):
+    w = W.sphere_n64()
+    check_fp64(hq, w, nrhs=3)
+
+
+def test_tree_and_transforms_match_oracle(hq):
+    """Tree (bit-exact), bead order (bit-exact), per-node T22 and G."""
+    w = W.small_batch(7, [2, 3, 5, 64, 300, 1100])
+    h = build(hq, w, tile_units=64)
+    nd = h.node_data()
+    bt = hier.Batch(w.pos, w.offsets)
+    for j, b in enumerate(bt.bodies):
+        assert np.array_equal(h.sorted_beads(j), b.perm())
+        onodes = b.nodes()
+        by_range = {(o.first, o.last): o for o in onodes}
+        sel = np.nonzero(nd["body"] == j)[0]
+        assert len(sel) == len(onodes)
+        for g in sel:
+            o = by_range[(int(nd["first"][g]), int(nd["last"][g]))]
+            k = int(nd["k"][g])
+            assert k == o.k
+            assert int(nd["row"][g]) == o.off
+            scale = max(np.abs(o.T22).max(), 1e-300)
+            assert np.abs(nd["T22"][g] - o.T22).max() <= 1e-12 * scale
+            if o.kappa < 1e4:
+                assert np.abs(nd["G"][g][:k, :k] - o.G).max() <= 1e-12
+            assert np.abs(nd["centroid"][g] - o.c).max() <= 1e-12 * (1 + np.abs(o.c).max())
+
+
+@pytest.mark.parametrize("S", [4, 16, 64, 256])
+def test_batch_fp64_tile_sizes(hq, S):
+    """Several tiles, several phases and ragged tails for every tile size."""
+    w = W.small_batch(11, [2, 3, 4, 7, 33, 129, 500, 1500, 2600])
+    check_fp64(hq, w, S=S, nrhs=3)
+
+
+@pytest.mark.parametrize("R", [1, 5, 16, 32, 64, 70])
+def test_nrhs_shapes(hq, R):
+    w = W.small_batch(12, [40, 700, 1200])
+    check_fp64(hq, w, S=128, nrhs=R)
+
+
+def test_results_independent_of_tile_size(hq):
+    """The per-node arithmetic is fixed, so FP64 results agree bitwise."""
+    w = W.small_batch(13, [300, 900, 2000])
+    rng = np.random.default_rng(5)
+    v = _dev(rng.standard_normal((3 * w.N, 4)))
+    outs = []
+    for S in (8, 64, 1024):
+        h = build(hq, w, tile_units=S)
+        outs.append(h.apply(v).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_large_body_merge_sort(hq):
+    """A body above the LDS sort size goes through chunk sorts and merges."""
+    w = W.ellipsoid_n65536(n=20000, nrhs=2)
+    h = build(hq, w)
+    b = hier.Body(w.pos)
+    assert np.array_equal(h.sorted_beads(0), b.perm())
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal((3 * w.N, 2))
+    up = h.apply(_dev(v)).cpu().numpy()
+    up_o = b.apply(v)
+    if b.max_kappa <= 1e4:
+        assert rel_per_body(up, up_o, w.offsets, h.row_offsets) <= 1e-12
+
+
+def test_fp32_error_and_leak(hq):
+    w = W.small_batch(14, [50, 400, 1300, 2100], nrhs=8)
+    rng = np.random.default_rng(14)
+    v = rng.standard_normal((3 * w.N, 8))
+    wv = rng.standard_normal((w.rows, 8))
+    h = build(hq, w)
+    up64 = h.apply(_dev(v)).cpu().numpy()
+    dn64 = h.apply(_dev(wv), transpose=True).cpu().numpy()
+    up32 = h.apply(_dev(v, torch.float32)).cpu().numpy().astype(np.float64)
+    dn32 = h.apply(_dev(wv, torch.float32), transpose=True).cpu().numpy().astype(np.float64)
+    for j in range(w.m):
+        r0, r1 = h.row_offsets[j], h.row_offsets[j + 1]
+        b0, b1 = 3 * w.offsets[j], 3 * w.offsets[j + 1]
+        e_up = np.linalg.norm(up32[r0:r1] - up64[r0:r1], axis=0) / np.linalg.norm(v[b0:b1], axis=0)
+        e_dn = np.linalg.norm(dn32[b0:b1] - dn64[b0:b1], axis=0) / np.linalg.norm(wv[r0:r1], axis=0)
+        assert e_up.max() <= 1e-5 and e_dn.max() <= 1e-5
+        leak = dense.leak(w.pos[w.offsets[j]:w.offsets[j + 1]], dn32[b0:b1])
+        assert leak.max() <= 1e-5
+
+
+def test_explicit_dense(hq):
+    w = W.small_batch(15, [2, 3, 64, 250])
+    h = build(hq, w)
+    bt = hier.Batch(w.pos, w.offsets)
+    for j, b in enumerate(bt.bodies):
+        Qg = h.explicit(j).cpu().numpy()
+        Qo = b.explicit()
+        assert Qg.shape == Qo.shape
+        if Qo.size:
+            assert np.abs(Qg - Qo).max() <= 1e-12
+
+
+def test_explicit_blocks(hq):
+    w = W.small_batch(16, [700])
+    h = build(hq, w)
+    vals, val_off, row_off, bead_first, rows, cols = h.explicit_blocks(0)
+    vals = vals.cpu().numpy()
+    sb = h.sorted_beads(0)
+    n = w.N
+    Q = np.zeros((3 * n - 6, 3 * n))
+    for b in range(len(rows)):
+        blk = vals[val_off[b]:val_off[b + 1]].reshape(rows[b], cols[b])
+        beads = sb[bead_first[b]:bead_first[b] + cols[b] // 3]
+        colidx = (3 * beads[:, None] + np.arange(3)[None, :]).reshape(-1)
+        Q[row_off[b]:row_off[b] + rows[b]][:, colidx] = blk
+    Qo = hier.Body(w.pos).explicit()
+    assert np.abs(Q - Qo).max() <= 1e-12
+    assert val_off[-1] == sum(int(r) * int(c) for r, c in zip(rows, cols))
