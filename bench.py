@@ -1,0 +1,222 @@
+"""Benchmark: the Brownian-dynamics step of many rigid bodies on one MI355X.
+
+Workload (seeded, synthetic): m = 4096 bodies with lognormal sizes (median 500
+beads, sigma 0.6, clipped to [50, 20000]) on random ellipsoids in a 500^3 box,
+32 force vectors per body.  One step = rigid motion of every body (Haar
+rotation about its centroid + translation in [-1,1]^3), rebuild of the tree and
+FP64 transforms, then Q~^T (Q~ f) in FP32 for the 32 right-hand sides.  K steps
+are captured in one hipGraph and replayed; the timed region is bracketed by
+synchronisations.
+
+value = bead-vectors per second = N * R / (time per step).  The roofline row
+is the upward sweep Q~ v (FP32): algorithmic bytes (input vectors, residue
+output, compact reflectors, links, permutation) over its measured duration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bead-vectors/s for batched Q̃v+Q̃ᵀv; % HBM peak; FP32 err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(h, nrhs, elem=4):
+    """Bytes one sweep must move: vectors in and out, the compact reflectors
+    of every node (5, 15 or 24 values for k = 3, 6, 9), 16 bytes of links and
+    weights per node, and 4 bytes of permutation per bead."""
+    nd = h.node_data(with_G=False)
+    k = nd["k"]
+    w = np.where(k == 9, 24, np.where(k == 6, 15, 5)).sum()
+    return (elem * 3 * h.N * nrhs + elem * h.rows * nrhs + elem * int(w) + 16 * (h.N - h.m) + 4 * h.N)
+
+
+def cpu_baseline(wl, rng_seed, budget_s=15.0):
+    """The FP64 oracle (single thread) on a bounded sample of the same bodies:
+    per body a rebuild plus Q~ f and Q~^T (Q~ f) for all R right-hand sides."""
+    from oracle import hier
+    rng = np.random.default_rng(rng_seed)
+    R = wl.nrhs
+    order = rng.permutation(wl.m)
+    beads, t_total, nb = 0, 0.0, 0
+    t0 = time.perf_counter()
+    for j in order:
+        p = wl.pos[wl.offsets[j]:wl.offsets[j + 1]]
+        f = rng.standard_normal((3 * len(p), R))
+        ts = time.perf_counter()
+        b = hier.Body(p)
+        y = b.apply(f)
+        b.apply(y, transpose=True)
+        t_total += time.perf_counter() - ts
+        beads += len(p)
+        nb += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return {"value": beads * R / t_total, "unit": "bead-vectors/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nb} of {wl.m} bodies ({beads} beads, R={R}), FP64 plain C recursion, one thread, "
+                      f"rebuild + Q~f + Q~^T(Q~f) per body, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--tile-units", type=int, default=64)
+    ap.add_argument("--nrhs", type=int, default=32)
+    ap.add_argument("--bodies", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bodies of this workload "
+              "shard across GPUs with no communication, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1708_08427_amd as hq
+    import workloads as W
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    wl = W.bd_m4096(m=args.bodies, nrhs=args.nrhs)
+    N, m, R = wl.N, wl.m, wl.nrhs
+    rng = np.random.default_rng(33)
+    f = rng.standard_normal((3 * N, R))
+    total_steps = args.steps + args.warmup
+    rot, trans = W.rigid_motions(rng, total_steps, m)
+    log(f"workload {wl.name}: N={N} m={m} R={R} rows={wl.rows}")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pos = torch.from_numpy(wl.pos).to(dev)
+        pos0 = pos.clone()
+        f32 = torch.from_numpy(f).float().to(dev)
+        tmp = torch.empty((wl.rows, R), dtype=torch.float32, device=dev)
+        out = torch.empty((3 * N, R), dtype=torch.float32, device=dev)
+        rot_d = torch.from_numpy(rot.reshape(total_steps, m, 9)).to(dev)
+        trans_d = torch.from_numpy(trans).to(dev)
+        t0 = time.perf_counter()
+        # the step applies in FP32, so only the FP32 copy of the FP64-generated
+        # transforms is kept; the FP64 sweep is timed on its own handle below
+        h = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=2, stream=stream)
+        torch.cuda.synchronize()
+        log(f"first build {1e3 * (time.perf_counter() - t0):.1f} ms; {h.query()}")
+        h.reserve(R, torch.float32)
+
+        def step(i):
+            h.rigid_update(pos, rot_d[i], trans_d[i], stream=stream)
+            h.rebuild(pos, stream=stream)
+            h.apply(f32, out=tmp, stream=stream)
+            h.apply(tmp, transpose=True, out=out, stream=stream)
+
+        # graphs: warmup steps, then exactly K timed steps
+        hq.capture_begin(stream)
+        for i in range(args.warmup):
+            step(i)
+        g_warm = hq.capture_end(stream)
+        hq.capture_begin(stream)
+        for i in range(args.warmup, total_steps):
+            step(i)
+        g_timed = hq.capture_end(stream)
+        log("graphs captured")
+
+        g_warm.launch(stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        g_timed.launch(stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        q = h.query()
+        log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; flags {q['device_flags']}")
+        if q["device_flags"] != 0:
+            raise RuntimeError(f"device flags raised: {q}")
+
+        # accuracy on the final positions: FP32 sweep pair against the FP64 oracle
+        pos_host = pos.cpu().numpy()
+        out_host = out.cpu().numpy().astype(np.float64)
+        from oracle import dense, hier
+        sample = np.random.default_rng(7).choice(m, 16, replace=False)
+        err, leak = 0.0, 0.0
+        for j in sample:
+            b0, b1 = wl.offsets[j], wl.offsets[j + 1]
+            bo = hier.Body(pos_host[b0:b1])
+            ref = bo.apply(bo.apply(f[3 * b0:3 * b1]), transpose=True)
+            got = out_host[3 * b0:3 * b1]
+            e = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(f[3 * b0:3 * b1], axis=0)
+            err = max(err, float(e.max()))
+            leak = max(leak, float(dense.leak(pos_host[b0:b1], got).max()))
+        log(f"FP32 vs FP64 oracle on 16 bodies: rel err {err:.2e}, leak {leak:.2e}")
+
+        # per-sweep durations (eager launches on the same stream)
+        def timed(fn, reps):
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            fn()
+            torch.cuda.synchronize()
+            for a, b in evs:
+                a.record(stream)
+                fn()
+                b.record(stream)
+            torch.cuda.synchronize()
+            return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+        t_up = timed(lambda: h.apply(f32, out=tmp, stream=stream), args.apply_reps)
+        t_dn = timed(lambda: h.apply(tmp, transpose=True, out=out, stream=stream), args.apply_reps)
+        t_rb = timed(lambda: h.rebuild(pos, stream=stream), 5)
+        f64 = f32.double()
+        tmp64 = torch.empty((wl.rows, R), dtype=torch.float64, device=dev)
+        h64 = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=1, stream=stream)
+        t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream), 5)
+        h64.destroy()
+        log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms, up FP64 {t_up64:.3f} ms")
+        nbytes = algorithmic_bytes(h, R)
+        achieved = nbytes / (t_up * 1e-3) / 1e9
+        q = h.query()
+
+    result = {
+        "metric": METRIC,
+        "value": N * R / (ms_step * 1e-3),
+        "unit": "bead-vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"bd_step_m{m}_lognormal500_R{R}", "bodies": m, "beads": N, "nrhs": R,
+                   "rows": wl.rows, "tile_units": args.tile_units,
+                   "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "upward sweep Q~v FP32 (k_up, all tile phases)", "bytes": int(nbytes),
+                     "ms": t_up},
+        "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},
+        "apply_only_bead_vectors_per_s": N * R / ((t_up + t_dn) * 1e-3),
+        "fp32_rel_err_vs_fp64_oracle": err,
+        "fp32_leak": leak,
+        "tiles": q["tiles"], "phases": q["phases"],
+    }
+    if not args.no_cpu:
+        wl0 = W.bd_m4096(m=args.bodies, nrhs=args.nrhs)
+        result["cpu_baseline"] = cpu_baseline(wl0, 5)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

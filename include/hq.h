@@ -83,7 +83,7 @@ typedef enum { HQ_FP64 = 0, HQ_FP32 = 1 } hq_precision;
 #define HQ_BODY_DEGENERATE  2  /* rank Z < 6 (e.g. collinear beads, Section 2.2) */
 
 typedef struct {
-    int32_t tile_units;    /* max units (beads or sub-tile roots) per tile; 0 = 256; <= 1024 */
+    int32_t tile_units;    /* max units (beads or sub-tile roots) per tile; 0 = 64; <= 1024 */
     int32_t store;         /* transforms kept: 1 = FP64, 2 = FP32, 3 or 0 = both */
     int32_t explicit_dense_max_n; /* largest n_j for hq_explicit; 0 = 4096 */
     int32_t max_phases;    /* tile phases reserved for hq_rebuild; 0 = found at build + 2 */
@@ -167,8 +167,10 @@ hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index);
 
 /* Rigid motion of every body (a Brownian-dynamics step's position update):
  * r <- Rot_j (r - c_j) + c_j + t_j for the beads of body j, with c_j the
- * body centroid of the last build.  positions device N x 3 FP64 (in place),
- * rot device m x 9 FP64 row-major, trans device m x 3 FP64.  Capturable. */
+ * body centroid computed by the handle's last hq_build / hq_rebuild (state of
+ * the handle, so a replayed capture continues from the last rebuild).
+ * positions device N x 3 FP64 (in place), rot device m x 9 FP64 row-major,
+ * trans device m x 3 FP64.  Capturable. */
 hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot,
                           const double *trans, hq_stream stream);
 

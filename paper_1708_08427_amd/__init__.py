@@ -202,18 +202,19 @@ class Handle:
                                         kappa.ctypes.data_as(_lib.P_f64)), "hq_body_info")
         return flags, kappa
 
-    def node_data(self):
+    def node_data(self, with_G=True):
+        """Per-node tree and transform data (G needs the FP64 transforms)."""
         NI = self.N - self.m
         a = {k: np.zeros(NI, dtype=np.int32) for k in ("first", "last", "x", "y", "body", "n", "k", "row")}
         cen = np.zeros((NI, 3))
         T22 = np.zeros((NI, 3, 3))
-        G = np.zeros((NI, 9, 9))
+        G = np.zeros((NI, 9, 9)) if with_G else None
         P = _lib.P_i32
         _check(_lib.load().hq_node_data(self._h(), a["first"].ctypes.data_as(P), a["last"].ctypes.data_as(P),
                                         a["x"].ctypes.data_as(P), a["y"].ctypes.data_as(P),
                                         a["body"].ctypes.data_as(P), a["n"].ctypes.data_as(P),
                                         cen.ctypes.data_as(_lib.P_f64), T22.ctypes.data_as(_lib.P_f64),
-                                        G.ctypes.data_as(_lib.P_f64), a["k"].ctypes.data_as(P),
+                                        G.ctypes.data_as(_lib.P_f64) if with_G else None, a["k"].ctypes.data_as(P),
                                         a["row"].ctypes.data_as(P)), "hq_node_data")
         a.update(centroid=cen, T22=T22, G=G)
         return a

@@ -77,7 +77,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
         P.max_n = (int)std::max<int64_t>(P.max_n, n);
     }
     P.rows = P.row_off[m];
-    P.S = (opt && opt->tile_units) ? opt->tile_units : 256;
+    P.S = (opt && opt->tile_units) ? opt->tile_units : 64;
     P.store = (opt && opt->store) ? opt->store : 3;
     P.dense_max_n = (opt && opt->explicit_dense_max_n) ? opt->explicit_dense_max_n : 4096;
     P.phases_reserved = (opt && opt->max_phases) ? opt->max_phases : 0;
@@ -114,7 +114,8 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     for (int64_t j = 0; j < m; ++j) {
         const int64_t n = off[j + 1] - off[j];
         if (n <= kSortLdsMax) {
-            const int npad = std::max(64, next_pow2((int)n));
+            // two launches: segments up to 1024 beads, and up to kSortLdsMax
+            const int npad = (n <= 1024) ? 1024 : kSortLdsMax;
             auto &v = small_seg[floor_log2(npad)];
             v.push_back((int32_t)off[j]);
             v.push_back((int32_t)n);
@@ -128,7 +129,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
             P.large_passes = std::max(P.large_passes, passes);
             for (int64_t b = 0; b < n; b += kSortLdsMax) {
                 const int len = (int)std::min<int64_t>(kSortLdsMax, n - b);
-                const int npad = std::max(64, next_pow2(len));
+                const int npad = (len <= 1024) ? 1024 : kSortLdsMax;
                 auto &v = chunk_seg[floor_log2(npad)];
                 v.push_back((int32_t)(off[j] + b));
                 v.push_back(len);
@@ -196,6 +197,11 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_nn, NI));
     HQ_TRY(dalloc(P, &P.d_ncen, 3 * NI));
     HQ_TRY(dalloc(P, &P.d_T22, 6 * NI));
+    HQ_TRY(dalloc(P, &P.d_depth, NI));
+    HQ_TRY(dalloc(P, &P.d_bydepth, NI));
+    HQ_TRY(dalloc(P, &P.d_dhist, (int64_t)(kMaxDepth + 1) * kDepthBlocksHost));
+    HQ_TRY(dalloc(P, &P.d_dincl, (int64_t)(kMaxDepth + 1) * kDepthBlocksHost));
+    HQ_TRY(dalloc(P, &P.d_dstart, kMaxDepth + 2));
     HQ_TRY(dalloc(P, &P.d_tile_root, NI));
     HQ_TRY(dalloc(P, &P.d_tile_base, NI));
     HQ_TRY(dalloc(P, &P.d_tile_len, NI));
@@ -207,7 +213,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));
     HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
-    P.scan_blk_cap = scan_blocks_needed(std::max(N, NI)) + 8;
+    P.scan_blk_cap = scan_blocks_needed(std::max<int64_t>(std::max(N, NI), (int64_t)(kMaxDepth + 1) * kDepthBlocksHost)) + 8;
     HQ_TRY(dalloc(P, &P.d_scan_blk, P.scan_blk_cap));
     return HQ_OK;
 }

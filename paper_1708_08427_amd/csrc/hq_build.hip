@@ -153,15 +153,20 @@ __device__ inline bool key_less(unsigned long long ka, unsigned int va, unsigned
     return ka < kb || (ka == kb && va < vb);
 }
 
-// seg: (start, len, body) triples; every len <= npad.  final: write sorted
-// codes and the caller's bead index; otherwise write the sorted run back.
-__global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad, int final_out, unsigned long long *keys,
+// seg: (start, len, body) triples; every len <= npad_max.  Each block pads its
+// segment to the next power of two (at least 64) and sorts it bitonically in
+// LDS.  final: write sorted codes and the caller's bead index; otherwise write
+// the sorted run back.
+__global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad_max, int final_out, unsigned long long *keys,
                            int32_t *vals, const int32_t *__restrict__ bead_off, unsigned long long *scode,
                            int32_t *perm) {
     extern __shared__ unsigned char smem[];
     unsigned long long *K = reinterpret_cast<unsigned long long *>(smem);
-    unsigned int *V = reinterpret_cast<unsigned int *>(smem + sizeof(unsigned long long) * npad);
+    unsigned int *V = reinterpret_cast<unsigned int *>(smem + sizeof(unsigned long long) * npad_max);
     const int start = seg[3 * blockIdx.x], len = seg[3 * blockIdx.x + 1], body = seg[3 * blockIdx.x + 2];
+    int npad = 64;
+    while (npad < len) npad <<= 1;
+    if (npad > npad_max) return;  // never: segments are classed by size on the host
     for (int i = threadIdx.x; i < npad; i += blockDim.x) {
         if (i < len) {
             K[i] = keys[start + i];
@@ -175,12 +180,12 @@ __global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad, int final_
     for (int k = 2; k <= npad; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < npad; i += blockDim.x) {
-                int ixj = i ^ j;
+                const int ixj = i ^ j;
                 if (ixj > i) {
-                    unsigned long long ka = K[i], kb = K[ixj];
-                    unsigned int va = V[i], vb = V[ixj];
-                    bool up = (i & k) == 0;
-                    bool gt = key_less(kb, vb, ka, va);
+                    const unsigned long long ka = K[i], kb = K[ixj];
+                    const unsigned int va = V[i], vb = V[ixj];
+                    const bool up = (i & k) == 0;
+                    const bool gt = key_less(kb, vb, ka, va);
                     if (gt == up) {
                         K[i] = kb; K[ixj] = ka;
                         V[i] = vb; V[ixj] = va;
@@ -464,7 +469,8 @@ __global__ void k_check_phases(int32_t *cnt, int32_t *err) {
 __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, const int32_t *sched,
                         const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
                         const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
-                        const int32_t *perm, const int32_t *row_off, int32_t *links, int32_t *err) {
+                        const int32_t *perm, const int32_t *row_off, int32_t *links, int32_t *depth,
+                        int32_t *err) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] == 0) continue;
@@ -477,14 +483,16 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
             else if (cov[x] == cov[g] && tileof[x] == t) ref[c] = kRefStack;
             else ref[c] = -2 - tileof[x];
         }
-        int off = 0, q = g;
+        int off = 0, q = g, dep = 0;
         for (int guard = 0; guard <= kMaxDepth; ++guard) {
             if (guard == kMaxDepth) {
                 raise_flag(err, kFlagBounds);
+                dep = -1;
                 break;
             }
             const int p = par[q];
             if (p < 0) break;
+            ++dep;
             const int x = lc[p], y = rc[p];
             const int xi = x >= 0, yi = y >= 0;
             off += 3 * xi + 3 * yi;
@@ -501,170 +509,264 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
         links[4 * s + 1] = ref[1];
         links[4 * s + 2] = off;
         links[4 * s + 3] = meta;
+        depth[g] = dep;
     }
 }
 
 // ---------------------------------------------------------------------------
 // 5. FP64 transforms (Eqs. 3.4-3.13), one lane per tile, nodes in schedule order
 // ---------------------------------------------------------------------------
-// Eigenvalues of a symmetric 3x3 matrix (trigonometric closed form, Smith
-// 1961); returns sqrt(lmax / lmin) or a huge value when lmin <= 0.
-__device__ double cond_lower3(const double T[6]) {
+// Condition number of the lower-triangular T22 (its singular values are
+// those of K).  With S = T^T T, the smallest eigenvalue is the first root of
+// the characteristic cubic, reached from 0 by Newton's method (the cubic is
+// convex there); the largest is bounded by trace(S).  Returns
+// sqrt(trace / lambda_min), an upper bound of sigma_1 / sigma_3 within a
+// factor sqrt(3); a huge value for a singular T22.
+__device__ double cond_bound3(const double T[6]) {
     const double a = T[0], b = T[1], c = T[2], d = T[3], e = T[4], f = T[5];
     const double s00 = a * a + b * b + d * d, s01 = b * c + d * e, s02 = d * f;
     const double s11 = c * c + e * e, s12 = e * f, s22 = f * f;
-    const double p1 = s01 * s01 + s02 * s02 + s12 * s12;
-    const double q = (s00 + s11 + s22) / 3.0;
-    const double p2 = (s00 - q) * (s00 - q) + (s11 - q) * (s11 - q) + (s22 - q) * (s22 - q) + 2.0 * p1;
-    const double p = sqrt(p2 / 6.0);
-    if (!(p > 0.0)) return (q > 0.0) ? 1.0 : 1e300;
-    const double b00 = (s00 - q) / p, b11 = (s11 - q) / p, b22 = (s22 - q) / p;
-    const double b01 = s01 / p, b02 = s02 / p, b12 = s12 / p;
-    double r = 0.5 * (b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02));
-    r = fmin(fmax(r, -1.0), 1.0);
-    const double phi = acos(r) / 3.0;
-    const double l1 = q + 2.0 * p * cos(phi);
-    const double l3 = q + 2.0 * p * cos(phi + 2.0943951023931957);
-    if (!(l3 > 0.0)) return 1e300;
-    return sqrt(l1 / l3);
+    const double c2 = s00 + s11 + s22;
+    const double c1 = s00 * s11 - s01 * s01 + s00 * s22 - s02 * s02 + s11 * s22 - s12 * s12;
+    const double det = a * c * f;
+    const double c0 = det * det;
+    if (!(c0 > 0.0) || !(c2 > 0.0)) return 1e300;
+    double lam = 0.0;
+#pragma unroll
+    for (int it = 0; it < 12; ++it) {
+        const double p = ((-lam + c2) * lam - c1) * lam + c0;
+        const double dp = (-3.0 * lam + 2.0 * c2) * lam - c1;
+        lam -= p / dp;
+    }
+    if (!(lam > 0.0)) return 1e300;
+    return sqrt(c2 / lam);
 }
 
-__global__ void __launch_bounds__(64) k_gen(int phase, const int32_t *phase_tab, const int32_t *tile_base,
-                                            const int32_t *tile_len, const int32_t *sched_node,
-                                            const int32_t *links, const int32_t *lc, const int32_t *rc,
-                                            const int32_t *nbody, const int32_t *nn_arr, const double *pos,
-                                            const double *lo, double *ncen, double *T22, float *rec32,
-                                            double *rec64, int store, double *bcen,
-                                            unsigned long long *kappa, int32_t *bflags, int64_t N, int64_t NI,
-                                            int32_t *err) {
-    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
-    for (int t = tb + blockIdx.x * blockDim.x + threadIdx.x; t < te; t += gridDim.x * blockDim.x) {
-        const int base = tile_base[t], len = tile_len[t];
-        if (base < 0 || len < 0 || (int64_t)base + len > NI) {
+// Transforms of one node (Eqs. 3.4-3.13).  A = K^T with the blocks of
+// internal children first, then the shift block D = sqrt(n_x n_y / n)
+// [c_x - c_y]x; rows beyond k stay zero, so reflectors of length 9 act as
+// the length-k ones.
+__device__ __forceinline__ void put_lower(double (&A)[9][3], int r0, const double *T) {
+    // K block column jj = column jj of the lower-triangular T22 -> A row r0+jj
+    A[r0 + 0][0] = T[0]; A[r0 + 0][1] = T[1]; A[r0 + 0][2] = T[3];
+    A[r0 + 1][0] = 0.0;  A[r0 + 1][1] = T[2]; A[r0 + 1][2] = T[4];
+    A[r0 + 2][0] = 0.0;  A[r0 + 2][1] = 0.0;  A[r0 + 2][2] = T[5];
+}
+
+__device__ __forceinline__ void put_shift(double (&A)[9][3], int r0, double sc, const double *dv) {
+    A[r0 + 0][0] = 0.0;          A[r0 + 0][1] = sc * dv[2];   A[r0 + 0][2] = -sc * dv[1];
+    A[r0 + 1][0] = -sc * dv[2];  A[r0 + 1][1] = 0.0;          A[r0 + 1][2] = sc * dv[0];
+    A[r0 + 2][0] = sc * dv[1];   A[r0 + 2][1] = -sc * dv[0];  A[r0 + 2][2] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_gen_level(int level, const int32_t *dstart, const int32_t *bydepth,
+                                                   const int32_t *sched, const int32_t *links, const int32_t *lc,
+                                                   const int32_t *rc, const int32_t *nbody, const int32_t *nn_arr,
+                                                   const double *pos, const double *lo, double *ncen, double *T22,
+                                                   float *rec32, double *rec64, int store, double *bcen,
+                                                   unsigned long long *kappa, int32_t *bflags, int64_t N,
+                                                   int64_t NI, int32_t *err) {
+    const int i0 = dstart[level], i1 = dstart[level + 1];
+    for (int i = i0 + blockIdx.x * blockDim.x + threadIdx.x; i < i1; i += gridDim.x * blockDim.x) {
+        const int g = bydepth[i];
+        if (g < 0 || g >= NI) {
             raise_flag(err, kFlagBounds);
             continue;
         }
-        for (int s = base; s < base + len; ++s) {
-            const int g = sched_node[s];
-            if (g < 0 || g >= NI) {
-                raise_flag(err, kFlagBounds);
+        const int s = sched[g];
+        if (s < 0 || s >= NI) {
+            raise_flag(err, kFlagBounds);
+            continue;
+        }
+        const int body = nbody[g];
+        const int32_t *lk = links + 4 * (int64_t)s;
+        const int x = lc[g], y = rc[g];
+        const bool xi = x >= 0, yi = y >= 0;
+        double cx[3], cy[3], Tx[6], Ty[6];
+        double nx = 1.0, ny = 1.0;
+        bool bad = false;
+        if (xi) {
+            nx = (double)nn_arr[x];
+            for (int d = 0; d < 3; ++d) cx[d] = ncen[3 * (int64_t)x + d];
+            for (int d = 0; d < 6; ++d) Tx[d] = T22[6 * (int64_t)x + d];
+        } else {
+            const int u = lk[0];
+            if (u < 0 || u >= N) bad = true;
+            for (int d = 0; d < 3; ++d) cx[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
+        }
+        if (yi) {
+            ny = (double)nn_arr[y];
+            for (int d = 0; d < 3; ++d) cy[d] = ncen[3 * (int64_t)y + d];
+            for (int d = 0; d < 6; ++d) Ty[d] = T22[6 * (int64_t)y + d];
+        } else {
+            const int u = lk[1];
+            if (u < 0 || u >= N) bad = true;
+            for (int d = 0; d < 3; ++d) cy[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
+        }
+        if (bad) raise_flag(err, kFlagBounds);
+        const double n = nx + ny;
+        double cp[3], dv[3];
+        for (int d = 0; d < 3; ++d) {
+            cp[d] = (nx * cx[d] + ny * cy[d]) / n;
+            dv[d] = cx[d] - cy[d];
+        }
+        const double sc = sqrt(nx * ny / n);
+        double A[9][3];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
+        int k;
+        if (xi && yi) {
+            put_lower(A, 0, Tx);
+            put_lower(A, 3, Ty);
+            put_shift(A, 6, sc, dv);
+            k = 9;
+        } else if (xi) {
+            put_lower(A, 0, Tx);
+            put_shift(A, 3, sc, dv);
+            k = 6;
+        } else if (yi) {
+            put_lower(A, 0, Ty);
+            put_shift(A, 3, sc, dv);
+            k = 6;
+        } else {
+            put_shift(A, 0, sc, dv);
+            k = 3;
+        }
+        // Householder QR of A (LAPACK sign convention; tau = 0 for a zero tail)
+        double tail[3][8], tau[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) tail[j][r] = 0.0;
+            const double alpha = A[j][j];
+            double xs = 0.0;
+#pragma unroll
+            for (int r = j + 1; r < 9; ++r) xs = fma(A[r][j], A[r][j], xs);
+            if (xs == 0.0) {
+                tau[j] = 0.0;
                 continue;
             }
-            const int body = nbody[g];
-            const int ch[2] = {lc[g], rc[g]};
-            const int *lk = links + 4 * s;
-            double cc[2][3], Tc[2][6];
-            double ncnt[2];
-            bool internal[2];
-            for (int c = 0; c < 2; ++c) {
-                const int x = ch[c];
-                internal[c] = x >= 0;
-                if (x >= 0) {
-                    ncnt[c] = (double)nn_arr[x];
-                    for (int d = 0; d < 3; ++d) cc[c][d] = ncen[3 * (int64_t)x + d];
-                    for (int d = 0; d < 6; ++d) Tc[c][d] = T22[6 * (int64_t)x + d];
-                } else {
-                    const int u = lk[c];
-                    if (u < 0 || u >= N) {
-                        raise_flag(err, kFlagBounds);
-                        ncnt[c] = 1.0;
-                        for (int d = 0; d < 3; ++d) cc[c][d] = 0.0;
-                        continue;
-                    }
-                    ncnt[c] = 1.0;
-                    for (int d = 0; d < 3; ++d) cc[c][d] = pos[3 * (int64_t)u + d] - lo[3 * body + d];
-                }
+            const double nrm = sqrt(fma(alpha, alpha, xs));
+            const double beta = (alpha >= 0.0) ? -nrm : nrm;
+            tau[j] = (beta - alpha) / beta;
+            const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+            for (int r = j + 1; r < 9; ++r) tail[j][r - j - 1] = A[r][j] * scal;
+            A[j][j] = beta;
+#pragma unroll
+            for (int l = j + 1; l < 3; ++l) {
+                double w = A[j][l];
+#pragma unroll
+                for (int r = j + 1; r < 9; ++r) w = fma(tail[j][r - j - 1], A[r][l], w);
+                w *= tau[j];
+                A[j][l] -= w;
+#pragma unroll
+                for (int r = j + 1; r < 9; ++r) A[r][l] = fma(-w, tail[j][r - j - 1], A[r][l]);
             }
-            const double nx = ncnt[0], ny = ncnt[1], n = nx + ny;
-            double cp[3], dv[3];
-            for (int d = 0; d < 3; ++d) {
-                cp[d] = (nx * cc[0][d] + ny * cc[1][d]) / n;
-                dv[d] = cc[0][d] - cc[1][d];
-            }
-            // A = K^T, rows packed: x's T22 columns, y's T22 columns, then D
-            double A[9][3];
-            for (int i = 0; i < 9; ++i) A[i][0] = A[i][1] = A[i][2] = 0.0;
-            int k = 0;
-            for (int c = 0; c < 2; ++c) {
-                if (!internal[c]) continue;
-                const double *T = Tc[c];
-                // K block column jj = T22 column jj -> A row k+jj = (T[0][jj], T[1][jj], T[2][jj])
-                A[k + 0][0] = T[0]; A[k + 0][1] = T[1]; A[k + 0][2] = T[3];
-                A[k + 1][0] = 0.0;  A[k + 1][1] = T[2]; A[k + 1][2] = T[4];
-                A[k + 2][0] = 0.0;  A[k + 2][1] = 0.0;  A[k + 2][2] = T[5];
-                k += 3;
-            }
-            {
-                const double sc = sqrt(nx * ny / n);
-                // D = sc [d]x ; A row k+jj = D column jj
-                A[k + 0][0] = 0.0;          A[k + 0][1] = sc * dv[2];   A[k + 0][2] = -sc * dv[1];
-                A[k + 1][0] = -sc * dv[2];  A[k + 1][1] = 0.0;          A[k + 1][2] = sc * dv[0];
-                A[k + 2][0] = sc * dv[1];   A[k + 2][1] = -sc * dv[0];  A[k + 2][2] = 0.0;
-                k += 3;
-            }
-            double tail[3][8], tau[3];
-            for (int j = 0; j < 3; ++j) {
-                for (int i = 0; i < 8; ++i) tail[j][i] = 0.0;
-                const double alpha = A[j][j];
-                double xs = 0.0;
-                for (int i = j + 1; i < 9; ++i) xs = fma(A[i][j], A[i][j], xs);
-                if (xs == 0.0) {
-                    tau[j] = 0.0;
-                    continue;
-                }
-                const double nrm = sqrt(fma(alpha, alpha, xs));
-                const double beta = (alpha >= 0.0) ? -nrm : nrm;
-                tau[j] = (beta - alpha) / beta;
-                const double scal = 1.0 / (alpha - beta);
-                for (int i = j + 1; i < 9; ++i) tail[j][i - j - 1] = A[i][j] * scal;
-                A[j][j] = beta;
-                for (int l = j + 1; l < 3; ++l) {
-                    double w = A[j][l];
-                    for (int i = j + 1; i < 9; ++i) w = fma(tail[j][i - j - 1], A[i][l], w);
-                    w *= tau[j];
-                    A[j][l] -= w;
-                    for (int i = j + 1; i < 9; ++i) A[i][l] = fma(-w, tail[j][i - j - 1], A[i][l]);
-                }
-            }
-            double T[6];
-            T[0] = A[0][0];
-            T[1] = A[0][1];
-            T[2] = A[1][1];
-            T[3] = A[0][2];
-            T[4] = A[1][2];
-            T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
-            for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
-            for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
-            const double sx = sqrt(nx / n), sy = sqrt(ny / n);
-            double r[26];
-            for (int i = 0; i < 8; ++i) r[i] = tail[0][i];
-            for (int i = 0; i < 7; ++i) r[8 + i] = tail[1][i];
-            for (int i = 0; i < 6; ++i) r[15 + i] = tail[2][i];
-            r[21] = tau[0]; r[22] = tau[1]; r[23] = tau[2];
-            r[24] = sx; r[25] = sy;
-            if (store & 1) {
-                double *o = rec64 + (int64_t)kRecWords * s;
-                for (int i = 0; i < 26; ++i) o[i] = r[i];
-                int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-                for (int i = 0; i < 4; ++i) ol[i] = lk[i];
-            }
-            if (store & 2) {
-                float *o = rec32 + (int64_t)kRecWords * s;
-                for (int i = 0; i < 26; ++i) o[i] = (float)r[i];
-                int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-                for (int i = 0; i < 4; ++i) ol[i] = lk[i];
-            }
-            const bool body_root = (lk[3] & kMetaBodyRoot) != 0;
-            if (k > 3 || body_root) {
-                const double kap = (k > 3) ? cond_lower3(T) : 1e300;
-                if (k > 3) atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kap));
-                if (k > 3 && kap > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
-                if (body_root && kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
-            }
-            if (body_root)
-                for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
         }
+        double T[6];
+        T[0] = A[0][0];
+        T[1] = A[0][1];
+        T[2] = A[1][1];
+        T[3] = A[0][2];
+        T[4] = A[1][2];
+        T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
+        for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
+        for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
+        const double sx = sqrt(nx / n), sy = sqrt(ny / n);
+        double r[26];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = tail[0][q];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) r[8 + q] = tail[1][q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) r[15 + q] = tail[2][q];
+        r[21] = tau[0];
+        r[22] = tau[1];
+        r[23] = tau[2];
+        r[24] = sx;
+        r[25] = sy;
+        const int32_t l0 = lk[0], l1 = lk[1], l2 = lk[2], l3 = lk[3];
+        if (store & 1) {
+            double *o = rec64 + (int64_t)kRecWords * s;
+#pragma unroll
+            for (int q = 0; q < 26; ++q) o[q] = r[q];
+            int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
+            ol[0] = l0; ol[1] = l1; ol[2] = l2; ol[3] = l3;
+        }
+        if (store & 2) {
+            float *o = rec32 + (int64_t)kRecWords * s;
+#pragma unroll
+            for (int q = 0; q < 26; ++q) o[q] = (float)r[q];
+            int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
+            ol[0] = l0; ol[1] = l1; ol[2] = l2; ol[3] = l3;
+        }
+        const bool body_root = (l3 & kMetaBodyRoot) != 0;
+        if (k > 3 || body_root) {
+            const double kap = (k > 3) ? cond_bound3(T) : 1e300;
+            if (k > 3) atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kap));
+            if (k > 3 && kap > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
+            if (body_root && kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+        }
+        if (body_root)
+            for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
     }
+}
+
+// Nodes bucketed by depth below their body root, so that a launch per depth
+// (deepest first) finds both children of every node already done.  Counting
+// sort in three passes: per-block histograms, one scan over (depth, block),
+// and a scatter; no contended global atomics.
+constexpr int kDepthBins = kMaxDepth + 1;
+constexpr int kDepthBlocks = kDepthBlocksHost;
+
+__global__ void __launch_bounds__(256) k_depth_hist(int64_t NI, const int32_t *depth, int32_t *hist) {
+    __shared__ int32_t h[kDepthBins];
+    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t C = (NI + kDepthBlocks - 1) / kDepthBlocks;
+    const int64_t g0 = (int64_t)blockIdx.x * C, g1 = min(NI, g0 + C);
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        const int d = depth[g];
+        if (d >= 0 && d < kDepthBins) atomicAdd(&h[d], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) hist[i * kDepthBlocks + blockIdx.x] = h[i];
+}
+
+__global__ void k_depth_starts(const int32_t *hist, const int32_t *incl, int32_t *dstart, int32_t *cnt) {
+    // one block of 256 threads: bin i starts at the exclusive prefix of (i, block 0)
+    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x)
+        dstart[i] = incl[i * kDepthBlocks] - hist[i * kDepthBlocks];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = incl[kDepthBins * kDepthBlocks - 1];
+        dstart[kDepthBins] = tot;
+        int dmax = 0;
+        for (int i = 0; i < kDepthBins; ++i)
+            if (dstart[i + 1] > dstart[i]) dmax = i;
+        cnt[kCntMaxDepth] = dmax;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_depth_scatter(int64_t NI, const int32_t *depth, const int32_t *hist,
+                                                       const int32_t *incl, int32_t *bydepth) {
+    __shared__ int32_t cur[kDepthBins];
+    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) {
+        const int q = i * kDepthBlocks + blockIdx.x;
+        cur[i] = incl[q] - hist[q];
+    }
+    __syncthreads();
+    const int64_t C = (NI + kDepthBlocks - 1) / kDepthBlocks;
+    const int64_t g0 = (int64_t)blockIdx.x * C, g1 = min(NI, g0 + C);
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        const int d = depth[g];
+        if (d >= 0 && d < kDepthBins) bydepth[atomicAdd(&cur[d], 1)] = (int)g;
+    }
+}
+
+__global__ void k_check_depth(const int32_t *cnt, int reserved, int32_t *err) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[kCntMaxDepth] > reserved) atomicOr(err, kFlagPhases);
 }
 
 // Rigid motion: r <- Rot (r - c) + c + t per body.
@@ -716,6 +818,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         hipLaunchKernelGGL(k_lds_sort, dim3(c.nseg), dim3(thr), (size_t)c.npad * 12, s, c.d_seg, c.npad, 1,
                            P.d_keyA, P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
     }
+    HQ_HIP(hipGetLastError());
     if (P.nlarge > 0) {
         for (auto &c : P.sort_chunks) {
             const int thr = std::min(1024, std::max(64, c.npad / 2));
@@ -781,12 +884,29 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_links, P.d_err);
-    // --- 5. transforms, phase by phase (children before parents)
-    for (int ph = 1; ph <= phases; ++ph) {
-        hipLaunchKernelGGL(k_gen, dim3(1024), dim3(64), 0, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len,
-                           P.d_sched_node, P.d_links, P.d_lc, P.d_rc, P.d_nbody, P.d_nn, pos, P.d_lo, P.d_ncen,
-                           P.d_T22, P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kappa, P.d_bflags, N, NI, P.d_err);
+                       P.d_row_off, P.d_links, P.d_depth, P.d_err);
+    // --- 5. transforms, one launch per depth level, deepest first
+    hipLaunchKernelGGL(k_depth_hist, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist);
+    HQ_TRY(scan_i32_inclusive(P, P.d_dhist, P.d_dincl, (int64_t)kDepthBins * kDepthBlocks, s));
+    hipLaunchKernelGGL(k_depth_starts, dim3(1), dim3(kThreads), 0, s, P.d_dhist, P.d_dincl, P.d_dstart, P.d_cnt);
+    hipLaunchKernelGGL(k_depth_scatter, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist,
+                       P.d_dincl, P.d_bydepth);
+    HQ_HIP(hipGetLastError());
+    if (probe_phases) {
+        int32_t cnt[kCntNum];
+        HQ_HIP(hipMemcpyAsync(cnt, P.d_cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
+        HQ_HIP(hipStreamSynchronize(s));
+        P.depth_built = cnt[kCntMaxDepth];
+        P.depth_reserved = std::min(kMaxDepth, P.depth_built + 8);
+    } else {
+        hipLaunchKernelGGL(k_check_depth, dim3(1), dim3(64), 0, s, P.d_cnt, P.depth_reserved, P.d_err);
+    }
+    const int levels = probe_phases ? P.depth_built : P.depth_reserved;
+    const unsigned ggrid = (unsigned)std::min<int64_t>(2048, (NI + kThreads - 1) / kThreads);
+    for (int d = levels; d >= 0; --d) {
+        hipLaunchKernelGGL(k_gen_level, dim3(ggrid), dim3(kThreads), 0, s, d, P.d_dstart, P.d_bydepth, P.d_sched,
+                           P.d_links, P.d_lc, P.d_rc, P.d_nbody, P.d_nn, pos, P.d_lo, P.d_ncen, P.d_T22,
+                           P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kappa, P.d_bflags, N, NI, P.d_err);
     }
     HQ_HIP(hipGetLastError());
     return HQ_OK;

@@ -20,6 +20,7 @@ constexpr int kMaxTileUnits = 1024;     // largest tile (units) supported
 constexpr int kMaxPhases = 64;          // phase table capacity
 constexpr int kRecWords = 32;           // elements (float or double) per node record
 constexpr int kMaxDepth = 256;          // bound on tree depth walks (63 code bits + 32 index bits)
+constexpr int kDepthBlocksHost = 512;   // blocks of the depth counting sort
 
 // A node record (one per internal node, in schedule order) holds the three
 // Householder reflectors of G in a zero-padded length-9 layout, the two
@@ -61,6 +62,7 @@ enum Counter {
     kCntNodes = 1,      // internal nodes covered so far
     kCntPhases = 2,     // phases with at least one tile
     kCntRemain = 3,     // internal nodes still uncovered after the last phase
+    kCntMaxDepth = 4,   // deepest internal node below its body root
     kCntNum = 8
 };
 
@@ -121,6 +123,8 @@ struct Plan {
     int dense_max_n = 4096;
     int phases_reserved = 0;  // phases launched by hq_rebuild
     int phases_built = 0;     // phases found by the last hq_build
+    int depth_built = 0;      // deepest internal node of the last hq_build
+    int depth_reserved = 0;   // depth levels launched by hq_rebuild
     int64_t tiles_built = 0;
     int max_n = 0;
 
@@ -173,6 +177,10 @@ struct Plan {
     int32_t *d_nn = nullptr;         // beads below
     double *d_ncen = nullptr;        // NI x 3, body-local
     double *d_T22 = nullptr;         // NI x 6, lower triangle packed (00,10,11,20,21,22)
+    int32_t *d_depth = nullptr;      // depth below the body root
+    int32_t *d_bydepth = nullptr;    // nodes bucketed by depth
+    int32_t *d_dhist = nullptr, *d_dincl = nullptr;  // (kMaxDepth + 1) x kDepthBlocksHost
+    int32_t *d_dstart = nullptr;     // kMaxDepth + 2
 
     // tiles and schedule
     int32_t *d_tile_root = nullptr, *d_tile_base = nullptr, *d_tile_len = nullptr;

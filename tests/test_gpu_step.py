@@ -1,0 +1,124 @@
+"""The Brownian-dynamics step on the GPU: rigid motion, rebuild and the FP32
+sweep pair, eagerly and replayed from a captured hipGraph."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, hier
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import paper_1708_08427_amd as hq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return hq
+
+
+def _workload():
+    w = W.small_batch(21, [2, 3, 60, 400, 1300, 2500, 900], nrhs=32)
+    rng = np.random.default_rng(21)
+    rot, trans = W.rigid_motions(rng, 4, w.m)
+    f = rng.standard_normal((3 * w.N, 32))
+    return w, rot, trans, f
+
+
+def test_rigid_update_matches_numpy(hq):
+    w, rot, trans, _ = _workload()
+    pos = torch.from_numpy(w.pos).cuda()
+    h = hq.build(pos, w.offsets)
+    rot_d = torch.from_numpy(rot[0].reshape(w.m, 9)).cuda()
+    tr_d = torch.from_numpy(trans[0]).cuda()
+    h.rigid_update(pos, rot_d, tr_d)
+    got = pos.cpu().numpy()
+    for j in range(w.m):
+        p = w.pos[w.offsets[j]:w.offsets[j + 1]]
+        c = p.mean(axis=0)
+        want = (p - c) @ rot[0, j].T + c + trans[0, j]
+        assert np.abs(got[w.offsets[j]:w.offsets[j + 1]] - want).max() < 1e-9
+
+
+def test_rebuild_equals_fresh_build(hq):
+    w, rot, trans, f = _workload()
+    pos = torch.from_numpy(w.pos).cuda()
+    h = hq.build(pos, w.offsets, tile_units=32)
+    f64 = torch.from_numpy(f).cuda()
+    moved = w.pos.copy()
+    for j in range(w.m):
+        sl = slice(w.offsets[j], w.offsets[j + 1])
+        c = moved[sl].mean(axis=0)
+        moved[sl] = (moved[sl] - c) @ rot[1, j].T + c + trans[1, j]
+    pos2 = torch.from_numpy(moved).cuda()
+    h.rebuild(pos2)
+    a = h.apply(f64).cpu().numpy()
+    h2 = hq.build(pos2, w.offsets, tile_units=32)
+    b = h2.apply(f64).cpu().numpy()
+    assert h.query()["device_flags"] == 0
+    assert np.array_equal(a, b)
+    bt = hier.Batch(moved, w.offsets)
+    o = bt.apply(f)
+    assert np.abs(a - o).max() < 1e-10
+
+
+def test_graph_replay_matches_eager(hq):
+    """K steps captured once, replayed several times with eager work and
+    synchronisations between replays; every replay equals the eager run."""
+    w, rot, trans, f = _workload()
+    K = 3
+    rot_d = torch.from_numpy(rot.reshape(4, w.m, 9)).cuda()
+    tr_d = torch.from_numpy(trans).cuda()
+    f32 = torch.from_numpy(f).float().cuda()
+    tmp = torch.empty((w.rows, 32), dtype=torch.float32, device="cuda")
+    out = torch.empty((3 * w.N, 32), dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pos = torch.from_numpy(w.pos).cuda()
+        h = hq.build(pos, w.offsets, tile_units=32, store=2, stream=s)
+        h.reserve(32, torch.float32)
+
+        def steps():
+            for i in range(K):
+                h.rigid_update(pos, rot_d[i], tr_d[i], stream=s)
+                h.rebuild(pos, stream=s)
+                h.apply(f32, out=tmp, stream=s)
+                h.apply(tmp, transpose=True, out=out, stream=s)
+
+        pos.copy_(torch.from_numpy(w.pos).cuda())
+        steps()
+        torch.cuda.synchronize()
+        eager_out, eager_pos = out.cpu().numpy(), pos.cpu().numpy()
+
+        pos.copy_(torch.from_numpy(w.pos).cuda())
+        torch.cuda.synchronize()
+        hq.capture_begin(s)
+        steps()
+        g = hq.capture_end(s)
+        for rep in range(3):
+            # the motion turns each body about the centroid of the handle's last
+            # (re)build: restore positions and that state before a replay
+            pos.copy_(torch.from_numpy(w.pos).cuda())
+            h.rebuild(pos, stream=s)
+            out.zero_()
+            torch.cuda.synchronize()
+            g.launch(s)
+            torch.cuda.synchronize()
+            assert np.array_equal(pos.cpu().numpy(), eager_pos), rep
+            assert np.array_equal(out.cpu().numpy(), eager_out), rep
+            # eager work between replays
+            h.apply(f32, out=tmp, stream=s)
+            torch.cuda.synchronize()
+        g.destroy()
+        assert h.query()["device_flags"] == 0
+    # the replayed step is the projection P f on the moved bodies
+    for j in range(w.m):
+        if w.offsets[j + 1] - w.offsets[j] < 3:
+            continue
+        sl = slice(w.offsets[j], w.offsets[j + 1])
+        b0, b1 = 3 * w.offsets[j], 3 * w.offsets[j + 1]
+        want = dense.project(eager_pos[sl], f[b0:b1])
+        got = eager_out[b0:b1].astype(np.float64)
+        assert np.abs(got - want).max() <= 1e-4 * np.abs(f[b0:b1]).max()
