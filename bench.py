@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tile-units", type=int, default=64)
+    ap.add_argument("--tile-units", type=int, default=32)
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")

@@ -83,7 +83,7 @@ typedef enum { HQ_FP64 = 0, HQ_FP32 = 1 } hq_precision;
 #define HQ_BODY_DEGENERATE  2  /* rank Z < 6 (e.g. collinear beads, Section 2.2) */
 
 typedef struct {
-    int32_t tile_units;    /* max units (beads or sub-tile roots) per tile; 0 = 64; <= 1024 */
+    int32_t tile_units;    /* max units (beads or sub-tile roots) per tile; 0 = 32; <= 1024 */
     int32_t store;         /* transforms kept: 1 = FP64, 2 = FP32, 3 or 0 = both */
     int32_t explicit_dense_max_n; /* largest n_j for hq_explicit; 0 = 4096 */
     int32_t max_phases;    /* tile phases reserved for hq_rebuild; 0 = found at build + 2 */

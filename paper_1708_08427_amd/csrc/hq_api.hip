@@ -77,7 +77,8 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
         P.max_n = (int)std::max<int64_t>(P.max_n, n);
     }
     P.rows = P.row_off[m];
-    P.S = (opt && opt->tile_units) ? opt->tile_units : 64;
+    P.S = (opt && opt->tile_units) ? opt->tile_units : 32;
+    if (const char *e = getenv("HQ_RUN_NODES")) P.run_nodes = std::max(16, atoi(e));
     P.store = (opt && opt->store) ? opt->store : 3;
     P.dense_max_n = (opt && opt->explicit_dense_max_n) ? opt->explicit_dense_max_n : 4096;
     P.phases_reserved = (opt && opt->max_phases) ? opt->max_phases : 0;
@@ -192,6 +193,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_tileof, NI));
     HQ_TRY(dalloc(P, &P.d_sched, NI));
     HQ_TRY(dalloc(P, &P.d_yfirst, NI));
+    HQ_TRY(dalloc(P, &P.d_slot, NI));
     HQ_TRY(dalloc(P, &P.d_trval, NI));
     HQ_TRY(dalloc(P, &P.d_trscan, NI));
     HQ_TRY(dalloc(P, &P.d_nn, NI));
@@ -206,10 +208,14 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_tile_base, NI));
     HQ_TRY(dalloc(P, &P.d_tile_len, NI));
     HQ_TRY(dalloc(P, &P.d_sched_node, NI));
-    HQ_TRY(dalloc(P, &P.d_links, 4 * NI));
+    HQ_TRY(dalloc(P, &P.d_links, (int64_t)kLinkInts * NI));
     if (P.store & 2) HQ_TRY(dalloc(P, &P.d_rec32, (int64_t)kRecWords * NI));
     if (P.store & 1) HQ_TRY(dalloc(P, &P.d_rec64, (int64_t)kRecWords * NI));
     HQ_TRY(dalloc(P, &P.d_phase, 2 * kMaxPhases));
+    HQ_TRY(dalloc(P, &P.d_prun, 4 * kMaxPhases));
+    // a phase of n nodes uses ceil(n / run_nodes) + 1 entries
+    P.run_cap = NI / P.run_nodes + 2 * (int64_t)kMaxPhases + 4;
+    HQ_TRY(dalloc(P, &P.d_run, P.run_cap));
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));
     HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
@@ -499,7 +505,7 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
     BodyNodes B;
     int64_t nb, nin;
     HQ_TRY(read_body_nodes(*P, body, B, nb, nin));
-    std::vector<int32_t> links(4 * (size_t)P->NI);
+    std::vector<int32_t> links((size_t)kLinkInts * P->NI);
     HQ_HIP(hipMemcpy(links.data(), P->d_links, links.size() * 4, hipMemcpyDeviceToHost));
     std::vector<int64_t> blk_off(nin, -1);
     int64_t b = 0, acc = 0;
@@ -508,7 +514,7 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
         const int dim = 3 * (B.lc[q] >= 0) + 3 * (B.rc[q] >= 0);
         if (dim == 0) continue;
         blk_off[q] = acc;
-        row_off[b] = links[4 * (size_t)B.sched[q] + 2] - P->row_off[body];
+        row_off[b] = links[kLinkInts * (size_t)B.sched[q] + 2] - P->row_off[body];
         bead_first[b] = B.first[q] - nb;
         rows[b] = dim;
         cols[b] = 3 * B.nn[q];
@@ -627,8 +633,8 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
     }
     std::vector<int32_t> links;
     if (G || row) {
-        links.resize(4 * NI);
-        HQ_HIP(hipMemcpy(links.data(), P->d_links, 4 * NI * 4, hipMemcpyDeviceToHost));
+        links.resize((size_t)kLinkInts * NI);
+        HQ_HIP(hipMemcpy(links.data(), P->d_links, links.size() * 4, hipMemcpyDeviceToHost));
     }
     if (G) {
         if (!(P->store & 1)) {
@@ -660,7 +666,7 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
             double M[9] = {t[0], 0, 0, t[1], t[2], 0, t[3], t[4], t[5]};
             std::memcpy(T22 + 9 * g, M, sizeof M);
         }
-        if (row) row[g] = links[4 * (size_t)sched[g] + 2] - (int32_t)P->row_off[j];
+        if (row) row[g] = links[kLinkInts * (size_t)sched[g] + 2] - (int32_t)P->row_off[j];
         if (G) {
             const double *r = &rec[(size_t)kRecWords * sched[g]];
             double *Gg = G + 81 * g;

@@ -404,8 +404,8 @@ __global__ void k_tile_emit(int64_t NI, const long long *trval, const long long 
 // reaches first going up; the child with more units is evaluated first.
 __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc, const int32_t *rc,
                          const int32_t *units, const long long *trval, const int32_t *tile_base,
-                         int32_t *tileof, int32_t *sched, int32_t *sched_node, int32_t *yfirst, int32_t *err,
-                         int64_t sched_cap) {
+                         int32_t *tileof, int32_t *sched, int32_t *sched_node, int32_t *yfirst, int32_t *depth_slot,
+                         int32_t *err, int64_t sched_cap) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] != 0) continue;
@@ -413,7 +413,10 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, con
             const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
             yfirst[g] = (uy > ux) ? 1 : 0;
         }
-        int pos = units[g] - 2;
+        // pos: post-order position inside the tile; pend: results of the tile
+        // pending on its stack while this node's subtree is swept, i.e. the
+        // stack slot that receives this node's result
+        int pos = units[g] - 2, pend = 0;
         int q = g;
         bool found = false;
         bool too_deep = true;
@@ -425,7 +428,11 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, con
             const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
             const bool y_first = uy > ux;
             const int second = y_first ? x : y;
-            if (q == second) pos += (y_first ? uy : ux) - 1;
+            if (q == second) {
+                const int ufirst = y_first ? uy : ux;
+                pos += ufirst - 1;
+                pend += (ufirst > 1) ? 1 : 0;  // the first child is an internal node of this tile
+            }
             q = p;
         }
         if (too_deep) raise_flag(err, kFlagBounds);
@@ -437,6 +444,7 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, con
             continue;
         }
         tileof[g] = t;
+        depth_slot[g] = pend;
         sched[g] = (int)s;
         sched_node[s] = g;
     }
@@ -448,16 +456,47 @@ __global__ void k_commit(int64_t NI, int phase, int32_t *cov, const int32_t *til
 }
 
 __global__ void k_phase_close(int64_t NI, int phase, const long long *trval, const long long *trscan,
-                              int32_t *cnt, int32_t *phase_tab) {
+                              int32_t *cnt, int32_t *phase_tab, int run_nodes, int32_t *prun, int64_t run_cap,
+                              int32_t *err) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const long long tot = (NI > 0) ? trscan[NI - 1] + trval[NI - 1] : 0;
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
     phase_tab[2 * phase] = cnt[kCntTiles];
     phase_tab[2 * phase + 1] = cnt[kCntTiles] + ntiles;
+    // runs: the phase's schedule range cut at tile starts every ~run_nodes nodes
+    const int p0 = cnt[kCntNodes], c0 = cnt[kCntRuns];
+    int nrun = (nnodes + run_nodes - 1) / run_nodes;
+    if ((int64_t)c0 + nrun + 1 > run_cap) {
+        raise_flag(err, kFlagBounds);
+        nrun = -1;
+    }
+    prun[4 * phase] = p0;
+    prun[4 * phase + 1] = p0 + nnodes;
+    prun[4 * phase + 2] = c0;
+    prun[4 * phase + 3] = max(nrun, 0);
+    if (nrun >= 0) cnt[kCntRuns] = c0 + nrun + 1;
     cnt[kCntTiles] += ntiles;
     cnt[kCntNodes] += nnodes;
     if (ntiles > 0) cnt[kCntPhases] = phase;
     cnt[kCntRemain] = (int)(NI - cnt[kCntNodes]);
+}
+
+// Run starts of one phase: run c begins at the first tile that starts at or
+// after node c * run_nodes of the phase (phase end if none), so every run
+// holds whole tiles and a lane group can sweep it as one node stream.
+__global__ void k_runs(int phase, int run_nodes, const int32_t *phase_tab, const int32_t *tile_base,
+                       const int32_t *prun, int32_t *run) {
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    const int p0 = prun[4 * phase], p1 = prun[4 * phase + 1], c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
+    if (nrun == 0 && p1 > p0) return;  // table full: flagged by k_phase_close
+    for (int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tt <= te - tb;
+         tt += (int64_t)gridDim.x * blockDim.x) {
+        const int t = tb + (int)tt;
+        const int st = (t < te) ? tile_base[t] - p0 : p1 - p0;
+        const int lo = (t == tb) ? 0 : (tile_base[t - 1] - p0) / run_nodes + 1;
+        const int hi = (t < te) ? min(st / run_nodes, nrun - 1) : nrun;
+        for (int c = lo; c <= hi; ++c) run[c0 + c] = p0 + st;
+    }
 }
 
 __global__ void k_check_phases(int32_t *cnt, int32_t *err) {
@@ -469,8 +508,8 @@ __global__ void k_check_phases(int32_t *cnt, int32_t *err) {
 __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, const int32_t *sched,
                         const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
                         const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
-                        const int32_t *perm, const int32_t *row_off, int32_t *links, int32_t *depth,
-                        int32_t *err) {
+                        const int32_t *perm, const int32_t *row_off, const int32_t *depth_slot, int dstack,
+                        int32_t *links, int32_t *depth, int32_t *err) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] == 0) continue;
@@ -504,11 +543,26 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
         if (tile_root[t] == g) meta |= kMetaTileRoot | (t << kMetaSlotShift);
         if (par[g] < 0) meta |= kMetaBodyRoot;
         if (yfirst[g]) meta |= kMetaYFirst;
+        // LDS slots of the wide sweeps: the child evaluated first sits in this
+        // node's own slot, the second one above it; bead and earlier-tile
+        // children name the spare slot dstack
+        const int own = depth_slot[g];
+        const bool xin = ref[0] == kRefStack, yin = ref[1] == kRefStack;
+        const bool yf = yfirst[g] != 0;
+        const bool fin = yf ? yin : xin;
+        int xs = dstack, ys = dstack;
+        if (xin) xs = yf ? own + (fin ? 1 : 0) : own;
+        if (yin) ys = yf ? own : own + (fin ? 1 : 0);
+        const bool troot = (meta & kMetaTileRoot) != 0;
+        const int os = troot ? dstack : own;
+        if ((xin && xs >= dstack) || (yin && ys >= dstack) || (!troot && own >= dstack)) raise_flag(err, kFlagStack);
         const int s = sched[g];
-        links[4 * s + 0] = ref[0];
-        links[4 * s + 1] = ref[1];
-        links[4 * s + 2] = off;
-        links[4 * s + 3] = meta;
+        links[kLinkInts * s + 0] = ref[0];
+        links[kLinkInts * s + 1] = ref[1];
+        links[kLinkInts * s + 2] = off;
+        links[kLinkInts * s + 3] = meta;
+        links[kLinkInts * s + 4] = xs | (ys << 8) | (os << 16);
+        links[kLinkInts * s + 5] = 0;
         depth[g] = dep;
     }
 }
@@ -579,7 +633,7 @@ __global__ void __launch_bounds__(256) k_gen_level(int level, const int32_t *dst
             continue;
         }
         const int body = nbody[g];
-        const int32_t *lk = links + 4 * (int64_t)s;
+        const int32_t *lk = links + kLinkInts * (int64_t)s;
         const int x = lc[g], y = rc[g];
         const bool xi = x >= 0, yi = y >= 0;
         double cx[3], cy[3], Tx[6], Ty[6];
@@ -686,20 +740,25 @@ __global__ void __launch_bounds__(256) k_gen_level(int level, const int32_t *dst
         r[23] = tau[2];
         r[24] = sx;
         r[25] = sy;
-        const int32_t l0 = lk[0], l1 = lk[1], l2 = lk[2], l3 = lk[3];
+        int32_t li[kLinkInts];
+#pragma unroll
+        for (int q = 0; q < kLinkInts; ++q) li[q] = lk[q];
+        const int32_t l3 = li[3];
         if (store & 1) {
             double *o = rec64 + (int64_t)kRecWords * s;
 #pragma unroll
             for (int q = 0; q < 26; ++q) o[q] = r[q];
             int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-            ol[0] = l0; ol[1] = l1; ol[2] = l2; ol[3] = l3;
+#pragma unroll
+            for (int q = 0; q < kLinkInts; ++q) ol[q] = li[q];
         }
         if (store & 2) {
             float *o = rec32 + (int64_t)kRecWords * s;
 #pragma unroll
             for (int q = 0; q < 26; ++q) o[q] = (float)r[q];
             int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-            ol[0] = l0; ol[1] = l1; ol[2] = l2; ol[3] = l3;
+#pragma unroll
+            for (int q = 0; q < kLinkInts; ++q) ol[q] = li[q];
         }
         const bool body_root = (l3 & kMetaBodyRoot) != 0;
         if (k > 3 || body_root) {
@@ -808,6 +867,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_sched_node, NI, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, P.d_cnt, (int64_t)kCntNum, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_phase, (int64_t)(2 * kMaxPhases), 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_prun, (int64_t)(4 * kMaxPhases), 0);
     // --- 1. boxes and codes
     hipLaunchKernelGGL(k_bbox, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, P.d_bmin, P.d_bmax, P.d_err);
     hipLaunchKernelGGL(k_codes, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, P.d_bead_off, pos, P.d_bmin,
@@ -860,10 +920,12 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
                            P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof);
         hipLaunchKernelGGL(k_assign, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par, P.d_lc,
                            P.d_rc, P.d_units, P.d_trval, P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node,
-                           P.d_yfirst, P.d_err, NI);
+                           P.d_yfirst, P.d_slot, P.d_err, NI);
         hipLaunchKernelGGL(k_commit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.d_cov, P.d_tileof);
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, ph, P.d_trval, P.d_trscan, P.d_cnt,
-                           P.d_phase);
+                           P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err);
+        hipLaunchKernelGGL(k_runs, dim3(std::min(grid_for(NI), 1024u)), dim3(kThreads), 0, s, ph, P.run_nodes,
+                           P.d_phase, P.d_tile_base, P.d_prun, P.d_run);
         HQ_HIP(hipGetLastError());
         phases = ph;
         if (probe_phases) {
@@ -884,7 +946,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_links, P.d_depth, P.d_err);
+                       P.d_row_off, P.d_slot, scratch_slot(P.S), P.d_links, P.d_depth, P.d_err);
     // --- 5. transforms, one launch per depth level, deepest first
     hipLaunchKernelGGL(k_depth_hist, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist);
     HQ_TRY(scan_i32_inclusive(P, P.d_dhist, P.d_dincl, (int64_t)kDepthBins * kDepthBlocks, s));

@@ -30,12 +30,15 @@ constexpr int kDepthBlocksHost = 512;   // blocks of the depth counting sort
 //   [15,21) tail of reflector 2 (entries 3..8 of v_2; v_2[2] = 1)
 //   [21,24) tau_0, tau_1, tau_2
 //   [24]    sx = sqrt(n_x / n)       [25]  sy = sqrt(n_y / n)
-//   then four int32 links at element 26 (float records) or element 26
-//   reinterpreted as int32[4] (double records): xref, yref, off, meta.
+//   then six int32 links from element 26 on (the bytes of elements 26..31 of
+//   a float record, 26..28 of a double record): xref, yref, off, meta,
+//   slots (x slot | y slot << 8 | own slot << 16, LDS slots of the wide
+//   sweeps), and a reserved word.
 constexpr int kRecTau = 21;
 constexpr int kRecSx = 24;
 constexpr int kRecSy = 25;
 constexpr int kRecLinks = 26;
+constexpr int kLinkInts = 6;
 
 // Child references in the links:
 //   ref >= 0   a bead: the caller's global bead index (vector row 3*ref)
@@ -63,6 +66,7 @@ enum Counter {
     kCntPhases = 2,     // phases with at least one tile
     kCntRemain = 3,     // internal nodes still uncovered after the last phase
     kCntMaxDepth = 4,   // deepest internal node below its body root
+    kCntRuns = 5,       // run-table entries used so far
     kCntNum = 8
 };
 
@@ -112,6 +116,10 @@ inline int floor_log2(int v) {
 // at most floor(log2 S) + 1 pending results; one spare entry.
 inline int stack_depth(int S) { return floor_log2(S) + 2; }
 
+// Wide sweeps address LDS by slot: slots 0 .. floor(log2 S) hold pending
+// results, the next two stage a node's bead or earlier-tile inputs (x, y).
+inline int scratch_slot(int S) { return floor_log2(S) + 1; }
+
 // ---------------------------------------------------------------------------
 // the plan behind a handle
 // ---------------------------------------------------------------------------
@@ -127,6 +135,8 @@ struct Plan {
     int depth_reserved = 0;   // depth levels launched by hq_rebuild
     int64_t tiles_built = 0;
     int max_n = 0;
+    int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
+    int64_t run_cap = 0;      // entries of d_run
 
     std::vector<int64_t> offsets;  // host copy, m + 1
     std::vector<int64_t> row_off;  // host, m + 1
@@ -173,6 +183,7 @@ struct Plan {
     int32_t *d_tileof = nullptr;
     int32_t *d_sched = nullptr;      // schedule index of node
     int32_t *d_yfirst = nullptr;
+    int32_t *d_slot = nullptr;       // stack slot of the node's result inside its tile
     long long *d_trval = nullptr, *d_trscan = nullptr;  // packed (flag << 32 | len) and its scan
     int32_t *d_nn = nullptr;         // beads below
     double *d_ncen = nullptr;        // NI x 3, body-local
@@ -185,12 +196,14 @@ struct Plan {
     // tiles and schedule
     int32_t *d_tile_root = nullptr, *d_tile_base = nullptr, *d_tile_len = nullptr;
     int32_t *d_sched_node = nullptr; // schedule index -> node
-    int32_t *d_links = nullptr;      // schedule index -> int32[4] links
+    int32_t *d_links = nullptr;      // schedule index -> int32[kLinkInts] links
     float *d_rec32 = nullptr;        // NI x 32
     double *d_rec64 = nullptr;       // NI x 32
     double *d_troot = nullptr;       // tiles x 10: (n, c[3], T22[6]) of tile roots
 
     int32_t *d_phase = nullptr;      // 2 x kMaxPhases: [begin, end) tile ids per phase
+    int32_t *d_prun = nullptr;       // 4 x kMaxPhases: node begin, node end, first run entry, runs
+    int32_t *d_run = nullptr;        // run_cap: first schedule index of each run (+ one end entry per phase)
     int32_t *d_cnt = nullptr;        // counters
     int32_t *d_err = nullptr;        // device error flags
 
