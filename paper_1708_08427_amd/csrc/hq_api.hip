@@ -194,11 +194,14 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_sched, NI));
     HQ_TRY(dalloc(P, &P.d_yfirst, NI));
     HQ_TRY(dalloc(P, &P.d_slot, NI));
+    HQ_TRY(dalloc(P, &P.d_aw, NI));
+    HQ_TRY(dalloc(P, &P.d_lw, NI));
     HQ_TRY(dalloc(P, &P.d_trval, NI));
     HQ_TRY(dalloc(P, &P.d_trscan, NI));
     HQ_TRY(dalloc(P, &P.d_nn, NI));
     HQ_TRY(dalloc(P, &P.d_ncen, 3 * NI));
     HQ_TRY(dalloc(P, &P.d_T22, 6 * NI));
+    HQ_TRY(dalloc(P, &P.d_kapn, NI));
     HQ_TRY(dalloc(P, &P.d_depth, NI));
     HQ_TRY(dalloc(P, &P.d_bydepth, NI));
     HQ_TRY(dalloc(P, &P.d_dhist, (int64_t)(kMaxDepth + 1) * kDepthBlocksHost));

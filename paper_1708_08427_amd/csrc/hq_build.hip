@@ -289,7 +289,7 @@ __device__ inline int prefix_len(const unsigned long long *sc, int n, int i, int
 
 __global__ void k_tree(int64_t NI, int m, const int32_t *__restrict__ bead_off, const int32_t *__restrict__ node_off,
                        const unsigned long long *__restrict__ scode, int32_t *lc, int32_t *rc, int32_t *par,
-                       int32_t *first, int32_t *last, int32_t *nn, int32_t *nbody, int32_t *leafpar) {
+                       int32_t *first, int32_t *last, int32_t *nn, int32_t *nbody, int32_t *leafpar, int2 *lw) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         const int j = body_of_node(node_off, m, g);
@@ -333,7 +333,17 @@ __global__ void k_tree(int64_t NI, int m, const int32_t *__restrict__ bead_off, 
         last[g] = base + hi;
         nn[g] = hi - lo + 1;
         nbody[g] = j;
-        if (i == 0) par[g] = -1;
+        if (i == 0) {
+            par[g] = -1;
+            lw[g] = make_int2(-1, 0);
+        }
+        // residue rows that a walk from a child up to this node adds: this
+        // node's own residue rows, and the x subtree's rows for the y child
+        // (pre-order rows, Q~_p = [Residue_p; diag(Q~_x, Q~_y)])
+        const int xi = left >= 0, yi = right >= 0;
+        const int own = 3 * xi + 3 * yi;
+        if (xi) lw[left] = make_int2(g, own);
+        if (yi) lw[right] = make_int2(g, own + (xi ? 3 * (gamma - lo + 1) - 6 : 0));
     }
 }
 
@@ -355,12 +365,14 @@ __device__ inline int child_units(int c, const int32_t *cov, const int32_t *unit
     return units[c];
 }
 
-__global__ void k_mark_beads(int64_t N, const int32_t *leafpar, const int32_t *cov, int32_t *mark) {
+__global__ void k_mark_beads(int64_t N, const int32_t *leafpar, const int32_t *cov, int32_t *mark, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
         mark[i] = (cov[leafpar[i]] == 0) ? 1 : 0;
 }
 
-__global__ void k_mark_roots(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *first, int32_t *mark) {
+__global__ void k_mark_roots(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *first, int32_t *mark, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x) {
         const int p = par[g];
         if (cov[g] != 0 && p >= 0 && cov[p] == 0) mark[first[g]] = 1;
@@ -369,7 +381,8 @@ __global__ void k_mark_roots(int64_t NI, const int32_t *cov, const int32_t *par,
 
 __global__ void k_tile_roots(int64_t NI, int phase, int S, const int32_t *cov, const int32_t *par,
                              const int32_t *nn, const int32_t *first, const int32_t *last, const int32_t *msum,
-                             int32_t *units, long long *trval) {
+                             int32_t *units, long long *trval, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] != 0) {
@@ -386,7 +399,8 @@ __global__ void k_tile_roots(int64_t NI, int phase, int S, const int32_t *cov, c
 }
 
 __global__ void k_tile_emit(int64_t NI, const long long *trval, const long long *trscan, const int32_t *cnt,
-                            int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof) {
+                            int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const long long v = trval[gg];
@@ -400,12 +414,17 @@ __global__ void k_tile_emit(int64_t NI, const long long *trval, const long long 
     }
 }
 
-// Post-order position of every uncovered node inside the tile whose root it
-// reaches first going up; the child with more units is evaluated first.
-__global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc, const int32_t *rc,
-                         const int32_t *units, const long long *trval, const int32_t *tile_base,
-                         int32_t *tileof, int32_t *sched, int32_t *sched_node, int32_t *yfirst, int32_t *depth_slot,
-                         int32_t *err, int64_t sched_cap) {
+// Per uncovered node: evaluation order of its children (the one with more
+// units first) and the step of the walk up to its tile root: its parent, the
+// post-order positions skipped when it is its parent's second child (the
+// first child's subtree), whether that first child is an internal node of the
+// tile (one more pending result on the stack), and whether it is a tile root.
+constexpr int kAwPend = 1 << 16, kAwRoot = 1 << 17;
+
+__global__ void k_assign_prep(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc,
+                              const int32_t *rc, const int32_t *units, const long long *trval, int32_t *yfirst,
+                              int2 *aw, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] != 0) continue;
@@ -413,27 +432,43 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, con
             const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
             yfirst[g] = (uy > ux) ? 1 : 0;
         }
-        // pos: post-order position inside the tile; pend: results of the tile
-        // pending on its stack while this node's subtree is swept, i.e. the
-        // stack slot that receives this node's result
+        const int p = par[g];
+        int word = (trval[g] != 0) ? kAwRoot : 0;
+        if (p >= 0) {
+            const int x = lc[p], y = rc[p];
+            const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
+            const bool y_first = uy > ux;
+            if (g == (y_first ? x : y)) {
+                const int ufirst = y_first ? uy : ux;
+                word |= (ufirst - 1) | ((ufirst > 1) ? kAwPend : 0);
+            }
+        }
+        aw[g] = make_int2(p, word);
+    }
+}
+
+// Post-order position of every uncovered node inside the tile whose root it
+// reaches first going up (the child with more units is evaluated first), and
+// the stack slot that receives its result (results of the tile pending while
+// its subtree is swept).
+__global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *units, const int2 *aw,
+                         const int32_t *tile_base, int32_t *tileof, int32_t *sched, int32_t *sched_node,
+                         int32_t *depth_slot, int32_t *err, int64_t sched_cap, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)gg;
+        if (cov[g] != 0) continue;
         int pos = units[g] - 2, pend = 0;
         int q = g;
         bool found = false;
         bool too_deep = true;
         for (int guard = 0; guard < kMaxDepth; ++guard) {
-            if (trval[q] != 0) { found = true; too_deep = false; break; }
-            const int p = par[q];
-            if (p < 0) { too_deep = false; break; }
-            const int x = lc[p], y = rc[p];
-            const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
-            const bool y_first = uy > ux;
-            const int second = y_first ? x : y;
-            if (q == second) {
-                const int ufirst = y_first ? uy : ux;
-                pos += ufirst - 1;
-                pend += (ufirst > 1) ? 1 : 0;  // the first child is an internal node of this tile
-            }
-            q = p;
+            const int2 w = aw[q];
+            if (w.y & kAwRoot) { found = true; too_deep = false; break; }
+            if (w.x < 0) { too_deep = false; break; }
+            pos += w.y & 0xffff;
+            pend += (w.y & kAwPend) ? 1 : 0;
+            q = w.x;
         }
         if (too_deep) raise_flag(err, kFlagBounds);
         if (!found) continue;
@@ -450,14 +485,16 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *par, con
     }
 }
 
-__global__ void k_commit(int64_t NI, int phase, int32_t *cov, const int32_t *tileof) {
+__global__ void k_commit(int64_t NI, int phase, int32_t *cov, const int32_t *tileof, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x)
         if (cov[g] == 0 && tileof[g] >= 0) cov[g] = phase;
 }
 
 __global__ void k_phase_close(int64_t NI, int phase, const long long *trval, const long long *trscan,
                               int32_t *cnt, int32_t *phase_tab, int run_nodes, int32_t *prun, int64_t run_cap,
-                              int32_t *err) {
+                              int32_t *err, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const long long tot = (NI > 0) ? trscan[NI - 1] + trval[NI - 1] : 0;
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
@@ -485,7 +522,8 @@ __global__ void k_phase_close(int64_t NI, int phase, const long long *trval, con
 // after node c * run_nodes of the phase (phase end if none), so every run
 // holds whole tiles and a lane group can sweep it as one node stream.
 __global__ void k_runs(int phase, int run_nodes, const int32_t *phase_tab, const int32_t *tile_base,
-                       const int32_t *prun, int32_t *run) {
+                       const int32_t *prun, int32_t *run, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
     const int p0 = prun[4 * phase], p1 = prun[4 * phase + 1], c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
     if (nrun == 0 && p1 > p0) return;  // table full: flagged by k_phase_close
@@ -509,7 +547,7 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
                         const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
                         const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
                         const int32_t *perm, const int32_t *row_off, const int32_t *depth_slot, int dstack,
-                        int32_t *links, int32_t *depth, int32_t *err) {
+                        const int2 *lw, int32_t *links, int32_t *depth, int32_t *err) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] == 0) continue;
@@ -529,14 +567,11 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
                 dep = -1;
                 break;
             }
-            const int p = par[q];
-            if (p < 0) break;
+            const int2 w = lw[q];
+            if (w.x < 0) break;
             ++dep;
-            const int x = lc[p], y = rc[p];
-            const int xi = x >= 0, yi = y >= 0;
-            off += 3 * xi + 3 * yi;
-            if (q == y && xi) off += 3 * nn[x] - 6;
-            q = p;
+            off += w.y;
+            q = w.x;
         }
         off += row_off[nbody[g]];
         int meta = 0;
@@ -613,162 +648,201 @@ __device__ __forceinline__ void put_shift(double (&A)[9][3], int r0, double sc, 
     A[r0 + 2][0] = sc * dv[1];   A[r0 + 2][1] = -sc * dv[0];  A[r0 + 2][2] = 0.0;
 }
 
-__global__ void __launch_bounds__(256) k_gen_level(int level, const int32_t *dstart, const int32_t *bydepth,
-                                                   const int32_t *sched, const int32_t *links, const int32_t *lc,
-                                                   const int32_t *rc, const int32_t *nbody, const int32_t *nn_arr,
-                                                   const double *pos, const double *lo, double *ncen, double *T22,
-                                                   float *rec32, double *rec64, int store, double *bcen,
-                                                   unsigned long long *kappa, int32_t *bflags, int64_t N,
-                                                   int64_t NI, int32_t *err) {
+// Record words of the node in LDS row `row` (stride kGenStride): the three
+// reflector tails, taus, translation weights (elements 0..25) and the links.
+constexpr int kGenThreads = 256;
+constexpr int kGenStride = 33;  // words per LDS row (odd: no bank conflicts)
+
+__global__ void __launch_bounds__(kGenThreads) k_gen_level(int level, const int32_t *dstart, const int32_t *bydepth,
+                                                           const int32_t *sched, const int32_t *links,
+                                                           const int32_t *lc, const int32_t *rc,
+                                                           const int32_t *nbody, const int32_t *nn_arr,
+                                                           const double *pos, const double *lo, double *ncen,
+                                                           double *T22, float *rec32, double *rec64, int store,
+                                                           double *bcen, double *kapn, int32_t *bflags, int64_t N,
+                                                           int64_t NI, int32_t *err) {
+    __shared__ uint32_t srec[kGenThreads * kGenStride];
+    __shared__ int32_t sdst[kGenThreads];
     const int i0 = dstart[level], i1 = dstart[level + 1];
-    for (int i = i0 + blockIdx.x * blockDim.x + threadIdx.x; i < i1; i += gridDim.x * blockDim.x) {
-        const int g = bydepth[i];
-        if (g < 0 || g >= NI) {
-            raise_flag(err, kFlagBounds);
-            continue;
-        }
-        const int s = sched[g];
-        if (s < 0 || s >= NI) {
-            raise_flag(err, kFlagBounds);
-            continue;
-        }
-        const int body = nbody[g];
-        const int32_t *lk = links + kLinkInts * (int64_t)s;
-        const int x = lc[g], y = rc[g];
-        const bool xi = x >= 0, yi = y >= 0;
-        double cx[3], cy[3], Tx[6], Ty[6];
-        double nx = 1.0, ny = 1.0;
-        bool bad = false;
-        if (xi) {
-            nx = (double)nn_arr[x];
-            for (int d = 0; d < 3; ++d) cx[d] = ncen[3 * (int64_t)x + d];
-            for (int d = 0; d < 6; ++d) Tx[d] = T22[6 * (int64_t)x + d];
-        } else {
-            const int u = lk[0];
-            if (u < 0 || u >= N) bad = true;
-            for (int d = 0; d < 3; ++d) cx[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
-        }
-        if (yi) {
-            ny = (double)nn_arr[y];
-            for (int d = 0; d < 3; ++d) cy[d] = ncen[3 * (int64_t)y + d];
-            for (int d = 0; d < 6; ++d) Ty[d] = T22[6 * (int64_t)y + d];
-        } else {
-            const int u = lk[1];
-            if (u < 0 || u >= N) bad = true;
-            for (int d = 0; d < 3; ++d) cy[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
-        }
-        if (bad) raise_flag(err, kFlagBounds);
-        const double n = nx + ny;
-        double cp[3], dv[3];
-        for (int d = 0; d < 3; ++d) {
-            cp[d] = (nx * cx[d] + ny * cy[d]) / n;
-            dv[d] = cx[d] - cy[d];
-        }
-        const double sc = sqrt(nx * ny / n);
-        double A[9][3];
+    const int tid = threadIdx.x;
+    for (int base = i0 + blockIdx.x * kGenThreads; base < i1; base += gridDim.x * kGenThreads) {
+        const int i = base + tid;
+        int s = -1;
+        if (i < i1) {
+            const int g = bydepth[i];
+            const int s0 = (g >= 0 && g < NI) ? sched[g] : -1;
+            if (s0 < 0 || s0 >= NI) {
+                raise_flag(err, kFlagBounds);
+            } else {
+                s = s0;
+                const int body = nbody[g];
+                const int32_t *lk = links + kLinkInts * (int64_t)s;
+                int32_t li[kLinkInts];
 #pragma unroll
-        for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
-        int k;
-        if (xi && yi) {
-            put_lower(A, 0, Tx);
-            put_lower(A, 3, Ty);
-            put_shift(A, 6, sc, dv);
-            k = 9;
-        } else if (xi) {
-            put_lower(A, 0, Tx);
-            put_shift(A, 3, sc, dv);
-            k = 6;
-        } else if (yi) {
-            put_lower(A, 0, Ty);
-            put_shift(A, 3, sc, dv);
-            k = 6;
-        } else {
-            put_shift(A, 0, sc, dv);
-            k = 3;
-        }
-        // Householder QR of A (LAPACK sign convention; tau = 0 for a zero tail)
-        double tail[3][8], tau[3];
+                for (int q = 0; q < kLinkInts; ++q) li[q] = lk[q];
+                const int x = lc[g], y = rc[g];
+                const bool xi = x >= 0, yi = y >= 0;
+                double cx[3], cy[3], Tx[6], Ty[6];
+                double nx = 1.0, ny = 1.0;
+                bool bad = false;
+                if (xi) {
+                    nx = (double)nn_arr[x];
+                    for (int d = 0; d < 3; ++d) cx[d] = ncen[3 * (int64_t)x + d];
+                    for (int d = 0; d < 6; ++d) Tx[d] = T22[6 * (int64_t)x + d];
+                } else {
+                    const int u = li[0];
+                    if (u < 0 || u >= N) bad = true;
+                    for (int d = 0; d < 3; ++d) cx[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
+                }
+                if (yi) {
+                    ny = (double)nn_arr[y];
+                    for (int d = 0; d < 3; ++d) cy[d] = ncen[3 * (int64_t)y + d];
+                    for (int d = 0; d < 6; ++d) Ty[d] = T22[6 * (int64_t)y + d];
+                } else {
+                    const int u = li[1];
+                    if (u < 0 || u >= N) bad = true;
+                    for (int d = 0; d < 3; ++d) cy[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
+                }
+                if (bad) raise_flag(err, kFlagBounds);
+                const double n = nx + ny;
+                double cp[3], dv[3];
+                for (int d = 0; d < 3; ++d) {
+                    cp[d] = (nx * cx[d] + ny * cy[d]) / n;
+                    dv[d] = cx[d] - cy[d];
+                }
+                const double sc = sqrt(nx * ny / n);
+                double A[9][3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+                for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
+                int k;
+                if (xi && yi) {
+                    put_lower(A, 0, Tx);
+                    put_lower(A, 3, Ty);
+                    put_shift(A, 6, sc, dv);
+                    k = 9;
+                } else if (xi) {
+                    put_lower(A, 0, Tx);
+                    put_shift(A, 3, sc, dv);
+                    k = 6;
+                } else if (yi) {
+                    put_lower(A, 0, Ty);
+                    put_shift(A, 3, sc, dv);
+                    k = 6;
+                } else {
+                    put_shift(A, 0, sc, dv);
+                    k = 3;
+                }
+                // Householder QR of A in place (LAPACK sign convention; tau = 0
+                // for a zero tail): the scaled tail of reflector j replaces
+                // column j below the diagonal
+                double tau[3];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) tail[j][r] = 0.0;
-            const double alpha = A[j][j];
-            double xs = 0.0;
+                for (int j = 0; j < 3; ++j) {
+                    const double alpha = A[j][j];
+                    double xs = 0.0;
 #pragma unroll
-            for (int r = j + 1; r < 9; ++r) xs = fma(A[r][j], A[r][j], xs);
-            if (xs == 0.0) {
-                tau[j] = 0.0;
-                continue;
+                    for (int r = j + 1; r < 9; ++r) xs = fma(A[r][j], A[r][j], xs);
+                    if (xs == 0.0) {
+                        tau[j] = 0.0;
+                        continue;
+                    }
+                    const double nrm = sqrt(fma(alpha, alpha, xs));
+                    const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                    tau[j] = (beta - alpha) / beta;
+                    const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+                    for (int r = j + 1; r < 9; ++r) A[r][j] *= scal;
+                    A[j][j] = beta;
+#pragma unroll
+                    for (int l = j + 1; l < 3; ++l) {
+                        double w = A[j][l];
+#pragma unroll
+                        for (int r = j + 1; r < 9; ++r) w = fma(A[r][j], A[r][l], w);
+                        w *= tau[j];
+                        A[j][l] -= w;
+#pragma unroll
+                        for (int r = j + 1; r < 9; ++r) A[r][l] = fma(-w, A[r][j], A[r][l]);
+                    }
+                }
+                double T[6];
+                T[0] = A[0][0];
+                T[1] = A[0][1];
+                T[2] = A[1][1];
+                T[3] = A[0][2];
+                T[4] = A[1][2];
+                T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
+                for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
+                for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
+                const double sx = sqrt(nx / n);
+                const double sy = sqrt(ny / n);
+                // record element e: reflector tails (below the diagonal of A),
+                // taus, translation weights
+                auto word = [&](int e) -> double {
+                    if (e < 8) return A[1 + e][0];
+                    if (e < 15) return A[2 + (e - 8)][1];
+                    if (e < 21) return A[3 + (e - 15)][2];
+                    if (e < 24) return tau[e - 21];
+                    return e == 24 ? sx : sy;
+                };
+                if (store & 2) {
+                    uint32_t *row = srec + tid * kGenStride;
+#pragma unroll
+                    for (int e = 0; e < 26; ++e) row[e] = __float_as_uint((float)word(e));
+#pragma unroll
+                    for (int e = 0; e < kLinkInts; ++e) row[26 + e] = (uint32_t)li[e];
+                }
+                if (store & 1) {
+                    double2 *o = reinterpret_cast<double2 *>(rec64 + (int64_t)kRecWords * s);
+#pragma unroll
+                    for (int e = 0; e < 13; ++e) o[e] = make_double2(word(2 * e), word(2 * e + 1));
+                    int2 *ol = reinterpret_cast<int2 *>(rec64 + (int64_t)kRecWords * s + kRecLinks);
+#pragma unroll
+                    for (int e = 0; e < kLinkInts / 2; ++e) ol[e] = make_int2(li[2 * e], li[2 * e + 1]);
+                }
+                const bool body_root = (li[3] & kMetaBodyRoot) != 0;
+                const double kap = (k > 3) ? cond_bound3(T) : 1e300;
+                kapn[g] = (k > 3) ? kap : 0.0;
+                if (body_root) {
+                    if (kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+                    for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
+                }
             }
-            const double nrm = sqrt(fma(alpha, alpha, xs));
-            const double beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau[j] = (beta - alpha) / beta;
-            const double scal = 1.0 / (alpha - beta);
-#pragma unroll
-            for (int r = j + 1; r < 9; ++r) tail[j][r - j - 1] = A[r][j] * scal;
-            A[j][j] = beta;
-#pragma unroll
-            for (int l = j + 1; l < 3; ++l) {
-                double w = A[j][l];
-#pragma unroll
-                for (int r = j + 1; r < 9; ++r) w = fma(tail[j][r - j - 1], A[r][l], w);
-                w *= tau[j];
-                A[j][l] -= w;
-#pragma unroll
-                for (int r = j + 1; r < 9; ++r) A[r][l] = fma(-w, tail[j][r - j - 1], A[r][l]);
-            }
         }
-        double T[6];
-        T[0] = A[0][0];
-        T[1] = A[0][1];
-        T[2] = A[1][1];
-        T[3] = A[0][2];
-        T[4] = A[1][2];
-        T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
-        for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
-        for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
-        const double sx = sqrt(nx / n), sy = sqrt(ny / n);
-        double r[26];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] = tail[0][q];
-#pragma unroll
-        for (int q = 0; q < 7; ++q) r[8 + q] = tail[1][q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) r[15 + q] = tail[2][q];
-        r[21] = tau[0];
-        r[22] = tau[1];
-        r[23] = tau[2];
-        r[24] = sx;
-        r[25] = sy;
-        int32_t li[kLinkInts];
-#pragma unroll
-        for (int q = 0; q < kLinkInts; ++q) li[q] = lk[q];
-        const int32_t l3 = li[3];
-        if (store & 1) {
-            double *o = rec64 + (int64_t)kRecWords * s;
-#pragma unroll
-            for (int q = 0; q < 26; ++q) o[q] = r[q];
-            int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-#pragma unroll
-            for (int q = 0; q < kLinkInts; ++q) ol[q] = li[q];
+        if (!(store & 2)) continue;
+        // float records leave through LDS so that each one is written as a
+        // whole 128-byte line (two records per wave-wide store)
+        sdst[tid] = s;
+        __syncthreads();
+        const int lane = tid & 63, wv = tid >> 6, half = lane >> 5, q = lane & 31;
+#pragma unroll 4
+        for (int kk = 0; kk < 32; ++kk) {
+            const int rl = wv * 64 + 2 * kk + half;
+            const int sd = sdst[rl];
+            if (sd >= 0) reinterpret_cast<uint32_t *>(rec32)[(int64_t)kRecWords * sd + q] = srec[rl * kGenStride + q];
         }
-        if (store & 2) {
-            float *o = rec32 + (int64_t)kRecWords * s;
-#pragma unroll
-            for (int q = 0; q < 26; ++q) o[q] = (float)r[q];
-            int32_t *ol = reinterpret_cast<int32_t *>(o + kRecLinks);
-#pragma unroll
-            for (int q = 0; q < kLinkInts; ++q) ol[q] = li[q];
+        __syncthreads();
+    }
+}
+
+// Per body: the largest node condition bound (node values of k = 3 are 0)
+// and the ill-conditioning flag; one block per body, no atomics.
+__global__ void __launch_bounds__(256) k_body_kappa(int64_t m, const int32_t *node_off, const double *kapn,
+                                                    unsigned long long *kappa, int32_t *bflags) {
+    __shared__ double red[256];
+    for (int64_t j = blockIdx.x; j < m; j += gridDim.x) {
+        double mx = 0.0;
+        for (int g = node_off[j] + threadIdx.x; g < node_off[j + 1]; g += blockDim.x) mx = fmax(mx, kapn[g]);
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
         }
-        const bool body_root = (l3 & kMetaBodyRoot) != 0;
-        if (k > 3 || body_root) {
-            const double kap = (k > 3) ? cond_bound3(T) : 1e300;
-            if (k > 3) atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kap));
-            if (k > 3 && kap > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
-            if (body_root && kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+        if (threadIdx.x == 0) {
+            kappa[j] = (unsigned long long)__double_as_longlong(red[0]);
+            if (red[0] > 1e4) bflags[j] |= HQ_BODY_ILLCOND;
         }
-        if (body_root)
-            for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
+        __syncthreads();
     }
 }
 
@@ -900,32 +974,38 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     }
     // --- 3. tree
     hipLaunchKernelGGL(k_tree, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, (int)m, P.d_bead_off, P.d_node_off,
-                       P.d_scode, P.d_lc, P.d_rc, P.d_par, P.d_first, P.d_last, P.d_nn, P.d_nbody, P.d_leafpar);
+                       P.d_scode, P.d_lc, P.d_rc, P.d_par, P.d_first, P.d_last, P.d_nn, P.d_nbody, P.d_leafpar,
+                       P.d_lw);
     HQ_HIP(hipGetLastError());
     // --- 4. tiles
     int phases = 0;
     const int max_ph = probe_phases ? (kMaxPhases - 1) : P.phases_reserved;
     for (int ph = 1; ph <= max_ph; ++ph) {
+        // a phase after the one that covered the last node is a no-op on the
+        // device (reserved phases of a rebuild cost a few launches only)
+        const int32_t *gate = (ph >= 2) ? P.d_cnt + kCntRemain : nullptr;
         if (ph >= 2) {
             hipLaunchKernelGGL(k_mark_beads, dim3(grid_for(N)), dim3(kThreads), 0, s, N, P.d_leafpar, P.d_cov,
-                               P.d_mark);
+                               P.d_mark, gate);
             hipLaunchKernelGGL(k_mark_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par,
-                               P.d_first, P.d_mark);
-            HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, N, s));
+                               P.d_first, P.d_mark, gate);
+            HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, N, s, gate));
         }
         hipLaunchKernelGGL(k_tile_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.S, P.d_cov, P.d_par,
-                           P.d_nn, P.d_first, P.d_last, P.d_msum, P.d_units, P.d_trval);
-        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s));
+                           P.d_nn, P.d_first, P.d_last, P.d_msum, P.d_units, P.d_trval, gate);
+        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate));
         hipLaunchKernelGGL(k_tile_emit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_trval, P.d_trscan,
-                           P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof);
-        hipLaunchKernelGGL(k_assign, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par, P.d_lc,
-                           P.d_rc, P.d_units, P.d_trval, P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node,
-                           P.d_yfirst, P.d_slot, P.d_err, NI);
-        hipLaunchKernelGGL(k_commit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.d_cov, P.d_tileof);
+                           P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof, gate);
+        hipLaunchKernelGGL(k_assign_prep, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par, P.d_lc,
+                           P.d_rc, P.d_units, P.d_trval, P.d_yfirst, P.d_aw, gate);
+        hipLaunchKernelGGL(k_assign, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_units, P.d_aw,
+                           P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI, gate);
+        hipLaunchKernelGGL(k_commit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.d_cov, P.d_tileof, gate);
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, ph, P.d_trval, P.d_trscan, P.d_cnt,
-                           P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err);
+                           P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
+        // the run table of a phase is built when the phase holds nodes
         hipLaunchKernelGGL(k_runs, dim3(std::min(grid_for(NI), 1024u)), dim3(kThreads), 0, s, ph, P.run_nodes,
-                           P.d_phase, P.d_tile_base, P.d_prun, P.d_run);
+                           P.d_phase, P.d_tile_base, P.d_prun, P.d_run, P.d_prun + 4 * ph + 1);
         HQ_HIP(hipGetLastError());
         phases = ph;
         if (probe_phases) {
@@ -946,7 +1026,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_slot, scratch_slot(P.S), P.d_links, P.d_depth, P.d_err);
+                       P.d_row_off, P.d_slot, scratch_slot(P.S), P.d_lw, P.d_links, P.d_depth, P.d_err);
     // --- 5. transforms, one launch per depth level, deepest first
     hipLaunchKernelGGL(k_depth_hist, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist);
     HQ_TRY(scan_i32_inclusive(P, P.d_dhist, P.d_dincl, (int64_t)kDepthBins * kDepthBlocks, s));
@@ -964,12 +1044,14 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         hipLaunchKernelGGL(k_check_depth, dim3(1), dim3(64), 0, s, P.d_cnt, P.depth_reserved, P.d_err);
     }
     const int levels = probe_phases ? P.depth_built : P.depth_reserved;
-    const unsigned ggrid = (unsigned)std::min<int64_t>(2048, (NI + kThreads - 1) / kThreads);
+    const unsigned ggrid = (unsigned)std::min<int64_t>(2048, (NI + kGenThreads - 1) / kGenThreads);
     for (int d = levels; d >= 0; --d) {
-        hipLaunchKernelGGL(k_gen_level, dim3(ggrid), dim3(kThreads), 0, s, d, P.d_dstart, P.d_bydepth, P.d_sched,
+        hipLaunchKernelGGL(k_gen_level, dim3(ggrid), dim3(kGenThreads), 0, s, d, P.d_dstart, P.d_bydepth, P.d_sched,
                            P.d_links, P.d_lc, P.d_rc, P.d_nbody, P.d_nn, pos, P.d_lo, P.d_ncen, P.d_T22,
-                           P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kappa, P.d_bflags, N, NI, P.d_err);
+                           P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kapn, P.d_bflags, N, NI, P.d_err);
     }
+    hipLaunchKernelGGL(k_body_kappa, dim3((unsigned)std::min<int64_t>(m, 65535)), dim3(256), 0, s, m, P.d_node_off,
+                       P.d_kapn, P.d_kappa, P.d_bflags);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

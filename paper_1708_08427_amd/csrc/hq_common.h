@@ -184,10 +184,13 @@ struct Plan {
     int32_t *d_sched = nullptr;      // schedule index of node
     int32_t *d_yfirst = nullptr;
     int32_t *d_slot = nullptr;       // stack slot of the node's result inside its tile
+    int2 *d_aw = nullptr;            // walk to the tile root: (parent, packed position step)
+    int2 *d_lw = nullptr;            // walk to the body root: (parent, residue rows added)
     long long *d_trval = nullptr, *d_trscan = nullptr;  // packed (flag << 32 | len) and its scan
     int32_t *d_nn = nullptr;         // beads below
     double *d_ncen = nullptr;        // NI x 3, body-local
     double *d_T22 = nullptr;         // NI x 6, lower triangle packed (00,10,11,20,21,22)
+    double *d_kapn = nullptr;        // NI: condition bound of each node (0 for k = 3)
     int32_t *d_depth = nullptr;      // depth below the body root
     int32_t *d_bydepth = nullptr;    // nodes bucketed by depth
     int32_t *d_dhist = nullptr, *d_dincl = nullptr;  // (kMaxDepth + 1) x kDepthBlocksHost
@@ -243,8 +246,10 @@ void set_error(const std::string &msg);
 // ---------------------------------------------------------------------------
 // entry points between the library's own source files
 // ---------------------------------------------------------------------------
-hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
-hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s);
+hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s,
+                             const int32_t *gate = nullptr);
+hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s,
+                             const int32_t *gate = nullptr);
 
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases);
 hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs,

@@ -1,6 +1,7 @@
 // Device-wide prefix sums (three passes: block totals, scan of the totals,
 // block scans with carry-in).  Used by the build for unit counts and for
-// numbering tiles; every launch size depends only on n.
+// numbering tiles; every launch size depends only on n.  A non-null gate
+// that reads 0 on the device turns all three passes into no-ops.
 #include "hq_common.h"
 
 namespace hq {
@@ -40,7 +41,8 @@ __device__ T block_exclusive(T v, T *lds, T *total) {
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_block_sums(const T *__restrict__ in, int64_t n,
-                                                         T *__restrict__ blk) {
+                                                         T *__restrict__ blk, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     __shared__ T lds[kThreads / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
     T s = 0;
@@ -53,7 +55,8 @@ __global__ void __launch_bounds__(kThreads) k_block_sums(const T *__restrict__ i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, int64_t nb) {
+__global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, int64_t nb, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     __shared__ T lds[kThreads / 64 + 1];
     T carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
@@ -68,7 +71,9 @@ __global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, i
 
 template <typename T, bool kInclusive>
 __global__ void __launch_bounds__(kThreads) k_scan_apply(const T *__restrict__ in, T *__restrict__ out,
-                                                         int64_t n, const T *__restrict__ blk) {
+                                                         int64_t n, const T *__restrict__ blk,
+                                                         const int32_t *gate) {
+    if (gate && *gate == 0) return;
     __shared__ T lds[kThreads / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
     T v[kItems];
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const T *__restrict__ i
 }
 
 template <typename T, bool kInclusive>
-hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s) {
+hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s, const int32_t *gate) {
     if (n <= 0) return HQ_OK;
     const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
     if (nb > P.scan_blk_cap) {
@@ -97,10 +102,10 @@ hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s) {
         return HQ_E_UNSUPPORTED;
     }
     T *blk = reinterpret_cast<T *>(P.d_scan_blk);
-    hipLaunchKernelGGL((k_block_sums<T>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, blk);
-    hipLaunchKernelGGL((k_scan_blocks<T>), dim3(1), dim3(kThreads), 0, s, blk, nb);
+    hipLaunchKernelGGL((k_block_sums<T>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, blk, gate);
+    hipLaunchKernelGGL((k_scan_blocks<T>), dim3(1), dim3(kThreads), 0, s, blk, nb, gate);
     hipLaunchKernelGGL((k_scan_apply<T, kInclusive>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n,
-                       (const T *)blk);
+                       (const T *)blk, gate);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }
@@ -109,12 +114,14 @@ hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s) {
 
 int64_t scan_blocks_needed(int64_t n) { return (n + kPerBlock - 1) / kPerBlock; }
 
-hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
-    return scan_impl<int32_t, true>(P, in, out, n, s);
+hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s,
+                             const int32_t *gate) {
+    return scan_impl<int32_t, true>(P, in, out, n, s, gate);
 }
 
-hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s) {
-    return scan_impl<long long, false>(P, in, out, n, s);
+hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s,
+                             const int32_t *gate) {
+    return scan_impl<long long, false>(P, in, out, n, s, gate);
 }
 
 }  // namespace hq
