@@ -90,3 +90,62 @@ def leak(pos, x):
     x = np.asarray(x, dtype=np.float64).reshape(Z.shape[1], -1)
     nz = np.linalg.norm(Z, 2)
     return np.linalg.norm(Z @ x, axis=0) / (nz * np.maximum(np.linalg.norm(x, axis=0), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# The same quantities for bodies too large to form Z (millions of beads):
+# Z x, Z^T y and the 6 x 6 Gram matrix Z Z^T straight from the definition of
+# Eq. 1.2 in O(n).  Z is taken about the centroid as above; the projector is
+# P f = f - Z^T (Z Z^T)^{-1} Z f, which for a body that spans 3D has a
+# well-conditioned 6 x 6 Gram matrix.
+# ---------------------------------------------------------------------------
+def _centred(pos):
+    pos = np.asarray(pos, dtype=np.float64)
+    return pos - pos.mean(axis=0)
+
+
+def zmul(pos, x):
+    """Z x (6 x R) for x (3n x R): [sum_k x_k; sum_k r_k x x_k]."""
+    r = _centred(pos)
+    x = np.asarray(x, dtype=np.float64).reshape(len(r), 3, -1)
+    top = x.sum(axis=0)
+    bot = np.cross(r[:, :, None], x, axisa=1, axisb=1, axisc=1).sum(axis=0)
+    return np.concatenate([top, bot], axis=0)
+
+
+def zmul_t(pos, y):
+    """Z^T y (3n x R) for y (6 x R): block k is y_t + A_k^T y_r = y_t - r_k x y_r."""
+    r = _centred(pos)
+    y = np.asarray(y, dtype=np.float64).reshape(6, -1)
+    yt, yr = y[0:3], y[3:6]
+    blk = yt[None, :, :] - np.cross(r[:, :, None], yr[None, :, :], axisa=1, axisb=1, axisc=1)
+    return blk.reshape(3 * len(r), -1)
+
+
+def gram(pos):
+    """Z Z^T (6 x 6) about the centroid: [[n I, 0], [0, sum_k A_k A_k^T]]."""
+    r = _centred(pos)
+    G = np.zeros((6, 6))
+    G[0:3, 0:3] = len(r) * np.eye(3)
+    # A_k A_k^T = |r_k|^2 I - r_k r_k^T; the off-diagonal blocks sum_k A_k^T
+    # vanish about the centroid (sum_k r_k = 0) up to rounding
+    G[3:6, 3:6] = (r * r).sum() * np.eye(3) - r.T @ r
+    S = np.zeros((3, 3))
+    sx = r.sum(axis=0)
+    S[:] = cross_matrix(sx).T
+    G[0:3, 3:6] = S
+    G[3:6, 0:3] = S.T
+    return G
+
+
+def project_large(pos, f):
+    """P f (3n x R) in O(n)."""
+    f = np.asarray(f, dtype=np.float64).reshape(3 * len(pos), -1)
+    return f - zmul_t(pos, np.linalg.solve(gram(pos), zmul(pos, f)))
+
+
+def leak_large(pos, x):
+    """||Z x|| / (||Z||_2 ||x||) per column, in O(n)."""
+    x = np.asarray(x, dtype=np.float64).reshape(3 * len(pos), -1)
+    nz = np.sqrt(np.linalg.eigvalsh(gram(pos)).max())
+    return np.linalg.norm(zmul(pos, x), axis=0) / (nz * np.maximum(np.linalg.norm(x, axis=0), 1e-300))

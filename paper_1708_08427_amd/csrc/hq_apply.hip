@@ -30,7 +30,8 @@ namespace {
 struct Ctx {
     int64_t N, rows, nsched;
     int R, nchunks, dmax, xch_cap;
-    int xslot;  // first scratch slot of the wide sweeps
+    int nslot;  // LDS slots per lane of the wide sweeps
+    uint32_t in_bytes, out_bytes, xch_bytes;  // buffer sizes of the wide sweeps (each < 2 GiB)
 };
 
 template <typename T>
@@ -464,20 +465,84 @@ __global__ void __launch_bounds__(64) k_down(int phase, const int32_t *__restric
 // Wide sweeps: a lane group of 32 or 64 lanes (one right-hand side per lane)
 // sweeps a run of whole tiles; a wave holds two groups of 32 or one of 64.
 //
-// A node record is 32 elements; lane q of each 32-lane half holds element q,
-// so one coalesced load fetches a whole record and ds_swizzle broadcasts
-// element w inside the half when the node is processed.  The sweep order is
-// fixed at build time, and so is the stack depth at every node: the record
-// names the LDS slots of the two children and of the node's own result, so
-// a node step has no stack pointer and no data-dependent branches; the
-// case-dependent packing of the length-9 vector is done with selects.
+// The sweep order is fixed at build time, and so is the stack depth at every
+// node: the record names the LDS slots of the two children and of the node's
+// own result, so a node step has no stack pointer and no data-dependent
+// branches; the case-dependent packing of the length-9 vector is done with
+// selects.
 //
 // Latency: records are loaded PR nodes ahead and memory inputs NR - 1 nodes
-// ahead.  Every load is issued unconditionally (a child with nothing to load
-// reads a valid dummy address and the value is discarded), so the compiler
-// can wait for exactly the loads a node needs instead of draining all
-// outstanding ones; only stores are predicated.
+// ahead.  Vector data goes through raw buffer loads and stores whose lanes
+// are switched off by an out-of-range offset (loads return 0, stores are
+// dropped), so every memory instruction is issued unconditionally and the
+// compiler can wait for exactly the loads a node needs instead of draining
+// the stores of earlier nodes.  Each buffer must stay below 2 GiB.
 // ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kOOB = 0x80000000u;  // byte offset past the end of every buffer of a wide sweep
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bld(rsrc_t r, uint32_t vo, uint32_t so);
+template <>
+__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bst(T v, rsrc_t r, uint32_t vo, uint32_t so);
+template <>
+__device__ __forceinline__ void bst<float>(float v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+}
+template <>
+__device__ __forceinline__ void bst<double>(double v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+}
+
+// The six values of one exchange entry (slot, rhs) are contiguous.
+__device__ __forceinline__ void bld6(rsrc_t r, uint32_t vo, float (&m)[6]) {
+    const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 0, 0);
+    const u32x3 b = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 12, 0);
+    m[0] = __uint_as_float(a.x);
+    m[1] = __uint_as_float(a.y);
+    m[2] = __uint_as_float(a.z);
+    m[3] = __uint_as_float(b.x);
+    m[4] = __uint_as_float(b.y);
+    m[5] = __uint_as_float(b.z);
+}
+__device__ __forceinline__ void bld6(rsrc_t r, uint32_t vo, double (&m)[6]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 16 * k, 0);
+        m[2 * k] = __builtin_bit_cast(double, u32x2{a.x, a.y});
+        m[2 * k + 1] = __builtin_bit_cast(double, u32x2{a.z, a.w});
+    }
+}
+__device__ __forceinline__ void bst6(rsrc_t r, uint32_t vo, const float (&m)[6]) {
+    __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(m[0]), __float_as_uint(m[1]), __float_as_uint(m[2])},
+                                          r, vo, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(m[3]), __float_as_uint(m[4]), __float_as_uint(m[5])},
+                                          r, vo, 12, 0);
+}
+__device__ __forceinline__ void bst6(rsrc_t r, uint32_t vo, const double (&m)[6]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const u32x2 a = __builtin_bit_cast(u32x2, m[2 * k]), b = __builtin_bit_cast(u32x2, m[2 * k + 1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, 16 * k, 0);
+    }
+}
+
 template <int W>
 __device__ __forceinline__ float bcast(float v) {
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), W << 5));
@@ -491,10 +556,67 @@ __device__ __forceinline__ double bcast(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+// A prefetched node record, spread over the lanes of a 32-lane half.
+//   float: both 16-lane rows of the half hold the record, lane l words
+//          2 (l & 15) and 2 (l & 15) + 1; word w reaches all lanes of its row
+//          with one DPP row broadcast (a VALU move, no LDS traffic).
+//   double: lane q of the half holds word q; ds_swizzle broadcasts it.
+template <typename T>
+struct RecReg;
+
+template <int W>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + W, 0xf, 0xf, true));
+}
+
+#ifndef HQ_DPP_WORDS
+#define HQ_DPP_WORDS 12
+#endif
+// record words below kDppWords are broadcast with DPP (VALU), the rest with
+// ds_swizzle (LDS), to balance the two pipes
+constexpr int kDppWords = HQ_DPP_WORDS;
+
+template <>
+struct RecReg<float> {
+    float a, b;
+    __device__ __forceinline__ void load(const float *__restrict__ r, int lane) {
+        const float2 ab = reinterpret_cast<const float2 *>(r)[lane & 15];
+        a = ab.x;
+        b = ab.y;
+    }
+    template <int W>
+    __device__ __forceinline__ float get() const {
+        // word W sits in lane W / 2 of each 16-lane row, component W % 2
+        if constexpr (W < kDppWords) {
+            if constexpr (W & 1) return row_bcast<W / 2>(b);
+            else return row_bcast<W / 2>(a);
+        } else {
+            if constexpr (W & 1) return bcast<W / 2>(b);
+            else return bcast<W / 2>(a);
+        }
+    }
+    template <int W>
+    __device__ __forceinline__ int geti() const { return __float_as_int(get<W>()); }
+};
+
+template <>
+struct RecReg<double> {
+    double v;
+    __device__ __forceinline__ void load(const double *__restrict__ r, int lane) { v = r[lane & 31]; }
+    template <int W>
+    __device__ __forceinline__ double get() const { return bcast<W>(v); }
+    // int32 link word i (0..5) of a double record: bytes of elements 26..28
+    template <int I>
+    __device__ __forceinline__ int geti() const {
+        const long long b = __double_as_longlong(bcast<kRecLinks + I / 2>(v));
+        return (I & 1) ? (int)(b >> 32) : (int)(b & 0xffffffffll);
+    }
+};
+
 template <int W, typename T>
-__device__ __forceinline__ void bcast_g(T (&g)[26], T v) {
-    g[W] = bcast<W>(v);
-    if constexpr (W + 1 < 26) bcast_g<W + 1>(g, v);
+__device__ __forceinline__ void bcast_g(T (&g)[26], const RecReg<T> &r) {
+    g[W] = r.template get<W>();
+    if constexpr (W + 1 < 26) bcast_g<W + 1>(g, r);
 }
 
 // the link words of a record (elements 26.. as int32)
@@ -502,36 +624,29 @@ struct Links6 {
     int xref, yref, off, meta, slots;
 };
 
-__device__ __forceinline__ Links6 bcast_links6(float v) {
+__device__ __forceinline__ Links6 bcast_links6(const RecReg<float> &r) {
     Links6 l;
-    l.xref = __float_as_int(bcast<26>(v));
-    l.yref = __float_as_int(bcast<27>(v));
-    l.off = __float_as_int(bcast<28>(v));
-    l.meta = __float_as_int(bcast<29>(v));
-    l.slots = __float_as_int(bcast<30>(v));
+    l.xref = r.geti<26>();
+    l.yref = r.geti<27>();
+    l.off = r.geti<28>();
+    l.meta = r.geti<29>();
+    l.slots = r.geti<30>();
     return l;
 }
 
-__device__ __forceinline__ Links6 bcast_links6(double v) {
-    const long long a = __double_as_longlong(bcast<26>(v)), b = __double_as_longlong(bcast<27>(v));
-    const long long c = __double_as_longlong(bcast<28>(v));
+__device__ __forceinline__ Links6 bcast_links6(const RecReg<double> &r) {
     Links6 l;
-    l.xref = (int)(a & 0xffffffffll);
-    l.yref = (int)(a >> 32);
-    l.off = (int)(b & 0xffffffffll);
-    l.meta = (int)(b >> 32);
-    l.slots = (int)(c & 0xffffffffll);
+    l.xref = r.geti<0>();
+    l.yref = r.geti<1>();
+    l.off = r.geti<2>();
+    l.meta = r.geti<3>();
+    l.slots = r.geti<4>();
     return l;
 }
 
-__device__ __forceinline__ int2 bcast_refs(float v) {
-    return make_int2(__float_as_int(bcast<26>(v)), __float_as_int(bcast<27>(v)));
-}
+__device__ __forceinline__ int2 bcast_refs(const RecReg<float> &r) { return make_int2(r.geti<26>(), r.geti<27>()); }
 
-__device__ __forceinline__ int2 bcast_refs(double v) {
-    const long long a = __double_as_longlong(bcast<26>(v));
-    return make_int2((int)(a & 0xffffffffll), (int)(a >> 32));
-}
+__device__ __forceinline__ int2 bcast_refs(const RecReg<double> &r) { return make_int2(r.geti<0>(), r.geti<1>()); }
 
 // LDS slot layout: [slot][component 0..5][64 lanes]
 template <typename T>
@@ -553,34 +668,53 @@ __device__ __forceinline__ int rhs_count(const Ctx &C) {
     return RT ? RT : C.R;
 }
 
+// The buffers of one wide sweep and byte strides.
+struct WBufs {
+    rsrc_t in, out, xch;
+    uint32_t row;  // bytes of one vector row (R values)
+};
+
+template <typename T, int RT>
+__device__ __forceinline__ WBufs wide_bufs(const T *in, T *out, T *xch, const Ctx &C) {
+    WBufs b;
+    b.in = make_rsrc(in, C.in_bytes);
+    b.out = make_rsrc(out, C.out_bytes);
+    b.xch = make_rsrc(xch, C.xch_bytes);
+    b.row = (uint32_t)(rhs_count<RT>(C) * sizeof(T));
+    return b;
+}
+
+// Byte offset of bead ref's first row for lane rr: a negative ref (not a
+// bead) or off = false lands past the end of the buffer.
+template <typename T, int RT>
+__device__ __forceinline__ uint32_t bead_off(int ref, bool on, const Ctx &C, uint32_t lanebytes) {
+    const uint32_t u = on ? min((uint32_t)ref, (uint32_t)C.N) : (uint32_t)C.N;
+    return u * (uint32_t)(3 * rhs_count<RT>(C) * sizeof(T)) + lanebytes;
+}
+
+// Byte offset of exchange entry (slot, lane rr), past the end when off.
+template <typename T, int RT>
+__device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, uint32_t lanebytes) {
+    const uint32_t sl = on ? min((uint32_t)slot, (uint32_t)C.xch_cap) : (uint32_t)C.xch_cap;
+    return sl * (uint32_t)(6 * rhs_count<RT>(C) * sizeof(T)) + 6 * lanebytes;
+}
+
 // Upward memory input of one child, IW values: a bead's vector (3 values,
 // zero Info-set tail) or, with IW = 6, an earlier tile root's Info-set.  A
-// stack child reads the dummy rows at v instead.  IW = 3 serves the first
-// tile phase, whose only memory inputs are beads.
+// stack child loads nothing (zeros).  IW = 3 serves the first tile phase,
+// whose only memory inputs are beads.
 template <typename T, int RT, int IW>
-__device__ __forceinline__ void up_input(int ref, T (&m)[IW], const T *__restrict__ v, const T *__restrict__ xch,
-                                         const Ctx &C, int rr) {
-    const int R = rhs_count<RT>(C);
-    const bool isb = ref >= 0;
-    const int64_t u = min((int64_t)max(ref, 0), C.N - 1);
-    const T *pb = v + (3 * u) * R + rr;
-    if constexpr (IW == 3) {
-        const T *p = isb ? pb : v + rr;
-        m[0] = p[0];
-        m[1] = p[R];
-        m[2] = p[2 * R];
-    } else {
-        const bool isx = ref < kRefStack;
-        const int64_t sl = min((int64_t)max(ref_slot(ref), 0), (int64_t)C.xch_cap - 1);
-        const T *px = xch + sl * 6 * R + rr;
-        const T *p = isb ? pb : (isx ? px : v + rr);
-        const T *q = isx ? px + 3 * R : p;
-        m[0] = p[0];
-        m[1] = p[R];
-        m[2] = p[2 * R];
-        m[3] = q[0];
-        m[4] = q[R];
-        m[5] = q[2 * R];
+__device__ __forceinline__ void up_input(int ref, T (&m)[IW], const WBufs &B, const Ctx &C, uint32_t lb) {
+    const uint32_t vb = bead_off<T, RT>(ref, true, C, lb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[c] = bld<T>(B.in, vb, c * B.row);
+    if constexpr (IW == 6) {
+        T e[6];
+        bld6(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m[c] += e[c];
+#pragma unroll
+        for (int c = 3; c < 6; ++c) m[c] = e[c];
     }
 }
 
@@ -589,11 +723,12 @@ __device__ __forceinline__ void up_input(int ref, T (&m)[IW], const T *__restric
 // registers ax / ay.  Nothing is stored unless the node is live.
 template <typename T, int RT, int IW>
 __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW], const T (&ay)[IW],
-                                        T *lds, int lane, T *__restrict__ out, T *__restrict__ xch, const Ctx &C,
-                                        int rr, bool live, bool act, int &bad) {
-    const int R = rhs_count<RT>(C);
-    const int xs = min(lk.slots & 0xff, C.xslot), ys = min((lk.slots >> 8) & 0xff, C.xslot);
-    const int os = min((lk.slots >> 16) & 0xff, C.xslot);
+                                        T *lds, int lane, const WBufs &B, const Ctx &C, uint32_t lb, bool live,
+                                        bool act) {
+    // offsets and references were checked when the tile schedule was built;
+    // an access outside a buffer would be dropped by its range check
+    const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
+    const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
     const bool xst = lk.xref == kRefStack, yst = lk.yref == kRefStack;
     T mx[6], my[6];
     lds_get6(lds, xs, lane, mx);
@@ -622,34 +757,19 @@ __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, cons
     house_fwd<9>(t9, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) mp[3 + c] = t9[c];
-    const int dim = 3 * (int)xi + 3 * (int)yi;
-    const int64_t off = min((int64_t)max(lk.off, 0), C.rows - dim);
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
-    const int64_t slot = lk.meta >> kMetaSlotShift;
-    if (live) {
-        if (lk.off < 0 || (int64_t)lk.off + dim > C.rows) bad |= kFlagBounds;
-        if (troot && slot >= C.xch_cap) bad |= kFlagBounds;
-        if (act && dim > 0) {
-            T *o = out + off * R + rr;
-            o[0] = t9[3];
-            o[R] = t9[4];
-            o[2 * R] = t9[5];
-            if (dim == 6) {
-                o[3 * R] = t9[6];
-                o[4 * R] = t9[7];
-                o[5 * R] = t9[8];
-            }
-        }
-        if (troot) {
-            if (act) {
-                T *p = xch + min(slot, (int64_t)C.xch_cap - 1) * 6 * R + rr;
+    const bool en = live && act;
+    // residue rows [off, off + dim)
+    const uint32_t ob = (uint32_t)lk.off * B.row + lb;
+    const uint32_t o1 = (en && any) ? ob : kOOB;
+    const uint32_t o2 = (en && both) ? ob + 3 * B.row : kOOB;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) p[c * R] = mp[c];
-            }
-        } else {
-            lds_put6(lds, os, lane, mp);
-        }
-    }
+    for (int c = 0; c < 3; ++c) bst<T>(t9[3 + c], B.out, o1, c * B.row);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bst<T>(t9[6 + c], B.out, o2, c * B.row);
+    // a tile root's Info-set goes to the exchange buffer, others stay in LDS
+    bst6(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, en && troot, C, lb), mp);
+    if (live && !troot) lds_put6(lds, os, lane, mp);
 }
 
 // The run of lane group k of a phase: schedule range [base, base + len).
@@ -669,7 +789,7 @@ __device__ __forceinline__ void run_range(int k, int nrun, int c0, const int32_t
 }
 
 template <typename T, int LPT, int RT, int PR, int NR, int IW>
-__global__ void __launch_bounds__(64, 4) k_up_wide(int phase, const int32_t *__restrict__ prun,
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_up_wide(int phase, const int32_t *__restrict__ prun,
                                                    const int32_t *__restrict__ run, const T *__restrict__ rec,
                                                    const T *__restrict__ v, T *__restrict__ out,
                                                    T *__restrict__ xch, Ctx C, int32_t *err) {
@@ -680,10 +800,10 @@ __global__ void __launch_bounds__(64, 4) k_up_wide(int phase, const int32_t *__r
     constexpr int TPW = 64 / LPT;
     const int R = rhs_count<RT>(C);
     const int lane = threadIdx.x;
-    const int q = lane & 31;
     const int tslot = lane / LPT, rl = lane % LPT;
     const int c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
     const int items = ((nrun + TPW - 1) / TPW) * C.nchunks;
+    const WBufs B = wide_bufs<T, RT>(v, out, xch, C);
     int bad = 0;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
@@ -692,20 +812,21 @@ __global__ void __launch_bounds__(64, 4) k_up_wide(int phase, const int32_t *__r
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
         const bool act = r < R;
+        const uint32_t lb = (uint32_t)(rr * sizeof(T));
         int maxlen = len;
         if (LPT == 32) maxlen = max(maxlen, __shfl_xor(len, 32, 64));
         maxlen = __builtin_amdgcn_readfirstlane(maxlen);
         const int last = max(len - 1, 0);
-        const T *rp = rec + (int64_t)kRecWords * base + q;
-        T RW[PR];
-        T A[NR][IW], B[NR][IW];
+        const T *rp = rec + (int64_t)kRecWords * base;
+        RecReg<T> RW[PR];
+        T A[NR][IW], Bv[NR][IW];
 #pragma unroll
-        for (int k = 0; k < PR; ++k) RW[k] = rp[(int64_t)min(k, last) * kRecWords];
+        for (int k = 0; k < PR; ++k) RW[k].load(rp + (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
         for (int k = 0; k < NR - 1; ++k) {
             const int2 ref = bcast_refs(RW[k]);
-            up_input<T, RT, IW>(ref.x, A[k], v, xch, C, rr);
-            up_input<T, RT, IW>(ref.y, B[k], v, xch, C, rr);
+            up_input<T, RT, IW>(ref.x, A[k], B, C, lb);
+            up_input<T, RT, IW>(ref.y, Bv[k], B, C, lb);
         }
 #define HQ_UP_STEP(K)                                                                       \
         {                                                                                   \
@@ -713,13 +834,13 @@ __global__ void __launch_bounds__(64, 4) k_up_wide(int phase, const int32_t *__r
             T g[26];                                                                        \
             bcast_g<0>(g, RW[K]);                                                           \
             const Links6 lk = bcast_links6(RW[K]);                                          \
-            RW[K] = rp[(int64_t)min(n + PR, last) * kRecWords];                             \
+            RW[K].load(rp + (int64_t)min(n + PR, last) * kRecWords, lane);                  \
             {                                                                               \
                 const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                       \
-                up_input<T, RT, IW>(ref.x, A[((K) + NR - 1) % NR], v, xch, C, rr);          \
-                up_input<T, RT, IW>(ref.y, B[((K) + NR - 1) % NR], v, xch, C, rr);          \
+                up_input<T, RT, IW>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);               \
+                up_input<T, RT, IW>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);              \
             }                                                                               \
-            up_node<T, RT, IW>(g, lk, A[(K) % NR], B[(K) % NR], lds, lane, out, xch, C, rr, n < len, act, bad); \
+            up_node<T, RT, IW>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_UP_STEP(0)
@@ -736,59 +857,49 @@ __global__ void __launch_bounds__(64, 4) k_up_wide(int phase, const int32_t *__r
     if (bad) atomicOr(err, bad);
 }
 
-// Downward memory inputs of one node, always 12 loads: its residue
-// coefficients w_p (dim = 0, 3 or 6 values) and, for a tile root below a body
-// root, its Velocity-set from the exchange buffer; the rest reads dummy rows
-// of the exchange buffer.
+// Downward memory inputs of one node: its residue coefficients w_p (dim = 0,
+// 3 or 6 values) and, for a tile root below a body root, its Velocity-set from
+// the exchange buffer; absent values load as zeros.
 template <typename T, int RT>
-__device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6], T (&b)[6], const T *__restrict__ w,
-                                           const T *__restrict__ xch, const Ctx &C, int rr) {
-    const int R = rhs_count<RT>(C);
-    const int dim = 3 * (int)(lk.xref < 0) + 3 * (int)(lk.yref < 0);
-    const int64_t off = min((int64_t)max(lk.off, 0), max(C.rows - dim, (int64_t)0));
-    const T *dummy = xch + rr;
-    const T *p = (dim > 0) ? w + off * R + rr : dummy;
-    const T *p2 = (dim == 6) ? p + 3 * R : p;
-    a[0] = p[0];
-    a[1] = p[R];
-    a[2] = p[2 * R];
-    a[3] = p2[0];
-    a[4] = p2[R];
-    a[5] = p2[2 * R];
-    const bool lr = (lk.meta & kMetaTileRoot) && !(lk.meta & kMetaBodyRoot);
-    const int64_t sl = min((int64_t)(lk.meta >> kMetaSlotShift), (int64_t)C.xch_cap - 1);
-    const T *px = lr ? xch + sl * 6 * R + rr : dummy;
+__device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6], T (&b)[6], const WBufs &B, const Ctx &C,
+                                           uint32_t lb) {
+    const bool xi = lk.xref < 0, yi = lk.yref < 0;
+    const uint32_t ob = (uint32_t)lk.off * B.row + lb;
+    const uint32_t p1 = (xi || yi) ? ob : kOOB;
+    const uint32_t p2 = (xi && yi) ? ob + 3 * B.row : kOOB;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) b[c] = px[c * R];
+    for (int c = 0; c < 3; ++c) a[c] = bld<T>(B.in, p1, c * B.row);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[3 + c] = bld<T>(B.in, p2, c * B.row);
+    const bool lr = (lk.meta & (kMetaTileRoot | kMetaBodyRoot)) == kMetaTileRoot;
+    bld6(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, lr, C, lb), b);
 }
 
 // One downward node step (Theorem 4.3): L_p from its LDS slot (or the
 // exchange buffer for a tile root, zero for a body root), children's
-// Velocity-sets to their slots, to bead outputs, or to the exchange buffer.
-template <typename T, int RT>
+// Velocity-sets to their slots, to bead outputs, or (XC: phases after the
+// first) to the exchange buffer.
+template <typename T, int RT, bool XC>
 __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, const T (&wp)[6], const T (&lroot)[6],
-                                          T *lds, int lane, T *__restrict__ out, T *__restrict__ xch,
-                                          const Ctx &C, int rr, bool live, bool act, int &bad) {
-    const int R = rhs_count<RT>(C);
-    const int xs = min(lk.slots & 0xff, C.xslot), ys = min((lk.slots >> 8) & 0xff, C.xslot);
-    const int os = min((lk.slots >> 16) & 0xff, C.xslot);
-    const bool troot = (lk.meta & kMetaTileRoot) != 0, broot = (lk.meta & kMetaBodyRoot) != 0;
+                                          T *lds, int lane, const WBufs &B, const Ctx &C, uint32_t lb, bool live,
+                                          bool act) {
+    const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
+    const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
+    const bool troot = (lk.meta & kMetaTileRoot) != 0;
     T L[6];
     lds_get6(lds, os, lane, L);
+    // a tile root's Velocity-set comes from the exchange buffer (zeros for a
+    // body root, whose entry loads as zeros)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) L[c] = troot ? (broot ? T(0) : lroot[c]) : L[c];
+    for (int c = 0; c < 6; ++c) L[c] = troot ? lroot[c] : L[c];
     const T sx = g[kRecSx], sy = g[kRecSy];
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
     const bool both = xi && yi, any = xi || yi;
-    const int dim = 3 * (int)xi + 3 * (int)yi;
     T x9[9];
 #pragma unroll
     for (int c = 0; c < 3; ++c) x9[c] = L[3 + c];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        x9[3 + c] = (dim > 0) ? wp[c] : T(0);
-        x9[6 + c] = (dim == 6) ? wp[3 + c] : T(0);
-    }
+    for (int c = 0; c < 6; ++c) x9[3 + c] = wp[c];  // absent residue values loaded as zeros
     house_bwd<9>(x9, g);
     T st[3], Lx[6], Ly[6];
 #pragma unroll
@@ -799,40 +910,31 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
         Lx[c] = sx * L[c] + sy * st[c];
         Ly[c] = sy * L[c] - sx * st[c];
     }
-    if (!live) return;
-    // children of this tile go to their slots, others to the spare slot
-    lds_put6(lds, xs, lane, Lx);
-    lds_put6(lds, ys, lane, Ly);
+    const bool en = live && act;
     const int refs[2] = {lk.xref, lk.yref};
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
         const int ref = refs[ch];
         const T *Lc = ch ? Ly : Lx;
-        if (ref >= 0) {
-            if (ref >= C.N) bad |= kFlagBounds;
-            const int64_t u = min((int64_t)ref, C.N - 1);
-            if (act) {
-                T *o = out + (3 * u) * R + rr;
-                o[0] = Lc[0];
-                o[R] = Lc[1];
-                o[2 * R] = Lc[2];
-            }
-        } else if (ref != kRefStack) {
-            if (ref_slot(ref) >= C.xch_cap) bad |= kFlagBounds;
-            const int64_t sl = min((int64_t)ref_slot(ref), (int64_t)C.xch_cap - 1);
-            if (act) {
-                T *p = xch + sl * 6 * R + rr;
+        const uint32_t bo = bead_off<T, RT>(ref, en, C, lb);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) p[c * R] = Lc[c];
-            }
+        for (int c = 0; c < 3; ++c) bst<T>(Lc[c], B.out, bo, c * B.row);
+        if constexpr (XC) {
+            T Lv[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Lv[c] = Lc[c];
+            bst6(B.xch, xch_off<T, RT>(ref_slot(ref), en && ref < kRefStack, C, lb), Lv);
         }
     }
-    if (troot && !broot && (lk.meta >> kMetaSlotShift) >= C.xch_cap) bad |= kFlagBounds;
-    if (dim > 0 && (lk.off < 0 || (int64_t)lk.off + dim > C.rows)) bad |= kFlagBounds;
+    if (live) {
+        // children of this tile go to their slots
+        if (lk.xref == kRefStack) lds_put6(lds, xs, lane, Lx);
+        if (lk.yref == kRefStack) lds_put6(lds, ys, lane, Ly);
+    }
 }
 
-template <typename T, int LPT, int RT, int PR, int NR>
-__global__ void __launch_bounds__(64, 4) k_down_wide(int phase, const int32_t *__restrict__ prun,
+template <typename T, int LPT, int RT, int PR, int NR, bool XC>
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_down_wide(int phase, const int32_t *__restrict__ prun,
                                                      const int32_t *__restrict__ run, const T *__restrict__ rec,
                                                      const T *__restrict__ w, T *__restrict__ out,
                                                      T *__restrict__ xch, Ctx C, int32_t *err) {
@@ -843,10 +945,10 @@ __global__ void __launch_bounds__(64, 4) k_down_wide(int phase, const int32_t *_
     constexpr int TPW = 64 / LPT;
     const int R = rhs_count<RT>(C);
     const int lane = threadIdx.x;
-    const int q = lane & 31;
     const int tslot = lane / LPT, rl = lane % LPT;
     const int c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
     const int items = ((nrun + TPW - 1) / TPW) * C.nchunks;
+    const WBufs B = wide_bufs<T, RT>(w, out, xch, C);
     int bad = 0;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
@@ -855,28 +957,29 @@ __global__ void __launch_bounds__(64, 4) k_down_wide(int phase, const int32_t *_
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
         const bool act = r < R;
+        const uint32_t lb = (uint32_t)(rr * sizeof(T));
         int maxlen = len;
         if (LPT == 32) maxlen = max(maxlen, __shfl_xor(len, 32, 64));
         maxlen = __builtin_amdgcn_readfirstlane(maxlen);
         const int last = max(len - 1, 0);
         // node n of the sweep is schedule index base + len - 1 - n
-        const T *rp = rec + (int64_t)kRecWords * (base + last) + q;
-        T RW[PR];
-        T A[NR][6], B[NR][6];
+        const T *rp = rec + (int64_t)kRecWords * (base + last);
+        RecReg<T> RW[PR];
+        T A[NR][6], Bl[NR][6];
 #pragma unroll
-        for (int k = 0; k < PR; ++k) RW[k] = rp[-(int64_t)min(k, last) * kRecWords];
+        for (int k = 0; k < PR; ++k) RW[k].load(rp - (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
-        for (int k = 0; k < NR - 1; ++k) down_input<T, RT>(bcast_links6(RW[k]), A[k], B[k], w, xch, C, rr);
+        for (int k = 0; k < NR - 1; ++k) down_input<T, RT>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
 #define HQ_DOWN_STEP(K)                                                                     \
         {                                                                                   \
             const int n = n0 + (K);                                                         \
             T g[26];                                                                        \
             bcast_g<0>(g, RW[K]);                                                           \
             const Links6 lk = bcast_links6(RW[K]);                                          \
-            RW[K] = rp[-(int64_t)min(n + PR, last) * kRecWords];                            \
+            RW[K].load(rp - (int64_t)min(n + PR, last) * kRecWords, lane);                  \
             down_input<T, RT>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
-                              B[((K) + NR - 1) % NR], w, xch, C, rr);                       \
-            down_node<T, RT>(g, lk, A[(K) % NR], B[(K) % NR], lds, lane, out, xch, C, rr, n < len, act, bad); \
+                              Bl[((K) + NR - 1) % NR], B, C, lb);                           \
+            down_node<T, RT, XC>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_DOWN_STEP(0)
@@ -893,357 +996,6 @@ __global__ void __launch_bounds__(64, 4) k_down_wide(int phase, const int32_t *_
     if (bad) atomicOr(err, bad);
 }
 
-// ---------------------------------------------------------------------------
-// Uniform sweeps: one run of whole tiles per wave, one right-hand side per
-// lane (32 or 64 lanes).  The node record is wave-uniform, so it is read with
-// scalar loads and the node's shape (which children are internal nodes, and
-// whether they come from LDS or the exchange buffer) is a uniform branch:
-// each of the four shapes runs its own Householder length (k = 3, 6 or 9)
-// with no padding and no selects.
-// ---------------------------------------------------------------------------
-template <typename T>
-struct UNode {
-    T g[26];
-    int xref, yref, off, meta, slots;
-};
-
-template <typename T>
-__device__ __forceinline__ void uload(UNode<T> &u, const T *__restrict__ rp) {
-#pragma unroll
-    for (int i = 0; i < 26; ++i) u.g[i] = rp[i];
-    const int32_t *li = reinterpret_cast<const int32_t *>(rp + kRecLinks);
-    u.xref = li[0];
-    u.yref = li[1];
-    u.off = li[2];
-    u.meta = li[3];
-    u.slots = li[4];
-}
-
-// LDS slot layout of the uniform sweeps: [slot][component][lw lanes]
-template <typename T>
-__device__ __forceinline__ void ulds_put(T *lds, int slot, int lw, int lane, const T *m, int n) {
-    T *p = lds + slot * 6 * lw + lane;
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-        if (c < n) p[c * lw] = m[c];
-}
-
-template <typename T>
-__device__ __forceinline__ void ulds_get(const T *lds, int slot, int lw, int lane, T (&m)[6]) {
-    const T *p = lds + slot * 6 * lw + lane;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) m[c] = p[c * lw];
-}
-
-// Upward memory inputs of a node: a bead child's vector (3 values) or an
-// earlier tile root's Info-set (6 values); stack children are read later.
-// One uniform base pointer and two uniform conditions keep the values in
-// fixed registers.
-template <typename T, int RT>
-__device__ __forceinline__ void uup_fetch(int ref, T (&m)[6], const T *__restrict__ v, const T *__restrict__ xch,
-                                          const Ctx &C, int rr, int &bad) {
-    const int R = rhs_count<RT>(C);
-    const bool isb = ref >= 0, isx = ref < kRefStack;
-    if (isb && ref >= C.N) bad |= kFlagBounds;
-    if (isx && ref_slot(ref) >= C.xch_cap) bad |= kFlagBounds;
-    const int64_t u = min((int64_t)ref, C.N - 1);
-    const int64_t sl = min((int64_t)ref_slot(ref), (int64_t)C.xch_cap - 1);
-    const T *p = (isb ? v + (3 * u) * R : xch + sl * 6 * R) + rr;
-    if (isb || isx) {
-        m[0] = p[0];
-        m[1] = p[R];
-        m[2] = p[2 * R];
-    }
-    if (isx) {
-        m[3] = p[3 * R];
-        m[4] = p[4 * R];
-        m[5] = p[5 * R];
-    }
-}
-
-// One upward node step of shape (XI, YI) = (x is internal, y is internal).
-template <typename T, int RT, bool XI, bool YI>
-__device__ __forceinline__ void uup_node(const UNode<T> &u, const T (&ax)[6], const T (&ay)[6], T *lds, int lw,
-                                         int lane, T *__restrict__ out, T *__restrict__ xch, const Ctx &C, int rr,
-                                         bool act, int &bad) {
-    constexpr int K = 3 + 3 * (int)XI + 3 * (int)YI;
-    constexpr int dim = K - 3;
-    const int R = rhs_count<RT>(C);
-    T mx[6], my[6];
-    if (u.xref == kRefStack) {
-        ulds_get(lds, min(u.slots & 0xff, C.xslot), lw, lane, mx);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) mx[c] = ax[c];
-    }
-    if (u.yref == kRefStack) {
-        ulds_get(lds, min((u.slots >> 8) & 0xff, C.xslot), lw, lane, my);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) my[c] = ay[c];
-    }
-    const T sx = u.g[kRecSx], sy = u.g[kRecSy];
-    T mp[6], t[9];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        mp[c] = sx * mx[c] + sy * my[c];
-        const T tt = sy * mx[c] - sx * my[c];
-        if constexpr (XI) t[c] = mx[3 + c];
-        if constexpr (YI) t[3 * (int)XI + c] = my[3 + c];
-        t[dim + c] = tt;
-    }
-    house_fwd<K>(t, u.g);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) mp[3 + c] = t[c];
-    if constexpr (dim > 0) {
-        if (u.off < 0 || (int64_t)u.off + dim > C.rows) bad |= kFlagBounds;
-        const int64_t off = min((int64_t)max(u.off, 0), C.rows - dim);
-        if (act) {
-            T *o = out + off * R + rr;
-#pragma unroll
-            for (int c = 0; c < dim; ++c) o[c * R] = t[3 + c];
-        }
-    }
-    if (u.meta & kMetaTileRoot) {
-        if ((u.meta >> kMetaSlotShift) >= C.xch_cap) bad |= kFlagBounds;
-        const int64_t sl = min((int64_t)(u.meta >> kMetaSlotShift), (int64_t)C.xch_cap - 1);
-        if (act) {
-            T *p = xch + sl * 6 * R + rr;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) p[c * R] = mp[c];
-        }
-    } else {
-        ulds_put(lds, min((u.slots >> 16) & 0xff, C.xslot), lw, lane, mp, 6);
-    }
-}
-
-template <typename T, int RT>
-__device__ __forceinline__ void uup_dispatch(const UNode<T> &u, const T (&ax)[6], const T (&ay)[6], T *lds, int lw,
-                                             int lane, T *__restrict__ out, T *__restrict__ xch, const Ctx &C,
-                                             int rr, bool act, int &bad) {
-    const bool xi = u.xref < 0, yi = u.yref < 0;
-    if (xi && yi) uup_node<T, RT, true, true>(u, ax, ay, lds, lw, lane, out, xch, C, rr, act, bad);
-    else if (xi) uup_node<T, RT, true, false>(u, ax, ay, lds, lw, lane, out, xch, C, rr, act, bad);
-    else if (yi) uup_node<T, RT, false, true>(u, ax, ay, lds, lw, lane, out, xch, C, rr, act, bad);
-    else uup_node<T, RT, false, false>(u, ax, ay, lds, lw, lane, out, xch, C, rr, act, bad);
-}
-
-// Work item = (run, RHS chunk of 64); lanes at or above lw have no work.
-struct URun {
-    int base, len, chunk;
-};
-
-__device__ __forceinline__ bool urun(int item, int phase, const int32_t *__restrict__ prun,
-                                     const int32_t *__restrict__ run, const Ctx &C, URun &w, int &bad) {
-    const int c0 = prun[4 * phase + 2];
-    const int k = item / C.nchunks;
-    w.chunk = item - k * C.nchunks;
-    w.base = run[c0 + k];
-    w.len = run[c0 + k + 1] - w.base;
-    if (w.base < 0 || w.len < 0 || (int64_t)w.base + w.len > C.nsched) {
-        bad |= kFlagBounds;
-        w.len = 0;
-    }
-    return true;
-}
-
-template <typename T, int RT>
-__global__ void __launch_bounds__(64) k_up_u(int phase, const int32_t *__restrict__ prun,
-                                             const int32_t *__restrict__ run, const T *__restrict__ rec,
-                                             const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch,
-                                             Ctx C, int lw, int32_t *err) {
-    extern __shared__ unsigned char smem_raw[];
-    T *lds = reinterpret_cast<T *>(smem_raw);
-    const int lane = threadIdx.x;
-    if (lane >= lw) return;
-    const int R = rhs_count<RT>(C);
-    const int items = prun[4 * phase + 3] * C.nchunks;
-    int bad = 0;
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        URun w;
-        urun(item, phase, prun, run, C, w, bad);
-        const int r = w.chunk * 64 + lane;
-        const bool act = r < R;
-        const int rr = min(r, R - 1);
-        const T *rp = rec + (int64_t)kRecWords * w.base;
-        UNode<T> u;
-        T A[6], B[6];
-        if (w.len > 0) {
-            uload(u, rp);
-            uup_fetch<T, RT>(u.xref, A, v, xch, C, rr, bad);
-            uup_fetch<T, RT>(u.yref, B, v, xch, C, rr, bad);
-        }
-        for (int n = 0; n < w.len; ++n) {
-            UNode<T> un;
-            T An[6], Bn[6];
-            if (n + 1 < w.len) {
-                uload(un, rp + (int64_t)(n + 1) * kRecWords);
-                uup_fetch<T, RT>(un.xref, An, v, xch, C, rr, bad);
-                uup_fetch<T, RT>(un.yref, Bn, v, xch, C, rr, bad);
-            }
-            uup_dispatch<T, RT>(u, A, B, lds, lw, lane, out, xch, C, rr, act, bad);
-            u = un;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                A[c] = An[c];
-                B[c] = Bn[c];
-            }
-        }
-    }
-    if (bad) atomicOr(err, bad);
-}
-
-// Downward memory inputs of a node: its residue coefficients (dim values) and,
-// for a tile root below a body root, its Velocity-set from the exchange buffer.
-template <typename T, int RT>
-__device__ __forceinline__ void udown_fetch(const UNode<T> &u, T (&a)[6], T (&b)[6], const T *__restrict__ w,
-                                            const T *__restrict__ xch, const Ctx &C, int rr, int &bad) {
-    const int R = rhs_count<RT>(C);
-    const int dim = 3 * (int)(u.xref < 0) + 3 * (int)(u.yref < 0);
-    if (dim > 0) {
-        if (u.off < 0 || (int64_t)u.off + dim > C.rows) bad |= kFlagBounds;
-        const int64_t off = min((int64_t)max(u.off, 0), C.rows - dim);
-        const T *p = w + off * R + rr;
-        a[0] = p[0];
-        a[1] = p[R];
-        a[2] = p[2 * R];
-        if (dim == 6) {
-            a[3] = p[3 * R];
-            a[4] = p[4 * R];
-            a[5] = p[5 * R];
-        }
-    }
-    if ((u.meta & kMetaTileRoot) && !(u.meta & kMetaBodyRoot)) {
-        if ((u.meta >> kMetaSlotShift) >= C.xch_cap) bad |= kFlagBounds;
-        const int64_t sl = min((int64_t)(u.meta >> kMetaSlotShift), (int64_t)C.xch_cap - 1);
-        const T *p = xch + sl * 6 * R + rr;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) b[c] = p[c * R];
-    }
-}
-
-template <typename T, int RT>
-__device__ __forceinline__ void udown_emit(int ref, int slot, const T *Lc, T *lds, int lw, int lane,
-                                           T *__restrict__ out, T *__restrict__ xch, const Ctx &C, int rr, bool act,
-                                           int &bad) {
-    const int R = rhs_count<RT>(C);
-    if (ref >= 0) {
-        if (ref >= C.N) bad |= kFlagBounds;
-        const int64_t u = min((int64_t)ref, C.N - 1);
-        if (act) {
-            T *o = out + (3 * u) * R + rr;
-            o[0] = Lc[0];
-            o[R] = Lc[1];
-            o[2 * R] = Lc[2];
-        }
-    } else if (ref == kRefStack) {
-        ulds_put(lds, min(slot, C.xslot), lw, lane, Lc, 6);
-    } else {
-        if (ref_slot(ref) >= C.xch_cap) bad |= kFlagBounds;
-        const int64_t sl = min((int64_t)ref_slot(ref), (int64_t)C.xch_cap - 1);
-        if (act) {
-            T *p = xch + sl * 6 * R + rr;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) p[c * R] = Lc[c];
-        }
-    }
-}
-
-// One downward node step of shape (XI, YI) (Theorem 4.3).
-template <typename T, int RT, bool XI, bool YI>
-__device__ __forceinline__ void udown_node(const UNode<T> &u, const T (&wp)[6], const T (&lroot)[6], T *lds, int lw,
-                                           int lane, T *__restrict__ out, T *__restrict__ xch, const Ctx &C, int rr,
-                                           bool act, int &bad) {
-    constexpr int K = 3 + 3 * (int)XI + 3 * (int)YI;
-    constexpr int dim = K - 3;
-    T L[6];
-    if (u.meta & kMetaTileRoot) {
-        if (u.meta & kMetaBodyRoot) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) L[c] = T(0);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) L[c] = lroot[c];
-        }
-    } else {
-        ulds_get(lds, min((u.slots >> 16) & 0xff, C.xslot), lw, lane, L);
-    }
-    T x[9];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = L[3 + c];
-#pragma unroll
-    for (int c = 0; c < dim; ++c) x[3 + c] = wp[c];
-    house_bwd<K>(x, u.g);
-    const T sx = u.g[kRecSx], sy = u.g[kRecSy];
-    T Lx[6], Ly[6];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const T st = x[dim + c];
-        if constexpr (XI) Lx[3 + c] = x[c];
-        if constexpr (YI) Ly[3 + c] = x[3 * (int)XI + c];
-        Lx[c] = sx * L[c] + sy * st;
-        Ly[c] = sy * L[c] - sx * st;
-    }
-    udown_emit<T, RT>(u.xref, u.slots & 0xff, Lx, lds, lw, lane, out, xch, C, rr, act, bad);
-    udown_emit<T, RT>(u.yref, (u.slots >> 8) & 0xff, Ly, lds, lw, lane, out, xch, C, rr, act, bad);
-}
-
-template <typename T, int RT>
-__device__ __forceinline__ void udown_dispatch(const UNode<T> &u, const T (&wp)[6], const T (&lroot)[6], T *lds,
-                                               int lw, int lane, T *__restrict__ out, T *__restrict__ xch,
-                                               const Ctx &C, int rr, bool act, int &bad) {
-    const bool xi = u.xref < 0, yi = u.yref < 0;
-    if (xi && yi) udown_node<T, RT, true, true>(u, wp, lroot, lds, lw, lane, out, xch, C, rr, act, bad);
-    else if (xi) udown_node<T, RT, true, false>(u, wp, lroot, lds, lw, lane, out, xch, C, rr, act, bad);
-    else if (yi) udown_node<T, RT, false, true>(u, wp, lroot, lds, lw, lane, out, xch, C, rr, act, bad);
-    else udown_node<T, RT, false, false>(u, wp, lroot, lds, lw, lane, out, xch, C, rr, act, bad);
-}
-
-template <typename T, int RT>
-__global__ void __launch_bounds__(64) k_down_u(int phase, const int32_t *__restrict__ prun,
-                                               const int32_t *__restrict__ run, const T *__restrict__ rec,
-                                               const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch,
-                                               Ctx C, int lw, int32_t *err) {
-    extern __shared__ unsigned char smem_raw[];
-    T *lds = reinterpret_cast<T *>(smem_raw);
-    const int lane = threadIdx.x;
-    if (lane >= lw) return;
-    const int R = rhs_count<RT>(C);
-    const int items = prun[4 * phase + 3] * C.nchunks;
-    int bad = 0;
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        URun ru;
-        urun(item, phase, prun, run, C, ru, bad);
-        const int r = ru.chunk * 64 + lane;
-        const bool act = r < R;
-        const int rr = min(r, R - 1);
-        // node n of the sweep is schedule index base + len - 1 - n
-        const T *rp = rec + (int64_t)kRecWords * (ru.base + ru.len - 1);
-        UNode<T> u;
-        T A[6], B[6];
-        if (ru.len > 0) {
-            uload(u, rp);
-            udown_fetch<T, RT>(u, A, B, w, xch, C, rr, bad);
-        }
-        for (int n = 0; n < ru.len; ++n) {
-            UNode<T> un;
-            T An[6], Bn[6];
-            if (n + 1 < ru.len) {
-                uload(un, rp - (int64_t)(n + 1) * kRecWords);
-                udown_fetch<T, RT>(un, An, Bn, w, xch, C, rr, bad);
-            }
-            udown_dispatch<T, RT>(u, A, B, lds, lw, lane, out, xch, C, rr, act, bad);
-            u = un;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                A[c] = An[c];
-                B[c] = Bn[c];
-            }
-        }
-    }
-    if (bad) atomicOr(err, bad);
-}
-
 template <typename T, int LPT>
 void launch_phase(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
                   hipStream_t s) {
@@ -1251,7 +1003,8 @@ void launch_phase(const Plan &P, int phase, int transpose, const T *rec, const T
     constexpr int TPW = 64 / LPT;
     const char *genv = getenv("HQ_APPLY_GRID");
     if constexpr (LPT >= 32) {
-        const size_t lds_w = (size_t)(C.xslot + 1) * 6 * 64 * sizeof(T);
+        size_t lds_w = (size_t)C.nslot * 6 * 64 * sizeof(T);
+        if (const char *e = getenv("HQ_LDS_PAD")) lds_w += (size_t)atoll(e);
         // work items: pairs of runs (a phase has at most NI / run_nodes + 1
         // runs) x RHS chunks, one per wave, so the dispatcher balances the
         // load; waves of later phases with fewer runs exit at once
@@ -1269,29 +1022,16 @@ void launch_phase(const Plan &P, int phase, int transpose, const T *rec, const T
                 hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6>), dim3(grid), dim3(64), lds_w, s, phase, \
                                    P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                         \
         } else {                                                                                             \
-            hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD>), dim3(grid), dim3(64), lds_w, s, phase,      \
-                               P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                             \
+            if (phase == 1)                                                                                  \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false>), dim3(grid), dim3(64), lds_w, s,    \
+                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
+            else                                                                                             \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, true>), dim3(grid), dim3(64), lds_w, s,     \
+                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
         }                                                                                                    \
     } while (0)
         int variant = 0;
         if (const char *e = getenv("HQ_WIDE_VARIANT")) variant = atoi(e);
-        if (variant == 9) {
-            // one run per wave
-            const int lw = (C.R <= 32) ? 32 : 64;
-            const size_t lds_u = (size_t)(C.xslot + 1) * 6 * lw * sizeof(T);
-            const int64_t items_u = (P.NI / P.run_nodes + 2) * (int64_t)C.nchunks;
-            const int64_t per_cu_u = std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(160 * 1024) / (int64_t)lds_u));
-            int64_t gu = std::min<int64_t>(items_u, 256 * per_cu_u);
-            if (genv) gu = std::max<int64_t>(1, atoll(genv));
-            const unsigned grid_u = (unsigned)std::min<int64_t>(gu, 1 << 20);
-            if (!transpose)
-                hipLaunchKernelGGL((k_up_u<T, 0>), dim3(grid_u), dim3(64), lds_u, s, phase, P.d_prun, P.d_run,
-                                   rec, v, out, xch, C, lw, P.d_err);
-            else
-                hipLaunchKernelGGL((k_down_u<T, 0>), dim3(grid_u), dim3(64), lds_u, s, phase, P.d_prun, P.d_run,
-                                   rec, v, out, xch, C, lw, P.d_err);
-            return;
-        }
         if (LPT == 32 && C.R == 32) {
             switch (variant) {
             case 1: HQ_WIDE(32, 6, 2, 6, 3, 2); break;
@@ -1355,11 +1095,21 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
         const int v = atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) lpt = v;
     }
-    C.nchunks = (int)((nrhs + lpt - 1) / lpt);
-    C.dmax = stack_depth(P.S);
-    C.xslot = scratch_slot(P.S);
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
     C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(P.xch_bytes / (6 * elem * (size_t)nrhs)));
+    // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB;
+    // larger problems take the narrow sweeps
+    const int64_t vin = (transpose ? P.rows : 3 * P.N) * nrhs * (int64_t)elem;
+    const int64_t vout = (transpose ? 3 * P.N : P.rows) * nrhs * (int64_t)elem;
+    const int64_t vx = (int64_t)C.xch_cap * 6 * nrhs * (int64_t)elem;
+    const int64_t lim = (int64_t)kOOB - (int64_t)(1 << 20);
+    if (lpt >= 32 && (vin >= lim || vout >= lim || vx >= lim)) lpt = 16;
+    C.in_bytes = (uint32_t)std::min<int64_t>(vin, lim);
+    C.out_bytes = (uint32_t)std::min<int64_t>(vout, lim);
+    C.xch_bytes = (uint32_t)std::min<int64_t>(vx, lim);
+    C.nchunks = (int)((nrhs + lpt - 1) / lpt);
+    C.dmax = stack_depth(P.S);
+    C.nslot = stack_slots(P.S);
     if (prec == HQ_FP64)
         launch_all<double>(P, transpose, lpt, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s);
     else

@@ -419,7 +419,10 @@ __global__ void k_tile_emit(int64_t NI, const long long *trval, const long long 
 // post-order positions skipped when it is its parent's second child (the
 // first child's subtree), whether that first child is an internal node of the
 // tile (one more pending result on the stack), and whether it is a tile root.
-constexpr int kAwPend = 1 << 16, kAwRoot = 1 << 17;
+// Word layout: bits 0..28 positions skipped (clamped: only walks that end in a
+// tile use the value, and there it is below the tile size), bit 29 the pending
+// flag, bit 30 the tile-root flag.
+constexpr int kAwPend = 1 << 29, kAwRoot = 1 << 30, kAwSkip = (1 << 29) - 1;
 
 __global__ void k_assign_prep(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc,
                               const int32_t *rc, const int32_t *units, const long long *trval, int32_t *yfirst,
@@ -440,7 +443,7 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *cov, const int32_t *par
             const bool y_first = uy > ux;
             if (g == (y_first ? x : y)) {
                 const int ufirst = y_first ? uy : ux;
-                word |= (ufirst - 1) | ((ufirst > 1) ? kAwPend : 0);
+                word |= min(ufirst - 1, kAwSkip) | ((ufirst > 1) ? kAwPend : 0);
             }
         }
         aw[g] = make_int2(p, word);
@@ -466,13 +469,17 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *units, c
             const int2 w = aw[q];
             if (w.y & kAwRoot) { found = true; too_deep = false; break; }
             if (w.x < 0) { too_deep = false; break; }
-            pos += w.y & 0xffff;
+            pos += w.y & kAwSkip;
             pend += (w.y & kAwPend) ? 1 : 0;
             q = w.x;
         }
         if (too_deep) raise_flag(err, kFlagBounds);
         if (!found) continue;
         const int t = tileof[q];
+        if (t < 0 || t >= NI) {
+            raise_flag(err, kFlagBounds);
+            continue;
+        }
         const int64_t s = (int64_t)tile_base[t] + pos;
         if (pos < 0 || s < 0 || s >= sched_cap) {
             raise_flag(err, kFlagBounds);
@@ -578,18 +585,19 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
         if (tile_root[t] == g) meta |= kMetaTileRoot | (t << kMetaSlotShift);
         if (par[g] < 0) meta |= kMetaBodyRoot;
         if (yfirst[g]) meta |= kMetaYFirst;
-        // LDS slots of the wide sweeps: the child evaluated first sits in this
-        // node's own slot, the second one above it; bead and earlier-tile
-        // children name the spare slot dstack
+        // LDS slots of the wide sweeps (dstack of them): the child evaluated
+        // first sits in this node's own slot, the second one above it; bead
+        // and earlier-tile children, and the result of a tile root, name
+        // slot 0, which the sweeps never write for them
         const int own = depth_slot[g];
         const bool xin = ref[0] == kRefStack, yin = ref[1] == kRefStack;
         const bool yf = yfirst[g] != 0;
         const bool fin = yf ? yin : xin;
-        int xs = dstack, ys = dstack;
+        int xs = 0, ys = 0;
         if (xin) xs = yf ? own + (fin ? 1 : 0) : own;
         if (yin) ys = yf ? own : own + (fin ? 1 : 0);
         const bool troot = (meta & kMetaTileRoot) != 0;
-        const int os = troot ? dstack : own;
+        const int os = troot ? 0 : own;
         if ((xin && xs >= dstack) || (yin && ys >= dstack) || (!troot && own >= dstack)) raise_flag(err, kFlagStack);
         const int s = sched[g];
         links[kLinkInts * s + 0] = ref[0];
@@ -1026,7 +1034,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_slot, scratch_slot(P.S), P.d_lw, P.d_links, P.d_depth, P.d_err);
+                       P.d_row_off, P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_depth, P.d_err);
     // --- 5. transforms, one launch per depth level, deepest first
     hipLaunchKernelGGL(k_depth_hist, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist);
     HQ_TRY(scan_i32_inclusive(P, P.d_dhist, P.d_dincl, (int64_t)kDepthBins * kDepthBlocks, s));

@@ -116,9 +116,9 @@ inline int floor_log2(int v) {
 // at most floor(log2 S) + 1 pending results; one spare entry.
 inline int stack_depth(int S) { return floor_log2(S) + 2; }
 
-// Wide sweeps address LDS by slot: slots 0 .. floor(log2 S) hold pending
-// results, the next two stage a node's bead or earlier-tile inputs (x, y).
-inline int scratch_slot(int S) { return floor_log2(S) + 1; }
+// Wide sweeps address LDS by slot: slots 0 .. floor(log2 S) hold the pending
+// results of a tile.
+inline int stack_slots(int S) { return floor_log2(S) + 1; }
 
 // ---------------------------------------------------------------------------
 // the plan behind a handle

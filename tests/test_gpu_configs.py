@@ -1,0 +1,147 @@
+"""GPU path on the full-size workloads, in the launch configuration the
+benchmark uses (default tile size and run length, wide sweeps for R >= 32).
+
+* One ellipsoid body of 65,536 beads, 16 right-hand sides: FP64 products
+  against the hierarchical oracle element by element (<= 1e-12 relative
+  2-norm per RHS), FP32 products against FP64 (<= 1e-5) and the FP32 leak.
+* 1,000 bodies of 200-2,000 beads, one right-hand side: FP64 and FP32 against
+  the oracle body by body, and the leak.
+* One body of 4,194,304 beads with near-collinear clusters (nodes with
+  condition numbers up to ~1e9, where Q~ is not determined beyond rounding):
+  basis-free properties only -- the projector Q~^T Q~ = I - Z^T (Z Z^T)^-1 Z,
+  orthonormal rows Q~ Q~^T = I and the FP32 leak -- with Z applied in O(n).
+* The batched Brownian-dynamics workload (4,096 bodies, 32 RHS): sampled bodies
+  against the oracle after the bench's rigid motion and rebuild.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, hier
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import paper_1708_08427_amd as hq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return hq
+
+
+def _build(hq, w, **kw):
+    print(f"[gpu] build {w.name} N={w.N} m={w.m} {kw}", flush=True)
+    h = hq.build(_dev(w.pos), w.offsets, **kw)
+    assert h.query()["device_flags"] == 0
+    return h
+
+
+def _rel(a, b):
+    return float((np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)).max())
+
+
+def test_ellipsoid_n65536_fp64_and_fp32(hq):
+    w = W.ellipsoid_n65536()
+    v, wv = w.draw_vectors()
+    h = _build(hq, w)
+    b = hier.Body(w.pos)
+    assert b.max_kappa <= 1e4
+    up_o, dn_o = b.apply(v), b.apply(wv, transpose=True)
+    up = h.apply(_dev(v)).cpu().numpy()
+    dn = h.apply(_dev(wv), transpose=True).cpu().numpy()
+    assert _rel(up, up_o) <= 1e-12
+    assert _rel(dn, dn_o) <= 1e-12
+    up32 = h.apply(_dev(v, torch.float32)).cpu().numpy().astype(np.float64)
+    dn32 = h.apply(_dev(wv, torch.float32), transpose=True).cpu().numpy().astype(np.float64)
+    assert float((np.linalg.norm(up32 - up_o, axis=0) / np.linalg.norm(v, axis=0)).max()) <= 1e-5
+    assert float((np.linalg.norm(dn32 - dn_o, axis=0) / np.linalg.norm(wv, axis=0)).max()) <= 1e-5
+    assert dense.leak_large(w.pos, dn32).max() <= 1e-5
+    assert h.query()["device_flags"] == 0
+
+
+def test_batched_m1000_fp64_and_fp32(hq):
+    w = W.batched_m1000()
+    v, wv = w.draw_vectors()
+    h = _build(hq, w)
+    bt = hier.Batch(w.pos, w.offsets)
+    up_o, dn_o = bt.apply(v), bt.apply(wv, transpose=True)
+    up = h.apply(_dev(v)).cpu().numpy()
+    dn = h.apply(_dev(wv), transpose=True).cpu().numpy()
+    up32 = h.apply(_dev(v, torch.float32)).cpu().numpy().astype(np.float64)
+    dn32 = h.apply(_dev(wv, torch.float32), transpose=True).cpu().numpy().astype(np.float64)
+    rows, beads3 = h.row_offsets, 3 * w.offsets
+    checked = 0
+    for j, b in enumerate(bt.bodies):
+        r0, r1, b0, b1 = rows[j], rows[j + 1], beads3[j], beads3[j + 1]
+        pj = w.pos[w.offsets[j]:w.offsets[j + 1]]
+        if b.max_kappa <= 1e4:
+            assert _rel(up[r0:r1], up_o[r0:r1]) <= 1e-12
+            assert _rel(dn[b0:b1], dn_o[b0:b1]) <= 1e-12
+            checked += 1
+        # FP32 against FP64, relative to the input norm
+        assert float(np.linalg.norm(up32[r0:r1] - up[r0:r1]) / np.linalg.norm(v[b0:b1])) <= 1e-5
+        assert float(np.linalg.norm(dn32[b0:b1] - dn[b0:b1]) / np.linalg.norm(wv[r0:r1])) <= 1e-5
+        assert dense.leak_large(pj, dn32[b0:b1]).max() <= 1e-5
+    assert checked >= 900
+    assert h.query()["device_flags"] == 0
+
+
+def test_large_clustered_body_properties(hq):
+    w = W.large_clustered()
+    rng = np.random.default_rng(44)
+    f = rng.standard_normal((3 * w.N, 1))
+    g = rng.standard_normal((w.rows, 1))
+    h = _build(hq, w)
+    _, kappa = h.body_info()
+    print(f"[gpu] max kappa {kappa.max():.3e}", flush=True)
+    # FP64: Q~^T (Q~ f) is the projection of f; Q~ (Q~^T g) = g
+    pf = h.apply(h.apply(_dev(f)), transpose=True).cpu().numpy()
+    want = dense.project_large(w.pos, f)
+    assert float(np.linalg.norm(pf - want) / np.linalg.norm(f)) <= 1e-9
+    qg = h.apply(h.apply(_dev(g), transpose=True)).cpu().numpy()
+    assert float(np.linalg.norm(qg - g) / np.linalg.norm(g)) <= 1e-9
+    # FP32 sweeps: leak of Q~^T g and the projection error
+    g32 = h.apply(_dev(g, torch.float32), transpose=True).cpu().numpy().astype(np.float64)
+    assert dense.leak_large(w.pos, g32).max() <= 1e-5
+    pf32 = h.apply(h.apply(_dev(f, torch.float32)), transpose=True).cpu().numpy().astype(np.float64)
+    assert float(np.linalg.norm(pf32 - want) / np.linalg.norm(f)) <= 1e-5
+    assert h.query()["device_flags"] == 0
+
+
+def test_bd_step_workload_sampled_bodies(hq):
+    """The benchmark's workload and configuration (4,096 bodies, R = 32, FP32
+    wide sweeps) after one rigid motion and an in-place rebuild: 24 sampled
+    bodies against the oracle, and the leak of every body."""
+    w = W.bd_m4096()
+    rng = np.random.default_rng(33)
+    f = rng.standard_normal((3 * w.N, w.nrhs))
+    rot, trans = W.rigid_motions(rng, 1, w.m)
+    pos = _dev(w.pos)
+    h = hq.build(pos, w.offsets, store=3)
+    h.rigid_update(pos, _dev(rot.reshape(1, w.m, 9)[0]), _dev(trans[0]))
+    h.rebuild(pos)
+    p = pos.cpu().numpy()
+    out64 = h.apply(h.apply(_dev(f)), transpose=True).cpu().numpy()
+    out32 = h.apply(h.apply(_dev(f, torch.float32)), transpose=True).cpu().numpy().astype(np.float64)
+    assert h.query()["device_flags"] == 0
+    sample = np.random.default_rng(7).choice(w.m, 24, replace=False)
+    for j in sample:
+        b0, b1 = w.offsets[j], w.offsets[j + 1]
+        bo = hier.Body(p[b0:b1])
+        ref = bo.apply(bo.apply(f[3 * b0:3 * b1]), transpose=True)
+        assert _rel(out64[3 * b0:3 * b1], ref) <= 1e-12 or bo.max_kappa > 1e4
+        e32 = np.linalg.norm(out32[3 * b0:3 * b1] - ref, axis=0) / np.linalg.norm(f[3 * b0:3 * b1], axis=0)
+        assert e32.max() <= 1e-5
+    for j in range(0, w.m, 97):
+        b0, b1 = w.offsets[j], w.offsets[j + 1]
+        assert dense.leak_large(p[b0:b1], out32[3 * b0:3 * b1]).max() <= 1e-5

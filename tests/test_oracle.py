@@ -257,3 +257,24 @@ def test_batch_block_diagonal():
     for j, b in enumerate(bt.bodies):
         r0, r1 = bt.row_off[j], bt.row_off[j + 1]
         assert np.array_equal(out[r0:r1], b.apply(v[3 * w.offsets[j]:3 * w.offsets[j + 1]]))
+
+
+def test_large_body_helpers_match_dense_definitions():
+    """The O(n) forms of Z x, Z^T y, Z Z^T, P f and the leak (used for
+    bodies too large for a dense Z) against the dense Z of Eq. 1.2."""
+    rng = np.random.default_rng(21)
+    for n in (3, 7, 64, 300):
+        p = rng.standard_normal((n, 3)) * rng.uniform(1, 20, 3) + rng.uniform(-50, 50, 3)
+        x = rng.standard_normal((3 * n, 3))
+        y = rng.standard_normal((6, 3))
+        Z = dense.zmatrix_centroid(p)
+        scale = np.abs(Z).max() ** 2 * n
+        assert np.abs(dense.zmul(p, x) - Z @ x).max() <= 1e-12 * np.abs(Z).max() * np.abs(x).sum(axis=0).max()
+        assert np.abs(dense.zmul_t(p, y) - Z.T @ y).max() <= 1e-12 * np.abs(Z).max() * np.abs(y).sum()
+        assert np.abs(dense.gram(p) - Z @ Z.T).max() <= 1e-12 * scale
+        assert np.abs(dense.project_large(p, x) - dense.project(p, x)).max() <= 1e-10
+        assert np.abs(dense.leak_large(p, x) - dense.leak(p, x)).max() <= 1e-12
+        # the projector annihilates the row space and is idempotent
+        px = dense.project_large(p, x)
+        assert np.abs(dense.zmul(p, px)).max() <= 1e-9 * np.abs(Z).max() * np.abs(x).max() * n
+        assert np.abs(dense.project_large(p, px) - px).max() <= 1e-10
