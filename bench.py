@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bead-vectors/s for batched Q̃v+Q̃ᵀv; % HBM peak; FP32 err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
+PROBE_SWEEPS = 3  # must match paper_1708_08427_amd.traffic
+TRAFFIC_FILE = "traffic_up_sweep_bd_m4096_R32.json"
 
 
 def algorithmic_bytes(h, nrhs, elem=4):
@@ -65,6 +67,44 @@ def cpu_baseline(wl, rng_seed, budget_s=15.0):
                       f"rebuild + Q~f + Q~^T(Q~f) per body, {t_total:.1f} s"}
 
 
+def probe(hq, torch, wl, f, args):
+    """The counter run: one 512 MiB device copy (calibrates FETCH_SIZE and
+    WRITE_SIZE against known bytes), then PROBE_SWEEPS upward and downward FP32
+    sweeps of the bench workload."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    pos = torch.from_numpy(wl.pos).to(dev)
+    f32 = torch.from_numpy(f).float().to(dev)
+    tmp = torch.empty((wl.rows, wl.nrhs), dtype=torch.float32, device=dev)
+    out = torch.empty((3 * wl.N, wl.nrhs), dtype=torch.float32, device=dev)
+    h = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=2)
+    for _ in range(PROBE_SWEEPS):
+        h.apply(f32, out=tmp)
+    for _ in range(PROBE_SWEEPS):
+        h.apply(tmp, transpose=True, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "algorithmic_bytes": algorithmic_bytes(h, wl.nrhs), "phases": h.query()["phases"]}),
+          flush=True)
+
+
+def traffic_from_profile():
+    """HBM bytes of one upward sweep from the committed counter summary, if it
+    was taken on the current sweep sources (else None)."""
+    from paper_1708_08427_amd.traffic import sweep_source_hash
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as fh:
+        prof = json.load(fh)
+    if prof.get("source_sha256") != sweep_source_hash():
+        return None, "sweep sources changed since the counters were taken"
+    return prof["up_sweep"]["hbm_bytes"], prof["command"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +115,8 @@ def main():
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--probe", action="store_true",
+                    help="only build, copy 512 MiB once and run 3 sweeps per direction (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bodies of this workload "
@@ -92,6 +134,9 @@ def main():
     N, m, R = wl.N, wl.m, wl.nrhs
     rng = np.random.default_rng(33)
     f = rng.standard_normal((3 * N, R))
+    if args.probe:
+        probe(hq, torch, wl, f, args)
+        return
     total_steps = args.steps + args.warmup
     rot, trans = W.rigid_motions(rng, total_steps, m)
     log(f"workload {wl.name}: N={N} m={m} R={R} rows={wl.rows}")
@@ -184,6 +229,8 @@ def main():
         log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms, up FP64 {t_up64:.3f} ms")
         nbytes = algorithmic_bytes(h, R)
         achieved = nbytes / (t_up * 1e-3) / 1e9
+        traffic, traffic_src = traffic_from_profile()
+        log(f"traffic: {traffic} ({traffic_src})")
         q = h.query()
 
     result = {
@@ -203,9 +250,9 @@ def main():
                    "rows": wl.rows, "tile_units": args.tile_units,
                    "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "upward sweep Q~v FP32 (k_up, all tile phases)", "bytes": int(nbytes),
-                     "ms": t_up},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "upward sweep Q~v FP32 (k_up_wide, one launch per tile phase)",
+                     "bytes": int(nbytes), "ms": t_up},
         "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},
         "apply_only_bead_vectors_per_s": N * R / ((t_up + t_dn) * 1e-3),
         "fp32_rel_err_vs_fp64_oracle": err,

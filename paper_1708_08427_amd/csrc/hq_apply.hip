@@ -543,9 +543,11 @@ __device__ __forceinline__ void bst6(rsrc_t r, uint32_t vo, const double (&m)[6]
     }
 }
 
+// lane W of each 16-lane group (ds_swizzle bit mode: and 0x10, or W)
 template <int W>
-__device__ __forceinline__ float bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), W << 5));
+__device__ __forceinline__ float bcast16(float v) {
+    static_assert(W < 16, "16-lane groups");
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x10 | (W << 5)));
 }
 
 template <int W>
@@ -591,8 +593,8 @@ struct RecReg<float> {
             if constexpr (W & 1) return row_bcast<W / 2>(b);
             else return row_bcast<W / 2>(a);
         } else {
-            if constexpr (W & 1) return bcast<W / 2>(b);
-            else return bcast<W / 2>(a);
+            if constexpr (W & 1) return bcast16<W / 2>(b);
+            else return bcast16<W / 2>(a);
         }
     }
     template <int W>
@@ -648,24 +650,133 @@ __device__ __forceinline__ int2 bcast_refs(const RecReg<float> &r) { return make
 
 __device__ __forceinline__ int2 bcast_refs(const RecReg<double> &r) { return make_int2(r.geti<0>(), r.geti<1>()); }
 
-// LDS slot layout: [slot][component 0..5][64 lanes]
-template <typename T>
-__device__ __forceinline__ void lds_put6(T *lds, int slot, int lane, const T (&m)[6]) {
-    T *p = lds + slot * 6 * 64 + lane;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) p[c * 64] = m[c];
-}
-
-template <typename T>
-__device__ __forceinline__ void lds_get6(const T *lds, int slot, int lane, T (&m)[6]) {
-    const T *p = lds + slot * 6 * 64 + lane;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) m[c] = p[c * 64];
-}
-
 template <int RT>
 __device__ __forceinline__ int rhs_count(const Ctx &C) {
     return RT ? RT : C.R;
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane vectors of NC adjacent right-hand sides (NC = 1 or 2): the lane
+// holds columns NC * rl .. NC * rl + NC - 1 of its lane group, so one row of a
+// vector is one coalesced access of NC values per lane, and the record
+// broadcast, the addressing and the selects of a node are shared by the NC
+// columns.
+// ---------------------------------------------------------------------------
+template <typename T, int NC>
+__device__ __forceinline__ void bldn(rsrc_t r, uint32_t vo, uint32_t so, T (&m)[NC]) {
+    if constexpr (NC == 1) {
+        m[0] = bld<T>(r, vo, so);
+    } else if constexpr (sizeof(T) == 4) {
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+        m[0] = __uint_as_float(a.x);
+        m[1] = __uint_as_float(a.y);
+    } else {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+        m[0] = __builtin_bit_cast(double, u32x2{a.x, a.y});
+        m[1] = __builtin_bit_cast(double, u32x2{a.z, a.w});
+    }
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void bstn(const T (&m)[NC], rsrc_t r, uint32_t vo, uint32_t so) {
+    if constexpr (NC == 1) {
+        bst<T>(m[0], r, vo, so);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(m[0]), __float_as_uint(m[1])}, r, vo, so, 0);
+    } else {
+        const u32x2 a = __builtin_bit_cast(u32x2, m[0]), b = __builtin_bit_cast(u32x2, m[1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, so, 0);
+    }
+}
+
+// Exchange entries are [slot][column][6 values]: a lane's NC entries are 6 NC
+// contiguous values.
+template <typename T, int NC>
+__device__ __forceinline__ void bld6n(rsrc_t r, uint32_t vo, T (&m)[6][NC]) {
+    if constexpr (NC == 1) {
+        T e[6];
+        bld6(r, vo, e);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m[k][0] = e[k];
+    } else {
+        static_assert(NC == 2 && sizeof(T) == 4, "two columns per lane are float");
+        // four 12-byte pieces: each column's two triples
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 24 * c + 12 * h, 0);
+                m[3 * h][c] = __uint_as_float(a.x);
+                m[3 * h + 1][c] = __uint_as_float(a.y);
+                m[3 * h + 2][c] = __uint_as_float(a.z);
+            }
+    }
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void bst6n(rsrc_t r, uint32_t vo, const T (&m)[6][NC]) {
+    if constexpr (NC == 1) {
+        T e[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[k] = m[k][0];
+        bst6(r, vo, e);
+    } else {
+        static_assert(NC == 2 && sizeof(T) == 4, "two columns per lane are float");
+        // four 12-byte pieces: each column's two triples
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                __builtin_amdgcn_raw_buffer_store_b96(
+                    u32x3{__float_as_uint(m[3 * h][c]), __float_as_uint(m[3 * h + 1][c]), __float_as_uint(m[3 * h + 2][c])},
+                    r, vo, 24 * c + 12 * h, 0);
+    }
+}
+
+// LDS slot layout: [slot][component 0..5][64 lanes][NC]
+template <typename T, int NC>
+__device__ __forceinline__ void lds_put6(T *lds, int slot, int lane, const T (&m)[6][NC]) {
+    T *p = lds + ((slot * 6) * 64 + lane) * NC;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p[k * 64 * NC + c] = m[k][c];
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void lds_get6(const T *lds, int slot, int lane, T (&m)[6][NC]) {
+    const T *p = lds + ((slot * 6) * 64 + lane) * NC;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) m[k][c] = p[k * 64 * NC + c];
+}
+
+// t <- G t / t <- G^T t for NC columns at once (the record words are shared)
+template <typename T, int NC>
+__device__ __forceinline__ void house_fwd9n(T (&t)[9][NC], const T (&g)[26]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        T u[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) u[i] = t[i][c];
+        house_fwd<9>(u, g);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) t[i][c] = u[i];
+    }
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void house_bwd9n(T (&t)[9][NC], const T (&g)[26]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        T u[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) u[i] = t[i][c];
+        house_bwd<9>(u, g);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) t[i][c] = u[i];
+    }
 }
 
 // The buffers of one wide sweep and byte strides.
@@ -684,79 +795,88 @@ __device__ __forceinline__ WBufs wide_bufs(const T *in, T *out, T *xch, const Ct
     return b;
 }
 
-// Byte offset of bead ref's first row for lane rr: a negative ref (not a
-// bead) or off = false lands past the end of the buffer.
+// Byte offset of bead ref's first row for the lane's first column (lanebytes):
+// a negative ref (not a bead) or on = false lands past the end of the buffer.
 template <typename T, int RT>
 __device__ __forceinline__ uint32_t bead_off(int ref, bool on, const Ctx &C, uint32_t lanebytes) {
     const uint32_t u = on ? min((uint32_t)ref, (uint32_t)C.N) : (uint32_t)C.N;
     return u * (uint32_t)(3 * rhs_count<RT>(C) * sizeof(T)) + lanebytes;
 }
 
-// Byte offset of exchange entry (slot, lane rr), past the end when off.
+// Byte offset of exchange entry (slot, lane's first column), past the end when off.
 template <typename T, int RT>
 __device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, uint32_t lanebytes) {
     const uint32_t sl = on ? min((uint32_t)slot, (uint32_t)C.xch_cap) : (uint32_t)C.xch_cap;
     return sl * (uint32_t)(6 * rhs_count<RT>(C) * sizeof(T)) + 6 * lanebytes;
 }
 
-// Upward memory input of one child, IW values: a bead's vector (3 values,
-// zero Info-set tail) or, with IW = 6, an earlier tile root's Info-set.  A
-// stack child loads nothing (zeros).  IW = 3 serves the first tile phase,
-// whose only memory inputs are beads.
-template <typename T, int RT, int IW>
-__device__ __forceinline__ void up_input(int ref, T (&m)[IW], const WBufs &B, const Ctx &C, uint32_t lb) {
+// Upward memory input of one child: a bead's vector (3 values; zero Info-set
+// tail) or, with IW = 6, an earlier tile root's Info-set.  A stack child loads
+// nothing (zeros).  IW = 3 serves the first tile phase, whose only memory
+// inputs are beads.
+template <typename T, int RT, int IW, int NC>
+__device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B, const Ctx &C, uint32_t lb) {
     const uint32_t vb = bead_off<T, RT>(ref, true, C, lb);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) m[c] = bld<T>(B.in, vb, c * B.row);
+    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, vb, k * B.row, m[k]);
     if constexpr (IW == 6) {
-        T e[6];
-        bld6(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
+        T e[6][NC];
+        bld6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m[c] += e[c];
+        for (int c = 0; c < NC; ++c) {
 #pragma unroll
-        for (int c = 3; c < 6; ++c) m[c] = e[c];
+            for (int k = 0; k < 3; ++k) m[k][c] += e[k][c];
+#pragma unroll
+            for (int k = 3; k < 6; ++k) m[k][c] = e[k][c];
+        }
     }
 }
 
 // One upward node step (Eqs. 4.2-4.3).  A child of the same tile is read from
 // its LDS slot; a bead or an earlier tile's root comes from the prefetched
 // registers ax / ay.  Nothing is stored unless the node is live.
-template <typename T, int RT, int IW>
-__device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW], const T (&ay)[IW],
-                                        T *lds, int lane, const WBufs &B, const Ctx &C, uint32_t lb, bool live,
-                                        bool act) {
+template <typename T, int RT, int IW, int NC>
+__device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW][NC],
+                                        const T (&ay)[IW][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
+                                        uint32_t lb, bool live, bool act) {
     // offsets and references were checked when the tile schedule was built;
     // an access outside a buffer would be dropped by its range check
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
     const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
     const bool xst = lk.xref == kRefStack, yst = lk.yref == kRefStack;
-    T mx[6], my[6];
-    lds_get6(lds, xs, lane, mx);
-    lds_get6(lds, ys, lane, my);
-#pragma unroll
-    for (int c = 0; c < IW; ++c) {
-        mx[c] = xst ? mx[c] : ax[c];
-        my[c] = yst ? my[c] : ay[c];
-    }
+    T mx[6][NC], my[6][NC];
+    lds_get6<T, NC>(lds, xs, lane, mx);
+    lds_get6<T, NC>(lds, ys, lane, my);
     const T sx = g[kRecSx], sy = g[kRecSy];
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
     const bool both = xi && yi, any = xi || yi;
-    T mp[6], t9[9], tt[3];
+    T mp[6][NC], t9[9][NC];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        mp[c] = sx * mx[c] + sy * my[c];
-        tt[c] = sy * mx[c] - sx * my[c];
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int k = 0; k < IW; ++k) {
+            mx[k][c] = xst ? mx[k][c] : ax[k][c];
+            my[k][c] = yst ? my[k][c] : ay[k][c];
+        }
+        T tt[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mp[k][c] = sx * mx[k][c] + sy * my[k][c];
+            tt[k] = sy * mx[k][c] - sx * my[k][c];
+        }
+        // t = [M_x(4:6)?; M_y(4:6)?; tt] packed to the front, zeros behind
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            t9[k][c] = xi ? mx[3 + k][c] : (yi ? my[3 + k][c] : tt[k]);
+            t9[3 + k][c] = both ? my[3 + k][c] : (any ? tt[k] : T(0));
+            t9[6 + k][c] = both ? tt[k] : T(0);
+        }
     }
-    // t = [M_x(4:6)?; M_y(4:6)?; tt] packed to the front, zeros behind
+    house_fwd9n<T, NC>(t9, g);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        t9[c] = xi ? mx[3 + c] : (yi ? my[3 + c] : tt[c]);
-        t9[3 + c] = both ? my[3 + c] : (any ? tt[c] : T(0));
-        t9[6 + c] = both ? tt[c] : T(0);
-    }
-    house_fwd<9>(t9, g);
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mp[3 + c] = t9[c];
+        for (int c = 0; c < NC; ++c) mp[3 + k][c] = t9[k][c];
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
     const bool en = live && act;
     // residue rows [off, off + dim)
@@ -764,12 +884,12 @@ __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, cons
     const uint32_t o1 = (en && any) ? ob : kOOB;
     const uint32_t o2 = (en && both) ? ob + 3 * B.row : kOOB;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bst<T>(t9[3 + c], B.out, o1, c * B.row);
+    for (int k = 0; k < 3; ++k) bstn<T, NC>(t9[3 + k], B.out, o1, k * B.row);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bst<T>(t9[6 + c], B.out, o2, c * B.row);
+    for (int k = 0; k < 3; ++k) bstn<T, NC>(t9[6 + k], B.out, o2, k * B.row);
     // a tile root's Info-set goes to the exchange buffer, others stay in LDS
-    bst6(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, en && troot, C, lb), mp);
-    if (live && !troot) lds_put6(lds, os, lane, mp);
+    bst6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, en && troot, C, lb), mp);
+    if (live && !troot) lds_put6<T, NC>(lds, os, lane, mp);
 }
 
 // The run of lane group k of a phase: schedule range [base, base + len).
@@ -788,13 +908,21 @@ __device__ __forceinline__ void run_range(int k, int nrun, int c0, const int32_t
     }
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, int IW>
-__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_up_wide(int phase, const int32_t *__restrict__ prun,
-                                                   const int32_t *__restrict__ run, const T *__restrict__ rec,
-                                                   const T *__restrict__ v, T *__restrict__ out,
-                                                   T *__restrict__ xch, Ctx C, int32_t *err) {
-    static_assert(LPT == 32 || LPT == 64, "wide sweeps use 32 or 64 lanes per run");
+// the longest run of the wave (wave-uniform)
+template <int LPT>
+__device__ __forceinline__ int wave_max_len(int len) {
+    if constexpr (LPT <= 16) len = max(len, __shfl_xor(len, 16, 64));
+    if constexpr (LPT <= 32) len = max(len, __shfl_xor(len, 32, 64));
+    return __builtin_amdgcn_readfirstlane(len);
+}
+
+template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC>
+__global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_up_wide(
+    int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
+    const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
+    static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
     static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6), "ring sizes");
+    static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     constexpr int TPW = 64 / LPT;
@@ -807,26 +935,24 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_up_wide(int phas
     int bad = 0;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
-        const int r = chunk * LPT + rl;
-        const int rr = min(r, R - 1);
+        const int col = (chunk * LPT + rl) * NC;  // first column of the lane
+        const int rr = min(col, R - NC);
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
-        const bool act = r < R;
+        const bool act = col < R;
         const uint32_t lb = (uint32_t)(rr * sizeof(T));
-        int maxlen = len;
-        if (LPT == 32) maxlen = max(maxlen, __shfl_xor(len, 32, 64));
-        maxlen = __builtin_amdgcn_readfirstlane(maxlen);
+        const int maxlen = wave_max_len<LPT>(len);
         const int last = max(len - 1, 0);
         const T *rp = rec + (int64_t)kRecWords * base;
         RecReg<T> RW[PR];
-        T A[NR][IW], Bv[NR][IW];
+        T A[NR][IW][NC], Bv[NR][IW][NC];
 #pragma unroll
         for (int k = 0; k < PR; ++k) RW[k].load(rp + (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
         for (int k = 0; k < NR - 1; ++k) {
             const int2 ref = bcast_refs(RW[k]);
-            up_input<T, RT, IW>(ref.x, A[k], B, C, lb);
-            up_input<T, RT, IW>(ref.y, Bv[k], B, C, lb);
+            up_input<T, RT, IW, NC>(ref.x, A[k], B, C, lb);
+            up_input<T, RT, IW, NC>(ref.y, Bv[k], B, C, lb);
         }
 #define HQ_UP_STEP(K)                                                                       \
         {                                                                                   \
@@ -837,10 +963,10 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_up_wide(int phas
             RW[K].load(rp + (int64_t)min(n + PR, last) * kRecWords, lane);                  \
             {                                                                               \
                 const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                       \
-                up_input<T, RT, IW>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);               \
-                up_input<T, RT, IW>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);              \
+                up_input<T, RT, IW, NC>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);           \
+                up_input<T, RT, IW, NC>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);          \
             }                                                                               \
-            up_node<T, RT, IW>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            up_node<T, RT, IW, NC>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_UP_STEP(0)
@@ -860,86 +986,87 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_up_wide(int phas
 // Downward memory inputs of one node: its residue coefficients w_p (dim = 0,
 // 3 or 6 values) and, for a tile root below a body root, its Velocity-set from
 // the exchange buffer; absent values load as zeros.
-template <typename T, int RT>
-__device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6], T (&b)[6], const WBufs &B, const Ctx &C,
-                                           uint32_t lb) {
+template <typename T, int RT, int NC>
+__device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&b)[6][NC], const WBufs &B,
+                                           const Ctx &C, uint32_t lb) {
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
     const uint32_t ob = (uint32_t)lk.off * B.row + lb;
     const uint32_t p1 = (xi || yi) ? ob : kOOB;
     const uint32_t p2 = (xi && yi) ? ob + 3 * B.row : kOOB;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a[c] = bld<T>(B.in, p1, c * B.row);
+    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, p1, k * B.row, a[k]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a[3 + c] = bld<T>(B.in, p2, c * B.row);
+    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, p2, k * B.row, a[3 + k]);
     const bool lr = (lk.meta & (kMetaTileRoot | kMetaBodyRoot)) == kMetaTileRoot;
-    bld6(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, lr, C, lb), b);
+    bld6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, lr, C, lb), b);
 }
 
 // One downward node step (Theorem 4.3): L_p from its LDS slot (or the
 // exchange buffer for a tile root, zero for a body root), children's
 // Velocity-sets to their slots, to bead outputs, or (XC: phases after the
 // first) to the exchange buffer.
-template <typename T, int RT, bool XC>
-__device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, const T (&wp)[6], const T (&lroot)[6],
-                                          T *lds, int lane, const WBufs &B, const Ctx &C, uint32_t lb, bool live,
-                                          bool act) {
+template <typename T, int RT, bool XC, int NC>
+__device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, const T (&wp)[6][NC],
+                                          const T (&lroot)[6][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
+                                          uint32_t lb, bool live, bool act) {
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
     const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
-    T L[6];
-    lds_get6(lds, os, lane, L);
-    // a tile root's Velocity-set comes from the exchange buffer (zeros for a
-    // body root, whose entry loads as zeros)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) L[c] = troot ? lroot[c] : L[c];
+    T L[6][NC];
+    lds_get6<T, NC>(lds, os, lane, L);
     const T sx = g[kRecSx], sy = g[kRecSy];
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
     const bool both = xi && yi, any = xi || yi;
-    T x9[9];
+    T x9[9][NC], Lx[6][NC], Ly[6][NC];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x9[c] = L[3 + c];
+    for (int c = 0; c < NC; ++c) {
+        // a tile root's Velocity-set comes from the exchange buffer (zeros for
+        // a body root, whose entry loads as zeros)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) x9[3 + c] = wp[c];  // absent residue values loaded as zeros
-    house_bwd<9>(x9, g);
-    T st[3], Lx[6], Ly[6];
+        for (int k = 0; k < 6; ++k) L[k][c] = troot ? lroot[k][c] : L[k][c];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        st[c] = both ? x9[6 + c] : (any ? x9[3 + c] : x9[c]);
-        Lx[3 + c] = x9[c];
-        Ly[3 + c] = both ? x9[3 + c] : x9[c];
-        Lx[c] = sx * L[c] + sy * st[c];
-        Ly[c] = sy * L[c] - sx * st[c];
+        for (int k = 0; k < 3; ++k) x9[k][c] = L[3 + k][c];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) x9[3 + k][c] = wp[k][c];  // absent residue values loaded as zeros
     }
-    const bool en = live && act;
-    const int refs[2] = {lk.xref, lk.yref};
+    house_bwd9n<T, NC>(x9, g);
 #pragma unroll
-    for (int ch = 0; ch < 2; ++ch) {
-        const int ref = refs[ch];
-        const T *Lc = ch ? Ly : Lx;
-        const uint32_t bo = bead_off<T, RT>(ref, en, C, lb);
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bst<T>(Lc[c], B.out, bo, c * B.row);
-        if constexpr (XC) {
-            T Lv[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) Lv[c] = Lc[c];
-            bst6(B.xch, xch_off<T, RT>(ref_slot(ref), en && ref < kRefStack, C, lb), Lv);
+        for (int k = 0; k < 3; ++k) {
+            const T st = both ? x9[6 + k][c] : (any ? x9[3 + k][c] : x9[k][c]);
+            Lx[3 + k][c] = x9[k][c];
+            Ly[3 + k][c] = both ? x9[3 + k][c] : x9[k][c];
+            Lx[k][c] = sx * L[k][c] + sy * st;
+            Ly[k][c] = sy * L[k][c] - sx * st;
         }
+    const bool en = live && act;
+    {
+        const uint32_t bx = bead_off<T, RT>(lk.xref, en, C, lb), by = bead_off<T, RT>(lk.yref, en, C, lb);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bstn<T, NC>(Lx[k], B.out, bx, k * B.row);
+            bstn<T, NC>(Ly[k], B.out, by, k * B.row);
+        }
+    }
+    if constexpr (XC) {
+        bst6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(lk.xref), en && lk.xref < kRefStack, C, lb), Lx);
+        bst6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(lk.yref), en && lk.yref < kRefStack, C, lb), Ly);
     }
     if (live) {
         // children of this tile go to their slots
-        if (lk.xref == kRefStack) lds_put6(lds, xs, lane, Lx);
-        if (lk.yref == kRefStack) lds_put6(lds, ys, lane, Ly);
+        if (lk.xref == kRefStack) lds_put6<T, NC>(lds, xs, lane, Lx);
+        if (lk.yref == kRefStack) lds_put6<T, NC>(lds, ys, lane, Ly);
     }
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, bool XC>
-__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_down_wide(int phase, const int32_t *__restrict__ prun,
-                                                     const int32_t *__restrict__ run, const T *__restrict__ rec,
-                                                     const T *__restrict__ w, T *__restrict__ out,
-                                                     T *__restrict__ xch, Ctx C, int32_t *err) {
-    static_assert(LPT == 32 || LPT == 64, "wide sweeps use 32 or 64 lanes per run");
+template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC>
+__global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_down_wide(
+    int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
+    const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
+    static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
     static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6), "ring sizes");
+    static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     constexpr int TPW = 64 / LPT;
@@ -952,24 +1079,22 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_down_wide(int ph
     int bad = 0;
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
-        const int r = chunk * LPT + rl;
-        const int rr = min(r, R - 1);
+        const int col = (chunk * LPT + rl) * NC;
+        const int rr = min(col, R - NC);
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
-        const bool act = r < R;
+        const bool act = col < R;
         const uint32_t lb = (uint32_t)(rr * sizeof(T));
-        int maxlen = len;
-        if (LPT == 32) maxlen = max(maxlen, __shfl_xor(len, 32, 64));
-        maxlen = __builtin_amdgcn_readfirstlane(maxlen);
+        const int maxlen = wave_max_len<LPT>(len);
         const int last = max(len - 1, 0);
         // node n of the sweep is schedule index base + len - 1 - n
         const T *rp = rec + (int64_t)kRecWords * (base + last);
         RecReg<T> RW[PR];
-        T A[NR][6], Bl[NR][6];
+        T A[NR][6][NC], Bl[NR][6][NC];
 #pragma unroll
         for (int k = 0; k < PR; ++k) RW[k].load(rp - (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
-        for (int k = 0; k < NR - 1; ++k) down_input<T, RT>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
+        for (int k = 0; k < NR - 1; ++k) down_input<T, RT, NC>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
 #define HQ_DOWN_STEP(K)                                                                     \
         {                                                                                   \
             const int n = n0 + (K);                                                         \
@@ -977,9 +1102,9 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_down_wide(int ph
             bcast_g<0>(g, RW[K]);                                                           \
             const Links6 lk = bcast_links6(RW[K]);                                          \
             RW[K].load(rp - (int64_t)min(n + PR, last) * kRecWords, lane);                  \
-            down_input<T, RT>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
-                              Bl[((K) + NR - 1) % NR], B, C, lb);                           \
-            down_node<T, RT, XC>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            down_input<T, RT, NC>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
+                                  Bl[((K) + NR - 1) % NR], B, C, lb);                       \
+            down_node<T, RT, XC, NC>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_DOWN_STEP(0)
@@ -996,59 +1121,52 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) k_down_wide(int ph
     if (bad) atomicOr(err, bad);
 }
 
-template <typename T, int LPT>
-void launch_phase(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
-                  hipStream_t s) {
-    const size_t lds = (size_t)C.dmax * 6 * 64 * sizeof(T);
+// One tile phase of a wide sweep: LPT lanes per run, NC columns per lane.
+template <typename T, int LPT, int NC>
+void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
+                 hipStream_t s) {
     constexpr int TPW = 64 / LPT;
-    const char *genv = getenv("HQ_APPLY_GRID");
-    if constexpr (LPT >= 32) {
-        size_t lds_w = (size_t)C.nslot * 6 * 64 * sizeof(T);
-        if (const char *e = getenv("HQ_LDS_PAD")) lds_w += (size_t)atoll(e);
-        // work items: pairs of runs (a phase has at most NI / run_nodes + 1
-        // runs) x RHS chunks, one per wave, so the dispatcher balances the
-        // load; waves of later phases with fewer runs exit at once
-        const int64_t items = ((P.NI / P.run_nodes + 2 + TPW - 1) / TPW) * (int64_t)C.nchunks;
-        int64_t g = items;
-        if (genv) g = std::max<int64_t>(1, atoll(genv));
-        const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
+    size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
+    if (const char *e = getenv("HQ_LDS_PAD")) lds_w += (size_t)atoll(e);
+    // work items: groups of TPW runs (a phase has at most NI / run_nodes + 1
+    // runs) x RHS chunks, one per wave, so the dispatcher balances the load;
+    // waves of later phases with fewer runs exit at once
+    const int64_t items = ((P.NI / P.run_nodes + 2 + TPW - 1) / TPW) * (int64_t)C.nchunks;
+    int64_t g = items;
+    if (const char *e = getenv("HQ_APPLY_GRID")) g = std::max<int64_t>(1, atoll(e));
+    const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
 #define HQ_WIDE(RT, PR, NR, PR1, NR1, NRD)                                                                   \
     do {                                                                                                     \
         if (!transpose) {                                                                                    \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR1, NR1, 3>), dim3(grid), dim3(64), lds_w, s, phase, \
-                                   P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                         \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR1, NR1, 3, NC>), dim3(grid), dim3(64), lds_w, s,    \
+                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
             else                                                                                             \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6>), dim3(grid), dim3(64), lds_w, s, phase, \
-                                   P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                         \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6, NC>), dim3(grid), dim3(64), lds_w, s,      \
+                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
         } else {                                                                                             \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false>), dim3(grid), dim3(64), lds_w, s,    \
-                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false, NC>), dim3(grid), dim3(64), lds_w,   \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
             else                                                                                             \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, true>), dim3(grid), dim3(64), lds_w, s,     \
-                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, true, NC>), dim3(grid), dim3(64), lds_w,    \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
         }                                                                                                    \
     } while (0)
-        int variant = 0;
-        if (const char *e = getenv("HQ_WIDE_VARIANT")) variant = atoi(e);
-        if (LPT == 32 && C.R == 32) {
-            switch (variant) {
-            case 1: HQ_WIDE(32, 6, 2, 6, 3, 2); break;
-            case 2: HQ_WIDE(32, 6, 2, 6, 6, 3); break;
-            case 3: HQ_WIDE(32, 6, 2, 4, 4, 3); break;
-            default: HQ_WIDE(32, 6, 2, 6, 3, 3); break;
-            }
-        } else {
-            HQ_WIDE(0, 6, 2, 6, 3, 3);
-        }
+    if (C.R == 32) HQ_WIDE(32, 6, 2, 6, 3, (NC == 1 ? 3 : 2));
+    else HQ_WIDE(0, 6, 2, 6, 3, (NC == 1 ? 3 : 2));
 #undef HQ_WIDE
-        return;
-    }
+}
+
+template <typename T, int LPT>
+void launch_narrow(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
+                   hipStream_t s) {
+    const size_t lds = (size_t)C.dmax * 6 * 64 * sizeof(T);
+    constexpr int TPW = 64 / LPT;
     // one wave per work item of the largest phase (tile groups x RHS chunks);
     // waves without work exit at once
     int64_t items = ((2 * P.tiles_built + 64 + TPW - 1) / TPW) * (int64_t)C.nchunks;
-    if (genv) items = std::max<int64_t>(1, atoll(genv));
+    if (const char *e = getenv("HQ_APPLY_GRID")) items = std::max<int64_t>(1, atoll(e));
     const unsigned grid = (unsigned)std::min<int64_t>(items, 1 << 20);
     if (!transpose)
         hipLaunchKernelGGL((k_up<T, LPT>), dim3(grid), dim3(64), lds, s, phase, P.d_phase, P.d_tile_base,
@@ -1058,20 +1176,24 @@ void launch_phase(const Plan &P, int phase, int transpose, const T *rec, const T
                            P.d_tile_len, P.d_links, rec, v, out, xch, C, P.d_err);
 }
 
+// Sweep kinds: narrow (lanes per tile 1..16, tile stack in LDS) and wide
+// (runs of whole tiles, explicit slots, buffer addressing).
+enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWide64 };
+
 template <typename T>
-void launch_all(const Plan &P, int transpose, int lpt, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
-                hipStream_t s) {
+void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
+                const Ctx &C, hipStream_t s) {
     const int nph = std::max(P.phases_built, P.phases_reserved);
     for (int k = 0; k < nph; ++k) {
         const int phase = transpose ? (nph - k) : (k + 1);
-        switch (lpt) {
-        case 1: launch_phase<T, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case 2: launch_phase<T, 2>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case 4: launch_phase<T, 4>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case 8: launch_phase<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case 16: launch_phase<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case 32: launch_phase<T, 32>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        default: launch_phase<T, 64>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        switch (kind) {
+        case kNarrow1: launch_narrow<T, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kNarrow2: launch_narrow<T, 2>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kNarrow4: launch_narrow<T, 4>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kNarrow8: launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kWide32: launch_wide<T, 32, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kWide64: launch_wide<T, 64, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
         }
     }
 }
@@ -1090,30 +1212,41 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
     C.rows = P.rows;
     C.nsched = P.NI;
     C.R = (int)nrhs;
-    int lpt = lanes_per_tile(nrhs);
-    if (const char *e = getenv("HQ_LPT")) {
-        const int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) lpt = v;
-    }
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
     C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(P.xch_bytes / (6 * elem * (size_t)nrhs)));
-    // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB;
-    // larger problems take the narrow sweeps
+    // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB
     const int64_t vin = (transpose ? P.rows : 3 * P.N) * nrhs * (int64_t)elem;
     const int64_t vout = (transpose ? 3 * P.N : P.rows) * nrhs * (int64_t)elem;
     const int64_t vx = (int64_t)C.xch_cap * 6 * nrhs * (int64_t)elem;
     const int64_t lim = (int64_t)kOOB - (int64_t)(1 << 20);
-    if (lpt >= 32 && (vin >= lim || vout >= lim || vx >= lim)) lpt = 16;
+    const bool wide_ok = vin < lim && vout < lim && vx < lim;
     C.in_bytes = (uint32_t)std::min<int64_t>(vin, lim);
     C.out_bytes = (uint32_t)std::min<int64_t>(vout, lim);
     C.xch_bytes = (uint32_t)std::min<int64_t>(vx, lim);
-    C.nchunks = (int)((nrhs + lpt - 1) / lpt);
+    // more than 16 right-hand sides: wide sweeps (one column per lane; two
+    // columns per lane measured slower: 4 runs per wave lose more to uneven
+    // run lengths and to LDS-limited occupancy than they save in VALU work);
+    // otherwise, or beyond the buffer range, narrow sweeps
+    int lpt = lanes_per_tile(nrhs);
+    if (const char *e = getenv("HQ_LPT")) {
+        const int q = atoi(e);
+        if (q == 1 || q == 2 || q == 4 || q == 8 || q == 16 || q == 32 || q == 64) lpt = q;
+    }
+    if (lpt >= 32 && !wide_ok) lpt = 16;
+    SweepKind kind;
+    const int cols = lpt;  // right-hand sides per chunk
+    if (lpt >= 32) {
+        kind = (lpt == 32) ? kWide32 : kWide64;
+    } else {
+        kind = lpt == 1 ? kNarrow1 : lpt == 2 ? kNarrow2 : lpt == 4 ? kNarrow4 : lpt == 8 ? kNarrow8 : kNarrow16;
+    }
+    C.nchunks = (int)((nrhs + cols - 1) / cols);
     C.dmax = stack_depth(P.S);
     C.nslot = stack_slots(P.S);
     if (prec == HQ_FP64)
-        launch_all<double>(P, transpose, lpt, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s);
+        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s);
     else
-        launch_all<float>(P, transpose, lpt, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s);
+        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

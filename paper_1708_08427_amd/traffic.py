@@ -1,0 +1,87 @@
+"""HBM traffic of the sweeps from hardware counters.
+
+Two rocprofv3 counter runs of ``bench.py --probe`` (one with FETCH_SIZE, one
+with WRITE_SIZE; both in KiB per dispatch) are turned into the bytes one
+upward and one downward FP32 sweep move to and from HBM.  Each counter is
+scaled by what it reads for the probe's device copy of 512 MiB (bytes it
+must read and write), and the summary records a hash of the sweep sources so
+that a reader can tell whether it still describes the current kernels.
+
+    python -m paper_1708_08427_amd.traffic FETCH_DIR WRITE_DIR OUT.json --command "..."
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 128 * 1024 * 1024 * 4  # the probe's float32 copy
+PROBE_SWEEPS = 3
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("hq_apply.hip", "hq_common.h"):
+        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _read(dirname, counter):
+    files = glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {dirname}")
+    per = {}
+    for fn in files:
+        with open(fn) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (fn, int(r["Dispatch_Id"]))
+                e = per.setdefault(key, {"name": r["Kernel_Name"], "value": 0.0})
+                e["value"] += float(r["Counter_Value"])
+    return list(per.values())
+
+
+def summarise(rows):
+    copies = [r for r in rows if "copy" in r["name"].lower() and "hq::" not in r["name"]]
+    if not copies:
+        raise ValueError("the probe's copy kernel is missing")
+    copy_kib = max(r["value"] for r in copies)
+    up = sum(r["value"] for r in rows if "k_up_wide" in r["name"]) / PROBE_SWEEPS
+    down = sum(r["value"] for r in rows if "k_down_wide" in r["name"]) / PROBE_SWEEPS
+    return copy_kib, up, down
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("out")
+    ap.add_argument("--command", required=True)
+    a = ap.parse_args()
+    cf, uf, df = summarise(_read(a.fetch_dir, "FETCH_SIZE"))
+    cw, uw, dw = summarise(_read(a.write_dir, "WRITE_SIZE"))
+    ff = COPY_BYTES / (cf * 1024.0)
+    fw = COPY_BYTES / (cw * 1024.0)
+    res = {
+        "command": a.command,
+        "source_sha256": sweep_source_hash(),
+        "copy": {"bytes_each_way": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                 "fetch_factor": ff, "write_factor": fw},
+        "up_sweep": {"fetch_kib": uf, "write_kib": uw,
+                     "hbm_bytes": uf * 1024.0 * ff + uw * 1024.0 * fw},
+        "down_sweep": {"fetch_kib": df, "write_kib": dw,
+                       "hbm_bytes": df * 1024.0 * ff + dw * 1024.0 * fw},
+    }
+    with open(a.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
