@@ -215,9 +215,10 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     if (P.store & 2) HQ_TRY(dalloc(P, &P.d_rec32, (int64_t)kRecWords * NI));
     if (P.store & 1) HQ_TRY(dalloc(P, &P.d_rec64, (int64_t)kRecWords * NI));
     HQ_TRY(dalloc(P, &P.d_phase, 2 * kMaxPhases));
-    HQ_TRY(dalloc(P, &P.d_prun, 4 * kMaxPhases));
-    // a phase of n nodes uses ceil(n / run_nodes) + 1 entries
-    P.run_cap = NI / P.run_nodes + 2 * (int64_t)kMaxPhases + 4;
+    HQ_TRY(dalloc(P, &P.d_prun, kPrunStride * kMaxPhases));
+    // a phase of n nodes uses ceil(n / tp) + 1 entries, with tp = run_nodes or
+    // fewer than kRunTarget + 1 runs
+    P.run_cap = NI / P.run_nodes + (int64_t)kMaxPhases * (kRunTarget + 3) + 4;
     HQ_TRY(dalloc(P, &P.d_run, P.run_cap));
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));

@@ -917,7 +917,7 @@ __device__ __forceinline__ int wave_max_len(int len) {
 }
 
 template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC>
-__global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_up_wide(
+__global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_up_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
@@ -929,7 +929,7 @@ __global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_up_wide(
     const int R = rhs_count<RT>(C);
     const int lane = threadIdx.x;
     const int tslot = lane / LPT, rl = lane % LPT;
-    const int c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
+    const int c0 = prun[kPrunStride * phase + 2], nrun = prun[kPrunStride * phase + 3];
     const int items = ((nrun + TPW - 1) / TPW) * C.nchunks;
     const WBufs B = wide_bufs<T, RT>(v, out, xch, C);
     int bad = 0;
@@ -1061,7 +1061,7 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
 }
 
 template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC>
-__global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_down_wide(
+__global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_down_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
@@ -1073,7 +1073,7 @@ __global__ void __launch_bounds__(64, sizeof(T) * NC == 4 ? 4 : 2) k_down_wide(
     const int R = rhs_count<RT>(C);
     const int lane = threadIdx.x;
     const int tslot = lane / LPT, rl = lane % LPT;
-    const int c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
+    const int c0 = prun[kPrunStride * phase + 2], nrun = prun[kPrunStride * phase + 3];
     const int items = ((nrun + TPW - 1) / TPW) * C.nchunks;
     const WBufs B = wide_bufs<T, RT>(w, out, xch, C);
     int bad = 0;
@@ -1129,13 +1129,17 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
     if (const char *e = getenv("HQ_LDS_PAD")) lds_w += (size_t)atoll(e);
     // work items: groups of TPW runs (a phase has at most NI / run_nodes + 1
-    // runs) x RHS chunks, one per wave, so the dispatcher balances the load;
-    // waves of later phases with fewer runs exit at once
-    const int64_t items = ((P.NI / P.run_nodes + 2 + TPW - 1) / TPW) * (int64_t)C.nchunks;
-    int64_t g = items;
+    // runs, or kRunTarget + 1 when its runs are shortened) x RHS chunks, one
+    // per wave, so the dispatcher balances the load; waves of later phases
+    // with fewer runs exit at once
+    const int64_t nrun_max = std::max<int64_t>(P.NI / P.run_nodes + 2, kRunTarget + 2);
+    const int64_t items = ((nrun_max + TPW - 1) / TPW) * (int64_t)C.nchunks;
+    // later phases hold few runs (often none, for phases reserved for a
+    // rebuild): a grid of one wave per 2 CUs' worth of slots loops over them
+    int64_t g = (phase == 1) ? items : std::min<int64_t>(items, 4096);
     if (const char *e = getenv("HQ_APPLY_GRID")) g = std::max<int64_t>(1, atoll(e));
     const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
-#define HQ_WIDE(RT, PR, NR, PR1, NR1, NRD)                                                                   \
+#define HQ_WIDE(RT, PR, NR, PR1, NR1, NRD, NRD2)                                                             \
     do {                                                                                                     \
         if (!transpose) {                                                                                    \
             if (phase == 1)                                                                                  \
@@ -1149,12 +1153,16 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
                 hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false, NC>), dim3(grid), dim3(64), lds_w,   \
                                    s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
             else                                                                                             \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, true, NC>), dim3(grid), dim3(64), lds_w,    \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD2, true, NC>), dim3(grid), dim3(64), lds_w,   \
                                    s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
         }                                                                                                    \
     } while (0)
-    if (C.R == 32) HQ_WIDE(32, 6, 2, 6, 3, (NC == 1 ? 3 : 2));
-    else HQ_WIDE(0, 6, 2, 6, 3, (NC == 1 ? 3 : 2));
+    // the first phase carries almost all nodes and wants occupancy; later
+    // phases have few lane groups, each a long dependent chain, and want deep
+    // prefetch (inputs five nodes ahead)
+    constexpr int NRL = sizeof(T) == 4 ? 6 : 3;  // FP64 registers allow three
+    if (C.R == 32) HQ_WIDE(32, 6, NRL, 6, 3, 3, NRL);
+    else HQ_WIDE(0, 6, NRL, 6, 3, 3, NRL);
 #undef HQ_WIDE
 }
 

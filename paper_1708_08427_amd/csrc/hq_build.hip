@@ -507,17 +507,21 @@ __global__ void k_phase_close(int64_t NI, int phase, const long long *trval, con
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
     phase_tab[2 * phase] = cnt[kCntTiles];
     phase_tab[2 * phase + 1] = cnt[kCntTiles] + ntiles;
-    // runs: the phase's schedule range cut at tile starts every ~run_nodes nodes
+    // runs: the phase's schedule range cut at tile starts every ~tp nodes; a
+    // small phase gets shorter runs (down to single tiles) so that it still
+    // spreads over kRunTarget lane groups
+    const int tp = max(1, min(run_nodes, (nnodes + kRunTarget - 1) / kRunTarget));
     const int p0 = cnt[kCntNodes], c0 = cnt[kCntRuns];
-    int nrun = (nnodes + run_nodes - 1) / run_nodes;
+    int nrun = (nnodes + tp - 1) / tp;
     if ((int64_t)c0 + nrun + 1 > run_cap) {
         raise_flag(err, kFlagBounds);
         nrun = -1;
     }
-    prun[4 * phase] = p0;
-    prun[4 * phase + 1] = p0 + nnodes;
-    prun[4 * phase + 2] = c0;
-    prun[4 * phase + 3] = max(nrun, 0);
+    prun[kPrunStride * phase] = p0;
+    prun[kPrunStride * phase + 1] = p0 + nnodes;
+    prun[kPrunStride * phase + 2] = c0;
+    prun[kPrunStride * phase + 3] = max(nrun, 0);
+    prun[kPrunStride * phase + 4] = tp;
     if (nrun >= 0) cnt[kCntRuns] = c0 + nrun + 1;
     cnt[kCntTiles] += ntiles;
     cnt[kCntNodes] += nnodes;
@@ -526,20 +530,21 @@ __global__ void k_phase_close(int64_t NI, int phase, const long long *trval, con
 }
 
 // Run starts of one phase: run c begins at the first tile that starts at or
-// after node c * run_nodes of the phase (phase end if none), so every run
-// holds whole tiles and a lane group can sweep it as one node stream.
-__global__ void k_runs(int phase, int run_nodes, const int32_t *phase_tab, const int32_t *tile_base,
-                       const int32_t *prun, int32_t *run, const int32_t *gate) {
+// after node c * tp of the phase (phase end if none), so every run holds
+// whole tiles and a lane group can sweep it as one node stream.
+__global__ void k_runs(int phase, const int32_t *phase_tab, const int32_t *tile_base, const int32_t *prun,
+                       int32_t *run, const int32_t *gate) {
     if (gate && *gate == 0) return;
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
-    const int p0 = prun[4 * phase], p1 = prun[4 * phase + 1], c0 = prun[4 * phase + 2], nrun = prun[4 * phase + 3];
+    const int *pr = prun + kPrunStride * phase;
+    const int p0 = pr[0], p1 = pr[1], c0 = pr[2], nrun = pr[3], tp = max(pr[4], 1);
     if (nrun == 0 && p1 > p0) return;  // table full: flagged by k_phase_close
     for (int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tt <= te - tb;
          tt += (int64_t)gridDim.x * blockDim.x) {
         const int t = tb + (int)tt;
         const int st = (t < te) ? tile_base[t] - p0 : p1 - p0;
-        const int lo = (t == tb) ? 0 : (tile_base[t - 1] - p0) / run_nodes + 1;
-        const int hi = (t < te) ? min(st / run_nodes, nrun - 1) : nrun;
+        const int lo = (t == tb) ? 0 : (tile_base[t - 1] - p0) / tp + 1;
+        const int hi = (t < te) ? min(st / tp, nrun - 1) : nrun;
         for (int c = lo; c <= hi; ++c) run[c0 + c] = p0 + st;
     }
 }
@@ -949,7 +954,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_sched_node, NI, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, P.d_cnt, (int64_t)kCntNum, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_phase, (int64_t)(2 * kMaxPhases), 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_prun, (int64_t)(4 * kMaxPhases), 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_prun, (int64_t)(kPrunStride * kMaxPhases), 0);
     // --- 1. boxes and codes
     hipLaunchKernelGGL(k_bbox, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, P.d_bmin, P.d_bmax, P.d_err);
     hipLaunchKernelGGL(k_codes, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, P.d_bead_off, pos, P.d_bmin,
@@ -1012,8 +1017,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, ph, P.d_trval, P.d_trscan, P.d_cnt,
                            P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
         // the run table of a phase is built when the phase holds nodes
-        hipLaunchKernelGGL(k_runs, dim3(std::min(grid_for(NI), 1024u)), dim3(kThreads), 0, s, ph, P.run_nodes,
-                           P.d_phase, P.d_tile_base, P.d_prun, P.d_run, P.d_prun + 4 * ph + 1);
+        hipLaunchKernelGGL(k_runs, dim3(std::min(grid_for(NI), 1024u)), dim3(kThreads), 0, s, ph, P.d_phase,
+                           P.d_tile_base, P.d_prun, P.d_run, P.d_prun + kPrunStride * ph + 1);
         HQ_HIP(hipGetLastError());
         phases = ph;
         if (probe_phases) {

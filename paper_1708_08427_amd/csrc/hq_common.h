@@ -120,6 +120,12 @@ inline int stack_depth(int S) { return floor_log2(S) + 2; }
 // results of a tile.
 inline int stack_slots(int S) { return floor_log2(S) + 1; }
 
+// Run table: per phase (node begin, node end, first entry, runs, run length)
+// at stride kPrunStride; a phase is cut into at least ~kRunTarget runs when it
+// has that many tiles.
+constexpr int kPrunStride = 8;
+constexpr int kRunTarget = 16384;
+
 // ---------------------------------------------------------------------------
 // the plan behind a handle
 // ---------------------------------------------------------------------------
@@ -205,7 +211,7 @@ struct Plan {
     double *d_troot = nullptr;       // tiles x 10: (n, c[3], T22[6]) of tile roots
 
     int32_t *d_phase = nullptr;      // 2 x kMaxPhases: [begin, end) tile ids per phase
-    int32_t *d_prun = nullptr;       // 4 x kMaxPhases: node begin, node end, first run entry, runs
+    int32_t *d_prun = nullptr;       // kPrunStride x kMaxPhases: node begin, node end, first run entry, runs, run length
     int32_t *d_run = nullptr;        // run_cap: first schedule index of each run (+ one end entry per phase)
     int32_t *d_cnt = nullptr;        // counters
     int32_t *d_err = nullptr;        // device error flags

@@ -33,8 +33,8 @@ def sweep_source_hash() -> str:
 
 def _read(dirname, counter):
     files = glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise FileNotFoundError(f"no counter_collection.csv under {dirname}")
+    if len(files) != 1:
+        raise FileNotFoundError(f"expected one counter_collection.csv under {dirname}, found {files}")
     per = {}
     for fn in files:
         with open(fn) as fh:
