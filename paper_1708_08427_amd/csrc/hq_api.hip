@@ -201,12 +201,6 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_nn, NI));
     HQ_TRY(dalloc(P, &P.d_ncen, 3 * NI));
     HQ_TRY(dalloc(P, &P.d_T22, 6 * NI));
-    HQ_TRY(dalloc(P, &P.d_kapn, NI));
-    HQ_TRY(dalloc(P, &P.d_depth, NI));
-    HQ_TRY(dalloc(P, &P.d_bydepth, NI));
-    HQ_TRY(dalloc(P, &P.d_dhist, (int64_t)(kMaxDepth + 1) * kDepthBlocksHost));
-    HQ_TRY(dalloc(P, &P.d_dincl, (int64_t)(kMaxDepth + 1) * kDepthBlocksHost));
-    HQ_TRY(dalloc(P, &P.d_dstart, kMaxDepth + 2));
     HQ_TRY(dalloc(P, &P.d_tile_root, NI));
     HQ_TRY(dalloc(P, &P.d_tile_base, NI));
     HQ_TRY(dalloc(P, &P.d_tile_len, NI));
@@ -223,7 +217,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));
     HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
-    P.scan_blk_cap = scan_blocks_needed(std::max<int64_t>(std::max(N, NI), (int64_t)(kMaxDepth + 1) * kDepthBlocksHost)) + 8;
+    P.scan_blk_cap = scan_blocks_needed(std::max(N, NI)) + 8;
     HQ_TRY(dalloc(P, &P.d_scan_blk, P.scan_blk_cap));
     return HQ_OK;
 }
@@ -664,9 +658,9 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
         const int kk = 3 + 3 * (lc[g] >= 0) + 3 * (rc[g] >= 0);
         if (k) k[g] = kk;
         if (centroid)
-            for (int d = 0; d < 3; ++d) centroid[3 * g + d] = cen[3 * g + d];
+            for (int d = 0; d < 3; ++d) centroid[3 * g + d] = cen[3 * (size_t)sched[g] + d];
         if (T22) {
-            const double *t = &t22[6 * g];
+            const double *t = &t22[6 * (size_t)sched[g]];
             double M[9] = {t[0], 0, 0, t[1], t[2], 0, t[3], t[4], t[5]};
             std::memcpy(T22 + 9 * g, M, sizeof M);
         }

@@ -19,6 +19,7 @@
 // of the tile live on a per-lane stack in LDS; a tile root exchanges its
 // 6-vector with the tile above through a global exchange buffer.  Tiles of one
 // phase are independent; phases run as separate launches.
+#include "hq_buffer.h"
 #include "hq_common.h"
 
 #include <cstdlib>
@@ -478,15 +479,6 @@ __global__ void __launch_bounds__(64) k_down(int phase, const int32_t *__restric
 // compiler can wait for exactly the loads a node needs instead of draining
 // the stores of earlier nodes.  Each buffer must stay below 2 GiB.
 // ---------------------------------------------------------------------------
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr uint32_t kOOB = 0x80000000u;  // byte offset past the end of every buffer of a wide sweep
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
 
 template <typename T>
 __device__ __forceinline__ T bld(rsrc_t r, uint32_t vo, uint32_t so);
@@ -685,7 +677,9 @@ __device__ __forceinline__ void bstn(const T (&m)[NC], rsrc_t r, uint32_t vo, ui
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(m[0]), __float_as_uint(m[1])}, r, vo, so, 0);
     } else {
         const u32x2 a = __builtin_bit_cast(u32x2, m[0]), b = __builtin_bit_cast(u32x2, m[1]);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, so, 0);
+        // wider than 64 bits: the offset goes into the vector offset (an SGPR
+        // offset lets the next instruction overwrite the data register early)
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo == kOOB ? kOOB : vo + so, 0, 0);
     }
 }
 

@@ -14,6 +14,7 @@
 //      [c_x - c_y]x] (Eq. 3.5 with the leaf cases of Cases I and II) and its
 //      Householder QR, giving T22 and G (Eqs. 3.6-3.8); FP64 and FP32 records
 //      in schedule order.
+#include "hq_buffer.h"
 #include "hq_common.h"
 
 #include <climits>
@@ -559,7 +560,7 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
                         const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
                         const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
                         const int32_t *perm, const int32_t *row_off, const int32_t *depth_slot, int dstack,
-                        const int2 *lw, int32_t *links, int32_t *depth, int32_t *err) {
+                        const int2 *lw, int32_t *links, int32_t *err) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
         if (cov[g] == 0) continue;
@@ -572,16 +573,14 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
             else if (cov[x] == cov[g] && tileof[x] == t) ref[c] = kRefStack;
             else ref[c] = -2 - tileof[x];
         }
-        int off = 0, q = g, dep = 0;
+        int off = 0, q = g;
         for (int guard = 0; guard <= kMaxDepth; ++guard) {
             if (guard == kMaxDepth) {
                 raise_flag(err, kFlagBounds);
-                dep = -1;
                 break;
             }
             const int2 w = lw[q];
             if (w.x < 0) break;
-            ++dep;
             off += w.y;
             q = w.x;
         }
@@ -610,20 +609,45 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
         links[kLinkInts * s + 2] = off;
         links[kLinkInts * s + 3] = meta;
         links[kLinkInts * s + 4] = xs | (ys << 8) | (os << 16);
-        links[kLinkInts * s + 5] = 0;
-        depth[g] = dep;
+        links[kLinkInts * s + 5] = g;
     }
 }
 
 // ---------------------------------------------------------------------------
-// 5. FP64 transforms (Eqs. 3.4-3.13), one lane per tile, nodes in schedule order
+// 5. FP64 transforms (Eqs. 3.4-3.13)
 // ---------------------------------------------------------------------------
+// Reciprocal and square root from the hardware approximations refined by
+// Newton steps (two for the reciprocal, one coupled step for the root),
+// which leaves them within about an ulp of the rounded values at a third of
+// the instructions of the IEEE sequences; arguments here are positive and
+// normal.
+__device__ __forceinline__ double rcp_nr(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 // Condition number of the lower-triangular T22 (its singular values are
 // those of K).  With S = T^T T, the smallest eigenvalue is the first root of
-// the characteristic cubic, reached from 0 by Newton's method (the cubic is
-// convex there); the largest is bounded by trace(S).  Returns
+// the characteristic cubic, approached from 0 by Newton's method: the cubic
+// is convex there, so the iterates stay below the root and the result stays
+// an upper bound (six steps leave it within 4% of the converged value, also
+// for a double root).  The largest is bounded by trace(S).  Returns
 // sqrt(trace / lambda_min), an upper bound of sigma_1 / sigma_3 within a
-// factor sqrt(3); a huge value for a singular T22.
+// factor 1.04 sqrt(3); a huge value for a singular T22.
 __device__ double cond_bound3(const double T[6]) {
     const double a = T[0], b = T[1], c = T[2], d = T[3], e = T[4], f = T[5];
     const double s00 = a * a + b * b + d * d, s01 = b * c + d * e, s02 = d * f;
@@ -635,13 +659,13 @@ __device__ double cond_bound3(const double T[6]) {
     if (!(c0 > 0.0) || !(c2 > 0.0)) return 1e300;
     double lam = 0.0;
 #pragma unroll
-    for (int it = 0; it < 12; ++it) {
+    for (int it = 0; it < 6; ++it) {
         const double p = ((-lam + c2) * lam - c1) * lam + c0;
         const double dp = (-3.0 * lam + 2.0 * c2) * lam - c1;
-        lam -= p / dp;
+        lam = fma(-p, rcp_nr(dp), lam);
     }
     if (!(lam > 0.0)) return 1e300;
-    return sqrt(c2 / lam);
+    return sqrt_nr(c2 * rcp_nr(lam));
 }
 
 // Transforms of one node (Eqs. 3.4-3.13).  A = K^T with the blocks of
@@ -661,258 +685,364 @@ __device__ __forceinline__ void put_shift(double (&A)[9][3], int r0, double sc, 
     A[r0 + 2][0] = sc * dv[1];   A[r0 + 2][1] = -sc * dv[0];  A[r0 + 2][2] = 0.0;
 }
 
-// Record words of the node in LDS row `row` (stride kGenStride): the three
-// reflector tails, taus, translation weights (elements 0..25) and the links.
-constexpr int kGenThreads = 256;
-constexpr int kGenStride = 33;  // words per LDS row (odd: no bank conflicts)
+// Householder QR of A (9 x 3, rows beyond k zero) in place, LAPACK sign
+// convention (tau = 0 for a zero tail): the scaled tail of reflector j
+// replaces column j below the diagonal; T = R^T packed lower-triangular.
+__device__ __forceinline__ void householder_qr(double (&A)[9][3], double (&tau)[3], double (&T)[6], int k) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double alpha = A[j][j];
+        double xs = 0.0;
+#pragma unroll
+        for (int r = j + 1; r < 9; ++r) xs = fma(A[r][j], A[r][j], xs);
+        if (xs == 0.0) {
+            tau[j] = 0.0;
+            continue;
+        }
+        const double nrm = sqrt_nr(fma(alpha, alpha, xs));
+        const double beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau[j] = (beta - alpha) * rcp_nr(beta);
+        const double scal = rcp_nr(alpha - beta);
+#pragma unroll
+        for (int r = j + 1; r < 9; ++r) A[r][j] *= scal;
+        A[j][j] = beta;
+#pragma unroll
+        for (int l = j + 1; l < 3; ++l) {
+            double w = A[j][l];
+#pragma unroll
+            for (int r = j + 1; r < 9; ++r) w = fma(A[r][j], A[r][l], w);
+            w *= tau[j];
+            A[j][l] -= w;
+#pragma unroll
+            for (int r = j + 1; r < 9; ++r) A[r][l] = fma(-w, A[r][j], A[r][l]);
+        }
+    }
+    T[0] = A[0][0];
+    T[1] = A[0][1];
+    T[2] = A[1][1];
+    T[3] = A[0][2];
+    T[4] = A[1][2];
+    T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
+}
 
-__global__ void __launch_bounds__(kGenThreads) k_gen_level(int level, const int32_t *dstart, const int32_t *bydepth,
-                                                           const int32_t *sched, const int32_t *links,
-                                                           const int32_t *lc, const int32_t *rc,
-                                                           const int32_t *nbody, const int32_t *nn_arr,
-                                                           const double *pos, const double *lo, double *ncen,
-                                                           double *T22, float *rec32, double *rec64, int store,
-                                                           double *bcen, double *kapn, int32_t *bflags, int64_t N,
-                                                           int64_t NI, int32_t *err) {
-    __shared__ uint32_t srec[kGenThreads * kGenStride];
-    __shared__ int32_t sdst[kGenThreads];
-    const int i0 = dstart[level], i1 = dstart[level + 1];
-    const int tid = threadIdx.x;
-    for (int base = i0 + blockIdx.x * kGenThreads; base < i1; base += gridDim.x * kGenThreads) {
-        const int i = base + tid;
-        int s = -1;
-        if (i < i1) {
-            const int g = bydepth[i];
-            const int s0 = (g >= 0 && g < NI) ? sched[g] : -1;
-            if (s0 < 0 || s0 >= NI) {
-                raise_flag(err, kFlagBounds);
+// ---------------------------------------------------------------------------
+// Transforms tile by tile: one lane per tile of a phase walks the tile's nodes
+// in schedule order (children before parents, the order of the upward sweep).
+// A child of the same tile is read from the lane's LDS slot (the slot numbers
+// of the wide sweeps), the root of an earlier phase's tile from the tile-root
+// table, a bead from the positions.  The loop is software-pipelined: while a
+// node is computed, the children of the next node and the links of the one
+// after it are in flight.
+// ---------------------------------------------------------------------------
+constexpr int kGenWords = 10;  // n, c[3], T22[6] per LDS slot and lane, and per tile root
+
+struct GenIn {
+    double n, c[3], T[6];
+};
+
+__device__ __forceinline__ void gen_slot_put(double *lds, int slot, int lane, double n, const double (&c)[3],
+                                             const double (&T)[6]) {
+    double *p = lds + slot * kGenWords * 64 + lane;
+    p[0] = n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[(1 + d) * 64] = c[d];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) p[(4 + d) * 64] = T[d];
+}
+
+__device__ __forceinline__ void gen_slot_get(const double *lds, int slot, int lane, GenIn &o) {
+    const double *p = lds + slot * kGenWords * 64 + lane;
+    o.n = p[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o.c[d] = p[(1 + d) * 64];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) o.T[d] = p[(4 + d) * 64];
+}
+
+// Child data that lives in HBM: a bead (n = 1, absolute position, T22 = 0)
+// or, after the first phase, an earlier tile's root (n, body-local centroid,
+// T22).  The loads are issued unconditionally from clamped addresses and the
+// result is selected afterwards, so no branch separates a load from its use
+// (a same-tile child is replaced by the LDS read at compute time).
+template <bool kLater>
+__device__ __forceinline__ void gen_fetch(int ref, const double *pos, const double *troot, int64_t N, int64_t ntr,
+                                          GenIn &o, bool &bad) {
+    const bool bead = ref >= 0;
+    bad |= ref >= N || (!kLater && ref < kRefStack) || (ref < kRefStack && ref_slot(ref) >= ntr);
+    const int64_t u = bead ? min((int64_t)ref, N - 1) : 0;
+    double p[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[d] = pos[3 * u + d];
+    if (!kLater) {
+        o.n = 1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o.c[d] = p[d];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) o.T[d] = 0.0;
+        return;
+    }
+    const int64_t t = (ref < kRefStack) ? min((int64_t)ref_slot(ref), ntr - 1) : 0;
+    const double *q = troot + kGenWords * t;
+    double w[kGenWords];
+#pragma unroll
+    for (int e = 0; e < kGenWords; ++e) w[e] = q[e];
+    o.n = bead ? 1.0 : w[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o.c[d] = bead ? p[d] : w[1 + d];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) o.T[d] = bead ? 0.0 : w[4 + d];
+}
+
+// A same-tile child from the LDS slot (read unconditionally, then selected);
+// a bead's position made body-local.
+__device__ __forceinline__ void gen_child_fix(int ref, int slot, const double *lds, int lane, const double (&lo3)[3],
+                                              GenIn &o) {
+    GenIn l;
+    gen_slot_get(lds, slot, lane, l);
+    const bool st = ref == kRefStack, bead = ref >= 0;
+    o.n = st ? l.n : o.n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o.c[d] = st ? l.c[d] : (bead ? o.c[d] - lo3[d] : o.c[d]);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) o.T[d] = st ? l.T[d] : o.T[d];
+}
+
+__device__ __forceinline__ void load_links(const int32_t *links, int64_t s, int32_t (&li)[kLinkInts]) {
+    const int4 a = *reinterpret_cast<const int4 *>(links + kLinkInts * s);
+    const int2 b = *reinterpret_cast<const int2 *>(links + kLinkInts * s + 4);
+    li[0] = a.x;
+    li[1] = a.y;
+    li[2] = a.z;
+    li[3] = a.w;
+    li[4] = b.x;
+    li[5] = b.y;
+}
+
+// The stores of one node; an index of kOOB switches a group off.  The
+// prologue of the node loop issues the same stores switched off, so that the
+// compiler sees the same number of stores in flight on entry to the loop as
+// on its back edge and waits for loads only.
+template <int kStore>
+__device__ __forceinline__ void gen_store(rsrc_t r32, rsrc_t r64, rsrc_t rcen, rsrc_t rt22, rsrc_t rtr, rsrc_t rbc,
+                                          uint32_t rel, uint32_t trel, uint32_t brel, const float (&w32)[26],
+                                          const double (&w64)[26], const int32_t (&li)[kLinkInts],
+                                          const double (&cp)[3], const double (&T)[6], const double (&tv)[kGenWords],
+                                          const double (&bc)[3]) {
+    auto scaled = [](uint32_t i, uint32_t b) { return i == kOOB ? kOOB : i * b; };
+    if (kStore & 2) {
+        const uint32_t o = scaled(rel, 128u);
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(w32[4 * q]), __float_as_uint(w32[4 * q + 1]),
+                                                         __float_as_uint(w32[4 * q + 2]),
+                                                         __float_as_uint(w32[4 * q + 3])},
+                                                   r32, o + 16 * q, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(
+            u32x4{__float_as_uint(w32[24]), __float_as_uint(w32[25]), (uint32_t)li[0], (uint32_t)li[1]}, r32, o + 96,
+            0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{(uint32_t)li[2], (uint32_t)li[3], (uint32_t)li[4], (uint32_t)li[5]},
+                                               r32, o + 112, 0, 0);
+    }
+    if (kStore & 1) {
+        const uint32_t o = scaled(rel, 256u);
+#pragma unroll
+        for (int e = 0; e < 13; ++e) {
+            const u32x2 a = __builtin_bit_cast(u32x2, w64[2 * e]), b = __builtin_bit_cast(u32x2, w64[2 * e + 1]);
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r64, o + 16 * e, 0, 0);
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{(uint32_t)li[0], (uint32_t)li[1], (uint32_t)li[2], (uint32_t)li[3]},
+                                               r64, o + 208, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)li[4], (uint32_t)li[5]}, r64, o + 224, 0, 0);
+    }
+    const uint32_t oc = scaled(rel, 24u), ot = scaled(rel, 48u);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, cp[d]), rcen, oc + 8 * d, 0, 0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, T[d]), rt22, ot + 8 * d, 0, 0);
+    // tile root: (n, c, T22) for the phases above
+    const uint32_t otr = scaled(trel, 80u);
+#pragma unroll
+    for (int e = 0; e < kGenWords; ++e)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, tv[e]), rtr, otr + 8 * e, 0, 0);
+    // body root: the body's centroid (absolute)
+    const uint32_t ob = scaled(brel, 24u);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, bc[d]), rbc, ob + 8 * d, 0, 0);
+}
+
+// Records, node data and tile-root entries leave through buffer stores whose
+// resources start at the wave's first tile (all of a wave's tiles follow it
+// in schedule order, tile order and body order, so offsets stay far below
+// 2 GiB); a lane with nothing to write gets the offset kOOB.  Every store is
+// therefore issued unconditionally and waiting for the next node's children
+// never waits for this node's stores.
+template <bool kLater, int kStore>
+__global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase_tab, const int32_t *tile_base,
+                                                 const int32_t *tile_len, const int32_t *tile_root,
+                                                 const int32_t *links, const int32_t *nbody, const double *pos,
+                                                 const double *lo, double *troot, int64_t ntr, int nslot,
+                                                 double *ncen, double *T22, float *rec32, double *rec64,
+                                                 double *bcen, unsigned long long *kappa, int32_t *bflags,
+                                                 int64_t m, int64_t N, int64_t NI, int32_t *err) {
+    extern __shared__ unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);
+    const int lane = threadIdx.x;
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    bool bad = false;
+    for (int t0 = tb + blockIdx.x * 64; t0 < te; t0 += gridDim.x * 64) {
+        const int t = t0 + lane;
+        int s = 0, se = 0, body = 0;
+        if (t < te) {
+            const int base = tile_base[t], len = tile_len[t], r = tile_root[t];
+            if (base < 0 || len < 1 || (int64_t)base + len > NI || r < 0 || r >= NI) {
+                bad = true;
             } else {
-                s = s0;
-                const int body = nbody[g];
-                const int32_t *lk = links + kLinkInts * (int64_t)s;
-                int32_t li[kLinkInts];
-#pragma unroll
-                for (int q = 0; q < kLinkInts; ++q) li[q] = lk[q];
-                const int x = lc[g], y = rc[g];
-                const bool xi = x >= 0, yi = y >= 0;
-                double cx[3], cy[3], Tx[6], Ty[6];
-                double nx = 1.0, ny = 1.0;
-                bool bad = false;
-                if (xi) {
-                    nx = (double)nn_arr[x];
-                    for (int d = 0; d < 3; ++d) cx[d] = ncen[3 * (int64_t)x + d];
-                    for (int d = 0; d < 6; ++d) Tx[d] = T22[6 * (int64_t)x + d];
-                } else {
-                    const int u = li[0];
-                    if (u < 0 || u >= N) bad = true;
-                    for (int d = 0; d < 3; ++d) cx[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
-                }
-                if (yi) {
-                    ny = (double)nn_arr[y];
-                    for (int d = 0; d < 3; ++d) cy[d] = ncen[3 * (int64_t)y + d];
-                    for (int d = 0; d < 6; ++d) Ty[d] = T22[6 * (int64_t)y + d];
-                } else {
-                    const int u = li[1];
-                    if (u < 0 || u >= N) bad = true;
-                    for (int d = 0; d < 3; ++d) cy[d] = bad ? 0.0 : pos[3 * (int64_t)u + d] - lo[3 * body + d];
-                }
-                if (bad) raise_flag(err, kFlagBounds);
-                const double n = nx + ny;
-                double cp[3], dv[3];
-                for (int d = 0; d < 3; ++d) {
-                    cp[d] = (nx * cx[d] + ny * cy[d]) / n;
-                    dv[d] = cx[d] - cy[d];
-                }
-                const double sc = sqrt(nx * ny / n);
-                double A[9][3];
-#pragma unroll
-                for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
-                int k;
-                if (xi && yi) {
-                    put_lower(A, 0, Tx);
-                    put_lower(A, 3, Ty);
-                    put_shift(A, 6, sc, dv);
-                    k = 9;
-                } else if (xi) {
-                    put_lower(A, 0, Tx);
-                    put_shift(A, 3, sc, dv);
-                    k = 6;
-                } else if (yi) {
-                    put_lower(A, 0, Ty);
-                    put_shift(A, 3, sc, dv);
-                    k = 6;
-                } else {
-                    put_shift(A, 0, sc, dv);
-                    k = 3;
-                }
-                // Householder QR of A in place (LAPACK sign convention; tau = 0
-                // for a zero tail): the scaled tail of reflector j replaces
-                // column j below the diagonal
-                double tau[3];
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double alpha = A[j][j];
-                    double xs = 0.0;
-#pragma unroll
-                    for (int r = j + 1; r < 9; ++r) xs = fma(A[r][j], A[r][j], xs);
-                    if (xs == 0.0) {
-                        tau[j] = 0.0;
-                        continue;
-                    }
-                    const double nrm = sqrt(fma(alpha, alpha, xs));
-                    const double beta = (alpha >= 0.0) ? -nrm : nrm;
-                    tau[j] = (beta - alpha) / beta;
-                    const double scal = 1.0 / (alpha - beta);
-#pragma unroll
-                    for (int r = j + 1; r < 9; ++r) A[r][j] *= scal;
-                    A[j][j] = beta;
-#pragma unroll
-                    for (int l = j + 1; l < 3; ++l) {
-                        double w = A[j][l];
-#pragma unroll
-                        for (int r = j + 1; r < 9; ++r) w = fma(A[r][j], A[r][l], w);
-                        w *= tau[j];
-                        A[j][l] -= w;
-#pragma unroll
-                        for (int r = j + 1; r < 9; ++r) A[r][l] = fma(-w, A[r][j], A[r][l]);
-                    }
-                }
-                double T[6];
-                T[0] = A[0][0];
-                T[1] = A[0][1];
-                T[2] = A[1][1];
-                T[3] = A[0][2];
-                T[4] = A[1][2];
-                T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
-                for (int d = 0; d < 3; ++d) ncen[3 * (int64_t)g + d] = cp[d];
-                for (int d = 0; d < 6; ++d) T22[6 * (int64_t)g + d] = T[d];
-                const double sx = sqrt(nx / n);
-                const double sy = sqrt(ny / n);
-                // record element e: reflector tails (below the diagonal of A),
-                // taus, translation weights
-                auto word = [&](int e) -> double {
-                    if (e < 8) return A[1 + e][0];
-                    if (e < 15) return A[2 + (e - 8)][1];
-                    if (e < 21) return A[3 + (e - 15)][2];
-                    if (e < 24) return tau[e - 21];
-                    return e == 24 ? sx : sy;
-                };
-                if (store & 2) {
-                    uint32_t *row = srec + tid * kGenStride;
-#pragma unroll
-                    for (int e = 0; e < 26; ++e) row[e] = __float_as_uint((float)word(e));
-#pragma unroll
-                    for (int e = 0; e < kLinkInts; ++e) row[26 + e] = (uint32_t)li[e];
-                }
-                if (store & 1) {
-                    double2 *o = reinterpret_cast<double2 *>(rec64 + (int64_t)kRecWords * s);
-#pragma unroll
-                    for (int e = 0; e < 13; ++e) o[e] = make_double2(word(2 * e), word(2 * e + 1));
-                    int2 *ol = reinterpret_cast<int2 *>(rec64 + (int64_t)kRecWords * s + kRecLinks);
-#pragma unroll
-                    for (int e = 0; e < kLinkInts / 2; ++e) ol[e] = make_int2(li[2 * e], li[2 * e + 1]);
-                }
-                const bool body_root = (li[3] & kMetaBodyRoot) != 0;
-                const double kap = (k > 3) ? cond_bound3(T) : 1e300;
-                kapn[g] = (k > 3) ? kap : 0.0;
-                if (body_root) {
-                    if (kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
-                    for (int d = 0; d < 3; ++d) bcen[3 * body + d] = cp[d] + lo[3 * body + d];
-                }
+                s = base;
+                se = base + len;
+                body = nbody[r];
             }
         }
-        if (!(store & 2)) continue;
-        // float records leave through LDS so that each one is written as a
-        // whole 128-byte line (two records per wave-wide store)
-        sdst[tid] = s;
-        __syncthreads();
-        const int lane = tid & 63, wv = tid >> 6, half = lane >> 5, q = lane & 31;
-#pragma unroll 4
-        for (int kk = 0; kk < 32; ++kk) {
-            const int rl = wv * 64 + 2 * kk + half;
-            const int sd = sdst[rl];
-            if (sd >= 0) reinterpret_cast<uint32_t *>(rec32)[(int64_t)kRecWords * sd + q] = srec[rl * kGenStride + q];
+        if (body < 0 || body >= m) {
+            bad = true;
+            s = se = body = 0;
         }
-        __syncthreads();
-    }
-}
-
-// Per body: the largest node condition bound (node values of k = 3 are 0)
-// and the ill-conditioning flag; one block per body, no atomics.
-__global__ void __launch_bounds__(256) k_body_kappa(int64_t m, const int32_t *node_off, const double *kapn,
-                                                    unsigned long long *kappa, int32_t *bflags) {
-    __shared__ double red[256];
-    for (int64_t j = blockIdx.x; j < m; j += gridDim.x) {
-        double mx = 0.0;
-        for (int g = node_off[j] + threadIdx.x; g < node_off[j + 1]; g += blockDim.x) mx = fmax(mx, kapn[g]);
-        red[threadIdx.x] = mx;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-            __syncthreads();
+        // wave-uniform bases: the first tile's schedule index, tile id, body
+        const int s0 = __builtin_amdgcn_readfirstlane(s);
+        const int b0 = __builtin_amdgcn_readfirstlane(body);
+        // every offset below stays under 2 GiB: at most 2^23 records of 256 B
+        // and 2^24 bodies of 24 B from the wave's bases
+        if (s < se && (s < s0 || se - s0 > (1 << 23) || body < b0 || body - b0 > (1 << 24))) {
+            bad = true;
+            s = se = 0;
         }
-        if (threadIdx.x == 0) {
-            kappa[j] = (unsigned long long)__double_as_longlong(red[0]);
-            if (red[0] > 1e4) bflags[j] |= HQ_BODY_ILLCOND;
+        // byte sizes in integer arithmetic, capped below 2 GiB
+        auto cap = [](int64_t bytes) -> uint32_t {
+            return bytes <= 0 ? 0u : (bytes >= 0x7fffffffll ? 0x7fffffffu : (uint32_t)bytes);
+        };
+        const int64_t t0c = t0 < ntr ? t0 : ntr;
+        const rsrc_t r32 = make_rsrc_uniform(rec32 + (int64_t)kRecWords * s0, cap((NI - s0) * 128));
+        const rsrc_t r64 = make_rsrc_uniform(rec64 + (int64_t)kRecWords * s0, cap((NI - s0) * 256));
+        const rsrc_t rcen = make_rsrc_uniform(ncen + 3 * (int64_t)s0, cap((NI - s0) * 24));
+        const rsrc_t rt22 = make_rsrc_uniform(T22 + 6 * (int64_t)s0, cap((NI - s0) * 48));
+        const rsrc_t rtr = make_rsrc_uniform(troot + kGenWords * t0c, cap((ntr - t0c) * 80));
+        const rsrc_t rbc = make_rsrc_uniform(bcen + 3 * (int64_t)b0, cap((m - b0) * 24));
+        double lo3[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lo3[d] = lo[3 * body + d];
+        double kmax = 0.0;
+        bool deg = false;
+        // pipeline: the links two nodes ahead and the children one node ahead
+        // are in flight while a node is computed
+        int32_t li[kLinkInts], ln[kLinkInts];
+        load_links(links, min((int64_t)s, NI - 1), li);
+        GenIn cx, cy;
+        bool bad0 = false;
+        gen_fetch<kLater>(li[0], pos, troot, N, ntr, cx, bad0);
+        gen_fetch<kLater>(li[1], pos, troot, N, ntr, cy, bad0);
+        bad |= s < se && bad0;
+        load_links(links, min((int64_t)s + 1, NI - 1), ln);
+        {
+            const float z32[26] = {};
+            const double z64[26] = {}, z3[3] = {}, z6[6] = {}, z10[kGenWords] = {};
+            gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, kOOB, kOOB, kOOB, z32, z64, li, z3, z6, z10, z3);
         }
-        __syncthreads();
+        while (__ballot(s < se)) {
+            const bool act = s < se, actn = s + 1 < se;
+            GenIn cxn, cyn;
+            bool badn = false;
+            gen_fetch<kLater>(ln[0], pos, troot, N, ntr, cxn, badn);
+            gen_fetch<kLater>(ln[1], pos, troot, N, ntr, cyn, badn);
+            bad |= actn && badn;
+            int32_t lnn[kLinkInts];
+            load_links(links, min((int64_t)s + 2, NI - 1), lnn);
+            // --- this node (Eqs. 3.4-3.13)
+            const int xs = min(li[4] & 0xff, nslot - 1), ys = min((li[4] >> 8) & 0xff, nslot - 1);
+            const int os = min((li[4] >> 16) & 0xff, nslot - 1);
+            gen_child_fix(li[0], xs, lds, lane, lo3, cx);
+            gen_child_fix(li[1], ys, lds, lane, lo3, cy);
+            const bool xi = li[0] < 0, yi = li[1] < 0;
+            const double n = cx.n + cy.n, rn = rcp_nr(n);
+            double cp[3], dv[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                cp[d] = (cx.n * cx.c[d] + cy.n * cy.c[d]) * rn;
+                dv[d] = cx.c[d] - cy.c[d];
+            }
+            const double sc = sqrt_nr(cx.n * cy.n * rn);
+            double A[9][3];
+#pragma unroll
+            for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
+            int k;
+            if (xi && yi) {
+                put_lower(A, 0, cx.T);
+                put_lower(A, 3, cy.T);
+                put_shift(A, 6, sc, dv);
+                k = 9;
+            } else if (xi) {
+                put_lower(A, 0, cx.T);
+                put_shift(A, 3, sc, dv);
+                k = 6;
+            } else if (yi) {
+                put_lower(A, 0, cy.T);
+                put_shift(A, 3, sc, dv);
+                k = 6;
+            } else {
+                put_shift(A, 0, sc, dv);
+                k = 3;
+            }
+            double tau[3], T[6];
+            householder_qr(A, tau, T, k);
+            const double sx = sqrt_nr(cx.n * rn), sy = sqrt_nr(cy.n * rn);
+            const double kap = (k > 3) ? cond_bound3(T) : 0.0;
+            auto word = [&](int e) -> double {
+                if (e < 8) return A[1 + e][0];
+                if (e < 15) return A[2 + (e - 8)][1];
+                if (e < 21) return A[3 + (e - 15)][2];
+                if (e < 24) return tau[e - 21];
+                return e == 24 ? sx : sy;
+            };
+            const bool troot_node = (li[3] & kMetaTileRoot) != 0, body_root = (li[3] & kMetaBodyRoot) != 0;
+            // the result waits in the node's slot for its parent (a tile
+            // root's slot is never read again, nor is an idle lane's)
+            gen_slot_put(lds, os, lane, n, cp, T);
+            if (act) {
+                kmax = fmax(kmax, kap);
+                deg |= body_root && (k == 3 || kap > 1e12);
+            }
+            // --- stores of this node
+            {
+                float w32[26];
+                double w64[26];
+#pragma unroll
+                for (int e = 0; e < 26; ++e) {
+                    w64[e] = word(e);
+                    w32[e] = (float)w64[e];
+                }
+                const int64_t tr = li[3] >> kMetaSlotShift;
+                const bool wr = act && troot_node && tr == t && t < ntr;
+                bad |= act && troot_node && (tr != t || t >= ntr);
+                const uint32_t rel = (uint32_t)(s - s0);
+                const double tv[kGenWords] = {n, cp[0], cp[1], cp[2], T[0], T[1], T[2], T[3], T[4], T[5]};
+                const double bc[3] = {cp[0] + lo3[0], cp[1] + lo3[1], cp[2] + lo3[2]};
+                gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - t0) : kOOB,
+                                  (act && body_root) ? (uint32_t)(body - b0) : kOOB, w32, w64, li, cp, T, tv, bc);
+            }
+#pragma unroll
+            for (int q = 0; q < kLinkInts; ++q) {
+                li[q] = ln[q];
+                ln[q] = lnn[q];
+            }
+            cx = cxn;
+            cy = cyn;
+            ++s;
+        }
+        if (t < te && kmax > 0.0) {
+            atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kmax));
+            if (kmax > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
+        }
+        if (deg) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
     }
-}
-
-// Nodes bucketed by depth below their body root, so that a launch per depth
-// (deepest first) finds both children of every node already done.  Counting
-// sort in three passes: per-block histograms, one scan over (depth, block),
-// and a scatter; no contended global atomics.
-constexpr int kDepthBins = kMaxDepth + 1;
-constexpr int kDepthBlocks = kDepthBlocksHost;
-
-__global__ void __launch_bounds__(256) k_depth_hist(int64_t NI, const int32_t *depth, int32_t *hist) {
-    __shared__ int32_t h[kDepthBins];
-    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const int64_t C = (NI + kDepthBlocks - 1) / kDepthBlocks;
-    const int64_t g0 = (int64_t)blockIdx.x * C, g1 = min(NI, g0 + C);
-    for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-        const int d = depth[g];
-        if (d >= 0 && d < kDepthBins) atomicAdd(&h[d], 1);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) hist[i * kDepthBlocks + blockIdx.x] = h[i];
-}
-
-__global__ void k_depth_starts(const int32_t *hist, const int32_t *incl, int32_t *dstart, int32_t *cnt) {
-    // one block of 256 threads: bin i starts at the exclusive prefix of (i, block 0)
-    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x)
-        dstart[i] = incl[i * kDepthBlocks] - hist[i * kDepthBlocks];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int tot = incl[kDepthBins * kDepthBlocks - 1];
-        dstart[kDepthBins] = tot;
-        int dmax = 0;
-        for (int i = 0; i < kDepthBins; ++i)
-            if (dstart[i + 1] > dstart[i]) dmax = i;
-        cnt[kCntMaxDepth] = dmax;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_depth_scatter(int64_t NI, const int32_t *depth, const int32_t *hist,
-                                                       const int32_t *incl, int32_t *bydepth) {
-    __shared__ int32_t cur[kDepthBins];
-    for (int i = threadIdx.x; i < kDepthBins; i += blockDim.x) {
-        const int q = i * kDepthBlocks + blockIdx.x;
-        cur[i] = incl[q] - hist[q];
-    }
-    __syncthreads();
-    const int64_t C = (NI + kDepthBlocks - 1) / kDepthBlocks;
-    const int64_t g0 = (int64_t)blockIdx.x * C, g1 = min(NI, g0 + C);
-    for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-        const int d = depth[g];
-        if (d >= 0 && d < kDepthBins) bydepth[atomicAdd(&cur[d], 1)] = (int)g;
-    }
-}
-
-__global__ void k_check_depth(const int32_t *cnt, int reserved, int32_t *err) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[kCntMaxDepth] > reserved) atomicOr(err, kFlagPhases);
+    if (bad) raise_flag(err, kFlagBounds);
 }
 
 // Rigid motion: r <- Rot (r - c) + c + t per body.
@@ -1039,32 +1169,35 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_depth, P.d_err);
-    // --- 5. transforms, one launch per depth level, deepest first
-    hipLaunchKernelGGL(k_depth_hist, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist);
-    HQ_TRY(scan_i32_inclusive(P, P.d_dhist, P.d_dincl, (int64_t)kDepthBins * kDepthBlocks, s));
-    hipLaunchKernelGGL(k_depth_starts, dim3(1), dim3(kThreads), 0, s, P.d_dhist, P.d_dincl, P.d_dstart, P.d_cnt);
-    hipLaunchKernelGGL(k_depth_scatter, dim3(kDepthBlocks), dim3(kThreads), 0, s, NI, P.d_depth, P.d_dhist,
-                       P.d_dincl, P.d_bydepth);
-    HQ_HIP(hipGetLastError());
-    if (probe_phases) {
-        int32_t cnt[kCntNum];
-        HQ_HIP(hipMemcpyAsync(cnt, P.d_cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
-        HQ_HIP(hipStreamSynchronize(s));
-        P.depth_built = cnt[kCntMaxDepth];
-        P.depth_reserved = std::min(kMaxDepth, P.depth_built + 8);
-    } else {
-        hipLaunchKernelGGL(k_check_depth, dim3(1), dim3(64), 0, s, P.d_cnt, P.depth_reserved, P.d_err);
+                       P.d_row_off, P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_err);
+    // --- 5. transforms, one launch per tile phase; later phases read the
+    // roots of earlier phases' tiles from the tile-root table (sized after
+    // the first build: twice its tiles, the capacity of the exchange buffer)
+    if (probe_phases && P.troot_cap < 2 * P.tiles_built + 64) {
+        const int64_t cap = 2 * P.tiles_built + 64;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, (size_t)cap * kGenWords * sizeof(double));
+        if (e != hipSuccess) {
+            set_error(std::string("hipMalloc of the tile-root table: ") + hipGetErrorString(e));
+            return HQ_E_NOMEM;
+        }
+        P.allocs.push_back(q);
+        P.d_troot = reinterpret_cast<double *>(q);
+        P.troot_cap = cap;
     }
-    const int levels = probe_phases ? P.depth_built : P.depth_reserved;
-    const unsigned ggrid = (unsigned)std::min<int64_t>(2048, (NI + kGenThreads - 1) / kGenThreads);
-    for (int d = levels; d >= 0; --d) {
-        hipLaunchKernelGGL(k_gen_level, dim3(ggrid), dim3(kGenThreads), 0, s, d, P.d_dstart, P.d_bydepth, P.d_sched,
-                           P.d_links, P.d_lc, P.d_rc, P.d_nbody, P.d_nn, pos, P.d_lo, P.d_ncen, P.d_T22,
-                           P.d_rec32, P.d_rec64, P.store, P.d_cen, P.d_kapn, P.d_bflags, N, NI, P.d_err);
+    const int nslot = stack_slots(P.S);
+    const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double);
+    const unsigned gen_grid = (unsigned)std::min<int64_t>((P.tiles_built + P.tiles_built / 4) / 64 + 1, 65535);
+    using GenFn = decltype(&k_gen_tile<false, 0>);
+    const GenFn gen_fn[2][4] = {{k_gen_tile<false, 0>, k_gen_tile<false, 1>, k_gen_tile<false, 2>, k_gen_tile<false, 3>},
+                                {k_gen_tile<true, 0>, k_gen_tile<true, 1>, k_gen_tile<true, 2>, k_gen_tile<true, 3>}};
+    for (int ph = 1; ph <= phases; ++ph) {
+        const bool later = ph > 1;
+        hipLaunchKernelGGL(gen_fn[later][P.store & 3], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
+                           gen_lds, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len, P.d_tile_root, P.d_links,
+                           P.d_nbody, pos, P.d_lo, P.d_troot, P.troot_cap, nslot, P.d_ncen, P.d_T22, P.d_rec32,
+                           P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags, m, N, NI, P.d_err);
     }
-    hipLaunchKernelGGL(k_body_kappa, dim3((unsigned)std::min<int64_t>(m, 65535)), dim3(256), 0, s, m, P.d_node_off,
-                       P.d_kapn, P.d_kappa, P.d_bflags);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

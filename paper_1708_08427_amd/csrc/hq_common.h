@@ -20,7 +20,6 @@ constexpr int kMaxTileUnits = 1024;     // largest tile (units) supported
 constexpr int kMaxPhases = 64;          // phase table capacity
 constexpr int kRecWords = 32;           // elements (float or double) per node record
 constexpr int kMaxDepth = 256;          // bound on tree depth walks (63 code bits + 32 index bits)
-constexpr int kDepthBlocksHost = 512;   // blocks of the depth counting sort
 
 // A node record (one per internal node, in schedule order) holds the three
 // Householder reflectors of G in a zero-padded length-9 layout, the two
@@ -33,7 +32,7 @@ constexpr int kDepthBlocksHost = 512;   // blocks of the depth counting sort
 //   then six int32 links from element 26 on (the bytes of elements 26..31 of
 //   a float record, 26..28 of a double record): xref, yref, off, meta,
 //   slots (x slot | y slot << 8 | own slot << 16, LDS slots of the wide
-//   sweeps), and a reserved word.
+//   sweeps), and the node's index in tree order.
 constexpr int kRecTau = 21;
 constexpr int kRecSx = 24;
 constexpr int kRecSy = 25;
@@ -65,7 +64,6 @@ enum Counter {
     kCntNodes = 1,      // internal nodes covered so far
     kCntPhases = 2,     // phases with at least one tile
     kCntRemain = 3,     // internal nodes still uncovered after the last phase
-    kCntMaxDepth = 4,   // deepest internal node below its body root
     kCntRuns = 5,       // run-table entries used so far
     kCntNum = 8
 };
@@ -137,12 +135,11 @@ struct Plan {
     int dense_max_n = 4096;
     int phases_reserved = 0;  // phases launched by hq_rebuild
     int phases_built = 0;     // phases found by the last hq_build
-    int depth_built = 0;      // deepest internal node of the last hq_build
-    int depth_reserved = 0;   // depth levels launched by hq_rebuild
     int64_t tiles_built = 0;
     int max_n = 0;
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int64_t run_cap = 0;      // entries of d_run
+    int64_t troot_cap = 0;    // tile-root table entries (twice the tiles of hq_build)
 
     std::vector<int64_t> offsets;  // host copy, m + 1
     std::vector<int64_t> row_off;  // host, m + 1
@@ -194,13 +191,8 @@ struct Plan {
     int2 *d_lw = nullptr;            // walk to the body root: (parent, residue rows added)
     long long *d_trval = nullptr, *d_trscan = nullptr;  // packed (flag << 32 | len) and its scan
     int32_t *d_nn = nullptr;         // beads below
-    double *d_ncen = nullptr;        // NI x 3, body-local
-    double *d_T22 = nullptr;         // NI x 6, lower triangle packed (00,10,11,20,21,22)
-    double *d_kapn = nullptr;        // NI: condition bound of each node (0 for k = 3)
-    int32_t *d_depth = nullptr;      // depth below the body root
-    int32_t *d_bydepth = nullptr;    // nodes bucketed by depth
-    int32_t *d_dhist = nullptr, *d_dincl = nullptr;  // (kMaxDepth + 1) x kDepthBlocksHost
-    int32_t *d_dstart = nullptr;     // kMaxDepth + 2
+    double *d_ncen = nullptr;        // NI x 3 in schedule order, body-local
+    double *d_T22 = nullptr;         // NI x 6 in schedule order, lower triangle packed (00,10,11,20,21,22)
 
     // tiles and schedule
     int32_t *d_tile_root = nullptr, *d_tile_base = nullptr, *d_tile_len = nullptr;
@@ -208,7 +200,7 @@ struct Plan {
     int32_t *d_links = nullptr;      // schedule index -> int32[kLinkInts] links
     float *d_rec32 = nullptr;        // NI x 32
     double *d_rec64 = nullptr;       // NI x 32
-    double *d_troot = nullptr;       // tiles x 10: (n, c[3], T22[6]) of tile roots
+    double *d_troot = nullptr;       // troot_cap x 10: (n, c[3], T22[6]) of each tile root
 
     int32_t *d_phase = nullptr;      // 2 x kMaxPhases: [begin, end) tile ids per phase
     int32_t *d_prun = nullptr;       // kPrunStride x kMaxPhases: node begin, node end, first run entry, runs, run length
