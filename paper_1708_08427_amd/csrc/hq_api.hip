@@ -106,54 +106,41 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     P.nchunks = (int)(chunks.size() / 3);
     HQ_TRY(upload(P, &P.d_chunks, chunks));
 
-    // sort plan: bodies up to kSortLdsMax beads in one LDS sort, larger ones
-    // as LDS-sorted chunks followed by merge passes
-    std::vector<std::vector<int32_t>> small_seg(15), chunk_seg(15);
+    // sort plan: bodies up to kSortChunk beads sorted by one block each
+    // (longest first, so the longest sorts start earliest), larger ones as
+    // block-sorted chunks followed by merge passes
+    struct Seg {
+        int32_t start, len, body;  // body stored as ~body for a chunk of a large body
+    };
+    std::vector<Seg> small;
     std::vector<int32_t> large;
     std::vector<int64_t> large_prefix;
     int64_t lsum = 0;
     for (int64_t j = 0; j < m; ++j) {
         const int64_t n = off[j + 1] - off[j];
-        if (n <= kSortLdsMax) {
-            // two launches: segments up to 1024 beads, and up to kSortLdsMax
-            const int npad = (n <= 1024) ? 1024 : kSortLdsMax;
-            auto &v = small_seg[floor_log2(npad)];
-            v.push_back((int32_t)off[j]);
-            v.push_back((int32_t)n);
-            v.push_back((int32_t)j);
+        if (n <= kSortChunk) {
+            small.push_back({(int32_t)off[j], (int32_t)n, (int32_t)j});
         } else {
             large.push_back((int32_t)j);
             large_prefix.push_back(lsum);
             lsum += n;
             int passes = 0;
-            for (int64_t L = kSortLdsMax; L < n; L *= 2) ++passes;
+            for (int64_t L = kSortChunk; L < n; L *= 2) ++passes;
             P.large_passes = std::max(P.large_passes, passes);
-            for (int64_t b = 0; b < n; b += kSortLdsMax) {
-                const int len = (int)std::min<int64_t>(kSortLdsMax, n - b);
-                const int npad = (len <= 1024) ? 1024 : kSortLdsMax;
-                auto &v = chunk_seg[floor_log2(npad)];
-                v.push_back((int32_t)(off[j] + b));
-                v.push_back(len);
-                v.push_back((int32_t)j);
+            for (int64_t b = 0; b < n; b += kSortChunk) {
+                small.push_back({(int32_t)(off[j] + b), (int32_t)std::min<int64_t>(kSortChunk, n - b), ~(int32_t)j});
             }
         }
     }
-    for (int c = 0; c < 15; ++c) {
-        if (!small_seg[c].empty()) {
-            Plan::SortClass sc;
-            sc.npad = 1 << c;
-            sc.nseg = (int)(small_seg[c].size() / 3);
-            HQ_TRY(upload(P, &sc.d_seg, small_seg[c]));
-            P.sort_small.push_back(sc);
-        }
-        if (!chunk_seg[c].empty()) {
-            Plan::SortClass sc;
-            sc.npad = 1 << c;
-            sc.nseg = (int)(chunk_seg[c].size() / 3);
-            HQ_TRY(upload(P, &sc.d_seg, chunk_seg[c]));
-            P.sort_chunks.push_back(sc);
-        }
+    std::stable_sort(small.begin(), small.end(), [](const Seg &a, const Seg &b) { return a.len > b.len; });
+    std::vector<int32_t> segs;
+    for (const auto &e : small) {
+        segs.push_back(e.start);
+        segs.push_back(e.len);
+        segs.push_back(e.body);
     }
+    P.sort_segs.nseg = (int)small.size();
+    if (P.sort_segs.nseg) HQ_TRY(upload(P, &P.sort_segs.d_seg, segs));
     P.nlarge = (int)large.size();
     P.large_elems = lsum;
     if (P.nlarge) {

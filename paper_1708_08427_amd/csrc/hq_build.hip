@@ -1,8 +1,9 @@
 // Setup of the hierarchical transforms on the GPU (Sections 2.1 and 3).
 //
 //   1. per-body bounding cube and 21-bit z-y-x interleaved box codes
-//   2. per-body sort of (code, position in body): LDS bitonic sort for
-//      segments of up to 8192 beads, pairwise merges above that
+//   2. per-body sort of (code, position in body): bitonic sort in LDS of up
+//      to 2048 pairs per block, one launch for all bodies; larger bodies are
+//      sorted in chunks of 2048 and merged pairwise
 //   3. binary radix tree per body (Karras' construction on the sorted codes,
 //      which is the nested-box bisection with empty halves pruned)
 //   4. tiles: the tree is cut into connected pieces of at most S "units"
@@ -154,21 +155,32 @@ __device__ inline bool key_less(unsigned long long ka, unsigned int va, unsigned
     return ka < kb || (ka == kb && va < vb);
 }
 
-// seg: (start, len, body) triples; every len <= npad_max.  Each block pads its
-// segment to the next power of two (at least 64) and sorts it bitonically in
-// LDS.  final: write sorted codes and the caller's bead index; otherwise write
-// the sorted run back.
-__global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad_max, int final_out, unsigned long long *keys,
-                           int32_t *vals, const int32_t *__restrict__ bead_off, unsigned long long *scode,
-                           int32_t *perm) {
-    extern __shared__ unsigned char smem[];
-    unsigned long long *K = reinterpret_cast<unsigned long long *>(smem);
-    unsigned int *V = reinterpret_cast<unsigned int *>(smem + sizeof(unsigned long long) * npad_max);
-    const int start = seg[3 * blockIdx.x], len = seg[3 * blockIdx.x + 1], body = seg[3 * blockIdx.x + 2];
-    int npad = 64;
+// seg: (start, len, body) triples, len <= kSortChunk, longest first.  One block
+// of kSortThreads threads per segment pads it to the next power of two (at
+// least 128) and sorts it bitonically in LDS.  Pair p of a step with stride j
+// is (i, i + j) with i = 2j floor(p / j) + p mod j; a thread takes pairs p,
+// p + kSortThreads, ..., so for strides up to 64 the pairs of a wave stay
+// inside 128-element blocks no other wave touches: those steps need no block
+// barrier, only the wave's own ordering.  One launch covers all sizes, so the
+// latency of the longest segments overlaps the work on the short ones.
+// A segment of a whole body (body >= 0) writes sorted codes and the caller's
+// bead index; a chunk of a larger body (stored as ~body) writes keys and
+// values back in place for the merge passes.
+constexpr int kSortThreads = 256;
+
+__global__ void __launch_bounds__(kSortThreads) k_lds_sort(const int32_t *__restrict__ seg,
+                                                           unsigned long long *keys, int32_t *vals,
+                                                           const int32_t *__restrict__ bead_off,
+                                                           unsigned long long *scode, int32_t *perm) {
+    __shared__ unsigned long long K[kSortChunk];
+    __shared__ unsigned int V[kSortChunk];
+    const int start = seg[3 * blockIdx.x], len = seg[3 * blockIdx.x + 1], bcode = seg[3 * blockIdx.x + 2];
+    const bool final_out = bcode >= 0;
+    const int body = final_out ? bcode : ~bcode;
+    int npad = 128;
     while (npad < len) npad <<= 1;
-    if (npad > npad_max) return;  // never: segments are classed by size on the host
-    for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+    if (npad > kSortChunk) return;  // never: segments are cut on the host
+    for (int i = threadIdx.x; i < npad; i += kSortThreads) {
         if (i < len) {
             K[i] = keys[start + i];
             V[i] = (unsigned int)vals[start + i];
@@ -178,32 +190,40 @@ __global__ void k_lds_sort(const int32_t *__restrict__ seg, int npad_max, int fi
         }
     }
     __syncthreads();
+    const int half = npad >> 1;
     for (int k = 2; k <= npad; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < npad; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long ka = K[i], kb = K[ixj];
-                    const unsigned int va = V[i], vb = V[ixj];
-                    const bool up = (i & k) == 0;
-                    const bool gt = key_less(kb, vb, ka, va);
-                    if (gt == up) {
-                        K[i] = kb; K[ixj] = ka;
-                        V[i] = vb; V[ixj] = va;
-                    }
+            const int lj = 31 - __builtin_clz(j);
+            for (int p = threadIdx.x; p < half; p += kSortThreads) {
+                const int i = ((p >> lj) << (lj + 1)) | (p & (j - 1)), ixj = i + j;
+                const unsigned long long ka = K[i], kb = K[ixj];
+                const unsigned int va = V[i], vb = V[ixj];
+                const bool up = (i & k) == 0;
+                if (key_less(kb, vb, ka, va) == up) {
+                    K[i] = kb;
+                    K[ixj] = ka;
+                    V[i] = vb;
+                    V[ixj] = va;
                 }
             }
-            __syncthreads();
+            const int jn = (j > 1) ? (j >> 1) : k;  // stride of the next step
+            if (j >= 128 || jn >= 128) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
+    __syncthreads();
     if (final_out) {
         const int base = bead_off[body];
-        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        for (int i = threadIdx.x; i < len; i += kSortThreads) {
             scode[start + i] = K[i];
             perm[start + i] = base + (int)V[i];
         }
     } else {
-        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        for (int i = threadIdx.x; i < len; i += kSortThreads) {
             keys[start + i] = K[i];
             vals[start + i] = (int)V[i];
         }
@@ -1072,10 +1092,6 @@ inline unsigned grid_for(int64_t n, int threads = kThreads) {
 
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases) {
     const int64_t N = P.N, m = P.m, NI = P.NI;
-    if (probe_phases) {
-        HQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_sort),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSortLdsMax * 12));
-    }
     // --- init
     hipLaunchKernelGGL(k_init_bodies, dim3(grid_for(m)), dim3(kThreads), 0, s, m, P.d_bmin, P.d_bmax, P.d_kappa,
                        P.d_bflags);
@@ -1089,22 +1105,15 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_bbox, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, P.d_bmin, P.d_bmax, P.d_err);
     hipLaunchKernelGGL(k_codes, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, P.d_bead_off, pos, P.d_bmin,
                        P.d_bmax, P.d_lo, P.d_h, P.d_keyA, P.d_valA);
-    // --- 2. sort
-    for (auto &c : P.sort_small) {
-        const int thr = std::min(1024, std::max(64, c.npad / 2));
-        hipLaunchKernelGGL(k_lds_sort, dim3(c.nseg), dim3(thr), (size_t)c.npad * 12, s, c.d_seg, c.npad, 1,
-                           P.d_keyA, P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
-    }
+    // --- 2. sort (chunks of large bodies and whole bodies in one launch)
+    if (P.sort_segs.nseg > 0)
+        hipLaunchKernelGGL(k_lds_sort, dim3(P.sort_segs.nseg), dim3(kSortThreads), 0, s, P.sort_segs.d_seg, P.d_keyA,
+                           P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
     HQ_HIP(hipGetLastError());
     if (P.nlarge > 0) {
-        for (auto &c : P.sort_chunks) {
-            const int thr = std::min(1024, std::max(64, c.npad / 2));
-            hipLaunchKernelGGL(k_lds_sort, dim3(c.nseg), dim3(thr), (size_t)c.npad * 12, s, c.d_seg, c.npad, 0,
-                               P.d_keyA, P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
-        }
         unsigned long long *kin = P.d_keyA, *kout = P.d_keyB;
         int32_t *vin = P.d_valA, *vout = P.d_valB;
-        int L = kSortLdsMax;
+        int L = kSortChunk;
         for (int p = 0; p < P.large_passes; ++p) {
             hipLaunchKernelGGL(k_merge_pass, dim3(grid_for(P.large_elems)), dim3(kThreads), 0, s, P.d_large,
                                P.d_large_prefix, P.nlarge, P.large_elems, P.d_bead_off, L, kin, vin, kout, vout);

@@ -15,7 +15,7 @@ namespace hq {
 // limits and layout constants
 // ---------------------------------------------------------------------------
 constexpr int kQBits = 21;              // quantisation bits per axis
-constexpr int kSortLdsMax = 8192;       // largest segment sorted in LDS in one pass
+constexpr int kSortChunk = 2048;        // largest segment sorted by one block (LDS bitonic sort)
 constexpr int kMaxTileUnits = 1024;     // largest tile (units) supported
 constexpr int kMaxPhases = 64;          // phase table capacity
 constexpr int kRecWords = 32;           // elements (float or double) per node record
@@ -145,9 +145,8 @@ struct Plan {
     std::vector<int64_t> row_off;  // host, m + 1
 
     // sort plan (host-side, static per handle)
-    struct SortClass { int npad = 0; int nseg = 0; int32_t *d_seg = nullptr; };
-    std::vector<SortClass> sort_small;   // whole bodies sorted in LDS, written to scode/perm
-    std::vector<SortClass> sort_chunks;  // chunks of large bodies sorted in LDS (runs)
+    struct SortSegs { int nseg = 0; int32_t *d_seg = nullptr; };
+    SortSegs sort_segs;    // (start, len, body or ~body for a chunk of a large body), longest first
     int large_passes = 0;                // merge passes for large bodies
     int64_t large_elems = 0;
     int nlarge = 0;
