@@ -25,7 +25,7 @@ PROBE_SWEEPS = 3
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("hq_apply.hip", "hq_common.h"):
+    for name in ("hq_apply.hip", "hq_common.h", "hq_buffer.h"):
         with open(os.path.join(HERE, "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
