@@ -185,6 +185,10 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_lw, NI));
     HQ_TRY(dalloc(P, &P.d_trval, NI));
     HQ_TRY(dalloc(P, &P.d_trscan, NI));
+    HQ_TRY(dalloc(P, &P.d_rem, NI));
+    HQ_TRY(dalloc(P, &P.d_tord, NI));
+    HQ_TRY(dalloc(P, &P.d_lhist, (int64_t)P.S * 256));
+    HQ_TRY(dalloc(P, &P.d_lincl, (int64_t)P.S * 256));
     HQ_TRY(dalloc(P, &P.d_nn, NI));
     HQ_TRY(dalloc(P, &P.d_ncen, 3 * NI));
     HQ_TRY(dalloc(P, &P.d_T22, 6 * NI));
@@ -204,7 +208,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));
     HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
-    P.scan_blk_cap = scan_blocks_needed(std::max(N, NI)) + 8;
+    P.scan_blk_cap = scan_blocks_needed(std::max(std::max(N, NI), (int64_t)P.S * 256)) + 8;
     HQ_TRY(dalloc(P, &P.d_scan_blk, P.scan_blk_cap));
     return HQ_OK;
 }

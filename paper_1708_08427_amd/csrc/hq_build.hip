@@ -371,13 +371,6 @@ __global__ void k_tree(int64_t NI, int m, const int32_t *__restrict__ bead_off, 
 // ---------------------------------------------------------------------------
 // 4. tiles
 // ---------------------------------------------------------------------------
-__device__ inline int units_of(int g, int phase, const int32_t *nn, const int32_t *first, const int32_t *last,
-                               const int32_t *msum) {
-    if (phase == 1) return nn[g];
-    const int f = first[g], l = last[g];
-    return msum[l] - (f > 0 ? msum[f - 1] : 0);
-}
-
 // units of a child of an uncovered node: a bead or an earlier tile's root
 // counts as one unit
 __device__ inline int child_units(int c, const int32_t *cov, const int32_t *units) {
@@ -386,52 +379,102 @@ __device__ inline int child_units(int c, const int32_t *cov, const int32_t *unit
     return units[c];
 }
 
-__global__ void k_mark_beads(int64_t N, const int32_t *leafpar, const int32_t *cov, int32_t *mark, const int32_t *gate) {
+// Later phases iterate over the nodes the first phase left uncovered (a few
+// percent of all nodes), listed once in tree order: rem = null means all nodes
+// in order.  dn holds the list's length on the device.
+__device__ __forceinline__ int64_t node_count(int64_t NI, const int32_t *dn) {
+    return dn ? min(NI, (int64_t)max(*dn, 0)) : NI;
+}
+__device__ __forceinline__ int node_at(int64_t i, const int32_t *rem) { return rem ? rem[i] : (int)i; }
+
+__global__ void k_rem_flags(int64_t NI, const int32_t *cov, int32_t *flag, const int32_t *gate) {
     if (gate && *gate == 0) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        mark[i] = (cov[leafpar[i]] == 0) ? 1 : 0;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x)
+        flag[g] = (cov[g] == 0) ? 1 : 0;
 }
 
-__global__ void k_mark_roots(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *first, int32_t *mark, const int32_t *gate) {
+__global__ void k_rem_scatter(int64_t NI, const int32_t *cov, const int32_t *pos, int32_t *rem, int32_t *cnt,
+                              const int32_t *gate) {
     if (gate && *gate == 0) return;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x) {
-        const int p = par[g];
-        if (cov[g] != 0 && p >= 0 && cov[p] == 0) mark[first[g]] = 1;
+        if (cov[g] == 0) rem[pos[g] - 1] = (int)g;
+        if (g == NI - 1) cnt[kCntRemList] = pos[g];
     }
 }
 
-__global__ void k_tile_roots(int64_t NI, int phase, int S, const int32_t *cov, const int32_t *par,
-                             const int32_t *nn, const int32_t *first, const int32_t *last, const int32_t *msum,
-                             int32_t *units, long long *trval, const int32_t *gate) {
+// Units of the uncovered nodes after the first phase (beads and roots of
+// earlier tiles count one each): every uncovered node adds the units among its
+// own children to itself and to all its ancestors, which are uncovered too.
+__global__ void k_units_clear(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
+                              int32_t *units, const int32_t *gate) {
     if (gate && *gate == 0) return;
-    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
-        const int g = (int)gg;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
+        if (cov[g] == 0) units[g] = 0;
+    }
+}
+
+__global__ void k_units_walk(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
+                             const int32_t *lc, const int32_t *rc, const int32_t *par, int32_t *units,
+                             int32_t *err, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
+        if (cov[g] != 0) continue;
+        const int x = lc[g], y = rc[g];
+        const int c = ((x < 0 || cov[x] != 0) ? 1 : 0) + ((y < 0 || cov[y] != 0) ? 1 : 0);
+        if (c == 0) continue;
+        int q = g;
+        for (int guard = 0; q >= 0; ++guard) {
+            if (guard == kMaxDepth || q >= NI) {
+                raise_flag(err, kFlagBounds);
+                break;
+            }
+            atomicAdd(&units[q], c);
+            q = par[q];
+        }
+    }
+}
+
+__global__ void k_tile_roots(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int S,
+                             const int32_t *cov, const int32_t *par, const int32_t *nn, int32_t *units,
+                             long long *trval, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
         if (cov[g] != 0) {
-            trval[g] = 0;
+            trval[i] = 0;
             continue;
         }
-        const int u = units_of(g, phase, nn, first, last, msum);
+        // first phase: every bead is a unit; later: counted by k_units_walk
+        const int u = (phase == 1) ? nn[g] : units[g];
         const int p = par[g];
-        const int up = (p < 0) ? INT_MAX : units_of(p, phase, nn, first, last, msum);
-        units[g] = u;
+        const int up = (p < 0) ? INT_MAX : ((phase == 1) ? nn[p] : units[p]);
+        if (phase == 1) units[g] = u;
         const bool root = (u <= S) && (up > S);
-        trval[g] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
+        trval[i] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
     }
 }
 
-__global__ void k_tile_emit(int64_t NI, const long long *trval, const long long *trscan, const int32_t *cnt,
-                            int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof, const int32_t *gate) {
+__global__ void k_tile_emit(int64_t NI, const int32_t *rem, const int32_t *dn, const long long *trval,
+                            const long long *trscan, const int32_t *cnt, int32_t *tile_root, int32_t *tile_len,
+                            int32_t *tile_base, int32_t *tileof, const int32_t *gate) {
     if (gate && *gate == 0) return;
     const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
-    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
-        const long long v = trval[gg];
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const long long v = trval[i];
         if (v == 0) continue;
-        const long long sc = trscan[gg];
+        const int g = node_at(i, rem);
+        const long long sc = trscan[i];
         const int t = tiles0 + (int)(sc >> 32);
-        tile_root[t] = (int)gg;
+        tile_root[t] = g;
         tile_len[t] = (int)(v & 0xffffffffll);
         tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
-        tileof[gg] = t;
+        tileof[g] = t;
     }
 }
 
@@ -445,19 +488,20 @@ __global__ void k_tile_emit(int64_t NI, const long long *trval, const long long 
 // flag, bit 30 the tile-root flag.
 constexpr int kAwPend = 1 << 29, kAwRoot = 1 << 30, kAwSkip = (1 << 29) - 1;
 
-__global__ void k_assign_prep(int64_t NI, const int32_t *cov, const int32_t *par, const int32_t *lc,
-                              const int32_t *rc, const int32_t *units, const long long *trval, int32_t *yfirst,
-                              int2 *aw, const int32_t *gate) {
+__global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
+                              const int32_t *par, const int32_t *lc, const int32_t *rc, const int32_t *units,
+                              const long long *trval, int32_t *yfirst, int2 *aw, const int32_t *gate) {
     if (gate && *gate == 0) return;
-    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
-        const int g = (int)gg;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
         if (cov[g] != 0) continue;
         {
             const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
             yfirst[g] = (uy > ux) ? 1 : 0;
         }
         const int p = par[g];
-        int word = (trval[g] != 0) ? kAwRoot : 0;
+        int word = (trval[i] != 0) ? kAwRoot : 0;
         if (p >= 0) {
             const int x = lc[p], y = rc[p];
             const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
@@ -475,12 +519,14 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *cov, const int32_t *par
 // reaches first going up (the child with more units is evaluated first), and
 // the stack slot that receives its result (results of the tile pending while
 // its subtree is swept).
-__global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *units, const int2 *aw,
-                         const int32_t *tile_base, int32_t *tileof, int32_t *sched, int32_t *sched_node,
-                         int32_t *depth_slot, int32_t *err, int64_t sched_cap, const int32_t *gate) {
+__global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
+                         const int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
+                         int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int32_t *err, int64_t sched_cap,
+                         const int32_t *gate) {
     if (gate && *gate == 0) return;
-    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
-        const int g = (int)gg;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
         if (cov[g] != 0) continue;
         int pos = units[g] - 2, pend = 0;
         int q = g;
@@ -513,18 +559,23 @@ __global__ void k_assign(int64_t NI, const int32_t *cov, const int32_t *units, c
     }
 }
 
-__global__ void k_commit(int64_t NI, int phase, int32_t *cov, const int32_t *tileof, const int32_t *gate) {
+__global__ void k_commit(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
+                         const int32_t *tileof, const int32_t *gate) {
     if (gate && *gate == 0) return;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x)
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
         if (cov[g] == 0 && tileof[g] >= 0) cov[g] = phase;
+    }
 }
 
-__global__ void k_phase_close(int64_t NI, int phase, const long long *trval, const long long *trscan,
-                              int32_t *cnt, int32_t *phase_tab, int run_nodes, int32_t *prun, int64_t run_cap,
-                              int32_t *err, const int32_t *gate) {
+__global__ void k_phase_close(int64_t NI, const int32_t *dn, int phase, const long long *trval,
+                              const long long *trscan, int32_t *cnt, int32_t *phase_tab, int run_nodes,
+                              int32_t *prun, int64_t run_cap, int32_t *err, const int32_t *gate) {
     if (gate && *gate == 0) return;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const long long tot = (NI > 0) ? trscan[NI - 1] + trval[NI - 1] : 0;
+    const int64_t n = node_count(NI, dn);
+    const long long tot = (n > 0) ? trscan[n - 1] + trval[n - 1] : 0;
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
     phase_tab[2 * phase] = cnt[kCntTiles];
     phase_tab[2 * phase + 1] = cnt[kCntTiles] + ntiles;
@@ -745,6 +796,41 @@ __device__ __forceinline__ void householder_qr(double (&A)[9][3], double (&tau)[
     T[5] = (k == 3) ? 0.0 : A[2][2];  // Case I: rank 2, third column exactly 0 (Eq. 3.9)
 }
 
+// Tiles of one phase ordered longest first (a counting sort on the node
+// count, kLenBlocks blocks each taking a contiguous share of the tiles), so
+// that the lanes of a generation wave walk tiles of about the same length.
+constexpr int kLenBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_len_hist(int phase, const int32_t *phase_tab, const int32_t *tile_len,
+                                                  int nbins, int32_t *hist) {
+    __shared__ int32_t h[kMaxTileUnits];
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    const int C = (te - tb + kLenBlocks - 1) / kLenBlocks;
+    const int a = tb + blockIdx.x * C, b = min(te, a + C);
+    for (int t = a + threadIdx.x; t < b; t += blockDim.x)
+        atomicAdd(&h[nbins - 1 - min(max(tile_len[t], 0), nbins - 1)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i * kLenBlocks + blockIdx.x] = h[i];
+}
+
+__global__ void __launch_bounds__(256) k_len_scatter(int phase, const int32_t *phase_tab, const int32_t *tile_len,
+                                                     int nbins, const int32_t *hist, const int32_t *incl,
+                                                     int32_t *tord) {
+    __shared__ int32_t cur[kMaxTileUnits];
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+        const int q = i * kLenBlocks + blockIdx.x;
+        cur[i] = incl[q] - hist[q];
+    }
+    __syncthreads();
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    const int C = (te - tb + kLenBlocks - 1) / kLenBlocks;
+    const int a = tb + blockIdx.x * C, b = min(te, a + C);
+    for (int t = a + threadIdx.x; t < b; t += blockDim.x)
+        tord[tb + atomicAdd(&cur[nbins - 1 - min(max(tile_len[t], 0), nbins - 1)], 1)] = t;
+}
+
 // ---------------------------------------------------------------------------
 // Transforms tile by tile: one lane per tile of a phase walks the tile's nodes
 // in schedule order (children before parents, the order of the upward sweep).
@@ -903,14 +989,19 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
                                                  const double *lo, double *troot, int64_t ntr, int nslot,
                                                  double *ncen, double *T22, float *rec32, double *rec64,
                                                  double *bcen, unsigned long long *kappa, int32_t *bflags,
-                                                 int64_t m, int64_t N, int64_t NI, int32_t *err) {
+                                                 const int32_t *tord, int64_t m, int64_t N, int64_t NI,
+                                                 int32_t *err) {
     extern __shared__ unsigned char smem_raw[];
     double *lds = reinterpret_cast<double *>(smem_raw);
     const int lane = threadIdx.x;
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    // tord: the phase's tiles longest first (then every buffer is addressed
+    // from its start, which the host checked stays below 2 GiB); otherwise
+    // tiles in order, addressed from the wave's first tile
+    const bool sorted = tord != nullptr;
     bool bad = false;
     for (int t0 = tb + blockIdx.x * 64; t0 < te; t0 += gridDim.x * 64) {
-        const int t = t0 + lane;
+        const int t = (sorted && t0 + lane < te) ? tord[t0 + lane] : t0 + lane;
         int s = 0, se = 0, body = 0;
         if (t < te) {
             const int base = tile_base[t], len = tile_len[t], r = tile_root[t];
@@ -927,11 +1018,13 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
             s = se = body = 0;
         }
         // wave-uniform bases: the first tile's schedule index, tile id, body
-        const int s0 = __builtin_amdgcn_readfirstlane(s);
-        const int b0 = __builtin_amdgcn_readfirstlane(body);
+        const int s0 = sorted ? 0 : __builtin_amdgcn_readfirstlane(s);
+        const int b0 = sorted ? 0 : __builtin_amdgcn_readfirstlane(body);
+        const int tr0 = sorted ? 0 : t0;
         // every offset below stays under 2 GiB: at most 2^23 records of 256 B
         // and 2^24 bodies of 24 B from the wave's bases
-        if (s < se && (s < s0 || se - s0 > (1 << 23) || body < b0 || body - b0 > (1 << 24))) {
+        if (s < se && (s < s0 || se - s0 > (1 << 23) || body < b0 || body - b0 > (1 << 24) || t < tr0 ||
+                       t - tr0 > (1 << 24))) {
             bad = true;
             s = se = 0;
         }
@@ -939,7 +1032,7 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
         auto cap = [](int64_t bytes) -> uint32_t {
             return bytes <= 0 ? 0u : (bytes >= 0x7fffffffll ? 0x7fffffffu : (uint32_t)bytes);
         };
-        const int64_t t0c = t0 < ntr ? t0 : ntr;
+        const int64_t t0c = tr0 < ntr ? tr0 : ntr;
         const rsrc_t r32 = make_rsrc_uniform(rec32 + (int64_t)kRecWords * s0, cap((NI - s0) * 128));
         const rsrc_t r64 = make_rsrc_uniform(rec64 + (int64_t)kRecWords * s0, cap((NI - s0) * 256));
         const rsrc_t rcen = make_rsrc_uniform(ncen + 3 * (int64_t)s0, cap((NI - s0) * 24));
@@ -1044,7 +1137,7 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
                 const uint32_t rel = (uint32_t)(s - s0);
                 const double tv[kGenWords] = {n, cp[0], cp[1], cp[2], T[0], T[1], T[2], T[3], T[4], T[5]};
                 const double bc[3] = {cp[0] + lo3[0], cp[1] + lo3[1], cp[2] + lo3[2]};
-                gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - t0) : kOOB,
+                gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - tr0) : kOOB,
                                   (act && body_root) ? (uint32_t)(body - b0) : kOOB, w32, w64, li, cp, T, tv, bc);
             }
 #pragma unroll
@@ -1136,24 +1229,32 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         // a phase after the one that covered the last node is a no-op on the
         // device (reserved phases of a rebuild cost a few launches only)
         const int32_t *gate = (ph >= 2) ? P.d_cnt + kCntRemain : nullptr;
-        if (ph >= 2) {
-            hipLaunchKernelGGL(k_mark_beads, dim3(grid_for(N)), dim3(kThreads), 0, s, N, P.d_leafpar, P.d_cov,
-                               P.d_mark, gate);
-            hipLaunchKernelGGL(k_mark_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par,
-                               P.d_first, P.d_mark, gate);
-            HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, N, s, gate));
+        // later phases work on the list of nodes the first phase left over
+        const int32_t *rem = (ph >= 2) ? P.d_rem : nullptr;
+        const int32_t *dn = (ph >= 2) ? P.d_cnt + kCntRemList : nullptr;
+        const unsigned grid = (ph >= 2) ? std::min(grid_for(NI), 1024u) : grid_for(NI);
+        if (ph == 2) {
+            hipLaunchKernelGGL(k_rem_flags, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_mark, gate);
+            HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, NI, s, gate));
+            hipLaunchKernelGGL(k_rem_scatter, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_msum,
+                               P.d_rem, P.d_cnt, gate);
         }
-        hipLaunchKernelGGL(k_tile_roots, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.S, P.d_cov, P.d_par,
-                           P.d_nn, P.d_first, P.d_last, P.d_msum, P.d_units, P.d_trval, gate);
-        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate));
-        hipLaunchKernelGGL(k_tile_emit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_trval, P.d_trscan,
+        if (ph >= 2) {
+            hipLaunchKernelGGL(k_units_clear, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_units, gate);
+            hipLaunchKernelGGL(k_units_walk, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_lc, P.d_rc,
+                               P.d_par, P.d_units, P.d_err, gate);
+        }
+        hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.S, P.d_cov, P.d_par,
+                           P.d_nn, P.d_units, P.d_trval, gate);
+        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
+        hipLaunchKernelGGL(k_tile_emit, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_trval, P.d_trscan,
                            P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof, gate);
-        hipLaunchKernelGGL(k_assign_prep, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_par, P.d_lc,
+        hipLaunchKernelGGL(k_assign_prep, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_par, P.d_lc,
                            P.d_rc, P.d_units, P.d_trval, P.d_yfirst, P.d_aw, gate);
-        hipLaunchKernelGGL(k_assign, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_units, P.d_aw,
+        hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_units, P.d_aw,
                            P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI, gate);
-        hipLaunchKernelGGL(k_commit, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, ph, P.d_cov, P.d_tileof, gate);
-        hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, ph, P.d_trval, P.d_trscan, P.d_cnt,
+        hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_tileof, gate);
+        hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, dn, ph, P.d_trval, P.d_trscan, P.d_cnt,
                            P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
         // the run table of a phase is built when the phase holds nodes
         hipLaunchKernelGGL(k_runs, dim3(std::min(grid_for(NI), 1024u)), dim3(kThreads), 0, s, ph, P.d_phase,
@@ -1200,12 +1301,24 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     using GenFn = decltype(&k_gen_tile<false, 0>);
     const GenFn gen_fn[2][4] = {{k_gen_tile<false, 0>, k_gen_tile<false, 1>, k_gen_tile<false, 2>, k_gen_tile<false, 3>},
                                 {k_gen_tile<true, 0>, k_gen_tile<true, 1>, k_gen_tile<true, 2>, k_gen_tile<true, 3>}};
+    // the first phase's tiles longest first, when every buffer the generation
+    // writes can be addressed from its start with 32-bit offsets
+    const int64_t lim = 0x7fffffffll;
+    const bool sort_tiles = NI * 256 < lim && P.troot_cap * 80 < lim && m * 24 < lim;
+    if (sort_tiles) {
+        const int nbins = P.S;
+        hipLaunchKernelGGL(k_len_hist, dim3(kLenBlocks), dim3(256), 0, s, 1, P.d_phase, P.d_tile_len, nbins, P.d_lhist);
+        HQ_TRY(scan_i32_inclusive(P, P.d_lhist, P.d_lincl, (int64_t)nbins * kLenBlocks, s));
+        hipLaunchKernelGGL(k_len_scatter, dim3(kLenBlocks), dim3(256), 0, s, 1, P.d_phase, P.d_tile_len, nbins,
+                           P.d_lhist, P.d_lincl, P.d_tord);
+    }
     for (int ph = 1; ph <= phases; ++ph) {
         const bool later = ph > 1;
         hipLaunchKernelGGL(gen_fn[later][P.store & 3], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
                            gen_lds, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len, P.d_tile_root, P.d_links,
                            P.d_nbody, pos, P.d_lo, P.d_troot, P.troot_cap, nslot, P.d_ncen, P.d_T22, P.d_rec32,
-                           P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags, m, N, NI, P.d_err);
+                           P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags,
+                           (sort_tiles && !later) ? (const int32_t *)P.d_tord : nullptr, m, N, NI, P.d_err);
     }
     HQ_HIP(hipGetLastError());
     return HQ_OK;

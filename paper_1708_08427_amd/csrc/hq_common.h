@@ -64,6 +64,7 @@ enum Counter {
     kCntNodes = 1,      // internal nodes covered so far
     kCntPhases = 2,     // phases with at least one tile
     kCntRemain = 3,     // internal nodes still uncovered after the last phase
+    kCntRemList = 4,    // length of the list of nodes left uncovered by the first phase
     kCntRuns = 5,       // run-table entries used so far
     kCntNum = 8
 };
@@ -174,7 +175,7 @@ struct Plan {
     unsigned long long *d_scode = nullptr;  // sorted codes
     int32_t *d_perm = nullptr;       // sorted global position -> caller's global bead index
     int32_t *d_leafpar = nullptr;    // sorted global position -> parent node
-    int32_t *d_mark = nullptr, *d_msum = nullptr;
+    int32_t *d_mark = nullptr, *d_msum = nullptr;  // flags and their scan (compaction)
 
     // node level (node g = internal node, Karras order per body)
     int32_t *d_lc = nullptr, *d_rc = nullptr, *d_par = nullptr;
@@ -189,6 +190,9 @@ struct Plan {
     int2 *d_aw = nullptr;            // walk to the tile root: (parent, packed position step)
     int2 *d_lw = nullptr;            // walk to the body root: (parent, residue rows added)
     long long *d_trval = nullptr, *d_trscan = nullptr;  // packed (flag << 32 | len) and its scan
+    int32_t *d_rem = nullptr;        // nodes left uncovered by the first phase, tree order
+    int32_t *d_tord = nullptr;       // first-phase tiles, longest first (generation order)
+    int32_t *d_lhist = nullptr, *d_lincl = nullptr;  // S x 256 length histograms and their scan
     int32_t *d_nn = nullptr;         // beads below
     double *d_ncen = nullptr;        // NI x 3 in schedule order, body-local
     double *d_T22 = nullptr;         // NI x 6 in schedule order, lower triangle packed (00,10,11,20,21,22)
@@ -246,7 +250,7 @@ void set_error(const std::string &msg);
 hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s,
                              const int32_t *gate = nullptr);
 hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s,
-                             const int32_t *gate = nullptr);
+                             const int32_t *gate = nullptr, const int32_t *dn = nullptr);
 
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases);
 hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs,

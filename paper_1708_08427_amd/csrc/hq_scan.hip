@@ -39,10 +39,22 @@ __device__ T block_exclusive(T v, T *lds, T *total) {
     return excl;
 }
 
+// dn: when not null, the element count is min(n, *dn), read on the device
+// (launch sizes still follow n; blocks past the count do nothing).
+__device__ __forceinline__ int64_t scan_count(int64_t n, const int32_t *dn) {
+    return dn ? min(n, (int64_t)max(*dn, 0)) : n;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_block_sums(const T *__restrict__ in, int64_t n,
-                                                         T *__restrict__ blk, const int32_t *gate) {
+                                                         T *__restrict__ blk, const int32_t *gate,
+                                                         const int32_t *dn) {
     if (gate && *gate == 0) return;
+    n = scan_count(n, dn);
+    if ((int64_t)blockIdx.x * kPerBlock >= n) {
+        if (threadIdx.x == 0) blk[blockIdx.x] = 0;
+        return;
+    }
     __shared__ T lds[kThreads / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
     T s = 0;
@@ -55,8 +67,10 @@ __global__ void __launch_bounds__(kThreads) k_block_sums(const T *__restrict__ i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, int64_t nb, const int32_t *gate) {
+__global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, int64_t nb, const int32_t *gate,
+                                                          const int32_t *dn) {
     if (gate && *gate == 0) return;
+    if (dn) nb = min(nb, (scan_count(nb * kPerBlock, dn) + kPerBlock - 1) / kPerBlock);
     __shared__ T lds[kThreads / 64 + 1];
     T carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
@@ -72,8 +86,10 @@ __global__ void __launch_bounds__(kThreads) k_scan_blocks(T *__restrict__ blk, i
 template <typename T, bool kInclusive>
 __global__ void __launch_bounds__(kThreads) k_scan_apply(const T *__restrict__ in, T *__restrict__ out,
                                                          int64_t n, const T *__restrict__ blk,
-                                                         const int32_t *gate) {
+                                                         const int32_t *gate, const int32_t *dn) {
     if (gate && *gate == 0) return;
+    n = scan_count(n, dn);
+    if ((int64_t)blockIdx.x * kPerBlock >= n) return;
     __shared__ T lds[kThreads / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
     T v[kItems];
@@ -94,7 +110,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const T *__restrict__ i
 }
 
 template <typename T, bool kInclusive>
-hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s, const int32_t *gate) {
+hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s, const int32_t *gate,
+                    const int32_t *dn = nullptr) {
     if (n <= 0) return HQ_OK;
     const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
     if (nb > P.scan_blk_cap) {
@@ -102,10 +119,10 @@ hq_status scan_impl(Plan &P, const T *in, T *out, int64_t n, hipStream_t s, cons
         return HQ_E_UNSUPPORTED;
     }
     T *blk = reinterpret_cast<T *>(P.d_scan_blk);
-    hipLaunchKernelGGL((k_block_sums<T>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, blk, gate);
-    hipLaunchKernelGGL((k_scan_blocks<T>), dim3(1), dim3(kThreads), 0, s, blk, nb, gate);
+    hipLaunchKernelGGL((k_block_sums<T>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, blk, gate, dn);
+    hipLaunchKernelGGL((k_scan_blocks<T>), dim3(1), dim3(kThreads), 0, s, blk, nb, gate, dn);
     hipLaunchKernelGGL((k_scan_apply<T, kInclusive>), dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n,
-                       (const T *)blk, gate);
+                       (const T *)blk, gate, dn);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }
@@ -120,8 +137,8 @@ hq_status scan_i32_inclusive(Plan &P, const int32_t *in, int32_t *out, int64_t n
 }
 
 hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64_t n, hipStream_t s,
-                             const int32_t *gate) {
-    return scan_impl<long long, false>(P, in, out, n, s, gate);
+                             const int32_t *gate, const int32_t *dn) {
+    return scan_impl<long long, false>(P, in, out, n, s, gate, dn);
 }
 
 }  // namespace hq
