@@ -155,6 +155,74 @@ __device__ inline bool key_less(unsigned long long ka, unsigned int va, unsigned
     return ka < kb || (ka == kb && va < vb);
 }
 
+// Length of the common prefix of the keys (code, position in the body) at i
+// and j; -1 outside the body.
+template <typename CodePtr>
+__device__ inline int prefix_len(CodePtr sc, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    unsigned long long a = sc[i], b = sc[j];
+    if (a != b) return __clzll((long long)(a ^ b));
+    return 64 + __clz(i ^ j);
+}
+
+// Internal node i of one body in Karras' construction over the body's sorted
+// codes sc (global memory or LDS), n beads, first bead base, first internal
+// node g0: its children, parent links, bead range and walk words.
+template <typename CodePtr>
+__device__ __forceinline__ void karras_node(CodePtr sc, int n, int i, int base, int g0, int j, int32_t *lc,
+                                            int32_t *rc, int32_t *par, int32_t *first, int32_t *last, int32_t *nn,
+                                            int32_t *nbody, int32_t *leafpar, int2 *lw) {
+    const int g = g0 + i;
+    const int d = (prefix_len(sc, n, i, i + 1) - prefix_len(sc, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = prefix_len(sc, n, i, i - d);
+    int lmax = 2;
+    while (prefix_len(sc, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(sc, n, i, i + (l + t) * d) > dmin) l += t;
+    const int jj = i + l * d;
+    const int dnode = prefix_len(sc, n, i, jj);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(sc, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int gamma = i + s * d + min(d, 0);
+    const int lo = min(i, jj), hi = max(i, jj);
+    int left, right;
+    if (lo == gamma) {
+        left = -(base + gamma) - 1;
+        leafpar[base + gamma] = g;
+    } else {
+        left = g0 + gamma;
+        par[left] = g;
+    }
+    if (hi == gamma + 1) {
+        right = -(base + gamma + 1) - 1;
+        leafpar[base + gamma + 1] = g;
+    } else {
+        right = g0 + gamma + 1;
+        par[right] = g;
+    }
+    lc[g] = left;
+    rc[g] = right;
+    first[g] = base + lo;
+    last[g] = base + hi;
+    nn[g] = hi - lo + 1;
+    nbody[g] = j;
+    if (i == 0) {
+        par[g] = -1;
+        lw[g] = make_int2(-1, 0);
+    }
+    // residue rows that a walk from a child up to this node adds: this
+    // node's own residue rows, and the x subtree's rows for the y child
+    // (pre-order rows, Q~_p = [Residue_p; diag(Q~_x, Q~_y)])
+    const int xi = left >= 0, yi = right >= 0;
+    const int own = 3 * xi + 3 * yi;
+    if (xi) lw[left] = make_int2(g, own);
+    if (yi) lw[right] = make_int2(g, own + (xi ? 3 * (gamma - lo + 1) - 6 : 0));
+}
+
 // seg: (start, len, body) triples, len <= kSortChunk, longest first.  One block
 // of kSortThreads threads per segment pads it to the next power of two (at
 // least 128) and sorts it bitonically in LDS.  Pair p of a step with stride j
@@ -164,14 +232,18 @@ __device__ inline bool key_less(unsigned long long ka, unsigned int va, unsigned
 // barrier, only the wave's own ordering.  One launch covers all sizes, so the
 // latency of the longest segments overlaps the work on the short ones.
 // A segment of a whole body (body >= 0) writes sorted codes and the caller's
-// bead index; a chunk of a larger body (stored as ~body) writes keys and
-// values back in place for the merge passes.
+// bead index and builds the body's tree from the codes in LDS; a chunk of a
+// larger body (stored as ~body) writes keys and values back in place for the
+// merge passes (its tree is built after them).
 constexpr int kSortThreads = 256;
 
 __global__ void __launch_bounds__(kSortThreads) k_lds_sort(const int32_t *__restrict__ seg,
                                                            unsigned long long *keys, int32_t *vals,
                                                            const int32_t *__restrict__ bead_off,
-                                                           unsigned long long *scode, int32_t *perm) {
+                                                           unsigned long long *scode, int32_t *perm, int32_t *lc,
+                                                           int32_t *rc, int32_t *par, int32_t *first,
+                                                           int32_t *last, int32_t *nn, int32_t *nbody,
+                                                           int32_t *leafpar, int2 *lw) {
     __shared__ unsigned long long K[kSortChunk];
     __shared__ unsigned int V[kSortChunk];
     const int start = seg[3 * blockIdx.x], len = seg[3 * blockIdx.x + 1], bcode = seg[3 * blockIdx.x + 2];
@@ -222,6 +294,9 @@ __global__ void __launch_bounds__(kSortThreads) k_lds_sort(const int32_t *__rest
             scode[start + i] = K[i];
             perm[start + i] = base + (int)V[i];
         }
+        // the body's tree, from the sorted codes still in LDS
+        for (int i = threadIdx.x; i < len - 1; i += kSortThreads)
+            karras_node(K, len, i, base, base - body, body, lc, rc, par, first, last, nn, nbody, leafpar, lw);
     } else {
         for (int i = threadIdx.x; i < len; i += kSortThreads) {
             keys[start + i] = K[i];
@@ -291,80 +366,24 @@ __global__ void k_large_final(const int32_t *__restrict__ large, const int64_t *
 // ---------------------------------------------------------------------------
 // 3. binary radix tree (Karras 2012) over each body's sorted keys
 // ---------------------------------------------------------------------------
-__device__ inline int body_of_node(const int32_t *node_off, int m, int g) {
-    int lo = 0, hi = m - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (node_off[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Length of the common prefix of the keys (code, position) at i and j.
-__device__ inline int prefix_len(const unsigned long long *sc, int n, int i, int j) {
-    if (j < 0 || j >= n) return -1;
-    unsigned long long a = sc[i], b = sc[j];
-    if (a != b) return __clzll((long long)(a ^ b));
-    return 64 + __clz(i ^ j);
-}
-
-__global__ void k_tree(int64_t NI, int m, const int32_t *__restrict__ bead_off, const int32_t *__restrict__ node_off,
-                       const unsigned long long *__restrict__ scode, int32_t *lc, int32_t *rc, int32_t *par,
-                       int32_t *first, int32_t *last, int32_t *nn, int32_t *nbody, int32_t *leafpar, int2 *lw) {
-    for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
-        const int g = (int)gg;
-        const int j = body_of_node(node_off, m, g);
-        const int i = g - node_off[j];
+// Trees of the bodies sorted in chunks and merged (the large-body list with
+// its bead prefix; body li holds n - 1 internal nodes).
+__global__ void k_tree_large(const int32_t *__restrict__ large, const int64_t *__restrict__ prefix, int nlarge,
+                             int64_t total_nodes, const int32_t *__restrict__ bead_off,
+                             const unsigned long long *__restrict__ scode, int32_t *lc, int32_t *rc, int32_t *par,
+                             int32_t *first, int32_t *last, int32_t *nn, int32_t *nbody, int32_t *leafpar,
+                             int2 *lw) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total_nodes;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nlarge - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] - mid <= e) lo = mid; else hi = mid - 1;
+        }
+        const int j = large[lo];
         const int base = bead_off[j], n = bead_off[j + 1] - base;
-        const unsigned long long *sc = scode + base;
-        const int d = (prefix_len(sc, n, i, i + 1) - prefix_len(sc, n, i, i - 1)) > 0 ? 1 : -1;
-        const int dmin = prefix_len(sc, n, i, i - d);
-        int lmax = 2;
-        while (prefix_len(sc, n, i, i + lmax * d) > dmin) lmax <<= 1;
-        int l = 0;
-        for (int t = lmax >> 1; t >= 1; t >>= 1)
-            if (prefix_len(sc, n, i, i + (l + t) * d) > dmin) l += t;
-        const int jj = i + l * d;
-        const int dnode = prefix_len(sc, n, i, jj);
-        int s = 0, t = l;
-        do {
-            t = (t + 1) >> 1;
-            if (prefix_len(sc, n, i, i + (s + t) * d) > dnode) s += t;
-        } while (t > 1);
-        const int gamma = i + s * d + min(d, 0);
-        const int lo = min(i, jj), hi = max(i, jj);
-        int left, right;
-        if (lo == gamma) {
-            left = -(base + gamma) - 1;
-            leafpar[base + gamma] = g;
-        } else {
-            left = node_off[j] + gamma;
-            par[left] = g;
-        }
-        if (hi == gamma + 1) {
-            right = -(base + gamma + 1) - 1;
-            leafpar[base + gamma + 1] = g;
-        } else {
-            right = node_off[j] + gamma + 1;
-            par[right] = g;
-        }
-        lc[g] = left;
-        rc[g] = right;
-        first[g] = base + lo;
-        last[g] = base + hi;
-        nn[g] = hi - lo + 1;
-        nbody[g] = j;
-        if (i == 0) {
-            par[g] = -1;
-            lw[g] = make_int2(-1, 0);
-        }
-        // residue rows that a walk from a child up to this node adds: this
-        // node's own residue rows, and the x subtree's rows for the y child
-        // (pre-order rows, Q~_p = [Residue_p; diag(Q~_x, Q~_y)])
-        const int xi = left >= 0, yi = right >= 0;
-        const int own = 3 * xi + 3 * yi;
-        if (xi) lw[left] = make_int2(g, own);
-        if (yi) lw[right] = make_int2(g, own + (xi ? 3 * (gamma - lo + 1) - 6 : 0));
+        karras_node(scode + base, n, (int)(e - (prefix[lo] - lo)), base, base - j, j, lc, rc, par, first, last, nn,
+                    nbody, leafpar, lw);
     }
 }
 
@@ -1201,7 +1220,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     // --- 2. sort (chunks of large bodies and whole bodies in one launch)
     if (P.sort_segs.nseg > 0)
         hipLaunchKernelGGL(k_lds_sort, dim3(P.sort_segs.nseg), dim3(kSortThreads), 0, s, P.sort_segs.d_seg, P.d_keyA,
-                           P.d_valA, P.d_bead_off, P.d_scode, P.d_perm);
+                           P.d_valA, P.d_bead_off, P.d_scode, P.d_perm, P.d_lc, P.d_rc, P.d_par, P.d_first, P.d_last,
+                           P.d_nn, P.d_nbody, P.d_leafpar, P.d_lw);
     HQ_HIP(hipGetLastError());
     if (P.nlarge > 0) {
         unsigned long long *kin = P.d_keyA, *kout = P.d_keyB;
@@ -1217,10 +1237,13 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         hipLaunchKernelGGL(k_large_final, dim3(grid_for(P.large_elems)), dim3(kThreads), 0, s, P.d_large,
                            P.d_large_prefix, P.nlarge, P.large_elems, P.d_bead_off, kin, vin, P.d_scode, P.d_perm);
     }
-    // --- 3. tree
-    hipLaunchKernelGGL(k_tree, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, (int)m, P.d_bead_off, P.d_node_off,
-                       P.d_scode, P.d_lc, P.d_rc, P.d_par, P.d_first, P.d_last, P.d_nn, P.d_nbody, P.d_leafpar,
-                       P.d_lw);
+    // --- 3. tree (bodies sorted whole got theirs in the sort kernel)
+    if (P.nlarge > 0) {
+        const int64_t large_nodes = P.large_elems - P.nlarge;
+        hipLaunchKernelGGL(k_tree_large, dim3(grid_for(large_nodes)), dim3(kThreads), 0, s, P.d_large,
+                           P.d_large_prefix, P.nlarge, large_nodes, P.d_bead_off, P.d_scode, P.d_lc, P.d_rc, P.d_par,
+                           P.d_first, P.d_last, P.d_nn, P.d_nbody, P.d_leafpar, P.d_lw);
+    }
     HQ_HIP(hipGetLastError());
     // --- 4. tiles
     int phases = 0;
