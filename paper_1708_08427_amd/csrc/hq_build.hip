@@ -41,9 +41,22 @@ __device__ inline void raise_flag(int32_t *err, int f) { atomicOr(err, f); }
 // ---------------------------------------------------------------------------
 // initialisation
 // ---------------------------------------------------------------------------
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+
+// Per-build reset of the node arrays the tiling fills in, the counters and
+// the phase tables.
+__global__ void k_init_nodes(int64_t NI, int32_t *cov, int32_t *tileof, int32_t *sched_node, int32_t *cnt,
+                             int32_t *phase_tab, int32_t *prun) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t g = i0; g < NI; g += (int64_t)gridDim.x * blockDim.x) {
+        cov[g] = 0;
+        tileof[g] = -1;
+        sched_node[g] = -1;
+    }
+    for (int64_t i = i0; i < kPrunStride * kMaxPhases; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < kCntNum) cnt[i] = 0;
+        if (i < 2 * kMaxPhases) phase_tab[i] = 0;
+        prun[i] = 0;
+    }
 }
 
 __global__ void k_init_bodies(int64_t m, unsigned long long *bmin, unsigned long long *bmax,
@@ -644,12 +657,39 @@ __global__ void k_check_phases(int32_t *cnt, int32_t *err) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[kCntRemain] != 0) raise_flag(err, kFlagPhases);
 }
 
+// First residue row of every tile root (pre-order rows, Section 3's
+// Q~_p = [Residue_p; diag(Q~_x, Q~_y)]): its walk up to the body root.  Other
+// nodes then only walk up to their own tile root.
+__global__ void k_troot_off(int64_t NI, const int32_t *cnt, const int32_t *tile_root, const int2 *lw,
+                            const int32_t *nbody, const int32_t *row_off, int32_t *toff, int32_t *err) {
+    const int nt = cnt[kCntTiles];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int r = tile_root[t];
+        if (r < 0 || r >= NI) {
+            raise_flag(err, kFlagBounds);
+            continue;
+        }
+        int off = 0, q = r;
+        for (int guard = 0;; ++guard) {
+            if (guard == kMaxDepth) {
+                raise_flag(err, kFlagBounds);
+                break;
+            }
+            const int2 w = lw[q];
+            if (w.x < 0) break;
+            off += w.y;
+            q = w.x;
+        }
+        toff[t] = off + row_off[nbody[r]];
+    }
+}
+
 // Links of every node: child references, residue row (pre-order, Section 3's
 // Q~_p = [Residue_p; diag(Q~_x, Q~_y)]) and flags.
 __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, const int32_t *sched,
                         const int32_t *lc, const int32_t *rc, const int32_t *par, const int32_t *nn,
                         const int32_t *nbody, const int32_t *yfirst, const int32_t *tile_root,
-                        const int32_t *perm, const int32_t *row_off, const int32_t *depth_slot, int dstack,
+                        const int32_t *perm, const int32_t *toff, const int32_t *depth_slot, int dstack,
                         const int2 *lw, int32_t *links, int32_t *err) {
     for (int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gg < NI; gg += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)gg;
@@ -663,18 +703,20 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
             else if (cov[x] == cov[g] && tileof[x] == t) ref[c] = kRefStack;
             else ref[c] = -2 - tileof[x];
         }
+        // residue rows before this node: the walk up to its tile root, plus
+        // the tile root's own offset
+        const int r = (t >= 0 && t < NI) ? tile_root[t] : -1;
         int off = 0, q = g;
-        for (int guard = 0; guard <= kMaxDepth; ++guard) {
-            if (guard == kMaxDepth) {
+        for (int guard = 0; q != r; ++guard) {
+            if (guard == kMaxDepth || q < 0) {
                 raise_flag(err, kFlagBounds);
                 break;
             }
             const int2 w = lw[q];
-            if (w.x < 0) break;
             off += w.y;
             q = w.x;
         }
-        off += row_off[nbody[g]];
+        if (r >= 0) off += toff[t];
         int meta = 0;
         if (tile_root[t] == g) meta |= kMetaTileRoot | (t << kMetaSlotShift);
         if (par[g] < 0) meta |= kMetaBodyRoot;
@@ -1207,12 +1249,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     // --- init
     hipLaunchKernelGGL(k_init_bodies, dim3(grid_for(m)), dim3(kThreads), 0, s, m, P.d_bmin, P.d_bmax, P.d_kappa,
                        P.d_bflags);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_cov, NI, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_tileof, NI, -1);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NI)), dim3(kThreads), 0, s, P.d_sched_node, NI, -1);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, P.d_cnt, (int64_t)kCntNum, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_phase, (int64_t)(2 * kMaxPhases), 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, P.d_prun, (int64_t)(kPrunStride * kMaxPhases), 0);
+    hipLaunchKernelGGL(k_init_nodes, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof,
+                       P.d_sched_node, P.d_cnt, P.d_phase, P.d_prun);
     // --- 1. boxes and codes
     hipLaunchKernelGGL(k_bbox, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, P.d_bmin, P.d_bmax, P.d_err);
     hipLaunchKernelGGL(k_codes, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, P.d_bead_off, pos, P.d_bmin,
@@ -1300,9 +1338,13 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     }
     if (probe_phases) P.phases_built = phases;
     hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
+    // the compaction flags are free again: they hold the tile roots' offsets
+    int32_t *toff = P.d_mark;
+    hipLaunchKernelGGL(k_troot_off, dim3(std::min(grid_for(NI), 2048u)), dim3(kThreads), 0, s, NI, P.d_cnt,
+                       P.d_tile_root, P.d_lw, P.d_nbody, P.d_row_off, toff, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
-                       P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm,
-                       P.d_row_off, P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_err);
+                       P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm, toff,
+                       P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_err);
     // --- 5. transforms, one launch per tile phase; later phases read the
     // roots of earlier phases' tiles from the tile-root table (sized after
     // the first build: twice its tiles, the capacity of the exchange buffer)
