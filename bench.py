@@ -81,19 +81,37 @@ def probe(hq, torch, wl, f, args):
     f32 = torch.from_numpy(f).float().to(dev)
     tmp = torch.empty((wl.rows, wl.nrhs), dtype=torch.float32, device=dev)
     out = torch.empty((3 * wl.N, wl.nrhs), dtype=torch.float32, device=dev)
-    h = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=2)
+    h = hq.build(pos, wl.offsets, store=2, **fixed_options(args))
     for _ in range(PROBE_SWEEPS):
         h.apply(f32, out=tmp)
     for _ in range(PROBE_SWEEPS):
         h.apply(tmp, transpose=True, out=out)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "done", "algorithmic_bytes": algorithmic_bytes(h, wl.nrhs), "phases": h.query()["phases"]}),
-          flush=True)
+    print(json.dumps({"probe": "done", "algorithmic_bytes": algorithmic_bytes(h, wl.nrhs), "phases": h.query()["phases"],
+                      "options": options_tag(fixed_options(args))}), flush=True)
 
 
-def traffic_from_profile():
+def fixed_options(args):
+    return {"tile_units": args.tile_units, "run_nodes": args.run_nodes, "waves_per_cu": args.waves_per_cu}
+
+
+DEFAULT_OPTIONS = {"tile_units": 32, "run_nodes": 48, "waves_per_cu": 16}  # the library's defaults for 0
+
+
+def effective(opts):
+    return {k: int(opts.get(k) or v) for k, v in DEFAULT_OPTIONS.items()}
+
+
+def options_tag(opts):
+    """The launch configuration a counter summary belongs to."""
+    e = effective(opts)
+    return ",".join(f"{k}={e[k]}" for k in DEFAULT_OPTIONS)
+
+
+def traffic_from_profile(opts):
     """HBM bytes of one upward sweep from the committed counter summary, if it
-    was taken on the current sweep sources (else None)."""
+    was taken on the current sweep sources in the same launch configuration
+    (else None)."""
     from paper_1708_08427_amd.traffic import sweep_source_hash
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
@@ -102,6 +120,8 @@ def traffic_from_profile():
         prof = json.load(fh)
     if prof.get("source_sha256") != sweep_source_hash():
         return None, "sweep sources changed since the counters were taken"
+    if prof.get("options") != options_tag(opts):
+        return None, f"counters taken with {prof.get('options')}, bench runs {options_tag(opts)}"
     return prof["up_sweep"]["hbm_bytes"], prof["command"]
 
 
@@ -110,7 +130,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tile-units", type=int, default=32)
+    ap.add_argument("--tile-units", type=int, default=0, help="0: autotuned (with run length and waves per CU)")
+    ap.add_argument("--run-nodes", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="library defaults for options left at 0")
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
@@ -151,10 +174,20 @@ def main():
         out = torch.empty((3 * N, R), dtype=torch.float32, device=dev)
         rot_d = torch.from_numpy(rot.reshape(total_steps, m, 9)).to(dev)
         trans_d = torch.from_numpy(trans).to(dev)
+        # launch configuration: given, or picked by the autotuner for this
+        # workload (rebuild + both sweeps, FP32, R right-hand sides)
+        opts = fixed_options(args)
+        autotuned = False
+        if not args.no_autotune and args.tile_units == 0:
+            t0 = time.perf_counter()
+            tuned = hq.autotune(pos, wl.offsets, R, torch.float32, include_rebuild=True, stream=stream)
+            opts = {k: tuned[k] for k in opts}
+            autotuned = True
+            log(f"autotune {1e3 * (time.perf_counter() - t0):.0f} ms: {opts}, {tuned['ms']:.3f} ms per round")
         t0 = time.perf_counter()
         # the step applies in FP32, so only the FP32 copy of the FP64-generated
         # transforms is kept; the FP64 sweep is timed on its own handle below
-        h = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=2, stream=stream)
+        h = hq.build(pos, wl.offsets, store=2, stream=stream, **opts)
         torch.cuda.synchronize()
         log(f"first build {1e3 * (time.perf_counter() - t0):.1f} ms; {h.query()}")
         h.reserve(R, torch.float32)
@@ -223,13 +256,13 @@ def main():
         t_rb = timed(lambda: h.rebuild(pos, stream=stream), 5)
         f64 = f32.double()
         tmp64 = torch.empty((wl.rows, R), dtype=torch.float64, device=dev)
-        h64 = hq.build(pos, wl.offsets, tile_units=args.tile_units, store=1, stream=stream)
+        h64 = hq.build(pos, wl.offsets, store=1, stream=stream, **opts)
         t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream), 5)
         h64.destroy()
         log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms, up FP64 {t_up64:.3f} ms")
         nbytes = algorithmic_bytes(h, R)
         achieved = nbytes / (t_up * 1e-3) / 1e9
-        traffic, traffic_src = traffic_from_profile()
+        traffic, traffic_src = traffic_from_profile(opts)
         log(f"traffic: {traffic} ({traffic_src})")
         q = h.query()
 
@@ -247,7 +280,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"bd_step_m{m}_lognormal500_R{R}", "bodies": m, "beads": N, "nrhs": R,
-                   "rows": wl.rows, "tile_units": args.tile_units,
+                   "rows": wl.rows, **effective(opts), "autotuned": autotuned,
                    "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

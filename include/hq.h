@@ -87,6 +87,10 @@ typedef struct {
     int32_t store;         /* transforms kept: 1 = FP64, 2 = FP32, 3 or 0 = both */
     int32_t explicit_dense_max_n; /* largest n_j for hq_explicit; 0 = 4096 */
     int32_t max_phases;    /* tile phases reserved for hq_rebuild; 0 = found at build + 2 */
+    int32_t run_nodes;     /* nodes per run of whole tiles swept by one lane group in the
+                              first phase of a wide sweep (>= 32 RHS); 0 = 48; 8..4096 */
+    int32_t waves_per_cu;  /* grid of the later tile phases' sweeps, in waves per compute
+                              unit; 0 = 16; 1..64 */
 } hq_options;
 
 typedef struct {
@@ -103,6 +107,24 @@ typedef struct {
     int64_t ill_conditioned_bodies;
     int64_t degenerate_bodies;
 } hq_info;
+
+/* Pick tile_units, run_nodes and waves_per_cu for a workload by measurement:
+ * the subtree size of Section 2's tree cut into tiles, and the launch shape of
+ * the sweeps (Algorithms 2 and 3).  For every candidate, builds a handle on
+ * the given positions, then times (median of 5 after 2 warm-up rounds, HIP
+ * events on the stream) one round of: hq_rebuild if include_rebuild, an
+ * upward and a downward hq_apply with nrhs right-hand sides in precision
+ * prec.  Candidates: tile_units 16, 32, 64; run_nodes 32, 48, 64; waves_per_cu
+ * 8, 16, 32.
+ *   positions, body_offsets, m  as for hq_build.
+ *   base          host, may be NULL: the other options of the trial builds.
+ *   best          host: receives base with the three chosen fields set.
+ *   best_ms       host, may be NULL: the chosen candidate's time per round.
+ * Allocates (and frees) trial handles and two vector buffers; synchronises
+ * the stream.  Errors as for hq_build and hq_apply. */
+hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int64_t m, int64_t nrhs,
+                      hq_precision prec, int include_rebuild, const hq_options *base, hq_stream stream,
+                      hq_options *best, double *best_ms);
 
 /* Build the tree and the FP64 local transforms of m bodies.
  *   positions     device, N x 3 FP64, x,y,z interleaved, caller's bead order.

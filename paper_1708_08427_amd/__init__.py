@@ -16,6 +16,7 @@ Generation and Matrix-Vector Multiplications in Rigid Body Simulations"
 from __future__ import annotations
 
 import ctypes
+import hashlib
 
 import numpy as np
 
@@ -220,9 +221,7 @@ class Handle:
         return a
 
 
-def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max_phases=0, stream=None):
-    """Build the tree and FP64 transforms for bodies given by ``offsets``
-    (host, m + 1 int64) over ``positions`` (device, N x 3 float64)."""
+def _offsets(positions, offsets):
     _check_dev(positions, "positions")
     torch = _torch()
     if positions.dtype != torch.float64:
@@ -232,12 +231,53 @@ def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max
         raise ValueError("offsets must hold m + 1 entries")
     if positions.dim() != 2 or positions.shape[1] != 3 or positions.shape[0] != int(off[-1]):
         raise ValueError("positions must be N x 3 with N = offsets[-1]")
-    opt = Options(int(tile_units), int(store), int(explicit_dense_max_n), int(max_phases))
+    return off
+
+
+def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max_phases=0, run_nodes=0,
+          waves_per_cu=0, stream=None):
+    """Build the tree and FP64 transforms for bodies given by ``offsets``
+    (host, m + 1 int64) over ``positions`` (device, N x 3 float64)."""
+    off = _offsets(positions, offsets)
+    opt = Options(int(tile_units), int(store), int(explicit_dense_max_n), int(max_phases), int(run_nodes),
+                  int(waves_per_cu))
     raw = ctypes.c_void_p()
     lib = _lib.load()
     _check(lib.hq_build(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, ctypes.byref(opt),
                         _stream(stream), ctypes.byref(raw)), "hq_build")
     return Handle(raw, off)
+
+
+_TUNED = {}
+
+
+def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=None, **base):
+    """hq_autotune: the tile size, run length and later-phase waves per CU
+    with the shortest measured (rebuild +) upward + downward round for this
+    workload.  Returns a dict of hq_options fields plus ``ms``; results are
+    remembered per (offsets, nrhs, dtype, include_rebuild, base options) for
+    the life of the process."""
+    torch = _torch()
+    dtype = dtype or torch.float32
+    off = _offsets(positions, offsets)
+    key = (hashlib.sha1(off.tobytes()).hexdigest(), int(nrhs), str(dtype), bool(include_rebuild),
+           tuple(sorted(base.items())))
+    if key in _TUNED:
+        return dict(_TUNED[key])
+    names = [f for f, _ in Options._fields_]
+    unknown = set(base) - set(names)
+    if unknown:
+        raise TypeError(f"unknown options {sorted(unknown)}")
+    b = Options(*[int(base.get(f, 0)) for f in names])
+    best = Options()
+    ms = ctypes.c_double()
+    _check(_lib.load().hq_autotune(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, int(nrhs),
+                                   _prec(dtype), int(bool(include_rebuild)), ctypes.byref(b), _stream(stream),
+                                   ctypes.byref(best), ctypes.byref(ms)), "hq_autotune")
+    res = {f: getattr(best, f) for f in names}
+    res["ms"] = ms.value
+    _TUNED[key] = res
+    return dict(res)
 
 
 def capture_begin(stream=None):

@@ -21,7 +21,8 @@ HQ_BODY_ILLCOND, HQ_BODY_DEGENERATE = 1, 2
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("tile_units", c_i32), ("store", c_i32), ("explicit_dense_max_n", c_i32), ("max_phases", c_i32)]
+    _fields_ = [("tile_units", c_i32), ("store", c_i32), ("explicit_dense_max_n", c_i32), ("max_phases", c_i32),
+                ("run_nodes", c_i32), ("waves_per_cu", c_i32)]
 
 
 class Info(ctypes.Structure):
@@ -33,6 +34,8 @@ class Info(ctypes.Structure):
 # (name, restype, argtypes) of every exported function
 SIGNATURES = [
     ("hq_build", c_i32, [c_vp, P_i64, c_i64, ctypes.POINTER(Options), c_vp, ctypes.POINTER(c_vp)]),
+    ("hq_autotune", c_i32, [c_vp, P_i64, c_i64, c_i64, c_i32, ctypes.c_int, ctypes.POINTER(Options), c_vp,
+                            ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)]),
     ("hq_rebuild", c_i32, [c_vp, c_vp, c_vp]),
     ("hq_reserve", c_i32, [c_vp, c_i64, c_i32]),
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),

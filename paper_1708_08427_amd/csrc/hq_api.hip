@@ -78,7 +78,14 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     }
     P.rows = P.row_off[m];
     P.S = (opt && opt->tile_units) ? opt->tile_units : 32;
-    if (const char *e = getenv("HQ_RUN_NODES")) P.run_nodes = std::max(16, atoi(e));
+    if (opt && opt->run_nodes) P.run_nodes = opt->run_nodes;
+    if (opt && opt->waves_per_cu) P.waves_per_cu = opt->waves_per_cu;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            P.ncu = ncu;
+    }
     P.store = (opt && opt->store) ? opt->store : 3;
     P.dense_max_n = (opt && opt->explicit_dense_max_n) ? opt->explicit_dense_max_n : 4096;
     P.phases_reserved = (opt && opt->max_phases) ? opt->max_phases : 0;
@@ -307,6 +314,14 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
             set_error("explicit_dense_max_n must be >= 0");
             return HQ_E_INVALID;
         }
+        if (opt->run_nodes != 0 && (opt->run_nodes < 8 || opt->run_nodes > 4096)) {
+            set_error("run_nodes must be 0 or in [8, 4096]");
+            return HQ_E_INVALID;
+        }
+        if (opt->waves_per_cu != 0 && (opt->waves_per_cu < 1 || opt->waves_per_cu > 64)) {
+            set_error("waves_per_cu must be 0 or in [1, 64]");
+            return HQ_E_INVALID;
+        }
     }
     Plan *P = new (std::nothrow) Plan;
     if (!P) {
@@ -339,6 +354,103 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
         return st;
     }
     *out = reinterpret_cast<hq_handle>(P);
+    return HQ_OK;
+}
+
+hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int64_t m, int64_t nrhs,
+                      hq_precision prec, int include_rebuild, const hq_options *base, hq_stream stream,
+                      hq_options *best, double *best_ms) {
+    if (!best) {
+        set_error("best is NULL");
+        return HQ_E_INVALID;
+    }
+    if (nrhs < 1 || nrhs > (1 << 20) || (prec != HQ_FP64 && prec != HQ_FP32)) {
+        set_error("nrhs must be in [1, 2^20] and prec HQ_FP64 or HQ_FP32");
+        return HQ_E_INVALID;
+    }
+    if (!body_offsets || m < 1) {
+        set_error("body_offsets is NULL or m < 1");
+        return HQ_E_INVALID;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hq_options opt = base ? *base : hq_options{};
+    opt.store = (prec == HQ_FP64) ? 1 : 2;
+    const int64_t N = body_offsets[m];
+    int64_t rows = 0;
+    for (int64_t j = 0; j < m; ++j) rows += 3 * (body_offsets[j + 1] - body_offsets[j]) - 6;
+    const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
+    const size_t vbytes = (size_t)std::max<int64_t>(3 * N, std::max<int64_t>(rows, 1)) * (size_t)nrhs * elem;
+    void *va = nullptr, *vb = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hq_status st = HQ_OK;
+    auto fail = [&](hq_status code, const std::string &msg) {
+        set_error(msg);
+        st = code;
+    };
+    if (hipMalloc(&va, vbytes) != hipSuccess || hipMalloc(&vb, vbytes) != hipSuccess) {
+        fail(HQ_E_NOMEM, "hipMalloc of the autotune vectors");
+    } else if (hipMemsetAsync(va, 0, vbytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess) {
+        fail(HQ_E_DEVICE, "autotune setup");
+    }
+    const int s_cand[] = {16, 32, 64}, r_cand[] = {32, 48, 64}, w_cand[] = {8, 16, 32};
+    double best_t = 1e300;
+    hq_options chosen = opt;
+    for (int si = 0; si < 3 && st == HQ_OK; ++si) {
+        for (int ri = 0; ri < 3 && st == HQ_OK; ++ri) {
+            hq_options o = opt;
+            o.tile_units = s_cand[si];
+            o.run_nodes = r_cand[ri];
+            hq_handle h = nullptr;
+            hq_status bs = hq_build(positions, body_offsets, m, &o, stream, &h);
+            if (bs != HQ_OK) {
+                st = bs;
+                break;
+            }
+            Plan *P = get_plan(h);
+            for (int wi = 0; wi < 3 && st == HQ_OK; ++wi) {
+                P->waves_per_cu = w_cand[wi];
+                double ts[5];
+                for (int rep = 0; rep < 7 && st == HQ_OK; ++rep) {
+                    if (hipEventRecord(e0, s) != hipSuccess) fail(HQ_E_DEVICE, "hipEventRecord");
+                    hq_status a = HQ_OK;
+                    if (include_rebuild) a = hq_rebuild(h, positions, stream);
+                    if (a == HQ_OK) a = hq_apply(h, va, vb, 0, nrhs, prec, stream);
+                    if (a == HQ_OK) a = hq_apply(h, vb, va, 1, nrhs, prec, stream);
+                    if (a != HQ_OK) {
+                        st = a;
+                        break;
+                    }
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        fail(HQ_E_DEVICE, "autotune timing");
+                        break;
+                    }
+                    if (rep >= 2) ts[rep - 2] = ms;
+                }
+                if (st != HQ_OK) break;
+                std::sort(ts, ts + 5);
+                if (ts[2] < best_t) {
+                    best_t = ts[2];
+                    chosen = o;
+                    chosen.waves_per_cu = w_cand[wi];
+                }
+            }
+            int32_t flags = 0;
+            if (st == HQ_OK && hipMemcpy(&flags, P->d_err, sizeof flags, hipMemcpyDeviceToHost) == hipSuccess && flags)
+                fail(HQ_E_DEVICE, "device flags raised during autotuning: " + std::to_string(flags));
+            hq_destroy(h);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (va) (void)hipFree(va);
+    if (vb) (void)hipFree(vb);
+    if (st != HQ_OK) return st;
+    chosen.store = base ? base->store : 0;
+    *best = chosen;
+    if (best_ms) *best_ms = best_t;
     return HQ_OK;
 }
 

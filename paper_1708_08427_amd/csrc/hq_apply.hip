@@ -22,7 +22,6 @@
 #include "hq_buffer.h"
 #include "hq_common.h"
 
-#include <cstdlib>
 
 namespace hq {
 
@@ -563,12 +562,9 @@ __device__ __forceinline__ float row_bcast(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + W, 0xf, 0xf, true));
 }
 
-#ifndef HQ_DPP_WORDS
-#define HQ_DPP_WORDS 12
-#endif
 // record words below kDppWords are broadcast with DPP (VALU), the rest with
 // ds_swizzle (LDS), to balance the two pipes
-constexpr int kDppWords = HQ_DPP_WORDS;
+constexpr int kDppWords = 12;
 
 template <>
 struct RecReg<float> {
@@ -1120,8 +1116,7 @@ template <typename T, int LPT, int NC>
 void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
                  hipStream_t s) {
     constexpr int TPW = 64 / LPT;
-    size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
-    if (const char *e = getenv("HQ_LDS_PAD")) lds_w += (size_t)atoll(e);
+    const size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
     // work items: groups of TPW runs (a phase has at most NI / run_nodes + 1
     // runs, or kRunTarget + 1 when its runs are shortened) x RHS chunks, one
     // per wave, so the dispatcher balances the load; waves of later phases
@@ -1129,9 +1124,8 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     const int64_t nrun_max = std::max<int64_t>(P.NI / P.run_nodes + 2, kRunTarget + 2);
     const int64_t items = ((nrun_max + TPW - 1) / TPW) * (int64_t)C.nchunks;
     // later phases hold few runs (often none, for phases reserved for a
-    // rebuild): a grid of one wave per 2 CUs' worth of slots loops over them
-    int64_t g = (phase == 1) ? items : std::min<int64_t>(items, 4096);
-    if (const char *e = getenv("HQ_APPLY_GRID")) g = std::max<int64_t>(1, atoll(e));
+    // rebuild): a grid of waves_per_cu waves per CU loops over them
+    const int64_t g = (phase == 1) ? items : std::min<int64_t>(items, (int64_t)P.waves_per_cu * P.ncu);
     const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
 #define HQ_WIDE(RT, PR, NR, PR1, NR1, NRD, NRD2)                                                             \
     do {                                                                                                     \
@@ -1167,8 +1161,7 @@ void launch_narrow(const Plan &P, int phase, int transpose, const T *rec, const 
     constexpr int TPW = 64 / LPT;
     // one wave per work item of the largest phase (tile groups x RHS chunks);
     // waves without work exit at once
-    int64_t items = ((2 * P.tiles_built + 64 + TPW - 1) / TPW) * (int64_t)C.nchunks;
-    if (const char *e = getenv("HQ_APPLY_GRID")) items = std::max<int64_t>(1, atoll(e));
+    const int64_t items = ((2 * P.tiles_built + 64 + TPW - 1) / TPW) * (int64_t)C.nchunks;
     const unsigned grid = (unsigned)std::min<int64_t>(items, 1 << 20);
     if (!transpose)
         hipLaunchKernelGGL((k_up<T, LPT>), dim3(grid), dim3(64), lds, s, phase, P.d_phase, P.d_tile_base,
@@ -1230,10 +1223,6 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
     // run lengths and to LDS-limited occupancy than they save in VALU work);
     // otherwise, or beyond the buffer range, narrow sweeps
     int lpt = lanes_per_tile(nrhs);
-    if (const char *e = getenv("HQ_LPT")) {
-        const int q = atoi(e);
-        if (q == 1 || q == 2 || q == 4 || q == 8 || q == 16 || q == 32 || q == 64) lpt = q;
-    }
     if (lpt >= 32 && !wide_ok) lpt = 16;
     SweepKind kind;
     const int cols = lpt;  // right-hand sides per chunk

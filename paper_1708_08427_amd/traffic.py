@@ -63,6 +63,7 @@ def main():
     ap.add_argument("write_dir")
     ap.add_argument("out")
     ap.add_argument("--command", required=True)
+    ap.add_argument("--options", required=True, help="launch configuration of the probe (its 'options' field)")
     a = ap.parse_args()
     cf, uf, df = summarise(_read(a.fetch_dir, "FETCH_SIZE"))
     cw, uw, dw = summarise(_read(a.write_dir, "WRITE_SIZE"))
@@ -71,6 +72,7 @@ def main():
     res = {
         "command": a.command,
         "source_sha256": sweep_source_hash(),
+        "options": a.options,
         "copy": {"bytes_each_way": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
                  "fetch_factor": ff, "write_factor": fw},
         "up_sweep": {"fetch_kib": uf, "write_kib": uw,
