@@ -91,6 +91,9 @@ typedef struct {
                               first phase of a wide sweep (>= 32 RHS); 0 = 48; 8..4096 */
     int32_t waves_per_cu;  /* grid of the later tile phases' sweeps, in waves per compute
                               unit; 0 = 16; 1..64 */
+    int32_t keep_node_data;/* 1: hq_rebuild also refreshes the per-node centroids and T22
+                              that hq_node_data returns (hq_build always writes them);
+                              0: it skips them (less memory traffic) */
 } hq_options;
 
 typedef struct {
@@ -209,7 +212,8 @@ hq_status hq_body_info(hq_handle h, int32_t *flags, double *kappa);
  * the children (>= 0: node index; < 0: -(sorted position within body) - 1),
  * body index, beads below, centroid (3, body-local: relative to the body's
  * lower corner), T22 (9, row-major), G (81, row-major k x k in the top-left),
- * k, and the first residue row within the body.  Synchronises. */
+ * k, and the first residue row within the body.  Synchronises.  Centroids and
+ * T22 after an hq_rebuild need hq_options.keep_node_data (else HQ_E_INVALID). */
 hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchild,
                        int32_t *ychild, int32_t *body, int32_t *nbeads, double *centroid,
                        double *T22, double *G, int32_t *k, int32_t *row);

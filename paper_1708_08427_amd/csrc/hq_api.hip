@@ -80,6 +80,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     P.S = (opt && opt->tile_units) ? opt->tile_units : 32;
     if (opt && opt->run_nodes) P.run_nodes = opt->run_nodes;
     if (opt && opt->waves_per_cu) P.waves_per_cu = opt->waves_per_cu;
+    P.keep_node_data = opt && opt->keep_node_data != 0;
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -316,6 +317,10 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
         }
         if (opt->run_nodes != 0 && (opt->run_nodes < 8 || opt->run_nodes > 4096)) {
             set_error("run_nodes must be 0 or in [8, 4096]");
+            return HQ_E_INVALID;
+        }
+        if (opt->keep_node_data != 0 && opt->keep_node_data != 1) {
+            set_error("keep_node_data must be 0 or 1");
             return HQ_E_INVALID;
         }
         if (opt->waves_per_cu != 0 && (opt->waves_per_cu < 1 || opt->waves_per_cu > 64)) {
@@ -713,6 +718,10 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
                        int32_t *nbeads, double *centroid, double *T22, double *G, int32_t *k, int32_t *row) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
+    if ((centroid || T22) && !P->node_data_fresh) {
+        set_error("centroids and T22 after hq_rebuild need hq_options.keep_node_data = 1");
+        return HQ_E_INVALID;
+    }
     const int64_t NI = P->NI;
     HQ_HIP(hipDeviceSynchronize());
     std::vector<int32_t> lc(NI), rc(NI), nbody(NI), fst(NI), lst(NI), nn(NI), sched(NI);

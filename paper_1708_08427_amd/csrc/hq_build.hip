@@ -989,7 +989,7 @@ __device__ __forceinline__ void load_links(const int32_t *links, int64_t s, int3
 // prologue of the node loop issues the same stores switched off, so that the
 // compiler sees the same number of stores in flight on entry to the loop as
 // on its back edge and waits for loads only.
-template <int kStore>
+template <int kStore, bool kNodes>
 __device__ __forceinline__ void gen_store(rsrc_t r32, rsrc_t r64, rsrc_t rcen, rsrc_t rt22, rsrc_t rtr, rsrc_t rbc,
                                           uint32_t rel, uint32_t trel, uint32_t brel, const float (&w32)[26],
                                           const double (&w64)[26], const int32_t (&li)[kLinkInts],
@@ -1021,20 +1021,26 @@ __device__ __forceinline__ void gen_store(rsrc_t r32, rsrc_t r64, rsrc_t rcen, r
                                                r64, o + 208, 0, 0);
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)li[4], (uint32_t)li[5]}, r64, o + 224, 0, 0);
     }
-    const uint32_t oc = scaled(rel, 24u), ot = scaled(rel, 48u);
+    auto pair = [](double a, double b) {
+        const u32x2 x = __builtin_bit_cast(u32x2, a), y = __builtin_bit_cast(u32x2, b);
+        return u32x4{x.x, x.y, y.x, y.y};
+    };
+    if (kNodes) {
+        const uint32_t oc = scaled(rel, 24u), ot = scaled(rel, 48u);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, cp[0]), rcen, oc, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(pair(cp[1], cp[2]), rcen, oc + 8, 0, 0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, cp[d]), rcen, oc + 8 * d, 0, 0);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, T[d]), rt22, ot + 8 * d, 0, 0);
+        for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b128(pair(T[2 * d], T[2 * d + 1]), rt22, ot + 16 * d, 0, 0);
+    }
     // tile root: (n, c, T22) for the phases above
     const uint32_t otr = scaled(trel, 80u);
 #pragma unroll
-    for (int e = 0; e < kGenWords; ++e)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, tv[e]), rtr, otr + 8 * e, 0, 0);
+    for (int e = 0; e < kGenWords / 2; ++e)
+        __builtin_amdgcn_raw_buffer_store_b128(pair(tv[2 * e], tv[2 * e + 1]), rtr, otr + 16 * e, 0, 0);
     // body root: the body's centroid (absolute)
     const uint32_t ob = scaled(brel, 24u);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, bc[d]), rbc, ob + 8 * d, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(pair(bc[0], bc[1]), rbc, ob, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, bc[2]), rbc, ob + 16, 0, 0);
 }
 
 // Records, node data and tile-root entries leave through buffer stores whose
@@ -1043,7 +1049,7 @@ __device__ __forceinline__ void gen_store(rsrc_t r32, rsrc_t r64, rsrc_t rcen, r
 // 2 GiB); a lane with nothing to write gets the offset kOOB.  Every store is
 // therefore issued unconditionally and waiting for the next node's children
 // never waits for this node's stores.
-template <bool kLater, int kStore>
+template <bool kLater, int kStore, bool kNodes>
 __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase_tab, const int32_t *tile_base,
                                                  const int32_t *tile_len, const int32_t *tile_root,
                                                  const int32_t *links, const int32_t *nbody, const double *pos,
@@ -1118,7 +1124,7 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
         {
             const float z32[26] = {};
             const double z64[26] = {}, z3[3] = {}, z6[6] = {}, z10[kGenWords] = {};
-            gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, kOOB, kOOB, kOOB, z32, z64, li, z3, z6, z10, z3);
+            gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, kOOB, kOOB, kOOB, z32, z64, li, z3, z6, z10, z3);
         }
         while (__ballot(s < se)) {
             const bool act = s < se, actn = s + 1 < se;
@@ -1198,7 +1204,7 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
                 const uint32_t rel = (uint32_t)(s - s0);
                 const double tv[kGenWords] = {n, cp[0], cp[1], cp[2], T[0], T[1], T[2], T[3], T[4], T[5]};
                 const double bc[3] = {cp[0] + lo3[0], cp[1] + lo3[1], cp[2] + lo3[2]};
-                gen_store<kStore>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - tr0) : kOOB,
+                gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - tr0) : kOOB,
                                   (act && body_root) ? (uint32_t)(body - b0) : kOOB, w32, w64, li, cp, T, tv, bc);
             }
 #pragma unroll
@@ -1363,9 +1369,17 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     const int nslot = stack_slots(P.S);
     const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double);
     const unsigned gen_grid = (unsigned)std::min<int64_t>((P.tiles_built + P.tiles_built / 4) / 64 + 1, 65535);
-    using GenFn = decltype(&k_gen_tile<false, 0>);
-    const GenFn gen_fn[2][4] = {{k_gen_tile<false, 0>, k_gen_tile<false, 1>, k_gen_tile<false, 2>, k_gen_tile<false, 3>},
-                                {k_gen_tile<true, 0>, k_gen_tile<true, 1>, k_gen_tile<true, 2>, k_gen_tile<true, 3>}};
+    using GenFn = decltype(&k_gen_tile<false, 0, false>);
+    // [later phase][store][node data]
+    const GenFn gen_fn[2][4][2] = {
+        {{k_gen_tile<false, 0, false>, k_gen_tile<false, 0, true>}, {k_gen_tile<false, 1, false>, k_gen_tile<false, 1, true>},
+         {k_gen_tile<false, 2, false>, k_gen_tile<false, 2, true>}, {k_gen_tile<false, 3, false>, k_gen_tile<false, 3, true>}},
+        {{k_gen_tile<true, 0, false>, k_gen_tile<true, 0, true>}, {k_gen_tile<true, 1, false>, k_gen_tile<true, 1, true>},
+         {k_gen_tile<true, 2, false>, k_gen_tile<true, 2, true>}, {k_gen_tile<true, 3, false>, k_gen_tile<true, 3, true>}}};
+    // per-node centroids and T22 (introspection only): on hq_build, and on
+    // hq_rebuild when the handle keeps them
+    const bool nodes = probe_phases || P.keep_node_data;
+    P.node_data_fresh = nodes;
     // the first phase's tiles longest first, when every buffer the generation
     // writes can be addressed from its start with 32-bit offsets
     const int64_t lim = 0x7fffffffll;
@@ -1379,7 +1393,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     }
     for (int ph = 1; ph <= phases; ++ph) {
         const bool later = ph > 1;
-        hipLaunchKernelGGL(gen_fn[later][P.store & 3], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
+        hipLaunchKernelGGL(gen_fn[later][P.store & 3][nodes ? 1 : 0], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
                            gen_lds, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len, P.d_tile_root, P.d_links,
                            P.d_nbody, pos, P.d_lo, P.d_troot, P.troot_cap, nslot, P.d_ncen, P.d_T22, P.d_rec32,
                            P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags,

@@ -141,6 +141,8 @@ struct Plan {
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int waves_per_cu = 16;    // grid of the later phases' sweeps, waves per CU
     int ncu = 256;            // compute units of the device
+    bool keep_node_data = false;  // hq_rebuild writes per-node centroids and T22
+    bool node_data_fresh = false; // they describe the last (re)build
     int64_t run_cap = 0;      // entries of d_run
     int64_t troot_cap = 0;    // tile-root table entries (twice the tiles of hq_build)
 

@@ -122,3 +122,26 @@ def test_graph_replay_matches_eager(hq):
         want = dense.project(eager_pos[sl], f[b0:b1])
         got = eager_out[b0:b1].astype(np.float64)
         assert np.abs(got - want).max() <= 1e-4 * np.abs(f[b0:b1]).max()
+
+
+def test_node_data_after_rebuild(hq):
+    """Centroids and T22 are refreshed by hq_rebuild only for handles built
+    with keep_node_data; otherwise hq_node_data refuses them."""
+    w, rot, trans, _ = _workload()
+    moved = w.pos.copy()
+    for j in range(w.m):
+        sl = slice(w.offsets[j], w.offsets[j + 1])
+        c = moved[sl].mean(axis=0)
+        moved[sl] = (moved[sl] - c) @ rot[2, j].T + c + trans[2, j]
+    pos2 = torch.from_numpy(moved).cuda()
+    fresh = hq.build(pos2, w.offsets).node_data()
+    h = hq.build(torch.from_numpy(w.pos).cuda(), w.offsets)
+    h.rebuild(pos2)
+    with pytest.raises(hq.HQError):
+        h.node_data()
+    hk = hq.build(torch.from_numpy(w.pos).cuda(), w.offsets, keep_node_data=1)
+    hk.rebuild(pos2)
+    got = hk.node_data()
+    assert np.array_equal(got["centroid"], fresh["centroid"])
+    assert np.array_equal(got["T22"], fresh["T22"])
+    assert hk.query()["device_flags"] == 0
