@@ -902,6 +902,8 @@ __global__ void __launch_bounds__(256) k_len_scatter(int phase, const int32_t *p
 // after it are in flight.
 // ---------------------------------------------------------------------------
 constexpr int kGenWords = 10;  // n, c[3], T22[6] per LDS slot and lane, and per tile root
+constexpr int kStageStride = 36;  // words per lane row of the record staging area (144 B)
+constexpr size_t kStageBytes = (size_t)64 * kStageStride * 4 + 64 * 4;  // rows + schedule offsets
 
 struct GenIn {
     double n, c[3], T[6];
@@ -991,24 +993,36 @@ __device__ __forceinline__ void load_links(const int32_t *links, int64_t s, int3
 // on its back edge and waits for loads only.
 template <int kStore, bool kNodes>
 __device__ __forceinline__ void gen_store(rsrc_t r32, rsrc_t r64, rsrc_t rcen, rsrc_t rt22, rsrc_t rtr, rsrc_t rbc,
-                                          uint32_t rel, uint32_t trel, uint32_t brel, const float (&w32)[26],
+                                          uint32_t *stage, uint32_t *srel, int lane, uint32_t rel, uint32_t trel,
+                                          uint32_t brel, const float (&w32)[26],
                                           const double (&w64)[26], const int32_t (&li)[kLinkInts],
                                           const double (&cp)[3], const double (&T)[6], const double (&tv)[kGenWords],
                                           const double (&bc)[3]) {
     auto scaled = [](uint32_t i, uint32_t b) { return i == kOOB ? kOOB : i * b; };
     if (kStore & 2) {
-        const uint32_t o = scaled(rel, 128u);
+        // the 64 lanes' float records pass through LDS (one row per lane) and
+        // leave as whole 128-byte lines: lanes 8i..8i+7 write record i of the
+        // step, eight records per store
+        u32x4 *row = reinterpret_cast<u32x4 *>(stage + kStageStride * lane);
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(w32[4 * q]), __float_as_uint(w32[4 * q + 1]),
-                                                         __float_as_uint(w32[4 * q + 2]),
-                                                         __float_as_uint(w32[4 * q + 3])},
-                                                   r32, o + 16 * q, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(
-            u32x4{__float_as_uint(w32[24]), __float_as_uint(w32[25]), (uint32_t)li[0], (uint32_t)li[1]}, r32, o + 96,
-            0, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{(uint32_t)li[2], (uint32_t)li[3], (uint32_t)li[4], (uint32_t)li[5]},
-                                               r32, o + 112, 0, 0);
+            row[q] = u32x4{__float_as_uint(w32[4 * q]), __float_as_uint(w32[4 * q + 1]),
+                           __float_as_uint(w32[4 * q + 2]), __float_as_uint(w32[4 * q + 3])};
+        row[6] = u32x4{__float_as_uint(w32[24]), __float_as_uint(w32[25]), (uint32_t)li[0], (uint32_t)li[1]};
+        row[7] = u32x4{(uint32_t)li[2], (uint32_t)li[3], (uint32_t)li[4], (uint32_t)li[5]};
+        srel[lane] = rel;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int c = lane & 7;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = 8 * q + (lane >> 3);
+            const u32x4 v = reinterpret_cast<const u32x4 *>(stage + kStageStride * r)[c];
+            const uint32_t rr = srel[r];
+            __builtin_amdgcn_raw_buffer_store_b128(v, r32, rr == kOOB ? kOOB : rr * 128u + 16u * c, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     if (kStore & 1) {
         const uint32_t o = scaled(rel, 256u);
@@ -1060,6 +1074,9 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
                                                  int32_t *err) {
     extern __shared__ unsigned char smem_raw[];
     double *lds = reinterpret_cast<double *>(smem_raw);
+    // record staging after the nslot slots of pending results
+    uint32_t *stage = reinterpret_cast<uint32_t *>(smem_raw + (size_t)nslot * kGenWords * 64 * sizeof(double));
+    uint32_t *srel = stage + 64 * kStageStride;
     const int lane = threadIdx.x;
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
     // tord: the phase's tiles longest first (then every buffer is addressed
@@ -1124,7 +1141,8 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
         {
             const float z32[26] = {};
             const double z64[26] = {}, z3[3] = {}, z6[6] = {}, z10[kGenWords] = {};
-            gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, kOOB, kOOB, kOOB, z32, z64, li, z3, z6, z10, z3);
+            gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, stage, srel, lane, kOOB, kOOB, kOOB, z32, z64, li, z3, z6,
+                                      z10, z3);
         }
         while (__ballot(s < se)) {
             const bool act = s < se, actn = s + 1 < se;
@@ -1204,7 +1222,7 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
                 const uint32_t rel = (uint32_t)(s - s0);
                 const double tv[kGenWords] = {n, cp[0], cp[1], cp[2], T[0], T[1], T[2], T[3], T[4], T[5]};
                 const double bc[3] = {cp[0] + lo3[0], cp[1] + lo3[1], cp[2] + lo3[2]};
-                gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, act ? rel : kOOB, wr ? (uint32_t)(t - tr0) : kOOB,
+                gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, stage, srel, lane, act ? rel : kOOB, wr ? (uint32_t)(t - tr0) : kOOB,
                                   (act && body_root) ? (uint32_t)(body - b0) : kOOB, w32, w64, li, cp, T, tv, bc);
             }
 #pragma unroll
@@ -1367,7 +1385,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         P.troot_cap = cap;
     }
     const int nslot = stack_slots(P.S);
-    const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double);
+    const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double) + ((P.store & 2) ? kStageBytes : 0);
     const unsigned gen_grid = (unsigned)std::min<int64_t>((P.tiles_built + P.tiles_built / 4) / 64 + 1, 65535);
     using GenFn = decltype(&k_gen_tile<false, 0, false>);
     // [later phase][store][node data]
