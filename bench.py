@@ -35,7 +35,7 @@ def algorithmic_bytes(h, nrhs, elem=4):
     """Bytes one sweep must move: vectors in and out, the compact reflectors
     of every node (5, 15 or 24 values for k = 3, 6, 9), 16 bytes of links and
     weights per node, and 4 bytes of permutation per bead."""
-    nd = h.node_data(with_G=False)
+    nd = h.node_data(with_G=False, with_geometry=False)
     k = nd["k"]
     w = np.where(k == 9, 24, np.where(k == 6, 15, 5)).sum()
     return (elem * 3 * h.N * nrhs + elem * h.rows * nrhs + elem * int(w) + 16 * (h.N - h.m) + 4 * h.N)

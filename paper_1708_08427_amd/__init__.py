@@ -203,19 +203,20 @@ class Handle:
                                         kappa.ctypes.data_as(_lib.P_f64)), "hq_body_info")
         return flags, kappa
 
-    def node_data(self, with_G=True):
-        """Per-node tree and transform data (G needs the FP64 transforms)."""
+    def node_data(self, with_G=True, with_geometry=True):
+        """Per-node tree and transform data (G needs the FP64 transforms;
+        centroids and T22 after a rebuild need keep_node_data)."""
         NI = self.N - self.m
         a = {k: np.zeros(NI, dtype=np.int32) for k in ("first", "last", "x", "y", "body", "n", "k", "row")}
-        cen = np.zeros((NI, 3))
-        T22 = np.zeros((NI, 3, 3))
+        cen = np.zeros((NI, 3)) if with_geometry else None
+        T22 = np.zeros((NI, 3, 3)) if with_geometry else None
         G = np.zeros((NI, 9, 9)) if with_G else None
         P = _lib.P_i32
+        f64 = (lambda x: x.ctypes.data_as(_lib.P_f64) if x is not None else None)
         _check(_lib.load().hq_node_data(self._h(), a["first"].ctypes.data_as(P), a["last"].ctypes.data_as(P),
                                         a["x"].ctypes.data_as(P), a["y"].ctypes.data_as(P),
                                         a["body"].ctypes.data_as(P), a["n"].ctypes.data_as(P),
-                                        cen.ctypes.data_as(_lib.P_f64), T22.ctypes.data_as(_lib.P_f64),
-                                        G.ctypes.data_as(_lib.P_f64) if with_G else None, a["k"].ctypes.data_as(P),
+                                        f64(cen), f64(T22), f64(G), a["k"].ctypes.data_as(P),
                                         a["row"].ctypes.data_as(P)), "hq_node_data")
         a.update(centroid=cen, T22=T22, G=G)
         return a
