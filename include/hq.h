@@ -164,6 +164,22 @@ hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec);
 hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
                    hq_precision prec, hq_stream stream);
 
+/* Measurement form of hq_apply (Algorithms 2 and 3): the same sweep, with a
+ * HIP event recorded on the stream before each tile phase's launch and after
+ * the last; waits for them and returns each phase's launch time in ms in
+ * phase_ms[phase - 1] (host, max_phases entries; the downward sweep runs the
+ * phases in reverse, the entries are still by phase) and the number of
+ * phases in *nphases.  Creates and destroys its events; not for stream
+ * capture.  Errors as for hq_apply; HQ_E_INVALID if max_phases is below the
+ * handle's phases. */
+hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
+                         hq_precision prec, hq_stream stream, float *phase_ms, int32_t max_phases,
+                         int32_t *nphases);
+
+/* Tile phase of every internal node (host, N - m entries, the handle's node
+ * order; 1 = first phase).  Synchronises. */
+hq_status hq_node_phase(hq_handle h, int32_t *phase);
+
 /* Dense Q~ of one body (Algorithm 1): out device FP64, (3n_j - 6) rows with
  * leading dimension ld >= 3n_j, columns in the caller's bead order.  A
  * two-bead body has no rows: HQ_OK without touching out (which may be NULL).

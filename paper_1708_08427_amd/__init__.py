@@ -116,8 +116,9 @@ class Handle:
             pass
 
     # -- products ---------------------------------------------------------
-    def apply(self, v, transpose=False, out=None, stream=None):
-        """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v."""
+    def apply(self, v, transpose=False, out=None, stream=None, timed=False):
+        """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v.  With
+        timed=True returns (out, per-phase launch ms) via hq_apply_timed."""
         torch = _torch()
         _check_dev(v, "v")
         squeeze = v.dim() == 1
@@ -135,9 +136,22 @@ class Handle:
             if out.dtype != v.dtype:
                 raise TypeError("out and v must have the same dtype")
         lib = _lib.load()
+        if timed:
+            ms = (ctypes.c_float * 64)()
+            nph = ctypes.c_int32()
+            _check(lib.hq_apply_timed(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
+                                      _stream(stream), ms, 64, ctypes.byref(nph)), "hq_apply_timed")
+            res = out.reshape(nout) if squeeze else out
+            return res, [ms[i] for i in range(nph.value)]
         _check(lib.hq_apply(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
                             _stream(stream)), "hq_apply")
         return out.reshape(nout) if squeeze else out
+
+    def node_phase(self):
+        """Tile phase of every internal node (handle order)."""
+        ph = np.zeros(self.N - self.m, dtype=np.int32)
+        _check(_lib.load().hq_node_phase(self._h(), ph.ctypes.data_as(_lib.P_i32)), "hq_node_phase")
+        return ph
 
     def reserve(self, nrhs, dtype):
         _check(_lib.load().hq_reserve(self._h(), int(nrhs), _prec(dtype)), "hq_reserve")

@@ -39,6 +39,9 @@ SIGNATURES = [
     ("hq_rebuild", c_i32, [c_vp, c_vp, c_vp]),
     ("hq_reserve", c_i32, [c_vp, c_i64, c_i32]),
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),
+    ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp, ctypes.POINTER(ctypes.c_float),
+                               c_i32, P_i32]),
+    ("hq_node_phase", c_i32, [c_vp, P_i32]),
     ("hq_explicit", c_i32, [c_vp, c_i64, c_vp, c_i64, c_vp]),
     ("hq_explicit_blocks_size", c_i32, [c_vp, c_i64, P_i64, P_i64]),
     ("hq_explicit_blocks", c_i32, [c_vp, c_i64, c_i32, c_vp, P_i64, P_i64, P_i64, P_i32, P_i32, c_vp]),

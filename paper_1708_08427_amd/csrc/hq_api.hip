@@ -248,6 +248,41 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
     return HQ_OK;
 }
 
+// Argument checks and launch of hq_apply (ev: optional per-phase events).
+hq_status hq_apply_checked(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
+                           hipStream_t s, hipEvent_t *ev) {
+    if (!v || !out) {
+        set_error("v or out is NULL");
+        return HQ_E_INVALID;
+    }
+    if (v == out) {
+        set_error("v and out must not overlap");
+        return HQ_E_INVALID;
+    }
+    if (transpose != 0 && transpose != 1) {
+        set_error("transpose must be 0 or 1");
+        return HQ_E_INVALID;
+    }
+    if (nrhs < 1 || nrhs > (1 << 20)) {
+        set_error("nrhs must be in [1, 2^20]");
+        return HQ_E_INVALID;
+    }
+    if (prec != HQ_FP64 && prec != HQ_FP32) {
+        set_error("prec must be HQ_FP64 or HQ_FP32");
+        return HQ_E_INVALID;
+    }
+    if ((prec == HQ_FP64 && !(P.store & 1)) || (prec == HQ_FP32 && !(P.store & 2))) {
+        set_error("transforms of this precision were not kept (hq_options.store)");
+        return HQ_E_INVALID;
+    }
+    if ((3 * P.N) * nrhs > (int64_t(1) << 40)) {
+        set_error("vector too large");
+        return HQ_E_UNSUPPORTED;
+    }
+    HQ_TRY(ensure_xch(P, nrhs, prec, s));
+    return apply_device(P, v, out, transpose, nrhs, prec, s, ev);
+}
+
 }  // namespace
 }  // namespace hq
 
@@ -481,41 +516,65 @@ hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec) {
     return HQ_OK;
 }
 
+hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
+                         hq_stream stream, float *phase_ms, int32_t max_phases, int32_t *nphases) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!phase_ms || !nphases || max_phases < 1) {
+        set_error("phase_ms and nphases must be given, max_phases >= 1");
+        return HQ_E_INVALID;
+    }
+    const int nph = std::max(P->phases_built, P->phases_reserved);
+    if (nph > max_phases) {
+        set_error("max_phases is below the handle's tile phases (" + std::to_string(nph) + ")");
+        return HQ_E_INVALID;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<hipEvent_t> ev(nph + 1, nullptr);
+    hq_status st = HQ_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            set_error("hipEventCreate");
+            st = HQ_E_DEVICE;
+        }
+    if (st == HQ_OK) st = hq_apply_checked(*P, v, out, transpose, nrhs, prec, s, ev.data());
+    if (st == HQ_OK && hipEventSynchronize(ev[nph]) != hipSuccess) {
+        set_error("hipEventSynchronize");
+        st = HQ_E_DEVICE;
+    }
+    for (int k = 0; st == HQ_OK && k < nph; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) {
+            set_error("hipEventElapsedTime");
+            st = HQ_E_DEVICE;
+            break;
+        }
+        const int phase = transpose ? (nph - k) : (k + 1);  // launch k sweeps this phase
+        phase_ms[phase - 1] = ms;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st == HQ_OK) *nphases = nph;
+    return st;
+}
+
+hq_status hq_node_phase(hq_handle h, int32_t *phase) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!phase) {
+        set_error("phase is NULL");
+        return HQ_E_INVALID;
+    }
+    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipMemcpy(phase, P->d_cov, P->NI * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return HQ_OK;
+}
+
 hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
                    hq_stream stream) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
-    if (!v || !out) {
-        set_error("v or out is NULL");
-        return HQ_E_INVALID;
-    }
-    if (v == out) {
-        set_error("v and out must not overlap");
-        return HQ_E_INVALID;
-    }
-    if (transpose != 0 && transpose != 1) {
-        set_error("transpose must be 0 or 1");
-        return HQ_E_INVALID;
-    }
-    if (nrhs < 1 || nrhs > (1 << 20)) {
-        set_error("nrhs must be in [1, 2^20]");
-        return HQ_E_INVALID;
-    }
-    if (prec != HQ_FP64 && prec != HQ_FP32) {
-        set_error("prec must be HQ_FP64 or HQ_FP32");
-        return HQ_E_INVALID;
-    }
-    if ((prec == HQ_FP64 && !(P->store & 1)) || (prec == HQ_FP32 && !(P->store & 2))) {
-        set_error("transforms of this precision were not kept (hq_options.store)");
-        return HQ_E_INVALID;
-    }
-    if ((3 * P->N) * nrhs > (int64_t(1) << 40)) {
-        set_error("vector too large");
-        return HQ_E_UNSUPPORTED;
-    }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    HQ_TRY(ensure_xch(*P, nrhs, prec, s));
-    return apply_device(*P, v, out, transpose, nrhs, prec, s);
+    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 hq_status hq_explicit(hq_handle h, int64_t body, double *out, int64_t ld, hq_stream stream) {

@@ -1177,10 +1177,11 @@ enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWi
 
 template <typename T>
 void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
-                const Ctx &C, hipStream_t s) {
+                const Ctx &C, hipStream_t s, hipEvent_t *ev) {
     const int nph = std::max(P.phases_built, P.phases_reserved);
     for (int k = 0; k < nph; ++k) {
         const int phase = transpose ? (nph - k) : (k + 1);
+        if (ev) (void)hipEventRecord(ev[k], s);
         switch (kind) {
         case kNarrow1: launch_narrow<T, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow2: launch_narrow<T, 2>(P, phase, transpose, rec, v, out, xch, C, s); break;
@@ -1191,6 +1192,7 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
         case kWide64: launch_wide<T, 64, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
         }
     }
+    if (ev) (void)hipEventRecord(ev[nph], s);
 }
 
 }  // namespace
@@ -1201,7 +1203,8 @@ int lanes_per_tile(int64_t nrhs) {
     return l;
 }
 
-hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, hipStream_t s) {
+hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, hipStream_t s,
+                       hipEvent_t *ev) {
     Ctx C;
     C.N = P.N;
     C.rows = P.rows;
@@ -1235,9 +1238,10 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
     C.dmax = stack_depth(P.S);
     C.nslot = stack_slots(P.S);
     if (prec == HQ_FP64)
-        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s);
+        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s,
+                           ev);
     else
-        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s);
+        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s, ev);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

@@ -2,7 +2,8 @@
 
 Two rocprofv3 counter runs of ``bench.py --probe`` (one with FETCH_SIZE, one
 with WRITE_SIZE; both in KiB per dispatch) are turned into the bytes one
-upward and one downward FP32 sweep move to and from HBM.  Each counter is
+upward and one downward FP32 sweep move to and from HBM, in total and for
+the launch of the first tile phase (the dominant kernel).  Each counter is
 scaled by what it reads for the probe's device copy of 512 MiB (bytes it
 must read and write), and the summary records a hash of the sweep sources so
 that a reader can tell whether it still describes the current kernels.
@@ -47,6 +48,20 @@ def _read(dirname, counter):
     return list(per.values())
 
 
+def first_phase(rows, kernel):
+    """The first tile phase's launches: the instantiation of ``kernel`` that
+    carries the most counted bytes (later phases use another one); returns
+    its name and the mean per launch."""
+    groups = {}
+    for r in rows:
+        if kernel in r["name"]:
+            groups.setdefault(r["name"], []).append(r["value"])
+    if not groups:
+        raise ValueError(f"no {kernel} launches")
+    name = max(groups, key=lambda n: sum(groups[n]))
+    return name, sum(groups[name]) / len(groups[name])
+
+
 def summarise(rows):
     copies = [r for r in rows if "copy" in r["name"].lower() and "hq::" not in r["name"]]
     if not copies:
@@ -54,7 +69,7 @@ def summarise(rows):
     copy_kib = max(r["value"] for r in copies)
     up = sum(r["value"] for r in rows if "k_up_wide" in r["name"]) / PROBE_SWEEPS
     down = sum(r["value"] for r in rows if "k_down_wide" in r["name"]) / PROBE_SWEEPS
-    return copy_kib, up, down
+    return copy_kib, up, down, first_phase(rows, "k_up_wide"), first_phase(rows, "k_down_wide")
 
 
 def main():
@@ -65,8 +80,8 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--options", required=True, help="launch configuration of the probe (its 'options' field)")
     a = ap.parse_args()
-    cf, uf, df = summarise(_read(a.fetch_dir, "FETCH_SIZE"))
-    cw, uw, dw = summarise(_read(a.write_dir, "WRITE_SIZE"))
+    cf, uf, df, (n_up, u1f), (n_dn, d1f) = summarise(_read(a.fetch_dir, "FETCH_SIZE"))
+    cw, uw, dw, (_, u1w), (_, d1w) = summarise(_read(a.write_dir, "WRITE_SIZE"))
     ff = COPY_BYTES / (cf * 1024.0)
     fw = COPY_BYTES / (cw * 1024.0)
     res = {
@@ -79,6 +94,10 @@ def main():
                      "hbm_bytes": uf * 1024.0 * ff + uw * 1024.0 * fw},
         "down_sweep": {"fetch_kib": df, "write_kib": dw,
                        "hbm_bytes": df * 1024.0 * ff + dw * 1024.0 * fw},
+        "up_phase1": {"kernel": n_up, "fetch_kib": u1f, "write_kib": u1w,
+                      "hbm_bytes": u1f * 1024.0 * ff + u1w * 1024.0 * fw},
+        "down_phase1": {"kernel": n_dn, "fetch_kib": d1f, "write_kib": d1w,
+                        "hbm_bytes": d1f * 1024.0 * ff + d1w * 1024.0 * fw},
     }
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)

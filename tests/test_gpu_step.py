@@ -145,3 +145,21 @@ def test_node_data_after_rebuild(hq):
     assert np.array_equal(got["centroid"], fresh["centroid"])
     assert np.array_equal(got["T22"], fresh["T22"])
     assert hk.query()["device_flags"] == 0
+
+
+def test_apply_timed_and_node_phase(hq):
+    """hq_apply_timed computes what hq_apply computes and times every tile
+    phase; hq_node_phase names a phase for every node."""
+    w, _, _, f = _workload()
+    pos = torch.from_numpy(w.pos).cuda()
+    h = hq.build(pos, w.offsets, tile_units=16)
+    fd = torch.from_numpy(f).float().cuda()
+    ref = h.apply(fd)
+    got, ms = h.apply(fd, timed=True)
+    assert torch.equal(got, ref)
+    q = h.query()
+    assert len(ms) >= q["phases"] and all(x >= 0.0 for x in ms)
+    back, ms2 = h.apply(ref, transpose=True, timed=True)
+    assert torch.equal(back, h.apply(ref, transpose=True)) and len(ms2) == len(ms)
+    ph = h.node_phase()
+    assert ph.min() >= 1 and ph.max() == q["phases"]
