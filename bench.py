@@ -6,7 +6,8 @@ beads, sigma 0.6, clipped to [50, 20000]) on random ellipsoids in a 500^3 box,
 rotation about its centroid + translation in [-1,1]^3), rebuild of the tree and
 FP64 transforms, then Q~^T (Q~ f) in FP32 for the 32 right-hand sides.  K steps
 are captured in one hipGraph and replayed; the timed region is bracketed by
-synchronisations.
+synchronisations.  Force vectors are held as [bead][system][xyz] (the
+library's triples layout) unless --layout rows is given.
 
 value = bead-vectors per second = N * R / (time per step).  The roofline row
 is the upward sweep Q~ v (FP32): algorithmic bytes (input vectors, residue
@@ -79,6 +80,23 @@ def cpu_baseline(wl, rng_seed, budget_s=15.0):
                       f"rebuild + Q~f + Q~^T(Q~f) per body, {t_total:.1f} s"}
 
 
+def to_layout(a, layout):
+    """(3T, R) rows -> the layout's host array ((T, R, 3) for triples)."""
+    if layout == "rows":
+        return np.ascontiguousarray(a)
+    return np.ascontiguousarray(a.reshape(a.shape[0] // 3, 3, a.shape[1]).transpose(0, 2, 1))
+
+
+def from_layout(a, layout):
+    if layout == "rows":
+        return a
+    return np.ascontiguousarray(a.transpose(0, 2, 1).reshape(3 * a.shape[0], a.shape[1]))
+
+
+def vec_shape(nrows, R, layout):
+    return (nrows, R) if layout == "rows" else (nrows // 3, R, 3)
+
+
 def probe(hq, torch, wl, f, args):
     """The counter run: one 512 MiB device copy (calibrates FETCH_SIZE and
     WRITE_SIZE against known bytes), then PROBE_SWEEPS upward and downward FP32
@@ -90,17 +108,18 @@ def probe(hq, torch, wl, f, args):
     torch.cuda.synchronize()
     del a, b
     pos = torch.from_numpy(wl.pos).to(dev)
-    f32 = torch.from_numpy(f).float().to(dev)
-    tmp = torch.empty((wl.rows, wl.nrhs), dtype=torch.float32, device=dev)
-    out = torch.empty((3 * wl.N, wl.nrhs), dtype=torch.float32, device=dev)
+    lay = args.layout
+    f32 = torch.from_numpy(to_layout(f, lay)).float().to(dev)
+    tmp = torch.empty(vec_shape(wl.rows, wl.nrhs, lay), dtype=torch.float32, device=dev)
+    out = torch.empty(vec_shape(3 * wl.N, wl.nrhs, lay), dtype=torch.float32, device=dev)
     h = hq.build(pos, wl.offsets, store=2, **fixed_options(args))
     for _ in range(PROBE_SWEEPS):
-        h.apply(f32, out=tmp)
+        h.apply(f32, out=tmp, layout=lay)
     for _ in range(PROBE_SWEEPS):
-        h.apply(tmp, transpose=True, out=out)
+        h.apply(tmp, transpose=True, out=out, layout=lay)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "done", "algorithmic_bytes": algorithmic_bytes(h, wl.nrhs), "phases": h.query()["phases"],
-                      "options": options_tag(fixed_options(args))}), flush=True)
+                      "options": options_tag(fixed_options(args), lay)}), flush=True)
 
 
 def fixed_options(args):
@@ -114,14 +133,14 @@ def effective(opts):
     return {k: int(opts.get(k) or v) for k, v in DEFAULT_OPTIONS.items()}
 
 
-def options_tag(opts):
+def options_tag(opts, layout):
     """The configuration of the first-phase launch a counter summary belongs
     to (waves_per_cu only shapes the later phases' grids)."""
     e = effective(opts)
-    return ",".join(f"{k}={e[k]}" for k in ("tile_units", "run_nodes"))
+    return ",".join([f"{k}={e[k]}" for k in ("tile_units", "run_nodes")] + [f"layout={layout}"])
 
 
-def traffic_from_profile(opts):
+def traffic_from_profile(opts, layout):
     """HBM bytes of one first-phase upward launch from the committed counter
     summary, if it was taken on the current sweep sources in the same launch
     configuration (else None)."""
@@ -133,8 +152,8 @@ def traffic_from_profile(opts):
         prof = json.load(fh)
     if prof.get("source_sha256") != sweep_source_hash():
         return None, "sweep sources changed since the counters were taken"
-    if prof.get("options") != options_tag(opts):
-        return None, f"counters taken with {prof.get('options')}, bench runs {options_tag(opts)}"
+    if prof.get("options") != options_tag(opts, layout):
+        return None, f"counters taken with {prof.get('options')}, bench runs {options_tag(opts, layout)}"
     return prof["up_phase1"]["hbm_bytes"], prof["command"]
 
 
@@ -147,6 +166,8 @@ def main():
     ap.add_argument("--run-nodes", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="library defaults for options left at 0")
+    ap.add_argument("--layout", choices=("triples", "rows"), default="triples",
+                    help="vector layout of the force and residue vectors (hq_layout)")
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
@@ -182,9 +203,10 @@ def main():
     with torch.cuda.stream(stream):
         pos = torch.from_numpy(wl.pos).to(dev)
         pos0 = pos.clone()
-        f32 = torch.from_numpy(f).float().to(dev)
-        tmp = torch.empty((wl.rows, R), dtype=torch.float32, device=dev)
-        out = torch.empty((3 * N, R), dtype=torch.float32, device=dev)
+        lay = args.layout
+        f32 = torch.from_numpy(to_layout(f, lay)).float().to(dev)
+        tmp = torch.empty(vec_shape(wl.rows, R, lay), dtype=torch.float32, device=dev)
+        out = torch.empty(vec_shape(3 * N, R, lay), dtype=torch.float32, device=dev)
         rot_d = torch.from_numpy(rot.reshape(total_steps, m, 9)).to(dev)
         trans_d = torch.from_numpy(trans).to(dev)
         # launch configuration: given, or picked by the autotuner for this
@@ -193,7 +215,7 @@ def main():
         autotuned = False
         if not args.no_autotune and args.tile_units == 0:
             t0 = time.perf_counter()
-            tuned = hq.autotune(pos, wl.offsets, R, torch.float32, include_rebuild=True, stream=stream)
+            tuned = hq.autotune(pos, wl.offsets, R, torch.float32, include_rebuild=True, stream=stream, layout=lay)
             opts = {k: tuned[k] for k in opts}
             autotuned = True
             log(f"autotune {1e3 * (time.perf_counter() - t0):.0f} ms: {opts}, {tuned['ms']:.3f} ms per round")
@@ -208,8 +230,8 @@ def main():
         def step(i):
             h.rigid_update(pos, rot_d[i], trans_d[i], stream=stream)
             h.rebuild(pos, stream=stream)
-            h.apply(f32, out=tmp, stream=stream)
-            h.apply(tmp, transpose=True, out=out, stream=stream)
+            h.apply(f32, out=tmp, stream=stream, layout=lay)
+            h.apply(tmp, transpose=True, out=out, stream=stream, layout=lay)
 
         # graphs: warmup steps, then exactly K timed steps
         hq.capture_begin(stream)
@@ -238,7 +260,7 @@ def main():
 
         # accuracy on the final positions: FP32 sweep pair against the FP64 oracle
         pos_host = pos.cpu().numpy()
-        out_host = out.cpu().numpy().astype(np.float64)
+        out_host = from_layout(out.cpu().numpy(), lay).astype(np.float64)
         from oracle import dense, hier
         sample = np.random.default_rng(7).choice(m, 16, replace=False)
         err, leak = 0.0, 0.0
@@ -264,13 +286,13 @@ def main():
             torch.cuda.synchronize()
             return float(np.median([a.elapsed_time(b) for a, b in evs]))
 
-        t_up = timed(lambda: h.apply(f32, out=tmp, stream=stream), args.apply_reps)
-        t_dn = timed(lambda: h.apply(tmp, transpose=True, out=out, stream=stream), args.apply_reps)
+        t_up = timed(lambda: h.apply(f32, out=tmp, stream=stream, layout=lay), args.apply_reps)
+        t_dn = timed(lambda: h.apply(tmp, transpose=True, out=out, stream=stream, layout=lay), args.apply_reps)
         t_rb = timed(lambda: h.rebuild(pos, stream=stream), 5)
         f64 = f32.double()
-        tmp64 = torch.empty((wl.rows, R), dtype=torch.float64, device=dev)
+        tmp64 = torch.empty(vec_shape(wl.rows, R, lay), dtype=torch.float64, device=dev)
         h64 = hq.build(pos, wl.offsets, store=1, stream=stream, **opts)
-        t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream), 5)
+        t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream, layout=lay), 5)
         h64.destroy()
         log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms, up FP64 {t_up64:.3f} ms")
         nbytes = algorithmic_bytes(h, R)
@@ -280,13 +302,21 @@ def main():
         assert sum(pbytes.values()) == nbytes
         p1 = []
         for _ in range(args.apply_reps):
-            _, ms_ph = h.apply(f32, out=tmp, stream=stream, timed=True)
+            _, ms_ph = h.apply(f32, out=tmp, stream=stream, timed=True, layout=lay)
             p1.append(ms_ph[0])
         t_p1 = float(np.median(p1))
         achieved = pbytes[1] / (t_p1 * 1e-3) / 1e9
         log(f"first-phase upward launch: {t_p1:.3f} ms, {pbytes[1] / 1e9:.3f} GB -> {achieved:.0f} GB/s; "
             f"whole sweep {nbytes / (t_up * 1e-3) / 1e9:.0f} GB/s")
-        traffic, traffic_src = traffic_from_profile(opts)
+        # the measured device-copy ceiling beside the published peak: 1 GiB
+        # read + 1 GiB written by a plain copy on the same stream
+        ca = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        cb = torch.empty_like(ca)
+        t_copy = timed(lambda: cb.copy_(ca), 10)
+        copy_gbs = 2 * ca.numel() * 4 / (t_copy * 1e-3) / 1e9
+        del ca, cb
+        log(f"device copy 1 GiB: {t_copy:.3f} ms -> {copy_gbs:.0f} GB/s read + write")
+        traffic, traffic_src = traffic_from_profile(opts, lay)
         log(f"traffic: {traffic} ({traffic_src})")
         q = h.query()
 
@@ -304,12 +334,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"bd_step_m{m}_lognormal500_R{R}", "bodies": m, "beads": N, "nrhs": R,
-                   "rows": wl.rows, **effective(opts), "autotuned": autotuned,
+                   "rows": wl.rows, **effective(opts), "autotuned": autotuned, "layout": lay,
                    "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_up_wide<float, 32, 32, 6, 3, 3, 1>: first tile phase of the upward FP32 sweep",
+                     "kernel": f"k_up_wide<float, 32, 32, 6, 3, 3, 1, {str(lay == 'triples').lower()}>: "
+                               "first tile phase of the upward FP32 sweep",
                      "bytes": int(pbytes[1]), "ms": t_p1,
+                     "copy_ceiling": {"achieved": copy_gbs, "unit": "GB/s", "frac": copy_gbs / HBM_PEAK_GBS,
+                                      "kernel_frac_of_copy": achieved / copy_gbs,
+                                      "what": "torch device copy of 1 GiB (read + write bytes / time)"},
                      "whole_sweep": {"bytes": int(nbytes), "ms": t_up,
                                      "achieved": nbytes / (t_up * 1e-3) / 1e9}},
         "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},

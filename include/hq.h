@@ -72,6 +72,17 @@ typedef enum {
 
 typedef enum { HQ_FP64 = 0, HQ_FP32 = 1 } hq_precision;
 
+/* Layout of a vector of nrhs right-hand sides whose rows come in triples (a
+ * bead's x, y, z rows; each node's residue rows, Algorithm 2, fill whole
+ * triples).  Row triple t, right-hand side r, component d:
+ *   HQ_ROWS     element (3t + d) * nrhs + r: row-major rows x nrhs;
+ *   HQ_TRIPLES  element (t * nrhs + r) * 3 + d: for each triple, nrhs
+ *               contiguous 3-vectors (e.g. per-bead forces of nrhs
+ *               independent systems stored as [bead][system][xyz]).
+ * Both hold the same values; HQ_TRIPLES lets the sweeps move a lane's three
+ * values in one access. */
+typedef enum { HQ_ROWS = 0, HQ_TRIPLES = 1 } hq_layout;
+
 /* Device flag bits reported by hq_query (hq_info.device_flags). */
 #define HQ_FLAG_NONFINITE   1  /* a position was NaN or infinite */
 #define HQ_FLAG_STACK       2  /* an internal per-tile stack limit was hit */
@@ -116,8 +127,8 @@ typedef struct {
  * the sweeps (Algorithms 2 and 3).  For every candidate, builds a handle on
  * the given positions, then times (median of 5 after 2 warm-up rounds, HIP
  * events on the stream) one round of: hq_rebuild if include_rebuild, an
- * upward and a downward hq_apply with nrhs right-hand sides in precision
- * prec.  Candidates: tile_units 16, 32, 64; run_nodes 32, 48, 64; waves_per_cu
+ * upward and a downward hq_apply_layout with nrhs right-hand sides in
+ * precision prec and vector layout layout.  Candidates: tile_units 16, 32, 64; run_nodes 32, 48, 64; waves_per_cu
  * 8, 16, 32.
  *   positions, body_offsets, m  as for hq_build.
  *   base          host, may be NULL: the other options of the trial builds.
@@ -126,7 +137,7 @@ typedef struct {
  * Allocates (and frees) trial handles and two vector buffers; synchronises
  * the stream.  Errors as for hq_build and hq_apply. */
 hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int64_t m, int64_t nrhs,
-                      hq_precision prec, int include_rebuild, const hq_options *base, hq_stream stream,
+                      hq_precision prec, hq_layout layout, int include_rebuild, const hq_options *base, hq_stream stream,
                       hq_options *best, double *best_ms);
 
 /* Build the tree and the FP64 local transforms of m bodies.
@@ -164,7 +175,13 @@ hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec);
 hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
                    hq_precision prec, hq_stream stream);
 
-/* Measurement form of hq_apply (Algorithms 2 and 3): the same sweep, with a
+/* hq_apply with both vectors in the given layout (hq_layout): the same
+ * products (Algorithms 2 and 3), element for element.  HQ_E_INVALID for an
+ * unknown layout; other errors as for hq_apply. */
+hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
+                          hq_precision prec, hq_layout layout, hq_stream stream);
+
+/* Measurement form of hq_apply_layout (Algorithms 2 and 3): the same sweep, with a
  * HIP event recorded on the stream before each tile phase's launch and after
  * the last; waits for them and returns each phase's launch time in ms in
  * phase_ms[phase - 1] (host, max_phases entries; the downward sweep runs the
@@ -173,7 +190,7 @@ hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t
  * capture.  Errors as for hq_apply; HQ_E_INVALID if max_phases is below the
  * handle's phases. */
 hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
-                         hq_precision prec, hq_stream stream, float *phase_ms, int32_t max_phases,
+                         hq_precision prec, hq_layout layout, hq_stream stream, float *phase_ms, int32_t max_phases,
                          int32_t *nphases);
 
 /* Tile phase of every internal node (host, N - m entries, the handle's node

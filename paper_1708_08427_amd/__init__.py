@@ -61,6 +61,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# vector layouts of hq_apply_layout (hq_layout)
+LAYOUTS = {"rows": _lib.HQ_ROWS, "triples": _lib.HQ_TRIPLES}
+
+
 def _prec(dtype):
     torch = _torch()
     if dtype == torch.float64:
@@ -116,35 +120,52 @@ class Handle:
             pass
 
     # -- products ---------------------------------------------------------
-    def apply(self, v, transpose=False, out=None, stream=None, timed=False):
-        """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v.  With
-        timed=True returns (out, per-phase launch ms) via hq_apply_timed."""
+    def apply(self, v, transpose=False, out=None, stream=None, timed=False, layout="rows"):
+        """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v.
+        layout="triples": v and out are (rows / 3, R, 3) tensors, row triple
+        t's right-hand side r at [t, r, :] (hq_apply_layout, HQ_TRIPLES).
+        With timed=True returns (out, per-phase launch ms) via hq_apply_timed."""
         torch = _torch()
         _check_dev(v, "v")
-        squeeze = v.dim() == 1
-        v2 = v.reshape(v.shape[0], 1) if squeeze else v
-        R = v2.shape[1]
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
         nin, nout = (self.rows, 3 * self.N) if transpose else (3 * self.N, self.rows)
-        if v2.shape[0] != nin:
-            raise ValueError(f"v has {v2.shape[0]} rows, expected {nin}")
+        squeeze = False
+        if layout == "triples":
+            if v.dim() != 3 or v.shape[0] * 3 != nin or v.shape[2] != 3:
+                raise ValueError(f"v must be ({nin // 3}, R, 3) in the triples layout, got {tuple(v.shape)}")
+            R = v.shape[1]
+            v2, oshape = v, (nout // 3, R, 3)
+        else:
+            squeeze = v.dim() == 1
+            v2 = v.reshape(v.shape[0], 1) if squeeze else v
+            R = v2.shape[1]
+            if v2.shape[0] != nin:
+                raise ValueError(f"v has {v2.shape[0]} rows, expected {nin}")
+            oshape = (nout, R)
+        if not v2.is_contiguous():
+            raise ValueError("v must be contiguous")
         if out is None:
-            out = torch.empty((nout, R), dtype=v.dtype, device=v.device)
+            out = torch.empty(oshape, dtype=v.dtype, device=v.device)
         else:
             _check_dev(out, "out")
-            if out.shape != (nout, R) and not (squeeze and out.shape == (nout,)):
+            if tuple(out.shape) != oshape and not (squeeze and out.shape == (nout,)):
                 raise ValueError("out has the wrong shape")
             if out.dtype != v.dtype:
                 raise TypeError("out and v must have the same dtype")
+            if not out.is_contiguous():
+                raise ValueError("out must be contiguous")
         lib = _lib.load()
+        lay = LAYOUTS[layout]
         if timed:
             ms = (ctypes.c_float * 64)()
             nph = ctypes.c_int32()
             _check(lib.hq_apply_timed(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
-                                      _stream(stream), ms, 64, ctypes.byref(nph)), "hq_apply_timed")
+                                      lay, _stream(stream), ms, 64, ctypes.byref(nph)), "hq_apply_timed")
             res = out.reshape(nout) if squeeze else out
             return res, [ms[i] for i in range(nph.value)]
-        _check(lib.hq_apply(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
-                            _stream(stream)), "hq_apply")
+        _check(lib.hq_apply_layout(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
+                                   lay, _stream(stream)), "hq_apply_layout")
         return out.reshape(nout) if squeeze else out
 
     def node_phase(self):
@@ -266,7 +287,7 @@ def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max
 _TUNED = {}
 
 
-def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=None, **base):
+def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=None, layout="rows", **base):
     """hq_autotune: the tile size, run length and later-phase waves per CU
     with the shortest measured (rebuild +) upward + downward round for this
     workload.  Returns a dict of hq_options fields plus ``ms``; results are
@@ -275,7 +296,9 @@ def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=
     torch = _torch()
     dtype = dtype or torch.float32
     off = _offsets(positions, offsets)
-    key = (hashlib.sha1(off.tobytes()).hexdigest(), int(nrhs), str(dtype), bool(include_rebuild),
+    if layout not in LAYOUTS:
+        raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+    key = (hashlib.sha1(off.tobytes()).hexdigest(), int(nrhs), str(dtype), bool(include_rebuild), layout,
            tuple(sorted(base.items())))
     if key in _TUNED:
         return dict(_TUNED[key])
@@ -287,7 +310,8 @@ def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=
     best = Options()
     ms = ctypes.c_double()
     _check(_lib.load().hq_autotune(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, int(nrhs),
-                                   _prec(dtype), int(bool(include_rebuild)), ctypes.byref(b), _stream(stream),
+                                   _prec(dtype), LAYOUTS[layout], int(bool(include_rebuild)), ctypes.byref(b),
+                                   _stream(stream),
                                    ctypes.byref(best), ctypes.byref(ms)), "hq_autotune")
     res = {f: getattr(best, f) for f in names}
     res["ms"] = ms.value

@@ -16,6 +16,7 @@ P_f64 = ctypes.POINTER(ctypes.c_double)
 
 HQ_OK, HQ_E_INVALID, HQ_E_DEGENERATE, HQ_E_NOMEM, HQ_E_DEVICE, HQ_E_UNSUPPORTED = range(6)
 HQ_FP64, HQ_FP32 = 0, 1
+HQ_ROWS, HQ_TRIPLES = 0, 1
 HQ_FLAG_NONFINITE, HQ_FLAG_STACK, HQ_FLAG_BOUNDS, HQ_FLAG_PHASES = 1, 2, 4, 8
 HQ_BODY_ILLCOND, HQ_BODY_DEGENERATE = 1, 2
 
@@ -34,13 +35,14 @@ class Info(ctypes.Structure):
 # (name, restype, argtypes) of every exported function
 SIGNATURES = [
     ("hq_build", c_i32, [c_vp, P_i64, c_i64, ctypes.POINTER(Options), c_vp, ctypes.POINTER(c_vp)]),
-    ("hq_autotune", c_i32, [c_vp, P_i64, c_i64, c_i64, c_i32, ctypes.c_int, ctypes.POINTER(Options), c_vp,
+    ("hq_autotune", c_i32, [c_vp, P_i64, c_i64, c_i64, c_i32, c_i32, ctypes.c_int, ctypes.POINTER(Options), c_vp,
                             ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)]),
     ("hq_rebuild", c_i32, [c_vp, c_vp, c_vp]),
     ("hq_reserve", c_i32, [c_vp, c_i64, c_i32]),
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),
-    ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp, ctypes.POINTER(ctypes.c_float),
-                               c_i32, P_i32]),
+    ("hq_apply_layout", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
+    ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp,
+                               ctypes.POINTER(ctypes.c_float), c_i32, P_i32]),
     ("hq_node_phase", c_i32, [c_vp, P_i32]),
     ("hq_explicit", c_i32, [c_vp, c_i64, c_vp, c_i64, c_vp]),
     ("hq_explicit_blocks_size", c_i32, [c_vp, c_i64, P_i64, P_i64]),

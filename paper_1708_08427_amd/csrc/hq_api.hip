@@ -250,7 +250,7 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
 
 // Argument checks and launch of hq_apply (ev: optional per-phase events).
 hq_status hq_apply_checked(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
-                           hipStream_t s, hipEvent_t *ev) {
+                           hq_layout layout, hipStream_t s, hipEvent_t *ev) {
     if (!v || !out) {
         set_error("v or out is NULL");
         return HQ_E_INVALID;
@@ -275,12 +275,16 @@ hq_status hq_apply_checked(Plan &P, const void *v, void *out, int transpose, int
         set_error("transforms of this precision were not kept (hq_options.store)");
         return HQ_E_INVALID;
     }
+    if (layout != HQ_ROWS && layout != HQ_TRIPLES) {
+        set_error("layout must be HQ_ROWS or HQ_TRIPLES");
+        return HQ_E_INVALID;
+    }
     if ((3 * P.N) * nrhs > (int64_t(1) << 40)) {
         set_error("vector too large");
         return HQ_E_UNSUPPORTED;
     }
     HQ_TRY(ensure_xch(P, nrhs, prec, s));
-    return apply_device(P, v, out, transpose, nrhs, prec, s, ev);
+    return apply_device(P, v, out, transpose, nrhs, prec, layout, s, ev);
 }
 
 }  // namespace
@@ -398,7 +402,7 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
 }
 
 hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int64_t m, int64_t nrhs,
-                      hq_precision prec, int include_rebuild, const hq_options *base, hq_stream stream,
+                      hq_precision prec, hq_layout layout, int include_rebuild, const hq_options *base, hq_stream stream,
                       hq_options *best, double *best_ms) {
     if (!best) {
         set_error("best is NULL");
@@ -406,6 +410,10 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
     }
     if (nrhs < 1 || nrhs > (1 << 20) || (prec != HQ_FP64 && prec != HQ_FP32)) {
         set_error("nrhs must be in [1, 2^20] and prec HQ_FP64 or HQ_FP32");
+        return HQ_E_INVALID;
+    }
+    if (layout != HQ_ROWS && layout != HQ_TRIPLES) {
+        set_error("layout must be HQ_ROWS or HQ_TRIPLES");
         return HQ_E_INVALID;
     }
     if (!body_offsets || m < 1) {
@@ -455,8 +463,8 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
                     if (hipEventRecord(e0, s) != hipSuccess) fail(HQ_E_DEVICE, "hipEventRecord");
                     hq_status a = HQ_OK;
                     if (include_rebuild) a = hq_rebuild(h, positions, stream);
-                    if (a == HQ_OK) a = hq_apply(h, va, vb, 0, nrhs, prec, stream);
-                    if (a == HQ_OK) a = hq_apply(h, vb, va, 1, nrhs, prec, stream);
+                    if (a == HQ_OK) a = hq_apply_layout(h, va, vb, 0, nrhs, prec, layout, stream);
+                    if (a == HQ_OK) a = hq_apply_layout(h, vb, va, 1, nrhs, prec, layout, stream);
                     if (a != HQ_OK) {
                         st = a;
                         break;
@@ -517,7 +525,7 @@ hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec) {
 }
 
 hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
-                         hq_stream stream, float *phase_ms, int32_t max_phases, int32_t *nphases) {
+                         hq_layout layout, hq_stream stream, float *phase_ms, int32_t max_phases, int32_t *nphases) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
     if (!phase_ms || !nphases || max_phases < 1) {
@@ -537,7 +545,7 @@ hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, i
             set_error("hipEventCreate");
             st = HQ_E_DEVICE;
         }
-    if (st == HQ_OK) st = hq_apply_checked(*P, v, out, transpose, nrhs, prec, s, ev.data());
+    if (st == HQ_OK) st = hq_apply_checked(*P, v, out, transpose, nrhs, prec, layout, s, ev.data());
     if (st == HQ_OK && hipEventSynchronize(ev[nph]) != hipSuccess) {
         set_error("hipEventSynchronize");
         st = HQ_E_DEVICE;
@@ -574,7 +582,16 @@ hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t
                    hq_stream stream) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
-    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, reinterpret_cast<hipStream_t>(stream), nullptr);
+    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, HQ_ROWS, reinterpret_cast<hipStream_t>(stream),
+                            nullptr);
+}
+
+hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
+                          hq_layout layout, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, layout, reinterpret_cast<hipStream_t>(stream),
+                            nullptr);
 }
 
 hq_status hq_explicit(hq_handle h, int64_t body, double *out, int64_t ld, hq_stream stream) {

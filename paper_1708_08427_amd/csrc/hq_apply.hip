@@ -31,8 +31,18 @@ struct Ctx {
     int64_t N, rows, nsched;
     int R, nchunks, dmax, xch_cap;
     int nslot;  // LDS slots per lane of the wide sweeps
+    // vector layout: element (row0 + k, r) of a row triple (row0 a multiple of
+    // 3, k < 3) sits at row0 * R + r * vlane + k * vcomp; rows (row-major
+    // rows x R): vlane 1, vcomp R; triples (each column's three values of a
+    // triple contiguous): vlane 3, vcomp 1
+    int vlane, vcomp;
     uint32_t in_bytes, out_bytes, xch_bytes;  // buffer sizes of the wide sweeps (each < 2 GiB)
 };
+
+// Index of element (row0 + k, r) of a vector, row0 a multiple of 3.
+__device__ __forceinline__ int64_t velem(int64_t row0, int k, int r, const Ctx &C) {
+    return row0 * C.R + (int64_t)r * C.vlane + (int64_t)k * C.vcomp;
+}
 
 template <typename T>
 __device__ __forceinline__ void push6(T *stk, int &sp, int dmax, const T (&m)[6], int lane, int32_t *err) {
@@ -114,7 +124,7 @@ __device__ __forceinline__ void fetch_child(int ref, T (&m)[6], const T *__restr
             atomicOr(err, kFlagBounds);
         } else if (act) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) m[c] = v[((int64_t)3 * ref + c) * C.R + r];
+            for (int c = 0; c < 3; ++c) m[c] = v[velem((int64_t)3 * ref, c, r, C)];
         }
     } else if (ref != kRefStack) {
         const int slot = ref_slot(ref);
@@ -196,14 +206,11 @@ __device__ __forceinline__ void node_up(const NodeIn<T> &n, T *stk, int &sp, T *
         if (off < 0 || (int64_t)off + dim > C.rows) {
             atomicOr(err, kFlagBounds);
         } else if (act) {
-            T *o = out + (int64_t)off * C.R + r;
-            o[0] = t9[3];
-            o[C.R] = t9[4];
-            o[2 * C.R] = t9[5];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) out[velem(off, k, r, C)] = t9[3 + k];
             if (dim == 6) {
-                o[3 * C.R] = t9[6];
-                o[4 * C.R] = t9[7];
-                o[5 * C.R] = t9[8];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) out[velem(off + 3, k, r, C)] = t9[6 + k];
             }
         }
     }
@@ -290,14 +297,11 @@ __device__ __forceinline__ void fetch_down(NodeIn<T> &n, int s, const T *__restr
         if (off < 0 || (int64_t)off + dim > C.rows) {
             atomicOr(err, kFlagBounds);
         } else if (act) {
-            const T *src = w + (int64_t)off * C.R + r;
-            n.a[0] = src[0];
-            n.a[1] = src[C.R];
-            n.a[2] = src[2 * C.R];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) n.a[k] = w[velem(off, k, r, C)];
             if (dim == 6) {
-                n.a[3] = src[3 * C.R];
-                n.a[4] = src[4 * C.R];
-                n.a[5] = src[5 * C.R];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) n.a[3 + k] = w[velem(off + 3, k, r, C)];
             }
         }
     }
@@ -321,10 +325,8 @@ __device__ __forceinline__ void emit_child(int ref, const T (&L)[6], T *__restri
             return;
         }
         if (act) {
-            T *o = out + (int64_t)3 * ref * C.R + r;
-            o[0] = L[0];
-            o[C.R] = L[1];
-            o[2 * C.R] = L[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) out[velem((int64_t)3 * ref, k, r, C)] = L[k];
         }
     } else if (ref == kRefStack) {
         push6(stk, sp, C.dmax, L, lane, err);
@@ -723,6 +725,50 @@ __device__ __forceinline__ void bst6n(rsrc_t r, uint32_t vo, const T (&m)[6][NC]
     }
 }
 
+// The three values m[S .. S + 2] of a row triple for the lane's columns.  Rows
+// layout: three accesses a vector row (row bytes) apart; triples layout (one
+// column per lane): the lane's three values are contiguous, one access.
+template <typename T, bool TRI, int NC, int S, int K>
+__device__ __forceinline__ void bld3n(rsrc_t r, uint32_t vo, uint32_t row, T (&m)[K][NC]) {
+    static_assert(S + 3 <= K, "triple inside the array");
+    if constexpr (!TRI) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bldn<T, NC>(r, vo, k * row, m[S + k]);
+    } else if constexpr (sizeof(T) == 4) {
+        static_assert(NC == 1, "the triples layout holds one column per lane");
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 0, 0);
+        m[S][0] = __uint_as_float(a.x);
+        m[S + 1][0] = __uint_as_float(a.y);
+        m[S + 2][0] = __uint_as_float(a.z);
+    } else {
+        static_assert(NC == 1, "the triples layout holds one column per lane");
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, vo, 16, 0);
+        m[S][0] = __builtin_bit_cast(double, u32x2{a.x, a.y});
+        m[S + 1][0] = __builtin_bit_cast(double, u32x2{a.z, a.w});
+        m[S + 2][0] = __builtin_bit_cast(double, b);
+    }
+}
+
+template <typename T, bool TRI, int NC, int S, int K>
+__device__ __forceinline__ void bst3n(const T (&m)[K][NC], rsrc_t r, uint32_t vo, uint32_t row) {
+    static_assert(S + 3 <= K, "triple inside the array");
+    if constexpr (!TRI) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bstn<T, NC>(m[S + k], r, vo, k * row);
+    } else if constexpr (sizeof(T) == 4) {
+        static_assert(NC == 1, "the triples layout holds one column per lane");
+        // zero SGPR offset: see bstn
+        __builtin_amdgcn_raw_buffer_store_b96(
+            u32x3{__float_as_uint(m[S][0]), __float_as_uint(m[S + 1][0]), __float_as_uint(m[S + 2][0])}, r, vo, 0, 0);
+    } else {
+        static_assert(NC == 1, "the triples layout holds one column per lane");
+        const u32x2 a = __builtin_bit_cast(u32x2, m[S][0]), b = __builtin_bit_cast(u32x2, m[S + 1][0]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, m[S + 2][0]), r, vo, 16, 0);
+    }
+}
+
 // LDS slot layout: [slot][component 0..5][64 lanes][NC]
 template <typename T, int NC>
 __device__ __forceinline__ void lds_put6(T *lds, int slot, int lane, const T (&m)[6][NC]) {
@@ -785,30 +831,34 @@ __device__ __forceinline__ WBufs wide_bufs(const T *in, T *out, T *xch, const Ct
     return b;
 }
 
-// Byte offset of bead ref's first row for the lane's first column (lanebytes):
-// a negative ref (not a bead) or on = false lands past the end of the buffer.
+// Byte offsets of the lane's first column inside a row triple of a vector
+// (v: r * vlane values) and inside an exchange entry (x: 6 r values).
+struct LaneB {
+    uint32_t v, x;
+};
+
+// Byte offset of bead ref's first row for the lane's first column: a negative
+// ref (not a bead) or on = false lands past the end of the buffer.
 template <typename T, int RT>
-__device__ __forceinline__ uint32_t bead_off(int ref, bool on, const Ctx &C, uint32_t lanebytes) {
+__device__ __forceinline__ uint32_t bead_off(int ref, bool on, const Ctx &C, LaneB lb) {
     const uint32_t u = on ? min((uint32_t)ref, (uint32_t)C.N) : (uint32_t)C.N;
-    return u * (uint32_t)(3 * rhs_count<RT>(C) * sizeof(T)) + lanebytes;
+    return u * (uint32_t)(3 * rhs_count<RT>(C) * sizeof(T)) + lb.v;
 }
 
 // Byte offset of exchange entry (slot, lane's first column), past the end when off.
 template <typename T, int RT>
-__device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, uint32_t lanebytes) {
+__device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, LaneB lb) {
     const uint32_t sl = on ? min((uint32_t)slot, (uint32_t)C.xch_cap) : (uint32_t)C.xch_cap;
-    return sl * (uint32_t)(6 * rhs_count<RT>(C) * sizeof(T)) + 6 * lanebytes;
+    return sl * (uint32_t)(6 * rhs_count<RT>(C) * sizeof(T)) + lb.x;
 }
 
 // Upward memory input of one child: a bead's vector (3 values; zero Info-set
 // tail) or, with IW = 6, an earlier tile root's Info-set.  A stack child loads
 // nothing (zeros).  IW = 3 serves the first tile phase, whose only memory
 // inputs are beads.
-template <typename T, int RT, int IW, int NC>
-__device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B, const Ctx &C, uint32_t lb) {
-    const uint32_t vb = bead_off<T, RT>(ref, true, C, lb);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, vb, k * B.row, m[k]);
+template <typename T, int RT, int IW, int NC, bool TRI>
+__device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B, const Ctx &C, LaneB lb) {
+    bld3n<T, TRI, NC, 0>(B.in, bead_off<T, RT>(ref, true, C, lb), B.row, m);
     if constexpr (IW == 6) {
         T e[6][NC];
         bld6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
@@ -825,10 +875,10 @@ __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B
 // One upward node step (Eqs. 4.2-4.3).  A child of the same tile is read from
 // its LDS slot; a bead or an earlier tile's root comes from the prefetched
 // registers ax / ay.  Nothing is stored unless the node is live.
-template <typename T, int RT, int IW, int NC>
+template <typename T, int RT, int IW, int NC, bool TRI>
 __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW][NC],
                                         const T (&ay)[IW][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
-                                        uint32_t lb, bool live, bool act) {
+                                        LaneB lb, bool live, bool act) {
     // offsets and references were checked when the tile schedule was built;
     // an access outside a buffer would be dropped by its range check
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
@@ -870,13 +920,11 @@ __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, cons
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
     const bool en = live && act;
     // residue rows [off, off + dim)
-    const uint32_t ob = (uint32_t)lk.off * B.row + lb;
+    const uint32_t ob = (uint32_t)lk.off * B.row + lb.v;
     const uint32_t o1 = (en && any) ? ob : kOOB;
     const uint32_t o2 = (en && both) ? ob + 3 * B.row : kOOB;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bstn<T, NC>(t9[3 + k], B.out, o1, k * B.row);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bstn<T, NC>(t9[6 + k], B.out, o2, k * B.row);
+    bst3n<T, TRI, NC, 3>(t9, B.out, o1, B.row);
+    bst3n<T, TRI, NC, 6>(t9, B.out, o2, B.row);
     // a tile root's Info-set goes to the exchange buffer, others stay in LDS
     bst6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, en && troot, C, lb), mp);
     if (live && !troot) lds_put6<T, NC>(lds, os, lane, mp);
@@ -906,7 +954,7 @@ __device__ __forceinline__ int wave_max_len(int len) {
     return __builtin_amdgcn_readfirstlane(len);
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC>
+template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC, bool TRI>
 __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_up_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
@@ -930,7 +978,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
         const bool act = col < R;
-        const uint32_t lb = (uint32_t)(rr * sizeof(T));
+        const LaneB lb{(uint32_t)(rr * (TRI ? 3 : 1) * sizeof(T)), (uint32_t)(rr * 6 * sizeof(T))};
         const int maxlen = wave_max_len<LPT>(len);
         const int last = max(len - 1, 0);
         const T *rp = rec + (int64_t)kRecWords * base;
@@ -941,8 +989,8 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
 #pragma unroll
         for (int k = 0; k < NR - 1; ++k) {
             const int2 ref = bcast_refs(RW[k]);
-            up_input<T, RT, IW, NC>(ref.x, A[k], B, C, lb);
-            up_input<T, RT, IW, NC>(ref.y, Bv[k], B, C, lb);
+            up_input<T, RT, IW, NC, TRI>(ref.x, A[k], B, C, lb);
+            up_input<T, RT, IW, NC, TRI>(ref.y, Bv[k], B, C, lb);
         }
 #define HQ_UP_STEP(K)                                                                       \
         {                                                                                   \
@@ -953,10 +1001,10 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
             RW[K].load(rp + (int64_t)min(n + PR, last) * kRecWords, lane);                  \
             {                                                                               \
                 const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                       \
-                up_input<T, RT, IW, NC>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);           \
-                up_input<T, RT, IW, NC>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);          \
+                up_input<T, RT, IW, NC, TRI>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);      \
+                up_input<T, RT, IW, NC, TRI>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);     \
             }                                                                               \
-            up_node<T, RT, IW, NC>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            up_node<T, RT, IW, NC, TRI>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_UP_STEP(0)
@@ -976,17 +1024,15 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
 // Downward memory inputs of one node: its residue coefficients w_p (dim = 0,
 // 3 or 6 values) and, for a tile root below a body root, its Velocity-set from
 // the exchange buffer; absent values load as zeros.
-template <typename T, int RT, int NC>
+template <typename T, int RT, int NC, bool TRI>
 __device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&b)[6][NC], const WBufs &B,
-                                           const Ctx &C, uint32_t lb) {
+                                           const Ctx &C, LaneB lb) {
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
-    const uint32_t ob = (uint32_t)lk.off * B.row + lb;
+    const uint32_t ob = (uint32_t)lk.off * B.row + lb.v;
     const uint32_t p1 = (xi || yi) ? ob : kOOB;
     const uint32_t p2 = (xi && yi) ? ob + 3 * B.row : kOOB;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, p1, k * B.row, a[k]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bldn<T, NC>(B.in, p2, k * B.row, a[3 + k]);
+    bld3n<T, TRI, NC, 0>(B.in, p1, B.row, a);
+    bld3n<T, TRI, NC, 3>(B.in, p2, B.row, a);
     const bool lr = (lk.meta & (kMetaTileRoot | kMetaBodyRoot)) == kMetaTileRoot;
     bld6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, lr, C, lb), b);
 }
@@ -995,10 +1041,10 @@ __device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&
 // exchange buffer for a tile root, zero for a body root), children's
 // Velocity-sets to their slots, to bead outputs, or (XC: phases after the
 // first) to the exchange buffer.
-template <typename T, int RT, bool XC, int NC>
+template <typename T, int RT, bool XC, int NC, bool TRI>
 __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, const T (&wp)[6][NC],
                                           const T (&lroot)[6][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
-                                          uint32_t lb, bool live, bool act) {
+                                          LaneB lb, bool live, bool act) {
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
     const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
@@ -1033,11 +1079,8 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
     const bool en = live && act;
     {
         const uint32_t bx = bead_off<T, RT>(lk.xref, en, C, lb), by = bead_off<T, RT>(lk.yref, en, C, lb);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            bstn<T, NC>(Lx[k], B.out, bx, k * B.row);
-            bstn<T, NC>(Ly[k], B.out, by, k * B.row);
-        }
+        bst3n<T, TRI, NC, 0>(Lx, B.out, bx, B.row);
+        bst3n<T, TRI, NC, 0>(Ly, B.out, by, B.row);
     }
     if constexpr (XC) {
         bst6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(lk.xref), en && lk.xref < kRefStack, C, lb), Lx);
@@ -1050,7 +1093,7 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
     }
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC>
+template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC, bool TRI>
 __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_down_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
@@ -1074,7 +1117,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
         const bool act = col < R;
-        const uint32_t lb = (uint32_t)(rr * sizeof(T));
+        const LaneB lb{(uint32_t)(rr * (TRI ? 3 : 1) * sizeof(T)), (uint32_t)(rr * 6 * sizeof(T))};
         const int maxlen = wave_max_len<LPT>(len);
         const int last = max(len - 1, 0);
         // node n of the sweep is schedule index base + len - 1 - n
@@ -1084,7 +1127,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
 #pragma unroll
         for (int k = 0; k < PR; ++k) RW[k].load(rp - (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
-        for (int k = 0; k < NR - 1; ++k) down_input<T, RT, NC>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
+        for (int k = 0; k < NR - 1; ++k) down_input<T, RT, NC, TRI>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
 #define HQ_DOWN_STEP(K)                                                                     \
         {                                                                                   \
             const int n = n0 + (K);                                                         \
@@ -1092,9 +1135,9 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
             bcast_g<0>(g, RW[K]);                                                           \
             const Links6 lk = bcast_links6(RW[K]);                                          \
             RW[K].load(rp - (int64_t)min(n + PR, last) * kRecWords, lane);                  \
-            down_input<T, RT, NC>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
-                                  Bl[((K) + NR - 1) % NR], B, C, lb);                       \
-            down_node<T, RT, XC, NC>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            down_input<T, RT, NC, TRI>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
+                                       Bl[((K) + NR - 1) % NR], B, C, lb);                  \
+            down_node<T, RT, XC, NC, TRI>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_DOWN_STEP(0)
@@ -1111,8 +1154,9 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
     if (bad) atomicOr(err, bad);
 }
 
-// One tile phase of a wide sweep: LPT lanes per run, NC columns per lane.
-template <typename T, int LPT, int NC>
+// One tile phase of a wide sweep: LPT lanes per run, NC columns per lane,
+// vectors in the rows or (TRI) the triples layout.
+template <typename T, int LPT, int NC, bool TRI>
 void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
                  hipStream_t s) {
     constexpr int TPW = 64 / LPT;
@@ -1131,17 +1175,17 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     do {                                                                                                     \
         if (!transpose) {                                                                                    \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR1, NR1, 3, NC>), dim3(grid), dim3(64), lds_w, s,    \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR1, NR1, 3, NC, TRI>), dim3(grid), dim3(64), lds_w, s,    \
                                    phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
             else                                                                                             \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6, NC>), dim3(grid), dim3(64), lds_w, s,      \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6, NC, TRI>), dim3(grid), dim3(64), lds_w, s,      \
                                    phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
         } else {                                                                                             \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false, NC>), dim3(grid), dim3(64), lds_w,   \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
                                    s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
             else                                                                                             \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD2, true, NC>), dim3(grid), dim3(64), lds_w,   \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD2, true, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
                                    s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
         }                                                                                                    \
     } while (0)
@@ -1178,6 +1222,7 @@ enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWi
 template <typename T>
 void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
                 const Ctx &C, hipStream_t s, hipEvent_t *ev) {
+    const bool tri = C.vlane == 3;
     const int nph = std::max(P.phases_built, P.phases_reserved);
     for (int k = 0; k < nph; ++k) {
         const int phase = transpose ? (nph - k) : (k + 1);
@@ -1188,8 +1233,14 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
         case kNarrow4: launch_narrow<T, 4>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow8: launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kWide32: launch_wide<T, 32, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kWide64: launch_wide<T, 64, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kWide32:
+            if (tri) launch_wide<T, 32, 1, true>(P, phase, transpose, rec, v, out, xch, C, s);
+            else launch_wide<T, 32, 1, false>(P, phase, transpose, rec, v, out, xch, C, s);
+            break;
+        case kWide64:
+            if (tri) launch_wide<T, 64, 1, true>(P, phase, transpose, rec, v, out, xch, C, s);
+            else launch_wide<T, 64, 1, false>(P, phase, transpose, rec, v, out, xch, C, s);
+            break;
         }
     }
     if (ev) (void)hipEventRecord(ev[nph], s);
@@ -1203,13 +1254,15 @@ int lanes_per_tile(int64_t nrhs) {
     return l;
 }
 
-hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, hipStream_t s,
-                       hipEvent_t *ev) {
+hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, int layout,
+                       hipStream_t s, hipEvent_t *ev) {
     Ctx C;
     C.N = P.N;
     C.rows = P.rows;
     C.nsched = P.NI;
     C.R = (int)nrhs;
+    C.vlane = (layout == HQ_TRIPLES) ? 3 : 1;
+    C.vcomp = (layout == HQ_TRIPLES) ? 1 : C.R;
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
     C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(P.xch_bytes / (6 * elem * (size_t)nrhs)));
     // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB
