@@ -105,6 +105,10 @@ typedef struct {
     int32_t keep_node_data;/* 1: hq_rebuild also refreshes the per-node centroids and T22
                               that hq_node_data returns (hq_build always writes them);
                               0: it skips them (less memory traffic) */
+    int32_t later_tile_units; /* max units per tile in the tile phases after the first,
+                              whose units are the roots of earlier tiles; smaller tiles give
+                              those short phases more parallel work at the cost of more
+                              phases; 0 = tile_units; <= 1024 */
 } hq_options;
 
 typedef struct {
@@ -122,17 +126,21 @@ typedef struct {
     int64_t degenerate_bodies;
 } hq_info;
 
-/* Pick tile_units, run_nodes and waves_per_cu for a workload by measurement:
- * the subtree size of Section 2's tree cut into tiles, and the launch shape of
- * the sweeps (Algorithms 2 and 3).  For every candidate, builds a handle on
- * the given positions, then times (median of 5 after 2 warm-up rounds, HIP
- * events on the stream) one round of: hq_rebuild if include_rebuild, an
- * upward and a downward hq_apply_layout with nrhs right-hand sides in
- * precision prec and vector layout layout.  Candidates: tile_units 16, 32, 64; run_nodes 32, 48, 64; waves_per_cu
- * 8, 16, 32.
+/* Pick tile_units, later_tile_units, run_nodes and waves_per_cu for a workload
+ * by measurement: the subtree sizes of Section 2's tree cut into tiles, and
+ * the launch shape of the sweeps (Algorithms 2 and 3).  For every candidate,
+ * builds a handle on the given positions, then times (median of 5 after 2
+ * warm-up rounds, HIP events on the stream) one round of: hq_rebuild if
+ * include_rebuild, an upward and a downward hq_apply_layout with nrhs
+ * right-hand sides in precision prec and vector layout layout.
+ * Stage 1: tile_units 16, 32, 64 x run_nodes 32, 48, 64 x waves_per_cu 8,
+ * 16, 32 (later_tile_units = tile_units).
+ * Stage 2, on the winner: later_tile_units 4, 8, 16 (those below its
+ * tile_units) x waves_per_cu 8, 16, 32; kept only if faster.
  *   positions, body_offsets, m  as for hq_build.
  *   base          host, may be NULL: the other options of the trial builds.
- *   best          host: receives base with the three chosen fields set.
+ *   best          host: receives base with the four chosen fields set
+ *                 (later_tile_units 0 when stage 2 kept tile_units).
  *   best_ms       host, may be NULL: the chosen candidate's time per round.
  * Allocates (and frees) trial handles and two vector buffers; synchronises
  * the stream.  Errors as for hq_build and hq_apply. */

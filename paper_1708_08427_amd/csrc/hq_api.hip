@@ -78,6 +78,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     }
     P.rows = P.row_off[m];
     P.S = (opt && opt->tile_units) ? opt->tile_units : 32;
+    P.S2 = (opt && opt->later_tile_units) ? opt->later_tile_units : P.S;
     if (opt && opt->run_nodes) P.run_nodes = opt->run_nodes;
     if (opt && opt->waves_per_cu) P.waves_per_cu = opt->waves_per_cu;
     P.keep_node_data = opt && opt->keep_node_data != 0;
@@ -338,6 +339,10 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
         return HQ_E_UNSUPPORTED;
     }
     if (opt) {
+        if (opt->later_tile_units != 0 && (opt->later_tile_units < 2 || opt->later_tile_units > kMaxTileUnits)) {
+            set_error("later_tile_units must be 0 or in [2, 1024]");
+            return HQ_E_INVALID;
+        }
         if (opt->tile_units != 0 && (opt->tile_units < 2 || opt->tile_units > kMaxTileUnits)) {
             set_error("tile_units must be 0 or in [2, 1024]");
             return HQ_E_INVALID;
@@ -442,18 +447,17 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
         fail(HQ_E_DEVICE, "autotune setup");
     }
     const int s_cand[] = {16, 32, 64}, r_cand[] = {32, 48, 64}, w_cand[] = {8, 16, 32};
+    const int s2_cand[] = {4, 8, 16};
     double best_t = 1e300;
     hq_options chosen = opt;
-    for (int si = 0; si < 3 && st == HQ_OK; ++si) {
-        for (int ri = 0; ri < 3 && st == HQ_OK; ++ri) {
-            hq_options o = opt;
-            o.tile_units = s_cand[si];
-            o.run_nodes = r_cand[ri];
+    // one trial build, timed at every waves_per_cu candidate
+    auto trial = [&](const hq_options &o) {
+        {
             hq_handle h = nullptr;
             hq_status bs = hq_build(positions, body_offsets, m, &o, stream, &h);
             if (bs != HQ_OK) {
                 st = bs;
-                break;
+                return;
             }
             Plan *P = get_plan(h);
             for (int wi = 0; wi < 3 && st == HQ_OK; ++wi) {
@@ -490,6 +494,24 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
                 fail(HQ_E_DEVICE, "device flags raised during autotuning: " + std::to_string(flags));
             hq_destroy(h);
         }
+    };
+    // stage 1: first-phase tile size and run length, later phases with the
+    // same tile size
+    for (int si = 0; si < 3 && st == HQ_OK; ++si)
+        for (int ri = 0; ri < 3 && st == HQ_OK; ++ri) {
+            hq_options o = opt;
+            o.tile_units = s_cand[si];
+            o.run_nodes = r_cand[ri];
+            o.later_tile_units = 0;
+            trial(o);
+        }
+    // stage 2: smaller tiles for the later phases under the chosen first phase
+    const hq_options first = chosen;
+    for (int k = 0; k < 3 && st == HQ_OK; ++k) {
+        if (s2_cand[k] >= first.tile_units) continue;
+        hq_options o = first;
+        o.later_tile_units = s2_cand[k];
+        trial(o);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -959,7 +959,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
-    static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6), "ring sizes");
+    static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6 || PR == 12), "ring sizes");
     static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -1015,6 +1015,14 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
                 HQ_UP_STEP(4)
                 HQ_UP_STEP(5)
             }
+            if constexpr (PR >= 12) {
+                HQ_UP_STEP(6)
+                HQ_UP_STEP(7)
+                HQ_UP_STEP(8)
+                HQ_UP_STEP(9)
+                HQ_UP_STEP(10)
+                HQ_UP_STEP(11)
+            }
         }
 #undef HQ_UP_STEP
     }
@@ -1023,18 +1031,25 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
 
 // Downward memory inputs of one node: its residue coefficients w_p (dim = 0,
 // 3 or 6 values) and, for a tile root below a body root, its Velocity-set from
-// the exchange buffer; absent values load as zeros.
+// the exchange buffer; absent values are zeros.  Unlike the other wide-sweep
+// accesses these loads are skipped, not sent out of range, when absent: the
+// exchange entry is absent for all but the tile roots, and an out-of-range
+// access still occupies the texture units (measured: skipping them takes 11%
+// off the first phase's downward launch, while the same change to the upward
+// sweep's bead loads made it slower).
 template <typename T, int RT, int NC, bool TRI>
 __device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&b)[6][NC], const WBufs &B,
                                            const Ctx &C, LaneB lb) {
     const bool xi = lk.xref < 0, yi = lk.yref < 0;
     const uint32_t ob = (uint32_t)lk.off * B.row + lb.v;
-    const uint32_t p1 = (xi || yi) ? ob : kOOB;
-    const uint32_t p2 = (xi && yi) ? ob + 3 * B.row : kOOB;
-    bld3n<T, TRI, NC, 0>(B.in, p1, B.row, a);
-    bld3n<T, TRI, NC, 3>(B.in, p2, B.row, a);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[k][c] = b[k][c] = T(0);
+    if (xi || yi) bld3n<T, TRI, NC, 0>(B.in, ob, B.row, a);
+    if (xi && yi) bld3n<T, TRI, NC, 3>(B.in, ob + 3 * B.row, B.row, a);
     const bool lr = (lk.meta & (kMetaTileRoot | kMetaBodyRoot)) == kMetaTileRoot;
-    bld6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, lr, C, lb), b);
+    if (lr) bld6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, true, C, lb), b);
 }
 
 // One downward node step (Theorem 4.3): L_p from its LDS slot (or the
@@ -1098,7 +1113,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
     const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
-    static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6), "ring sizes");
+    static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6 || PR == 12), "ring sizes");
     static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -1148,6 +1163,14 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
                 HQ_DOWN_STEP(4)
                 HQ_DOWN_STEP(5)
             }
+            if constexpr (PR >= 12) {
+                HQ_DOWN_STEP(6)
+                HQ_DOWN_STEP(7)
+                HQ_DOWN_STEP(8)
+                HQ_DOWN_STEP(9)
+                HQ_DOWN_STEP(10)
+                HQ_DOWN_STEP(11)
+            }
         }
 #undef HQ_DOWN_STEP
     }
@@ -1171,30 +1194,30 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     // rebuild): a grid of waves_per_cu waves per CU loops over them
     const int64_t g = (phase == 1) ? items : std::min<int64_t>(items, (int64_t)P.waves_per_cu * P.ncu);
     const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
-#define HQ_WIDE(RT, PR, NR, PR1, NR1, NRD, NRD2)                                                             \
+#define HQ_WIDE(RT, PRU1, NRU1, PRU, NRU, PRD1, NRD1, PRD, NRD)                                              \
     do {                                                                                                     \
         if (!transpose) {                                                                                    \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR1, NR1, 3, NC, TRI>), dim3(grid), dim3(64), lds_w, s,    \
-                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU1, NRU1, 3, NC, TRI>), dim3(grid), dim3(64), lds_w, \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
             else                                                                                             \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PR, NR, 6, NC, TRI>), dim3(grid), dim3(64), lds_w, s,      \
-                                   phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);                  \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU, NRU, 6, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
         } else {                                                                                             \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD, false, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
-                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD1, NRD1, false, NC, TRI>), dim3(grid), dim3(64),  \
+                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);        \
             else                                                                                             \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, 6, NRD2, true, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
-                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD, NRD, true, NC, TRI>), dim3(grid), dim3(64),     \
+                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);        \
         }                                                                                                    \
     } while (0)
-    // the first phase carries almost all nodes and wants occupancy; later
-    // phases have few lane groups, each a long dependent chain, and want deep
-    // prefetch (inputs five nodes ahead)
-    constexpr int NRL = sizeof(T) == 4 ? 6 : 3;  // FP64 registers allow three
-    if (C.R == 32) HQ_WIDE(32, 6, NRL, 6, 3, 3, NRL);
-    else HQ_WIDE(0, 6, NRL, 6, 3, 3, NRL);
+    // records six nodes ahead, inputs two nodes ahead, in every phase
+    // (measured: a deeper input ring for the later phases, five nodes ahead,
+    // was 8% slower on their upward launches; a 12-deep record ring slower
+    // still)
+    if (C.R == 32) HQ_WIDE(32, 6, 3, 6, 3, 6, 3, 6, 3);
+    else HQ_WIDE(0, 6, 3, 6, 3, 6, 3, 6, 3);
 #undef HQ_WIDE
 }
 
@@ -1288,8 +1311,8 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
         kind = lpt == 1 ? kNarrow1 : lpt == 2 ? kNarrow2 : lpt == 4 ? kNarrow4 : lpt == 8 ? kNarrow8 : kNarrow16;
     }
     C.nchunks = (int)((nrhs + cols - 1) / cols);
-    C.dmax = stack_depth(P.S);
-    C.nslot = stack_slots(P.S);
+    C.dmax = stack_depth(P.smax());
+    C.nslot = stack_slots(P.smax());
     if (prec == HQ_FP64)
         launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s,
                            ev);

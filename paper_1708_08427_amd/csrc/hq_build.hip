@@ -1329,7 +1329,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             hipLaunchKernelGGL(k_units_walk, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_lc, P.d_rc,
                                P.d_par, P.d_units, P.d_err, gate);
         }
-        hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.S, P.d_cov, P.d_par,
+        hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, (ph == 1) ? P.S : P.S2,
+                           P.d_cov, P.d_par,
                            P.d_nn, P.d_units, P.d_trval, gate);
         HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
         hipLaunchKernelGGL(k_tile_emit, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_trval, P.d_trscan,
@@ -1368,7 +1369,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
                        P.d_tile_root, P.d_lw, P.d_nbody, P.d_row_off, toff, P.d_err);
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm, toff,
-                       P.d_slot, stack_slots(P.S), P.d_lw, P.d_links, P.d_err);
+                       P.d_slot, stack_slots(P.smax()), P.d_lw, P.d_links, P.d_err);
     // --- 5. transforms, one launch per tile phase; later phases read the
     // roots of earlier phases' tiles from the tile-root table (sized after
     // the first build: twice its tiles, the capacity of the exchange buffer)
@@ -1384,7 +1385,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         P.d_troot = reinterpret_cast<double *>(q);
         P.troot_cap = cap;
     }
-    const int nslot = stack_slots(P.S);
+    const int nslot = stack_slots(P.smax());
     const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double) + ((P.store & 2) ? kStageBytes : 0);
     const unsigned gen_grid = (unsigned)std::min<int64_t>((P.tiles_built + P.tiles_built / 4) / 64 + 1, 65535);
     using GenFn = decltype(&k_gen_tile<false, 0, false>);

@@ -131,7 +131,9 @@ constexpr int kRunTarget = 16384;
 struct Plan {
     uint32_t magic = 0;
     int64_t N = 0, m = 0, NI = 0, rows = 0;
-    int S = 256;
+    int S = 256;   // tile size (units) of the first phase
+    int S2 = 256;  // tile size of the later phases
+    int smax() const { return S > S2 ? S : S2; }
     int store = 3;
     int dense_max_n = 4096;
     int phases_reserved = 0;  // phases launched by hq_rebuild

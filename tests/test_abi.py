@@ -73,7 +73,10 @@ def test_bad_options_rejected(lib):
     from paper_1708_08427_amd._lib import Options
     off = np.array([0, 4], dtype=np.int64)
     h = ctypes.c_void_p()
-    for opt in (Options(1, 0, 0, 0), Options(4096, 0, 0, 0), Options(0, 7, 0, 0), Options(0, 0, 0, 99)):
+    bad = [Options(1, 0, 0, 0), Options(4096, 0, 0, 0), Options(0, 7, 0, 0), Options(0, 0, 0, 99),
+           Options(run_nodes=4), Options(waves_per_cu=65), Options(keep_node_data=2),
+           Options(later_tile_units=1), Options(later_tile_units=2048)]
+    for opt in bad:
         st = lib.hq_build(ctypes.c_void_p(1), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1,
                           ctypes.byref(opt), None, ctypes.byref(h))
         assert st == 1

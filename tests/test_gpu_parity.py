@@ -59,12 +59,12 @@ def oracle_products(w, v, wv):
     return bt, bt.apply(v), bt.apply(wv, transpose=True)
 
 
-def check_fp64(hq, w, S=0, nrhs=None):
+def check_fp64(hq, w, S=0, nrhs=None, S2=0):
     rng = np.random.default_rng(123)
     R = nrhs or w.nrhs
     v = rng.standard_normal((3 * w.N, R))
     wv = rng.standard_normal((w.rows, R))
-    h = build(hq, w, tile_units=S)
+    h = build(hq, w, tile_units=S, later_tile_units=S2)
     bt, up_o, dn_o = oracle_products(w, v, wv)
     up = h.apply(_dev(v)).cpu().numpy()
     dn = h.apply(_dev(wv), transpose=True).cpu().numpy()
@@ -123,6 +123,16 @@ def test_batch_fp64_tile_sizes(hq, S):
     check_fp64(hq, w, S=S, nrhs=3)
 
 
+@pytest.mark.parametrize("S,S2", [(32, 2), (32, 4), (16, 8), (4, 64)])
+def test_batch_fp64_later_tile_sizes(hq, S, S2):
+    """A separate tile size for the phases after the first (more, shorter
+    later phases, or fewer, longer ones), with narrow and wide sweeps."""
+    w = W.small_batch(11, [2, 3, 4, 7, 33, 129, 500, 1500, 2600])
+    h = check_fp64(hq, w, S=S, nrhs=3, S2=S2)
+    assert h.query()["phases"] >= 2
+    check_fp64(hq, w, S=S, nrhs=40, S2=S2)
+
+
 @pytest.mark.parametrize("R", [1, 5, 16, 32, 64, 70])
 def test_nrhs_shapes(hq, R):
     w = W.small_batch(12, [40, 700, 1200])
@@ -135,10 +145,11 @@ def test_results_independent_of_tile_size(hq):
     rng = np.random.default_rng(5)
     v = _dev(rng.standard_normal((3 * w.N, 4)))
     outs = []
-    for S in (8, 64, 1024):
-        h = build(hq, w, tile_units=S)
+    for S, S2 in ((8, 0), (64, 0), (1024, 0), (32, 4), (16, 2)):
+        h = build(hq, w, tile_units=S, later_tile_units=S2)
         outs.append(h.apply(v).cpu().numpy())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_large_body_merge_sort(hq):

@@ -45,7 +45,7 @@ def test_rigid_update_matches_numpy(hq):
 def test_rebuild_equals_fresh_build(hq):
     w, rot, trans, f = _workload()
     pos = torch.from_numpy(w.pos).cuda()
-    h = hq.build(pos, w.offsets, tile_units=32)
+    h = hq.build(pos, w.offsets, tile_units=32, later_tile_units=4)
     f64 = torch.from_numpy(f).cuda()
     moved = w.pos.copy()
     for j in range(w.m):
@@ -55,7 +55,7 @@ def test_rebuild_equals_fresh_build(hq):
     pos2 = torch.from_numpy(moved).cuda()
     h.rebuild(pos2)
     a = h.apply(f64).cpu().numpy()
-    h2 = hq.build(pos2, w.offsets, tile_units=32)
+    h2 = hq.build(pos2, w.offsets, tile_units=32, later_tile_units=4)
     b = h2.apply(f64).cpu().numpy()
     assert h.query()["device_flags"] == 0
     assert np.array_equal(a, b)
