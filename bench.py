@@ -293,6 +293,11 @@ def main():
         t_up = timed(lambda: h.apply(f32, out=tmp, stream=stream, layout=lay), args.apply_reps)
         t_dn = timed(lambda: h.apply(tmp, transpose=True, out=out, stream=stream, layout=lay), args.apply_reps)
         t_rb = timed(lambda: h.rebuild(pos, stream=stream), 5)
+        # the full Q = [Q_Z; Q~]: the same sweeps keeping the root Info-sets
+        root_buf = torch.empty(vec_shape(6 * m, R, lay), dtype=torch.float32, device=dev)
+        t_fup = timed(lambda: h.apply_full(f32, out=tmp, root=root_buf, stream=stream, layout=lay), args.apply_reps)
+        t_fdn = timed(lambda: h.apply_full(tmp, transpose=True, root=root_buf, out=out, stream=stream, layout=lay),
+                      args.apply_reps)
         f64 = f32.double()
         tmp64 = torch.empty(vec_shape(wl.rows, R, lay), dtype=torch.float64, device=dev)
         h64 = hq.build(pos, wl.offsets, store=1, stream=stream, **opts)
@@ -355,6 +360,8 @@ def main():
                                      "achieved": nbytes / (t_up * 1e-3) / 1e9}},
         "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},
         "apply_only_bead_vectors_per_s": N * R / ((t_up + t_dn) * 1e-3),
+        "full_q": {"up_ms": t_fup, "down_ms": t_fdn, "bead_vectors_per_s": N * R / ((t_fup + t_fdn) * 1e-3),
+                   "what": "hq_apply_full: Q v = [Q_Z v; Q~ v] and Q^T [r; w], FP32, same workload"},
         "fp32_rel_err_vs_fp64_oracle": err,
         "fp32_leak": leak,
         "tiles": q["tiles"], "phases": q["phases"],

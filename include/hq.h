@@ -189,6 +189,22 @@ hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t
 hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
                           hq_precision prec, hq_layout layout, hq_stream stream);
 
+/* The full orthogonal Q = [Q_Z; Q~] of every body (Algorithms 2 and 3 with
+ * the root kept; Q_Z's six rows span the row space of Z, Eq. 1.2).
+ *   transpose = 0: out = Q~ v as hq_apply_layout, and root receives Q_Z v,
+ *                  each body's root Info-set (Definition 4.1).
+ *   transpose = 1: root supplies each body's root Velocity-set L_root:
+ *                  out = Q_Z^T root + Q~^T v (Algorithm 3, Theorem 4.3).
+ *   root  device, 6 rows per body (6m rows x nrhs) in the call's layout:
+ *         HQ_ROWS (6m x nrhs row-major) or HQ_TRIPLES (2m x nrhs x 3); for
+ *         body j, rows 6j..6j+2 hold the sum of its bead rows over
+ *         sqrt(n_j) (the translation part) and rows 6j+3..6j+5 the
+ *         rotational part.  Must not overlap v or out.
+ * Errors as for hq_apply_layout; HQ_E_INVALID if root is NULL or equals v or
+ * out. */
+hq_status hq_apply_full(hq_handle h, const void *v, void *out, void *root, int transpose, int64_t nrhs,
+                        hq_precision prec, hq_layout layout, hq_stream stream);
+
 /* Measurement form of hq_apply_layout (Algorithms 2 and 3): the same sweep, with a
  * HIP event recorded on the stream before each tile phase's launch and after
  * the last; waits for them and returns each phase's launch time in ms in

@@ -168,6 +168,44 @@ class Handle:
                                    lay, _stream(stream)), "hq_apply_layout")
         return out.reshape(nout) if squeeze else out
 
+    def apply_full(self, v, transpose=False, root=None, out=None, stream=None, layout="rows"):
+        """The full Q = [Q_Z; Q~] (hq_apply_full).  transpose=False: returns
+        (Q~ v, Q_Z v) with Q_Z v as 6 rows per body ((6m, R), or (2m, R, 3)
+        in the triples layout).  transpose=True: ``root`` (the same shape)
+        supplies the root Velocity-sets; returns Q_Z^T root + Q~^T v."""
+        torch = _torch()
+        _check_dev(v, "v")
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+        nin, nout = (self.rows, 3 * self.N) if transpose else (3 * self.N, self.rows)
+        if layout == "triples":
+            if v.dim() != 3 or v.shape[0] * 3 != nin or v.shape[2] != 3:
+                raise ValueError(f"v must be ({nin // 3}, R, 3) in the triples layout, got {tuple(v.shape)}")
+            R = v.shape[1]
+            oshape, rshape = (nout // 3, R, 3), (2 * self.m, R, 3)
+        else:
+            if v.dim() != 2 or v.shape[0] != nin:
+                raise ValueError(f"v must be ({nin}, R), got {tuple(v.shape)}")
+            R = v.shape[1]
+            oshape, rshape = (nout, R), (6 * self.m, R)
+        if root is None:
+            if transpose:
+                raise ValueError("transpose=True needs root (the root Velocity-sets)")
+            root = torch.empty(rshape, dtype=v.dtype, device=v.device)
+        else:
+            _check_dev(root, "root")
+            if tuple(root.shape) != rshape or root.dtype != v.dtype or not root.is_contiguous():
+                raise ValueError(f"root must be a contiguous {rshape} tensor of v's dtype")
+        if out is None:
+            out = torch.empty(oshape, dtype=v.dtype, device=v.device)
+        elif tuple(out.shape) != oshape or out.dtype != v.dtype or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
+        if not v.is_contiguous():
+            raise ValueError("v must be contiguous")
+        _check(_lib.load().hq_apply_full(self._h(), _ptr(v), _ptr(out), _ptr(root), int(bool(transpose)), R,
+                                         _prec(v.dtype), LAYOUTS[layout], _stream(stream)), "hq_apply_full")
+        return out if transpose else (out, root)
+
     def node_phase(self):
         """Tile phase of every internal node (handle order)."""
         ph = np.zeros(self.N - self.m, dtype=np.int32)

@@ -42,6 +42,7 @@ SIGNATURES = [
     ("hq_reserve", c_i32, [c_vp, c_i64, c_i32]),
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),
     ("hq_apply_layout", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
+    ("hq_apply_full", c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
     ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp,
                                ctypes.POINTER(ctypes.c_float), c_i32, P_i32]),
     ("hq_node_phase", c_i32, [c_vp, P_i32]),

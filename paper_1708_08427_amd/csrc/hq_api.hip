@@ -250,14 +250,14 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
 }
 
 // Argument checks and launch of hq_apply (ev: optional per-phase events).
-hq_status hq_apply_checked(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
-                           hq_layout layout, hipStream_t s, hipEvent_t *ev) {
+hq_status hq_apply_checked(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs,
+                           hq_precision prec, hq_layout layout, hipStream_t s, hipEvent_t *ev) {
     if (!v || !out) {
         set_error("v or out is NULL");
         return HQ_E_INVALID;
     }
-    if (v == out) {
-        set_error("v and out must not overlap");
+    if (v == out || root == v || root == out) {
+        set_error("v, out and root must not overlap");
         return HQ_E_INVALID;
     }
     if (transpose != 0 && transpose != 1) {
@@ -285,7 +285,7 @@ hq_status hq_apply_checked(Plan &P, const void *v, void *out, int transpose, int
         return HQ_E_UNSUPPORTED;
     }
     HQ_TRY(ensure_xch(P, nrhs, prec, s));
-    return apply_device(P, v, out, transpose, nrhs, prec, layout, s, ev);
+    return apply_device(P, v, out, root, transpose, nrhs, prec, layout, s, ev);
 }
 
 }  // namespace
@@ -567,7 +567,7 @@ hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, i
             set_error("hipEventCreate");
             st = HQ_E_DEVICE;
         }
-    if (st == HQ_OK) st = hq_apply_checked(*P, v, out, transpose, nrhs, prec, layout, s, ev.data());
+    if (st == HQ_OK) st = hq_apply_checked(*P, v, out, nullptr, transpose, nrhs, prec, layout, s, ev.data());
     if (st == HQ_OK && hipEventSynchronize(ev[nph]) != hipSuccess) {
         set_error("hipEventSynchronize");
         st = HQ_E_DEVICE;
@@ -604,15 +604,27 @@ hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t
                    hq_stream stream) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
-    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, HQ_ROWS, reinterpret_cast<hipStream_t>(stream),
-                            nullptr);
+    return hq_apply_checked(*P, v, out, nullptr, transpose, nrhs, prec, HQ_ROWS,
+                            reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
                           hq_layout layout, hq_stream stream) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
-    return hq_apply_checked(*P, v, out, transpose, nrhs, prec, layout, reinterpret_cast<hipStream_t>(stream),
+    return hq_apply_checked(*P, v, out, nullptr, transpose, nrhs, prec, layout,
+                            reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+hq_status hq_apply_full(hq_handle h, const void *v, void *out, void *root, int transpose, int64_t nrhs,
+                        hq_precision prec, hq_layout layout, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!root) {
+        set_error("root is NULL");
+        return HQ_E_INVALID;
+    }
+    return hq_apply_checked(*P, v, out, root, transpose, nrhs, prec, layout, reinterpret_cast<hipStream_t>(stream),
                             nullptr);
 }
 

@@ -36,6 +36,7 @@ struct Ctx {
     // rows x R): vlane 1, vcomp R; triples (each column's three values of a
     // triple contiguous): vlane 3, vcomp 1
     int vlane, vcomp;
+    int root_in;  // downward: body roots take their Velocity-set from the exchange buffer (full Q)
     uint32_t in_bytes, out_bytes, xch_bytes;  // buffer sizes of the wide sweeps (each < 2 GiB)
 };
 
@@ -305,7 +306,7 @@ __device__ __forceinline__ void fetch_down(NodeIn<T> &n, int s, const T *__restr
             }
         }
     }
-    if ((meta & kMetaTileRoot) && !(meta & kMetaBodyRoot)) {
+    if ((meta & kMetaTileRoot) && (!(meta & kMetaBodyRoot) || C.root_in)) {
         const int slot = meta >> kMetaSlotShift;
         if (slot >= C.xch_cap) {
             atomicOr(err, kFlagBounds);
@@ -349,10 +350,9 @@ __device__ __forceinline__ void node_down(const NodeIn<T> &n, T *stk, int &sp, T
                                           int32_t *err) {
     const int xref = n.lk.x, yref = n.lk.y, meta = n.lk.w;
     T L[6];
-    if (meta & kMetaBodyRoot) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L[c] = T(0);
-    } else if (meta & kMetaTileRoot) {
+    if (meta & kMetaTileRoot) {
+        // from the exchange buffer; zeros for a body root unless the root
+        // Velocity-set was given (full Q)
 #pragma unroll
         for (int c = 0; c < 6; ++c) L[c] = n.b[c];
     } else {
@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&
         for (int c = 0; c < NC; ++c) a[k][c] = b[k][c] = T(0);
     if (xi || yi) bld3n<T, TRI, NC, 0>(B.in, ob, B.row, a);
     if (xi && yi) bld3n<T, TRI, NC, 3>(B.in, ob + 3 * B.row, B.row, a);
-    const bool lr = (lk.meta & (kMetaTileRoot | kMetaBodyRoot)) == kMetaTileRoot;
+    const bool lr = (lk.meta & kMetaTileRoot) && (!(lk.meta & kMetaBodyRoot) || C.root_in);
     if (lr) bld6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, true, C, lb), b);
 }
 
@@ -1238,6 +1238,47 @@ void launch_narrow(const Plan &P, int phase, int transpose, const T *rec, const 
                            P.d_tile_len, P.d_links, rec, v, out, xch, C, P.d_err);
 }
 
+// The full Q = [Q_Z; Q~] (Algorithms 2 and 3 with the root kept): every body
+// root is the root of a tile, whose exchange entry holds the root's Info-set
+// after the upward sweep and supplies its Velocity-set to the downward one.
+// Copies between those entries and the caller's root vector (6 rows per body,
+// in the call's layout): to_xch = 0 gathers Q_Z v, 1 scatters L_root.
+template <typename T, bool WIDE>
+__global__ void k_root_io(int64_t m, const int32_t *__restrict__ node_off, const int32_t *__restrict__ tileof,
+                          T *xch, T *root, int to_xch, Ctx C, int32_t *err) {
+    const int64_t total = m * 6 * C.R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i / (6 * C.R);
+        const int rem = (int)(i - j * 6 * C.R);
+        const int d = rem / C.R, r = rem - d * C.R;
+        const int g = node_off[j];
+        const int t = (g >= 0 && g < C.nsched) ? tileof[g] : -1;
+        if (t < 0 || t >= C.xch_cap) {
+            atomicOr(err, kFlagBounds);
+            continue;
+        }
+        const int64_t xi = WIDE ? ((int64_t)t * C.R + r) * 6 + d : ((int64_t)t * 6 + d) * C.R + r;
+        const int64_t ri = velem(6 * j + 3 * (d / 3), d % 3, r, C);
+        if (to_xch)
+            xch[xi] = root[ri];
+        else
+            root[ri] = xch[xi];
+    }
+}
+
+template <typename T>
+void launch_root_io(const Plan &P, bool wide, T *xch, T *root, int to_xch, const Ctx &C, hipStream_t s) {
+    const int64_t total = P.m * 6 * (int64_t)C.R;
+    const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    if (wide)
+        hipLaunchKernelGGL((k_root_io<T, true>), dim3(grid), dim3(256), 0, s, P.m, P.d_node_off, P.d_tileof, xch, root,
+                           to_xch, C, P.d_err);
+    else
+        hipLaunchKernelGGL((k_root_io<T, false>), dim3(grid), dim3(256), 0, s, P.m, P.d_node_off, P.d_tileof, xch,
+                           root, to_xch, C, P.d_err);
+}
+
 // Sweep kinds: narrow (lanes per tile 1..16, tile stack in LDS) and wide
 // (runs of whole tiles, explicit slots, buffer addressing).
 enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWide64 };
@@ -1277,8 +1318,8 @@ int lanes_per_tile(int64_t nrhs) {
     return l;
 }
 
-hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, int layout,
-                       hipStream_t s, hipEvent_t *ev) {
+hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
+                       int layout, hipStream_t s, hipEvent_t *ev) {
     Ctx C;
     C.N = P.N;
     C.rows = P.rows;
@@ -1286,6 +1327,7 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
     C.R = (int)nrhs;
     C.vlane = (layout == HQ_TRIPLES) ? 3 : 1;
     C.vcomp = (layout == HQ_TRIPLES) ? 1 : C.R;
+    C.root_in = (root && transpose) ? 1 : 0;
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
     C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(P.xch_bytes / (6 * elem * (size_t)nrhs)));
     // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB
@@ -1313,11 +1355,17 @@ hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t
     C.nchunks = (int)((nrhs + cols - 1) / cols);
     C.dmax = stack_depth(P.smax());
     C.nslot = stack_slots(P.smax());
-    if (prec == HQ_FP64)
+    const bool wide = kind == kWide32 || kind == kWide64;
+    if (prec == HQ_FP64) {
+        if (root && transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 1, C, s);
         launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s,
                            ev);
-    else
+        if (root && !transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 0, C, s);
+    } else {
+        if (root && transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 1, C, s);
         launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s, ev);
+        if (root && !transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 0, C, s);
+    }
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

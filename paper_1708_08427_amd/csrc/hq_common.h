@@ -259,8 +259,8 @@ hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64
                              const int32_t *gate = nullptr, const int32_t *dn = nullptr);
 
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases);
-hq_status apply_device(Plan &P, const void *v, void *out, int transpose, int64_t nrhs, int prec, int layout,
-                       hipStream_t s, hipEvent_t *ev = nullptr);
+hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
+                       int layout, hipStream_t s, hipEvent_t *ev = nullptr);
 hq_status explicit_dense(Plan &P, int64_t body, double *out, int64_t ld, hipStream_t s);
 hq_status explicit_blocks_launch(Plan &P, int64_t body, int prec, void *values, const int64_t *d_blk_off,
                                  hipStream_t s);

@@ -192,6 +192,37 @@ def norm_error(body, rng):
     return abs(np.sum(root ** 2) + np.sum(eps ** 2) - np.sum(f ** 2)) / np.sum(f ** 2)
 
 
+def full_q_inverse_error(body, rng, nrhs=3):
+    """The full Q = [Q_Z; Q~] (Algorithms 2 and 3 with the root kept) is
+    orthogonal: Q^T (Q f) = f, and Q (Q^T [r; w]) = [r; w] for any root
+    Velocity-set r."""
+    f = rng.standard_normal((3 * body.n, nrhs))
+    eps, root = body.apply(f, root=np.zeros((6, nrhs)))
+    back, _ = body.apply(eps, transpose=True, root=root)
+    e1 = np.abs(back - f).max() / np.abs(f).max()
+    r = rng.standard_normal((6, nrhs))
+    w = rng.standard_normal((body.rows, nrhs))
+    g, _ = body.apply(w, transpose=True, root=r)
+    w2, r2 = body.apply(g, root=np.zeros((6, nrhs)))
+    amax = lambda x: float(np.abs(x).max()) if x.size else 0.0  # noqa: E731 (two-bead bodies have no rows)
+    e2 = max(amax(w2 - w), amax(r2 - r)) / max(amax(w), amax(r))
+    return max(e1, e2)
+
+
+def root_rows_error(body):
+    """The six root rows Q_Z, assembled column by column from unit vectors:
+    orthonormal, spanning the row space of Z (Q_Z^T Q_Z = I - P with P the
+    LAPACK projector onto the complement), and the first three rows are the
+    normalised sum [I ... I] / sqrt(n) (Definition 4.1 at the root)."""
+    n3 = 3 * body.n
+    _, Qz = body.apply(np.eye(n3), root=np.zeros((6, n3)))
+    P = dense.projector(body.pos)
+    e1 = np.abs(Qz @ Qz.T - np.eye(6)).max()
+    e2 = np.abs(Qz.T @ Qz - (np.eye(n3) - P)).max()
+    e3 = np.abs(Qz[0:3] - np.tile(np.eye(3), body.n) / np.sqrt(body.n)).max()
+    return max(e1, e2, e3)
+
+
 def explicit_error(body, rng, nrhs=2):
     """Explicit Q~ (Algorithm 1) against the implicit sweeps (Algorithms 2-3)."""
     Q = body.explicit()

@@ -201,6 +201,22 @@ def test_rotation_covariance_of_projector():
 # --------------------------------------------------------------------------
 
 
+@pytest.mark.parametrize("seed,n,kind", [(21, 2, "cube"), (22, 3, "cube"), (23, 64, "sphere"), (24, 300, "ellipsoid")])
+def test_full_q_orthogonal(seed, n, kind):
+    """Q = [Q_Z; Q~] with the root Info-set kept (Algorithm 2) and a given root
+    Velocity-set (Algorithm 3) is orthogonal."""
+    b = hier.Body(rand_body(seed, n, kind))
+    assert pins.full_q_inverse_error(b, np.random.default_rng(seed)) < 1e-13
+
+
+@pytest.mark.parametrize("seed,n,kind", [(25, 3, "cube"), (26, 5, "cube"), (27, 64, "sphere"), (28, 200, "ellipsoid")])
+def test_root_rows_span_z(seed, n, kind):
+    """(Two beads are collinear, rank Z = 5: their six root rows are a full
+    6 x 6 orthogonal matrix instead, checked by the orthogonality pin.)"""
+    b = hier.Body(rand_body(seed, n, kind))
+    assert pins.root_rows_error(b) < 1e-13
+
+
 def test_two_beads():
     pos = np.array([[0.0, 1.0, 2.0], [1.0, -1.0, 0.5]])
     b = hier.Body(pos)
