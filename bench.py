@@ -298,6 +298,41 @@ def main():
         t_fup = timed(lambda: h.apply_full(f32, out=tmp, root=root_buf, stream=stream, layout=lay), args.apply_reps)
         t_fdn = timed(lambda: h.apply_full(tmp, transpose=True, root=root_buf, out=out, stream=stream, layout=lay),
                       args.apply_reps)
+        # the Krylov harness of Eqs. 1.5-1.6 (hq_constrained_solve) with a
+        # per-bead 3x3 SPD mobility applied by a torch callback
+        kg = torch.Generator(device=dev)
+        kg.manual_seed(17)
+        Ak = torch.randn((N, 3, 3), device=dev, generator=kg)
+        Dk = torch.eye(3, device=dev).expand(N, 3, 3) + 0.2 * torch.bmm(Ak, Ak.transpose(1, 2).contiguous()) / 9.0
+        # y_k = D_k x_k per bead and right-hand side, as three broadcast FMAs
+        Dc = [Dk[:, :, c].contiguous() for c in range(3)]  # column c of every D_k, (N, 3)
+
+        def dapply(x, y):
+            if lay == "triples":  # x, y: (N, R, 3)
+                torch.mul(x[:, :, 0:1], Dc[0][:, None, :], out=y)
+                y.addcmul_(x[:, :, 1:2], Dc[1][:, None, :])
+                y.addcmul_(x[:, :, 2:3], Dc[2][:, None, :])
+            else:  # (3N, R) viewed as (N, 3, R)
+                xv, yv = x.view(N, 3, R), y.view(N, 3, R)
+                torch.mul(xv[:, 0:1, :], Dc[0][:, :, None], out=yv)
+                yv.addcmul_(xv[:, 1:2, :], Dc[1][:, :, None])
+                yv.addcmul_(xv[:, 2:3, :], Dc[2][:, :, None])
+
+        Fk = torch.randn(vec_shape(6 * m, R, lay), device=dev, generator=kg)
+
+        def ksolve(iters, rtol):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = hq.constrained_solve(h, dapply, Fk, layout=lay, rtol=rtol, max_iter=iters, stream=stream)
+            torch.cuda.synchronize()
+            return res[2], (time.perf_counter() - t0) * 1e3
+
+        ksolve(2, 1e-5)  # warm-up
+        _, t_k1 = ksolve(1, 1e-30)
+        kinfo, t_k = ksolve(200, 1e-5)
+        k_iter = (t_k - t_k1) / max(kinfo["iters"] - 1, 1)
+        log(f"Krylov solve: {kinfo['iters']} CG iterations to {kinfo['max_rel_residual']:.1e} in {t_k:.1f} ms "
+            f"({k_iter:.2f} ms per iteration)")
         f64 = f32.double()
         tmp64 = torch.empty(vec_shape(wl.rows, R, lay), dtype=torch.float64, device=dev)
         h64 = hq.build(pos, wl.offsets, store=1, stream=stream, **opts)
@@ -360,6 +395,11 @@ def main():
                                      "achieved": nbytes / (t_up * 1e-3) / 1e9}},
         "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},
         "apply_only_bead_vectors_per_s": N * R / ((t_up + t_dn) * 1e-3),
+        "krylov": {"iters": kinfo["iters"], "max_rel_residual": kinfo["max_rel_residual"], "ms_total": t_k,
+                   "ms_per_iter": k_iter,
+                   "what": "hq_constrained_solve (Eqs. 1.5-1.6), FP32, CG to 1e-5, per-bead 3x3 SPD mobility "
+                           "(torch callback), same workload and layout; per iteration = (total - one-iteration "
+                           "solve) / (iterations - 1)"},
         "full_q": {"up_ms": t_fup, "down_ms": t_fdn, "bead_vectors_per_s": N * R / ((t_fup + t_fdn) * 1e-3),
                    "what": "hq_apply_full: Q v = [Q_Z v; Q~ v] and Q^T [r; w], FP32, same workload"},
         "fp32_rel_err_vs_fp64_oracle": err,

@@ -205,6 +205,39 @@ hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, 
 hq_status hq_apply_full(hq_handle h, const void *v, void *out, void *root, int transpose, int64_t nrhs,
                         hq_precision prec, hq_layout layout, hq_stream stream);
 
+/* Mobility product for hq_constrained_solve: y = D x for nrhs vectors of 3N
+ * rows (the caller's bead order) in the solve's precision and layout.  x and
+ * y are the device buffers dx and dy given to the solve; the callback may
+ * run on the stream or synchronously, and returns 0 on success. */
+typedef int (*hq_dapply_fn)(const void *x, void *y, int64_t nrhs, void *user, hq_stream stream);
+
+typedef struct {
+    int32_t max_iter;          /* in: CG iteration limit; 0 = 500 */
+    double rtol;               /* in: relative residual target per RHS; 0 = 1e-8 */
+    int32_t iters;             /* out: iterations done */
+    double max_rel_residual;   /* out: largest ||r|| / ||b|| over the RHS */
+} hq_krylov_info;
+
+/* The constrained Brownian-dynamics solve of Section 1: the constraint forces
+ * g from 0 = Q~ D Q_Z^T F + Q~ D Q~^T g (Eq. 1.5) by conjugate gradients on
+ * Q~ D Q~^T (symmetric positive definite when D is), then the rigid-body
+ * velocities V = Q_Z D (Q_Z^T F + Q~^T g) (Eq. 1.6).  Q_Z and Q~ are this
+ * handle's full Q (hq_apply_full); D is the caller's mobility (dapply).
+ *   F   device, 6m x nrhs in the given layout (as hq_apply_full's root): the
+ *       generalised forces in Q_Z's coordinates.
+ *   V   device out, 6m x nrhs: the rigid-body velocities in the same
+ *       coordinates.  g  device out, rows x nrhs.
+ *   dx, dy  device workspace, 3N x nrhs elements each (caller-owned): the
+ *       solve writes D's input into dx and calls dapply(dx, dy, ...).
+ *   info  host, in/out (limits and results).
+ * Synchronises the stream every iteration (host-side CG scalars); allocates
+ * and frees its own workspace (four vectors of rows x nrhs).  HQ_E_INVALID if an argument
+ * is NULL, the callback fails or Q~ D Q~^T is not positive definite; other
+ * errors as for hq_apply_full. */
+hq_status hq_constrained_solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, void *V, void *g,
+                               int64_t nrhs, hq_precision prec, hq_layout layout, void *dx, void *dy,
+                               hq_krylov_info *info, hq_stream stream);
+
 /* Measurement form of hq_apply_layout (Algorithms 2 and 3): the same sweep, with a
  * HIP event recorded on the stream before each tile phase's launch and after
  * the last; waits for them and returns each phase's launch time in ms in

@@ -6,4 +6,6 @@ GPU library never imports, links or calls it, and the two share no code.
 
 * ``oracle.hier``  plain recursive C implementation (tree, Algorithm 1-3).
 * ``oracle.dense`` numpy/LAPACK dense Z, projector and complement basis.
+* ``oracle.bd``    the constrained Brownian-dynamics solve of Eqs. 1.5-1.6,
+  dense, in ``oracle.hier``'s basis (small systems).
 """

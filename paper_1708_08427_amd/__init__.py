@@ -322,6 +322,54 @@ def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max
     return Handle(raw, off)
 
 
+def constrained_solve(h, dapply, F, layout="rows", rtol=1e-8, max_iter=500, stream=None):
+    """hq_constrained_solve: the constraint forces g of Eq. 1.5 by conjugate
+    gradients on Q~ D Q~^T and the rigid-body velocities V of Eq. 1.6.
+    ``dapply(x, y)`` writes D x into y (torch tensors of the vector shape
+    (3N, R), or (N, R, 3) in the triples layout) on the current stream.
+    ``F``: (6m, R) or (2m, R, 3).  Returns (V, g, info dict)."""
+    torch = _torch()
+    _check_dev(F, "F")
+    if layout not in LAYOUTS:
+        raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+    if layout == "triples":
+        if F.dim() != 3 or F.shape[0] != 2 * h.m or F.shape[2] != 3:
+            raise ValueError(f"F must be ({2 * h.m}, R, 3) in the triples layout")
+        R = F.shape[1]
+        bshape, gshape = (h.N, R, 3), (h.rows // 3, R, 3)
+    else:
+        if F.dim() != 2 or F.shape[0] != 6 * h.m:
+            raise ValueError(f"F must be ({6 * h.m}, R)")
+        R = F.shape[1]
+        bshape, gshape = (3 * h.N, R), (h.rows, R)
+    if not F.is_contiguous():
+        raise ValueError("F must be contiguous")
+    dx = torch.empty(bshape, dtype=F.dtype, device=F.device)
+    dy = torch.empty(bshape, dtype=F.dtype, device=F.device)
+    V = torch.empty_like(F)
+    g = torch.empty(gshape, dtype=F.dtype, device=F.device)
+    errors = []
+    ts = stream or torch.cuda.current_stream()
+
+    def cb(x, y, nrhs, user, s):
+        try:
+            with torch.cuda.stream(ts):
+                dapply(dx, dy)
+            return 0
+        except Exception as e:  # reported through the status below
+            errors.append(e)
+            return 1
+
+    fn = _lib.DAPPLY_FN(cb)
+    info = _lib.KrylovInfo(int(max_iter), float(rtol), 0, 0.0)
+    st = _lib.load().hq_constrained_solve(h._h(), fn, None, _ptr(F), _ptr(V), _ptr(g), R, _prec(F.dtype),
+                                          LAYOUTS[layout], _ptr(dx), _ptr(dy), ctypes.byref(info), _stream(ts))
+    if errors:
+        raise errors[0]
+    _check(st, "hq_constrained_solve")
+    return V, g, {"iters": info.iters, "max_rel_residual": info.max_rel_residual}
+
+
 _TUNED = {}
 
 

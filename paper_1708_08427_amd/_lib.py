@@ -27,6 +27,15 @@ class Options(ctypes.Structure):
                 ("later_tile_units", c_i32)]
 
 
+class KrylovInfo(ctypes.Structure):
+    _fields_ = [("max_iter", c_i32), ("rtol", ctypes.c_double), ("iters", c_i32),
+                ("max_rel_residual", ctypes.c_double)]
+
+
+# int (*)(const void *x, void *y, int64_t nrhs, void *user, hq_stream stream)
+DAPPLY_FN = ctypes.CFUNCTYPE(ctypes.c_int, c_vp, c_vp, c_i64, c_vp, c_vp)
+
+
 class Info(ctypes.Structure):
     _fields_ = [("N", c_i64), ("m", c_i64), ("rows", c_i64), ("internal_nodes", c_i64), ("tiles", c_i64),
                 ("phases", c_i32), ("device_flags", c_i32), ("tile_units", c_i32), ("store", c_i32),
@@ -43,6 +52,8 @@ SIGNATURES = [
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),
     ("hq_apply_layout", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
     ("hq_apply_full", c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
+    ("hq_constrained_solve", c_i32, [c_vp, DAPPLY_FN, c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp,
+                                     ctypes.POINTER(KrylovInfo), c_vp]),
     ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp,
                                ctypes.POINTER(ctypes.c_float), c_i32, P_i32]),
     ("hq_node_phase", c_i32, [c_vp, P_i32]),

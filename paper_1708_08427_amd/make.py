@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhq.so")
-SOURCES = ["hq_api.hip", "hq_build.hip", "hq_apply.hip", "hq_explicit.hip", "hq_scan.hip"]
+SOURCES = ["hq_api.hip", "hq_build.hip", "hq_apply.hip", "hq_explicit.hip", "hq_scan.hip", "hq_krylov.hip"]
 ARCH = os.environ.get("HQ_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -217,6 +217,32 @@ def test_root_rows_span_z(seed, n, kind):
     assert pins.root_rows_error(b) < 1e-13
 
 
+@pytest.mark.parametrize("seed,sizes", [(33, [2, 9, 30]), (34, [3, 50])])
+def test_constrained_solve_satisfies_block_system(seed, sizes):
+    """Eqs. 1.5-1.6 solved densely reproduce the original mobility problem
+    Q D^-1 Q^T [V; 0] = [F; g] (Eq. 1.4), which uses D^-1 instead of D, and
+    the bead velocities Q_Z^T V are rigid motions (in the row space of Z)."""
+    from oracle import bd
+    rng = np.random.default_rng(seed)
+    pos = np.concatenate([rand_body(seed + i, n, "cube") for i, n in enumerate(sizes)])
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    N, m = int(offsets[-1]), len(sizes)
+    M = rng.standard_normal((3 * N, 3 * N))
+    D = np.eye(3 * N) + 0.2 * (M @ M.T) / np.linalg.norm(M, 2) ** 2
+    F = rng.standard_normal((6 * m, 3))
+    V, g = bd.constrained_solve(pos, offsets, D, F)
+    Qz, Qt = bd.full_q(pos, offsets)
+    Q = np.vstack([Qz, Qt])
+    lhs = Q @ np.linalg.inv(D) @ Q.T @ np.vstack([V, np.zeros_like(g)])
+    assert np.abs(lhs - np.vstack([F, g])).max() < 1e-10 * max(1.0, np.abs(F).max())
+    u = Qz.T @ V
+    for j in range(m):
+        b0, b1 = offsets[j], offsets[j + 1]
+        if dense.rank(pos[b0:b1]) == 6:
+            uj = u[3 * b0:3 * b1]
+            assert np.abs(uj - (np.eye(3 * (b1 - b0)) - dense.projector(pos[b0:b1])) @ uj).max() < 1e-12
+
+
 def test_two_beads():
     pos = np.array([[0.0, 1.0, 2.0], [1.0, -1.0, 0.5]])
     b = hier.Body(pos)
