@@ -858,7 +858,18 @@ __device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, Lan
 // inputs are beads.
 template <typename T, int RT, int IW, int NC, bool TRI>
 __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B, const Ctx &C, LaneB lb) {
-    bld3n<T, TRI, NC, 0>(B.in, bead_off<T, RT>(ref, true, C, lb), B.row, m);
+    if constexpr (IW == 6) {
+        // later phases: beads are rare children there, so their loads go
+        // under a branch (the first phase keeps them unconditional, measured
+        // faster)
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) m[k][c] = T(0);
+        if (ref >= 0) bld3n<T, TRI, NC, 0>(B.in, bead_off<T, RT>(ref, true, C, lb), B.row, m);
+    } else {
+        bld3n<T, TRI, NC, 0>(B.in, bead_off<T, RT>(ref, true, C, lb), B.row, m);
+    }
     if constexpr (IW == 6) {
         T e[6][NC];
         bld6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);

@@ -437,16 +437,6 @@ __global__ void k_rem_scatter(int64_t NI, const int32_t *cov, const int32_t *pos
 // Units of the uncovered nodes after the first phase (beads and roots of
 // earlier tiles count one each): every uncovered node adds the units among its
 // own children to itself and to all its ancestors, which are uncovered too.
-__global__ void k_units_clear(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
-                              int32_t *units, const int32_t *gate) {
-    if (gate && *gate == 0) return;
-    const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] == 0) units[g] = 0;
-    }
-}
-
 __global__ void k_units_walk(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
                              const int32_t *lc, const int32_t *rc, const int32_t *par, int32_t *units,
                              int32_t *err, const int32_t *gate) {
@@ -491,25 +481,6 @@ __global__ void k_tile_roots(int64_t NI, const int32_t *rem, const int32_t *dn, 
     }
 }
 
-__global__ void k_tile_emit(int64_t NI, const int32_t *rem, const int32_t *dn, const long long *trval,
-                            const long long *trscan, const int32_t *cnt, int32_t *tile_root, int32_t *tile_len,
-                            int32_t *tile_base, int32_t *tileof, const int32_t *gate) {
-    if (gate && *gate == 0) return;
-    const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
-    const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const long long v = trval[i];
-        if (v == 0) continue;
-        const int g = node_at(i, rem);
-        const long long sc = trscan[i];
-        const int t = tiles0 + (int)(sc >> 32);
-        tile_root[t] = g;
-        tile_len[t] = (int)(v & 0xffffffffll);
-        tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
-        tileof[g] = t;
-    }
-}
-
 // Per uncovered node: evaluation order of its children (the one with more
 // units first) and the step of the walk up to its tile root: its parent, the
 // post-order positions skipped when it is its parent's second child (the
@@ -520,20 +491,34 @@ __global__ void k_tile_emit(int64_t NI, const int32_t *rem, const int32_t *dn, c
 // flag, bit 30 the tile-root flag.
 constexpr int kAwPend = 1 << 29, kAwRoot = 1 << 30, kAwSkip = (1 << 29) - 1;
 
+// A tile root also enters its tile in the tile tables: root, node count and
+// first schedule index (from the scan of the root flags and node counts).
 __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
                               const int32_t *par, const int32_t *lc, const int32_t *rc, const int32_t *units,
-                              const long long *trval, int32_t *yfirst, int2 *aw, const int32_t *gate) {
+                              const long long *trval, const long long *trscan, const int32_t *cnt,
+                              int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof,
+                              int32_t *yfirst, int2 *aw, const int32_t *gate) {
     if (gate && *gate == 0) return;
+    const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
     const int64_t n = node_count(NI, dn);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int g = node_at(i, rem);
         if (cov[g] != 0) continue;
+        const long long tv = trval[i];
+        if (tv != 0) {
+            const long long sc = trscan[i];
+            const int t = tiles0 + (int)(sc >> 32);
+            tile_root[t] = g;
+            tile_len[t] = (int)(tv & 0xffffffffll);
+            tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
+            tileof[g] = t;
+        }
         {
             const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
             yfirst[g] = (uy > ux) ? 1 : 0;
         }
         const int p = par[g];
-        int word = (trval[i] != 0) ? kAwRoot : 0;
+        int word = (tv != 0) ? kAwRoot : 0;
         if (p >= 0) {
             const int x = lc[p], y = rc[p];
             const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
@@ -550,9 +535,10 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn,
 // Post-order position of every uncovered node inside the tile whose root it
 // reaches first going up (the child with more units is evaluated first), and
 // the stack slot that receives its result (results of the tile pending while
-// its subtree is swept).
-__global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
-                         const int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
+// its subtree is swept).  A node placed in a tile is covered by this phase; a
+// node left over gets its unit count cleared for the next phase's count.
+__global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
+                         int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
                          int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int32_t *err, int64_t sched_cap,
                          const int32_t *gate) {
     if (gate && *gate == 0) return;
@@ -573,31 +559,22 @@ __global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, cons
             q = w.x;
         }
         if (too_deep) raise_flag(err, kFlagBounds);
-        if (!found) continue;
-        const int t = tileof[q];
-        if (t < 0 || t >= NI) {
-            raise_flag(err, kFlagBounds);
-            continue;
+        bool placed = false;
+        if (found) {
+            const int t = tileof[q];
+            const int64_t s = (t >= 0 && t < NI) ? (int64_t)tile_base[t] + pos : -1;
+            if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
+                raise_flag(err, kFlagBounds);
+            } else {
+                tileof[g] = t;
+                depth_slot[g] = pend;
+                sched[g] = (int)s;
+                sched_node[s] = g;
+                cov[g] = phase;
+                placed = true;
+            }
         }
-        const int64_t s = (int64_t)tile_base[t] + pos;
-        if (pos < 0 || s < 0 || s >= sched_cap) {
-            raise_flag(err, kFlagBounds);
-            continue;
-        }
-        tileof[g] = t;
-        depth_slot[g] = pend;
-        sched[g] = (int)s;
-        sched_node[s] = g;
-    }
-}
-
-__global__ void k_commit(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
-                         const int32_t *tileof, const int32_t *gate) {
-    if (gate && *gate == 0) return;
-    const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] == 0 && tileof[g] >= 0) cov[g] = phase;
+        if (!placed) units[g] = 0;
     }
 }
 
@@ -1325,7 +1302,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
                                P.d_rem, P.d_cnt, gate);
         }
         if (ph >= 2) {
-            hipLaunchKernelGGL(k_units_clear, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_units, gate);
+            // (the previous phase's k_assign cleared the uncovered nodes' units)
             hipLaunchKernelGGL(k_units_walk, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_lc, P.d_rc,
                                P.d_par, P.d_units, P.d_err, gate);
         }
@@ -1333,13 +1310,11 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
                            P.d_cov, P.d_par,
                            P.d_nn, P.d_units, P.d_trval, gate);
         HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
-        hipLaunchKernelGGL(k_tile_emit, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_trval, P.d_trscan,
-                           P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base, P.d_tileof, gate);
         hipLaunchKernelGGL(k_assign_prep, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_par, P.d_lc,
-                           P.d_rc, P.d_units, P.d_trval, P.d_yfirst, P.d_aw, gate);
-        hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_units, P.d_aw,
+                           P.d_rc, P.d_units, P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root, P.d_tile_len,
+                           P.d_tile_base, P.d_tileof, P.d_yfirst, P.d_aw, gate);
+        hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_units, P.d_aw,
                            P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI, gate);
-        hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_tileof, gate);
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, dn, ph, P.d_trval, P.d_trscan, P.d_cnt,
                            P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
         // the run table of a phase is built when the phase holds nodes
