@@ -293,6 +293,18 @@ def main():
         t_up = timed(lambda: h.apply(f32, out=tmp, stream=stream, layout=lay), args.apply_reps)
         t_dn = timed(lambda: h.apply(tmp, transpose=True, out=out, stream=stream, layout=lay), args.apply_reps)
         t_rb = timed(lambda: h.rebuild(pos, stream=stream), 5)
+        # transform reuse across rigid motions: the products of the moved
+        # bodies from the handle's transforms and each body's accumulated
+        # rotation since the last rebuild (here that of the timed steps)
+        acc = np.tile(np.eye(3), (m, 1, 1))
+        for i in range(total_steps):
+            acc = np.einsum("jab,jbc->jac", rot[i].reshape(m, 3, 3), acc)
+        rot_acc = torch.from_numpy(np.ascontiguousarray(acc.reshape(m, 9))).to(dev)
+        rwork = torch.empty_like(f32)
+        t_rup = timed(lambda: h.apply_rotated(rot_acc, f32, out=tmp, work=rwork, stream=stream, layout=lay),
+                      args.apply_reps)
+        t_rdn = timed(lambda: h.apply_rotated(rot_acc, tmp, transpose=True, out=out, stream=stream, layout=lay),
+                      args.apply_reps)
         # the full Q = [Q_Z; Q~]: the same sweeps keeping the root Info-sets
         root_buf = torch.empty(vec_shape(6 * m, R, lay), dtype=torch.float32, device=dev)
         t_fup = timed(lambda: h.apply_full(f32, out=tmp, root=root_buf, stream=stream, layout=lay), args.apply_reps)
@@ -400,6 +412,10 @@ def main():
                    "what": "hq_constrained_solve (Eqs. 1.5-1.6), FP32, CG to 1e-5, per-bead 3x3 SPD mobility "
                            "(torch callback), same workload and layout; per iteration = (total - one-iteration "
                            "solve) / (iterations - 1)"},
+        "transform_reuse": {"up_ms": t_rup, "down_ms": t_rdn, "step_ms": t_rup + t_rdn, "rebuild_ms": t_rb,
+                            "bead_vectors_per_s": N * R / ((t_rup + t_rdn) * 1e-3),
+                            "what": "hq_apply_rotated: Q~(Rot r) v = Q~(r) (Rot^T v) per body, no rebuild; "
+                                    "a step of Q~^T(Q~ f) after rigid rotations, FP32, same workload"},
         "full_q": {"up_ms": t_fup, "down_ms": t_fdn, "bead_vectors_per_s": N * R / ((t_fup + t_fdn) * 1e-3),
                    "what": "hq_apply_full: Q v = [Q_Z v; Q~ v] and Q^T [r; w], FP32, same workload"},
         "fp32_rel_err_vs_fp64_oracle": err,

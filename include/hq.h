@@ -238,6 +238,24 @@ hq_status hq_constrained_solve(hq_handle h, hq_dapply_fn dapply, void *user, con
                                int64_t nrhs, hq_precision prec, hq_layout layout, void *dx, void *dy,
                                hq_krylov_info *info, hq_stream stream);
 
+/* Products of rigidly moved bodies without a rebuild (reuse of the handle's
+ * transforms): if body j moved to Rot_j r + t_j since the handle's last
+ * hq_build / hq_rebuild (positions r), then Q~(moved) = Q~ blockdiag(Rot_j^T)
+ * over its beads is an orthonormal basis of the complement of the moved
+ * body's Z (Eq. 1.2: Z of the moved body is diag(Rot_j, Rot_j) Z
+ * blockdiag(Rot_j^T) plus multiples of its translation rows).  It differs
+ * from the Q~ a rebuild would give by an orthogonal change of rows; the
+ * projector Q~^T Q~ is the same.
+ *   transpose = 0: out = Q~ (blockdiag(Rot^T) v), work receiving the rotated
+ *                  v (device, 3N x nrhs, distinct from v and out).
+ *   transpose = 1: out = blockdiag(Rot) (Q~^T v); work unused (may be NULL).
+ *   rot  device m x 9 FP64 row-major: each body's rotation since the last
+ *        build or rebuild (translations do not matter).
+ * Vectors as for hq_apply_layout.  Capturable (no allocation once the
+ * exchange buffer is reserved). */
+hq_status hq_apply_rotated(hq_handle h, const double *rot, const void *v, void *out, void *work, int transpose,
+                           int64_t nrhs, hq_precision prec, hq_layout layout, hq_stream stream);
+
 /* Measurement form of hq_apply_layout (Algorithms 2 and 3): the same sweep, with a
  * HIP event recorded on the stream before each tile phase's launch and after
  * the last; waits for them and returns each phase's launch time in ms in

@@ -206,6 +206,47 @@ class Handle:
                                          _prec(v.dtype), LAYOUTS[layout], _stream(stream)), "hq_apply_full")
         return out if transpose else (out, root)
 
+    def apply_rotated(self, rot, v, transpose=False, out=None, work=None, stream=None, layout="rows"):
+        """hq_apply_rotated: products of the bodies after rigid rotations
+        ``rot`` ((m, 3, 3) or (m, 9) float64, device) since the last build or
+        rebuild, with the handle's transforms (no rebuild).  Shapes as for
+        apply(); ``work`` (the upward product's rotated input) is allocated
+        when not given."""
+        torch = _torch()
+        _check_dev(v, "v")
+        _check_dev(rot, "rot")
+        if rot.dtype != torch.float64 or rot.numel() != 9 * self.m or not rot.is_contiguous():
+            raise ValueError("rot must be a contiguous float64 tensor of m x 9 (or m x 3 x 3) values")
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+        nin, nout = (self.rows, 3 * self.N) if transpose else (3 * self.N, self.rows)
+        if layout == "triples":
+            if v.dim() != 3 or v.shape[0] * 3 != nin or v.shape[2] != 3:
+                raise ValueError(f"v must be ({nin // 3}, R, 3) in the triples layout")
+            R = v.shape[1]
+            oshape = (nout // 3, R, 3)
+        else:
+            if v.dim() != 2 or v.shape[0] != nin:
+                raise ValueError(f"v must be ({nin}, R)")
+            R = v.shape[1]
+            oshape = (nout, R)
+        if not v.is_contiguous():
+            raise ValueError("v must be contiguous")
+        if out is None:
+            out = torch.empty(oshape, dtype=v.dtype, device=v.device)
+        elif tuple(out.shape) != oshape or out.dtype != v.dtype or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
+        wp = None
+        if not transpose:
+            if work is None:
+                work = torch.empty_like(v)
+            elif work.shape != v.shape or work.dtype != v.dtype or not work.is_contiguous():
+                raise ValueError("work must be a contiguous tensor like v")
+            wp = _ptr(work)
+        _check(_lib.load().hq_apply_rotated(self._h(), _ptr(rot), _ptr(v), _ptr(out), wp, int(bool(transpose)), R,
+                                            _prec(v.dtype), LAYOUTS[layout], _stream(stream)), "hq_apply_rotated")
+        return out
+
     def node_phase(self):
         """Tile phase of every internal node (handle order)."""
         ph = np.zeros(self.N - self.m, dtype=np.int32)

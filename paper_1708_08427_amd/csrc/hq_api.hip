@@ -249,9 +249,9 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
     return HQ_OK;
 }
 
-// Argument checks and launch of hq_apply (ev: optional per-phase events).
-hq_status hq_apply_checked(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs,
-                           hq_precision prec, hq_layout layout, hipStream_t s, hipEvent_t *ev) {
+// Argument checks of hq_apply and its variants.
+hq_status check_apply(const Plan &P, const void *v, const void *out, const void *root, int transpose, int64_t nrhs,
+                      hq_precision prec, hq_layout layout) {
     if (!v || !out) {
         set_error("v or out is NULL");
         return HQ_E_INVALID;
@@ -284,6 +284,13 @@ hq_status hq_apply_checked(Plan &P, const void *v, void *out, void *root, int tr
         set_error("vector too large");
         return HQ_E_UNSUPPORTED;
     }
+    return HQ_OK;
+}
+
+// Argument checks and launch of hq_apply (ev: optional per-phase events).
+hq_status hq_apply_checked(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs,
+                           hq_precision prec, hq_layout layout, hipStream_t s, hipEvent_t *ev) {
+    HQ_TRY(check_apply(P, v, out, root, transpose, nrhs, prec, layout));
     HQ_TRY(ensure_xch(P, nrhs, prec, s));
     return apply_device(P, v, out, root, transpose, nrhs, prec, layout, s, ev);
 }
@@ -614,6 +621,30 @@ hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, 
     if (!P) return HQ_E_INVALID;
     return hq_apply_checked(*P, v, out, nullptr, transpose, nrhs, prec, layout,
                             reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+hq_status hq_apply_rotated(hq_handle h, const double *rot, const void *v, void *out, void *work, int transpose,
+                           int64_t nrhs, hq_precision prec, hq_layout layout, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!rot) {
+        set_error("rot is NULL");
+        return HQ_E_INVALID;
+    }
+    if (!transpose && (!work || work == v || work == out)) {
+        set_error("the upward product needs a work vector distinct from v and out");
+        return HQ_E_INVALID;
+    }
+    HQ_TRY(check_apply(*P, v, out, nullptr, transpose, nrhs, prec, layout));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!transpose) {
+        // Q~(moved) v = Q~ (blockdiag(Rot^T) v)
+        HQ_TRY(rotate_vectors(*P, rot, v, work, nrhs, prec, layout, 1, s));
+        return hq_apply_checked(*P, work, out, nullptr, 0, nrhs, prec, layout, s, nullptr);
+    }
+    // Q~(moved)^T w = blockdiag(Rot) (Q~^T w)
+    HQ_TRY(hq_apply_checked(*P, v, out, nullptr, 1, nrhs, prec, layout, s, nullptr));
+    return rotate_vectors(*P, rot, out, out, nrhs, prec, layout, 0, s);
 }
 
 hq_status hq_apply_full(hq_handle h, const void *v, void *out, void *root, int transpose, int64_t nrhs,

@@ -1236,6 +1236,30 @@ __global__ void __launch_bounds__(kThreads) k_rigid(const int32_t *__restrict__ 
     }
 }
 
+// Vectors of a rigidly moved body (reuse of its transforms): Q~ of positions
+// Rot_j r + t equals Q~ of r times blockdiag(Rot_j^T) over the body's beads,
+// since Z of the moved body is diag(Rot_j, Rot_j) Z blockdiag(Rot_j^T) up to
+// adding multiples of its translation rows to the others (Eq. 1.2).  Each
+// bead's 3-vector of every right-hand side is multiplied by Rot_j^T
+// (transpose = 1, before an upward sweep) or Rot_j (after a downward one);
+// element (3i + d, r) at 3i R + r vlane + d vcomp.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rotate(const int32_t *__restrict__ chunks, const double *__restrict__ rot,
+                                                     const T *in, T *out, int R, int vlane, int vcomp, int transpose) {
+    const int body = chunks[3 * blockIdx.x], b0 = chunks[3 * blockIdx.x + 1], b1 = chunks[3 * blockIdx.x + 2];
+    double M[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[3 * a + b] = transpose ? rot[9 * body + 3 * b + a] : rot[9 * body + 3 * a + b];
+    const int64_t cnt = (int64_t)(b1 - b0) * R;
+    for (int64_t q = threadIdx.x; q < cnt; q += kThreads) {
+        const int64_t i = b0 + q / R;
+        const int r = (int)(q % R);
+        const int64_t e = 3 * i * R + (int64_t)r * vlane;
+        const double x0 = in[e], x1 = in[e + vcomp], x2 = in[e + 2 * vcomp];
+        for (int d = 0; d < 3; ++d) out[e + d * vcomp] = (T)(M[3 * d] * x0 + M[3 * d + 1] * x1 + M[3 * d + 2] * x2);
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads = kThreads) {
     int64_t b = (n + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -1393,6 +1417,20 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
                            P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags,
                            (sort_tiles && !later) ? (const int32_t *)P.d_tord : nullptr, m, N, NI, P.d_err);
     }
+    HQ_HIP(hipGetLastError());
+    return HQ_OK;
+}
+
+hq_status rotate_vectors(Plan &P, const double *rot, const void *in, void *out, int64_t nrhs, int prec, int layout,
+                         int transpose, hipStream_t s) {
+    const int R = (int)nrhs;
+    const int vlane = (layout == HQ_TRIPLES) ? 3 : 1, vcomp = (layout == HQ_TRIPLES) ? 1 : R;
+    if (prec == HQ_FP64)
+        hipLaunchKernelGGL(k_rotate<double>, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, rot,
+                           (const double *)in, (double *)out, R, vlane, vcomp, transpose);
+    else
+        hipLaunchKernelGGL(k_rotate<float>, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, rot,
+                           (const float *)in, (float *)out, R, vlane, vcomp, transpose);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }
