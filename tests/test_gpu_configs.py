@@ -165,3 +165,26 @@ def test_bd_step_wide_and_narrow_sweeps_agree(hq):
             assert np.abs(up[:, c0:c0 + 4] - up4).max() <= tol * np.abs(f).max()
             assert np.abs(dn[:, c0:c0 + 4] - dn4).max() <= tol * np.abs(g).max()
     assert h.query()["device_flags"] == 0
+
+
+def test_bd_vectors_beyond_2gib_take_the_narrow_sweeps(hq):
+    """96 right-hand sides in FP32 on the benchmark's workload: the vectors
+    (2.8 GB) are beyond the wide sweeps' 32-bit buffer offsets, so the narrow
+    sweeps run; their products equal the wide sweeps' on column blocks of 32
+    (FP32 rounding of a different operation order, <= 1e-5 relative)."""
+    w = W.bd_m4096()
+    rng = np.random.default_rng(71)
+    R = 96
+    f = torch.from_numpy(rng.standard_normal((3 * w.N, R)).astype(np.float32)).cuda()
+    h = _build(hq, w, store=2)
+    print(f"[gpu] narrow fallback R={R} bytes={f.numel() * 4}", flush=True)
+    big = h.apply(f)
+    for c0 in (0, 64):
+        part = h.apply(f[:, c0:c0 + 32].contiguous())
+        d = (big[:, c0:c0 + 32] - part).norm(dim=0) / f[:, c0:c0 + 32].norm(dim=0)
+        assert float(d.max()) <= 1e-5
+    back = h.apply(big, transpose=True)
+    part = h.apply(big[:, 32:64].contiguous(), transpose=True)
+    d = (back[:, 32:64] - part).norm(dim=0) / big[:, 32:64].norm(dim=0)
+    assert float(d.max()) <= 1e-5
+    assert h.query()["device_flags"] == 0

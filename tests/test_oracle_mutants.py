@@ -47,6 +47,9 @@ MUTANTS = [
     ("leaf read in sorted order", "else { int64_t u = B->perm[-(p->x + 1)]; for (int d = 0; d < 3; ++d) Mx[d] = v[3 * u + d]; }",
      "else { int64_t u = -(p->x + 1); for (int d = 0; d < 3; ++d) Mx[d] = v[3 * u + d]; }"),
     ("Case I rank-2 fix dropped", "if (k == 3) p->T22[2][2] = 0.0;", ""),
+    ("root Velocity-set ignored", "if (root) for (int d = 0; d < 6; ++d) L[d] = root[d * nrhs + r];", ""),
+    ("root Info-set halves swapped", "if (root) for (int d = 0; d < 6; ++d) root[d * nrhs + r] = M[d];",
+     "if (root) for (int d = 0; d < 6; ++d) root[d * nrhs + r] = M[(d + 3) % 6];"),
     ("explicit last block sign", "J[(q + d) * ncol + 3 * (nx + b) + d] = -p->sx / sqrt((double)ny);",
      "J[(q + d) * ncol + 3 * (nx + b) + d] = p->sx / sqrt((double)ny);"),
 ]
@@ -81,6 +84,8 @@ check('norm', pins.norm_error(b, rng) < 1e-12)
 check('explicit', pins.explicit_error(b, rng) < 1e-12)
 check('blocks', pins.block_structure_error(b) < 1e-13)
 check('case1', pins.case1_error(hier.Body, 0.3, 0.7, 1.1, lib=lib) < 1e-12)
+check('fullq', pins.full_q_inverse_error(b, rng) < 1e-12)
+check('rootrows', pins.root_rows_error(B(cube[:30])) < 1e-12)
 # translation invariance (rank-2 pivots must not flip reflector signs)
 pos = np.random.default_rng(30).uniform(-2, 7, (150, 3))
 tr = W.ellipsoid_body(np.random.default_rng(30), 150, (20, 12, 8), jitter=0.3)
