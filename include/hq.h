@@ -246,9 +246,12 @@ hq_status hq_constrained_solve(hq_handle h, hq_dapply_fn dapply, void *user, con
  * blockdiag(Rot_j^T) plus multiples of its translation rows).  It differs
  * from the Q~ a rebuild would give by an orthogonal change of rows; the
  * projector Q~^T Q~ is the same.
- *   transpose = 0: out = Q~ (blockdiag(Rot^T) v), work receiving the rotated
- *                  v (device, 3N x nrhs, distinct from v and out).
+ *   transpose = 0: out = Q~ (blockdiag(Rot^T) v); work (device, 3N x nrhs,
+ *                  distinct from v and out) may receive the rotated v.
  *   transpose = 1: out = blockdiag(Rot) (Q~^T v); work unused (may be NULL).
+ * With the wide sweeps (32 or more right-hand sides) the rotations are
+ * applied inside the sweeps as the bead vectors are read and written (no
+ * extra pass over the vectors); otherwise in separate passes.
  *   rot  device m x 9 FP64 row-major: each body's rotation since the last
  *        build or rebuild (translations do not matter).
  * Vectors as for hq_apply_layout.  Capturable (no allocation once the

@@ -101,6 +101,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     }
     HQ_TRY(upload(P, &P.d_bead_off, bead_off));
     HQ_TRY(upload(P, &P.d_node_off, node_off));
+    HQ_TRY(dalloc(P, &P.d_rotf, 9 * m));
     HQ_TRY(upload(P, &P.d_row_off, row_off));
 
     // chunk table for the per-bead kernels
@@ -637,6 +638,11 @@ hq_status hq_apply_rotated(hq_handle h, const double *rot, const void *v, void *
     }
     HQ_TRY(check_apply(*P, v, out, nullptr, transpose, nrhs, prec, layout));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // wide sweeps: the rotations are fused into their bead loads and stores
+    HQ_TRY(ensure_xch(*P, nrhs, prec, s));
+    const hq_status fused = apply_device(*P, v, out, nullptr, transpose, nrhs, prec, layout, s, nullptr, rot);
+    if (fused != HQ_E_UNSUPPORTED) return fused;
+    // narrow sweeps: separate rotation passes
     if (!transpose) {
         // Q~(moved) v = Q~ (blockdiag(Rot^T) v)
         HQ_TRY(rotate_vectors(*P, rot, v, work, nrhs, prec, layout, 1, s));

@@ -37,6 +37,7 @@ struct Ctx {
     // triple contiguous): vlane 3, vcomp 1
     int vlane, vcomp;
     int root_in;  // downward: body roots take their Velocity-set from the exchange buffer (full Q)
+    int m;        // bodies (rows of the rotation table of the fused rigid-motion products)
     uint32_t in_bytes, out_bytes, xch_bytes;  // buffer sizes of the wide sweeps (each < 2 GiB)
 };
 
@@ -640,6 +641,20 @@ __device__ __forceinline__ int2 bcast_refs(const RecReg<float> &r) { return make
 
 __device__ __forceinline__ int2 bcast_refs(const RecReg<double> &r) { return make_int2(r.geti<0>(), r.geti<1>()); }
 
+// the node's body (link word 5)
+__device__ __forceinline__ int bcast_body(const RecReg<float> &r) { return r.geti<31>(); }
+__device__ __forceinline__ int bcast_body(const RecReg<double> &r) { return r.geti<5>(); }
+
+// Rotation of a moved body (m x 9 row-major, the sweep's precision): the
+// upward sweep takes each bead's 3-vector times Rot^T, the downward one
+// gives each bead's result times Rot (transform reuse across rigid motions).
+template <typename T>
+__device__ __forceinline__ void load_rot(const T *__restrict__ rot, int body, int m, T (&r)[9]) {
+    const T *p = rot + 9 * (int64_t)min(max(body, 0), m - 1);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = p[i];
+}
+
 template <int RT>
 __device__ __forceinline__ int rhs_count(const Ctx &C) {
     return RT ? RT : C.R;
@@ -886,10 +901,10 @@ __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B
 // One upward node step (Eqs. 4.2-4.3).  A child of the same tile is read from
 // its LDS slot; a bead or an earlier tile's root comes from the prefetched
 // registers ax / ay.  Nothing is stored unless the node is live.
-template <typename T, int RT, int IW, int NC, bool TRI>
+template <typename T, int RT, int IW, int NC, bool TRI, bool ROT>
 __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW][NC],
-                                        const T (&ay)[IW][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
-                                        LaneB lb, bool live, bool act) {
+                                        const T (&ay)[IW][NC], const T (&rm)[9], T *lds, int lane, const WBufs &B,
+                                        const Ctx &C, LaneB lb, bool live, bool act) {
     // offsets and references were checked when the tile schedule was built;
     // an access outside a buffer would be dropped by its range check
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
@@ -908,6 +923,20 @@ __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, cons
         for (int k = 0; k < IW; ++k) {
             mx[k][c] = xst ? mx[k][c] : ax[k][c];
             my[k][c] = yst ? my[k][c] : ay[k][c];
+        }
+        if constexpr (ROT) {
+            // a bead child's vector times Rot^T
+            T rx[3], ry[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                rx[d] = rm[d] * ax[0][c] + rm[3 + d] * ax[1][c] + rm[6 + d] * ax[2][c];
+                ry[d] = rm[d] * ay[0][c] + rm[3 + d] * ay[1][c] + rm[6 + d] * ay[2][c];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                mx[d][c] = lk.xref >= 0 ? rx[d] : mx[d][c];
+                my[d][c] = lk.yref >= 0 ? ry[d] : my[d][c];
+            }
         }
         T tt[3];
 #pragma unroll
@@ -965,10 +994,11 @@ __device__ __forceinline__ int wave_max_len(int len) {
     return __builtin_amdgcn_readfirstlane(len);
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC, bool TRI>
+template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC, bool TRI, bool ROT>
 __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_up_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
-    const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
+    const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, const T *__restrict__ rot, Ctx C,
+    int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
     static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6 || PR == 12), "ring sizes");
     static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
@@ -995,6 +1025,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
         const T *rp = rec + (int64_t)kRecWords * base;
         RecReg<T> RW[PR];
         T A[NR][IW][NC], Bv[NR][IW][NC];
+        T RM[ROT ? NR : 1][9];
 #pragma unroll
         for (int k = 0; k < PR; ++k) RW[k].load(rp + (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
@@ -1002,6 +1033,7 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
             const int2 ref = bcast_refs(RW[k]);
             up_input<T, RT, IW, NC, TRI>(ref.x, A[k], B, C, lb);
             up_input<T, RT, IW, NC, TRI>(ref.y, Bv[k], B, C, lb);
+            if constexpr (ROT) load_rot(rot, bcast_body(RW[k]), C.m, RM[k]);
         }
 #define HQ_UP_STEP(K)                                                                       \
         {                                                                                   \
@@ -1014,8 +1046,11 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
                 const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                       \
                 up_input<T, RT, IW, NC, TRI>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);      \
                 up_input<T, RT, IW, NC, TRI>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);     \
+                if constexpr (ROT)                                                          \
+                    load_rot(rot, bcast_body(RW[((K) + NR - 1) % PR]), C.m, RM[((K) + NR - 1) % NR]); \
             }                                                                               \
-            up_node<T, RT, IW, NC, TRI>(g, lk, A[(K) % NR], Bv[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            up_node<T, RT, IW, NC, TRI, ROT>(g, lk, A[(K) % NR], Bv[(K) % NR], RM[ROT ? (K) % NR : 0], lds, lane, \
+                                             B, C, lb, n < len, act);                       \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_UP_STEP(0)
@@ -1067,10 +1102,10 @@ __device__ __forceinline__ void down_input(const Links6 &lk, T (&a)[6][NC], T (&
 // exchange buffer for a tile root, zero for a body root), children's
 // Velocity-sets to their slots, to bead outputs, or (XC: phases after the
 // first) to the exchange buffer.
-template <typename T, int RT, bool XC, int NC, bool TRI>
+template <typename T, int RT, bool XC, int NC, bool TRI, bool ROT>
 __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, const T (&wp)[6][NC],
-                                          const T (&lroot)[6][NC], T *lds, int lane, const WBufs &B, const Ctx &C,
-                                          LaneB lb, bool live, bool act) {
+                                          const T (&lroot)[6][NC], const T (&rm)[9], T *lds, int lane,
+                                          const WBufs &B, const Ctx &C, LaneB lb, bool live, bool act) {
     const int xs = min(lk.slots & 0xff, C.nslot - 1), ys = min((lk.slots >> 8) & 0xff, C.nslot - 1);
     const int os = min((lk.slots >> 16) & 0xff, C.nslot - 1);
     const bool troot = (lk.meta & kMetaTileRoot) != 0;
@@ -1105,8 +1140,22 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
     const bool en = live && act;
     {
         const uint32_t bx = bead_off<T, RT>(lk.xref, en, C, lb), by = bead_off<T, RT>(lk.yref, en, C, lb);
-        bst3n<T, TRI, NC, 0>(Lx, B.out, bx, B.row);
-        bst3n<T, TRI, NC, 0>(Ly, B.out, by, B.row);
+        if constexpr (ROT) {
+            // a bead child's result times Rot (only the bead stores use it)
+            T bxv[6][NC], byv[6][NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    bxv[d][c] = rm[3 * d] * Lx[0][c] + rm[3 * d + 1] * Lx[1][c] + rm[3 * d + 2] * Lx[2][c];
+                    byv[d][c] = rm[3 * d] * Ly[0][c] + rm[3 * d + 1] * Ly[1][c] + rm[3 * d + 2] * Ly[2][c];
+                }
+            bst3n<T, TRI, NC, 0>(bxv, B.out, bx, B.row);
+            bst3n<T, TRI, NC, 0>(byv, B.out, by, B.row);
+        } else {
+            bst3n<T, TRI, NC, 0>(Lx, B.out, bx, B.row);
+            bst3n<T, TRI, NC, 0>(Ly, B.out, by, B.row);
+        }
     }
     if constexpr (XC) {
         bst6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(lk.xref), en && lk.xref < kRefStack, C, lb), Lx);
@@ -1119,10 +1168,11 @@ __device__ __forceinline__ void down_node(const T (&g)[26], const Links6 &lk, co
     }
 }
 
-template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC, bool TRI>
+template <typename T, int LPT, int RT, int PR, int NR, bool XC, int NC, bool TRI, bool ROT>
 __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_down_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
-    const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
+    const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch, const T *__restrict__ rot, Ctx C,
+    int32_t *err) {
     static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
     static_assert(PR % NR == 0 && NR >= 2 && (PR == 3 || PR == 4 || PR == 6 || PR == 12), "ring sizes");
     static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
@@ -1150,10 +1200,14 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
         const T *rp = rec + (int64_t)kRecWords * (base + last);
         RecReg<T> RW[PR];
         T A[NR][6][NC], Bl[NR][6][NC];
+        T RM[ROT ? NR : 1][9];
 #pragma unroll
         for (int k = 0; k < PR; ++k) RW[k].load(rp - (int64_t)min(k, last) * kRecWords, lane);
 #pragma unroll
-        for (int k = 0; k < NR - 1; ++k) down_input<T, RT, NC, TRI>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
+        for (int k = 0; k < NR - 1; ++k) {
+            down_input<T, RT, NC, TRI>(bcast_links6(RW[k]), A[k], Bl[k], B, C, lb);
+            if constexpr (ROT) load_rot(rot, bcast_body(RW[k]), C.m, RM[k]);
+        }
 #define HQ_DOWN_STEP(K)                                                                     \
         {                                                                                   \
             const int n = n0 + (K);                                                         \
@@ -1163,7 +1217,10 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
             RW[K].load(rp - (int64_t)min(n + PR, last) * kRecWords, lane);                  \
             down_input<T, RT, NC, TRI>(bcast_links6(RW[((K) + NR - 1) % PR]), A[((K) + NR - 1) % NR], \
                                        Bl[((K) + NR - 1) % NR], B, C, lb);                  \
-            down_node<T, RT, XC, NC, TRI>(g, lk, A[(K) % NR], Bl[(K) % NR], lds, lane, B, C, lb, n < len, act); \
+            if constexpr (ROT)                                                              \
+                load_rot(rot, bcast_body(RW[((K) + NR - 1) % PR]), C.m, RM[((K) + NR - 1) % NR]); \
+            down_node<T, RT, XC, NC, TRI, ROT>(g, lk, A[(K) % NR], Bl[(K) % NR], RM[ROT ? (K) % NR : 0], lds, lane, \
+                                               B, C, lb, n < len, act);                     \
         }
         for (int n0 = 0; n0 < maxlen; n0 += PR) {
             HQ_DOWN_STEP(0)
@@ -1189,10 +1246,11 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
 }
 
 // One tile phase of a wide sweep: LPT lanes per run, NC columns per lane,
-// vectors in the rows or (TRI) the triples layout.
-template <typename T, int LPT, int NC, bool TRI>
-void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
-                 hipStream_t s) {
+// vectors in the rows or (TRI) the triples layout, bead vectors turned by
+// their body's rotation (ROT).
+template <typename T, int LPT, int NC, bool TRI, bool ROT>
+void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const T *rot,
+                 const Ctx &C, hipStream_t s) {
     constexpr int TPW = 64 / LPT;
     const size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
     // work items: groups of TPW runs (a phase has at most NI / run_nodes + 1
@@ -1209,18 +1267,18 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     do {                                                                                                     \
         if (!transpose) {                                                                                    \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU1, NRU1, 3, NC, TRI>), dim3(grid), dim3(64), lds_w, \
-                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU1, NRU1, 3, NC, TRI, ROT>), dim3(grid), dim3(64), lds_w, \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, rot, C, P.d_err);               \
             else                                                                                             \
-                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU, NRU, 6, NC, TRI>), dim3(grid), dim3(64), lds_w,   \
-                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);               \
+                hipLaunchKernelGGL((k_up_wide<T, LPT, RT, PRU, NRU, 6, NC, TRI, ROT>), dim3(grid), dim3(64), lds_w,   \
+                                   s, phase, P.d_prun, P.d_run, rec, v, out, xch, rot, C, P.d_err);               \
         } else {                                                                                             \
             if (phase == 1)                                                                                  \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD1, NRD1, false, NC, TRI>), dim3(grid), dim3(64),  \
-                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);        \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD1, NRD1, false, NC, TRI, ROT>), dim3(grid), dim3(64),  \
+                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, rot, C, P.d_err);        \
             else                                                                                             \
-                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD, NRD, true, NC, TRI>), dim3(grid), dim3(64),     \
-                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, C, P.d_err);        \
+                hipLaunchKernelGGL((k_down_wide<T, LPT, RT, PRD, NRD, true, NC, TRI, ROT>), dim3(grid), dim3(64),     \
+                                   lds_w, s, phase, P.d_prun, P.d_run, rec, v, out, xch, rot, C, P.d_err);        \
         }                                                                                                    \
     } while (0)
     // records six nodes ahead, inputs two nodes ahead, in every phase
@@ -1296,7 +1354,7 @@ enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWi
 
 template <typename T>
 void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
-                const Ctx &C, hipStream_t s, hipEvent_t *ev) {
+                const T *rot, const Ctx &C, hipStream_t s, hipEvent_t *ev) {
     const bool tri = C.vlane == 3;
     const int nph = std::max(P.phases_built, P.phases_reserved);
     for (int k = 0; k < nph; ++k) {
@@ -1309,12 +1367,22 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
         case kNarrow8: launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kWide32:
-            if (tri) launch_wide<T, 32, 1, true>(P, phase, transpose, rec, v, out, xch, C, s);
-            else launch_wide<T, 32, 1, false>(P, phase, transpose, rec, v, out, xch, C, s);
+            if (rot) {
+                if (tri) launch_wide<T, 32, 1, true, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                else launch_wide<T, 32, 1, false, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+            } else {
+                if (tri) launch_wide<T, 32, 1, true, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                else launch_wide<T, 32, 1, false, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+            }
             break;
         case kWide64:
-            if (tri) launch_wide<T, 64, 1, true>(P, phase, transpose, rec, v, out, xch, C, s);
-            else launch_wide<T, 64, 1, false>(P, phase, transpose, rec, v, out, xch, C, s);
+            if (rot) {
+                if (tri) launch_wide<T, 64, 1, true, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                else launch_wide<T, 64, 1, false, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+            } else {
+                if (tri) launch_wide<T, 64, 1, true, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                else launch_wide<T, 64, 1, false, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+            }
             break;
         }
     }
@@ -1329,9 +1397,16 @@ int lanes_per_tile(int64_t nrhs) {
     return l;
 }
 
+// the rotation table in FP32 for the FP32 sweeps
+__global__ void k_rot_to_float(int64_t n, const double *__restrict__ in, float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
 hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
-                       int layout, hipStream_t s, hipEvent_t *ev) {
+                       int layout, hipStream_t s, hipEvent_t *ev, const double *rot) {
     Ctx C;
+    C.m = (int)P.m;
     C.N = P.N;
     C.rows = P.rows;
     C.nsched = P.NI;
@@ -1367,14 +1442,24 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     C.dmax = stack_depth(P.smax());
     C.nslot = stack_slots(P.smax());
     const bool wide = kind == kWide32 || kind == kWide64;
+    // rigid-motion rotations are fused into the wide sweeps only; the caller
+    // turns the vectors in separate passes for the narrow ones
+    if (rot && !wide) return HQ_E_UNSUPPORTED;
     if (prec == HQ_FP64) {
         if (root && transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 1, C, s);
-        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, C, s,
-                           ev);
+        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, rot, C,
+                           s, ev);
         if (root && !transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 0, C, s);
     } else {
+        const float *rotf = nullptr;
+        if (rot) {
+            hipLaunchKernelGGL(k_rot_to_float, dim3(std::min<int64_t>((9 * P.m + 255) / 256, 1024)), dim3(256), 0, s,
+                               9 * P.m, rot, P.d_rotf);
+            rotf = P.d_rotf;
+        }
         if (root && transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 1, C, s);
-        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, C, s, ev);
+        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, rotf, C, s,
+                          ev);
         if (root && !transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 0, C, s);
     }
     HQ_HIP(hipGetLastError());

@@ -718,7 +718,7 @@ __global__ void k_links(int64_t NI, const int32_t *cov, const int32_t *tileof, c
         links[kLinkInts * s + 2] = off;
         links[kLinkInts * s + 3] = meta;
         links[kLinkInts * s + 4] = xs | (ys << 8) | (os << 16);
-        links[kLinkInts * s + 5] = g;
+        links[kLinkInts * s + 5] = nbody[g];
     }
 }
 

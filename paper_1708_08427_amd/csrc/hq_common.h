@@ -32,7 +32,7 @@ constexpr int kMaxDepth = 256;          // bound on tree depth walks (63 code bi
 //   then six int32 links from element 26 on (the bytes of elements 26..31 of
 //   a float record, 26..28 of a double record): xref, yref, off, meta,
 //   slots (x slot | y slot << 8 | own slot << 16, LDS slots of the wide
-//   sweeps), and the node's index in tree order.
+//   sweeps), and the node's body (the row of its rigid-motion rotation).
 constexpr int kRecTau = 21;
 constexpr int kRecSx = 24;
 constexpr int kRecSy = 25;
@@ -223,6 +223,7 @@ struct Plan {
 
     // exchange buffers
     void *d_xch = nullptr;
+    float *d_rotf = nullptr;  // m x 9: the FP32 copy of a rigid-motion rotation table
     size_t xch_bytes = 0;
 
     std::vector<void *> allocs;
@@ -259,8 +260,10 @@ hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64
                              const int32_t *gate = nullptr, const int32_t *dn = nullptr);
 
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases);
+// rot: each body's rigid-motion rotation (m x 9 FP64, device) fused into the
+// wide sweeps; HQ_E_UNSUPPORTED (nothing launched) when the sweeps are narrow
 hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
-                       int layout, hipStream_t s, hipEvent_t *ev = nullptr);
+                       int layout, hipStream_t s, hipEvent_t *ev = nullptr, const double *rot = nullptr);
 hq_status explicit_dense(Plan &P, int64_t body, double *out, int64_t ld, hipStream_t s);
 hq_status explicit_blocks_launch(Plan &P, int64_t body, int prec, void *values, const int64_t *d_blk_off,
                                  hipStream_t s);
