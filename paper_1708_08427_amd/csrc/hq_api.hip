@@ -43,9 +43,10 @@ hq_status upload(Plan &P, T **dst, const std::vector<T> &src) {
 
 void free_plan(Plan *P) {
     if (!P) return;
-    hipDeviceSynchronize();
-    for (void *p : P->allocs) hipFree(p);
-    if (P->d_xch) hipFree(P->d_xch);
+    // teardown: errors of earlier work were reported by the calls that queued it
+    (void)hipDeviceSynchronize();
+    for (void *p : P->allocs) (void)hipFree(p);
+    if (P->d_xch) (void)hipFree(P->d_xch);
     P->magic = 0;
     delete P;
 }
@@ -235,7 +236,7 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
     }
     HQ_HIP(hipDeviceSynchronize());
     if (P.d_xch) {
-        hipFree(P.d_xch);
+        (void)hipFree(P.d_xch);
         P.d_xch = nullptr;
         P.xch_bytes = 0;
     }
@@ -785,8 +786,12 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (st == HQ_OK) st = explicit_blocks_launch(*P, body, prec == HQ_FP64 ? 0 : 1, values, d_blk, s);
-    hipStreamSynchronize(s);
-    hipFree(d_blk);
+    const hipError_t se = hipStreamSynchronize(s);
+    (void)hipFree(d_blk);
+    if (st == HQ_OK && se != hipSuccess) {
+        set_error(std::string("hq_explicit_blocks: ") + hipGetErrorString(se));
+        st = HQ_E_DEVICE;
+    }
     return st;
 }
 
@@ -960,7 +965,7 @@ hq_status hq_capture_end(hq_stream stream, void **graph_exec) {
     HQ_HIP(hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &g));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         return HQ_E_DEVICE;
@@ -979,7 +984,7 @@ hq_status hq_graph_launch(void *graph_exec, hq_stream stream) {
 }
 
 void hq_graph_destroy(void *graph_exec) {
-    if (graph_exec) hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec));
+    if (graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec));
 }
 
 void hq_destroy(hq_handle h) {
