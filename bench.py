@@ -6,7 +6,9 @@ beads, sigma 0.6, clipped to [50, 20000]) on random ellipsoids in a 500^3 box,
 rotation about its centroid + translation in [-1,1]^3), rebuild of the tree and
 FP64 transforms, then Q~^T (Q~ f) in FP32 for the 32 right-hand sides.  K steps
 are captured in one hipGraph and replayed; the timed region is bracketed by
-synchronisations.  Force vectors are held as [bead][system][xyz] (the
+synchronisations.  By default consecutive steps alternate between two handles
+of the same bodies on two streams, so one step's rebuild overlaps the previous
+step's sweeps (--no-pipeline: one handle, one stream).  Force vectors are held as [bead][system][xyz] (the
 library's triples layout) unless --layout rows is given.
 
 value = bead-vectors per second = N * R / (time per step).  The roofline row
@@ -175,6 +177,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="one handle and one stream: step i+1's rebuild waits for step i's sweeps")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--probe", action="store_true",
                     help="only build, copy 512 MiB once and run 3 sweeps per direction (for rocprofv3 --pmc)")
@@ -230,21 +234,56 @@ def main():
         torch.cuda.synchronize()
         log(f"first build {1e3 * (time.perf_counter() - t0):.1f} ms; {h.query()}")
         h.reserve(R, torch.float32)
+        # software pipeline over two handles of the same bodies, each with its
+        # own stream and vectors: step i runs on handle i % 2, so the rebuild
+        # of step i + 1 (latency-bound launches) overlaps the sweeps of step i
+        # (bandwidth-bound).  Step i + 1's rigid motion waits for step i's
+        # rebuild (both touch the positions) and turns each body about the
+        # centroid that rebuild found (the motion is issued through step i's
+        # handle); a handle's rebuild follows its previous sweeps on its own
+        # stream.  Positions and products are those of the plain one-handle
+        # sequence, bit for bit.
+        npipe = 1 if args.no_pipeline else 2
+        hs, ss, tmps, outs = [h], [stream], [tmp], [out]
+        for _ in range(1, npipe):
+            hs.append(hq.build(pos, wl.offsets, store=2, stream=stream, **opts))
+            hs[-1].reserve(R, torch.float32)
+            ss.append(torch.cuda.Stream())
+            tmps.append(torch.empty_like(tmp))
+            outs.append(torch.empty_like(out))
+        torch.cuda.synchronize()
+        events = []  # kept alive while the graphs are captured
 
-        def step(i):
-            h.rigid_update(pos, rot_d[i], trans_d[i], stream=stream)
-            h.rebuild(pos, stream=stream)
-            h.apply(f32, out=tmp, stream=stream, layout=lay)
-            h.apply(tmp, transpose=True, out=out, stream=stream, layout=lay)
+        def event(s):
+            e = torch.cuda.Event()
+            e.record(s)
+            events.append(e)
+            return e
+
+        def steps(i0, i1):
+            fork = event(stream)
+            for s in ss[1:]:
+                s.wait_event(fork)
+            rebuilt = None
+            for i in range(i0, i1):
+                x = i % npipe
+                hx, sx = hs[x], ss[x]
+                if rebuilt is not None and npipe > 1:
+                    sx.wait_event(rebuilt)
+                hs[(i - 1) % npipe].rigid_update(pos, rot_d[i], trans_d[i], stream=sx)
+                hx.rebuild(pos, stream=sx)
+                rebuilt = event(sx)
+                hx.apply(f32, out=tmps[x], stream=sx, layout=lay)
+                hx.apply(tmps[x], transpose=True, out=outs[x], stream=sx, layout=lay)
+            for s in ss[1:]:
+                stream.wait_event(event(s))
 
         # graphs: warmup steps, then exactly K timed steps
         hq.capture_begin(stream)
-        for i in range(args.warmup):
-            step(i)
+        steps(0, args.warmup)
         g_warm = hq.capture_end(stream)
         hq.capture_begin(stream)
-        for i in range(args.warmup, total_steps):
-            step(i)
+        steps(args.warmup, total_steps)
         g_timed = hq.capture_end(stream)
         log("graphs captured")
 
@@ -257,14 +296,16 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_step = ev0.elapsed_time(ev1) / args.steps
-        q = h.query()
-        log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; flags {q['device_flags']}")
-        if q["device_flags"] != 0:
-            raise RuntimeError(f"device flags raised: {q}")
+        for hx in hs:
+            q = hx.query()
+            log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; flags {q['device_flags']}")
+            if q["device_flags"] != 0:
+                raise RuntimeError(f"device flags raised: {q}")
+        out_last = outs[(total_steps - 1) % npipe]
 
         # accuracy on the final positions: FP32 sweep pair against the FP64 oracle
         pos_host = pos.cpu().numpy()
-        out_host = from_layout(out.cpu().numpy(), lay).astype(np.float64)
+        out_host = from_layout(out_last.cpu().numpy(), lay).astype(np.float64)
         from oracle import dense, hier
         sample = np.random.default_rng(7).choice(m, 16, replace=False)
         err, leak = 0.0, 0.0
@@ -394,7 +435,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bd_step_m{m}_lognormal500_R{R}", "bodies": m, "beads": N, "nrhs": R,
                    "rows": wl.rows, **effective(opts), "autotuned": autotuned, "layout": lay,
-                   "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps"},
+                   "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps",
+                   "pipeline": (f"{npipe} handles on {npipe} streams: step i+1's rebuild overlaps step i's sweeps"
+                                if npipe > 1 else "one handle, one stream")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_up_wide<float, 32, 32, 6, 3, 3, 1, {str(lay == 'triples').lower()}>: "

@@ -124,6 +124,87 @@ def test_graph_replay_matches_eager(hq):
         assert np.abs(got - want).max() <= 1e-4 * np.abs(f[b0:b1]).max()
 
 
+def test_two_handle_pipeline_matches_sequence(hq):
+    """Steps alternating between two handles of the same bodies on two
+    streams (step i + 1's rebuild overlapping step i's sweeps, each motion
+    turning the bodies about the centroid of the previous step's rebuild)
+    give the positions and products of the one-handle sequence bit for bit,
+    eagerly and replayed from a graph captured across both streams."""
+    w, rot, trans, f = _workload()
+    K = 4
+    rot_d = torch.from_numpy(rot.reshape(K, w.m, 9)).cuda()
+    tr_d = torch.from_numpy(trans).cuda()
+    f32 = torch.from_numpy(f).float().cuda()
+    s0, s1 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s0):
+        pos = torch.from_numpy(w.pos).cuda()
+        # the plain sequence on one handle and one stream
+        h = hq.build(pos, w.offsets, tile_units=16, store=2, stream=s0)
+        tmp = torch.empty((w.rows, 32), dtype=torch.float32, device="cuda")
+        out = torch.empty((3 * w.N, 32), dtype=torch.float32, device="cuda")
+        for i in range(K):
+            h.rigid_update(pos, rot_d[i], tr_d[i], stream=s0)
+            h.rebuild(pos, stream=s0)
+            h.apply(f32, out=tmp, stream=s0)
+            h.apply(tmp, transpose=True, out=out, stream=s0)
+        torch.cuda.synchronize()
+        want_pos, want_out = pos.cpu().numpy(), out.cpu().numpy()
+
+        pos.copy_(torch.from_numpy(w.pos).cuda())
+        hs = [hq.build(pos, w.offsets, tile_units=16, store=2, stream=s0) for _ in range(2)]
+        for hx in hs:
+            hx.reserve(32, torch.float32)
+        ss = [s0, s1]
+        tmps = [torch.empty_like(tmp) for _ in range(2)]
+        outs = [torch.empty_like(out) for _ in range(2)]
+        events = []
+
+        def event(s):
+            e = torch.cuda.Event()
+            e.record(s)
+            events.append(e)
+            return e
+
+        def steps():
+            s1.wait_event(event(s0))
+            rebuilt = None
+            for i in range(K):
+                x = i % 2
+                if rebuilt is not None:
+                    ss[x].wait_event(rebuilt)
+                hs[(i - 1) % 2].rigid_update(pos, rot_d[i], tr_d[i], stream=ss[x])
+                hs[x].rebuild(pos, stream=ss[x])
+                rebuilt = event(ss[x])
+                hs[x].apply(f32, out=tmps[x], stream=ss[x])
+                hs[x].apply(tmps[x], transpose=True, out=outs[x], stream=ss[x])
+            s0.wait_event(event(s1))
+
+        torch.cuda.synchronize()
+        steps()
+        torch.cuda.synchronize()
+        assert np.array_equal(pos.cpu().numpy(), want_pos)
+        assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out)
+
+        hq.capture_begin(s0)
+        steps()
+        g = hq.capture_end(s0)
+        for rep in range(2):
+            # restore the positions and both handles' centroids before a replay
+            pos.copy_(torch.from_numpy(w.pos).cuda())
+            for hx in hs:
+                hx.rebuild(pos, stream=s0)
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            g.launch(s0)
+            torch.cuda.synchronize()
+            assert np.array_equal(pos.cpu().numpy(), want_pos), rep
+            assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out), rep
+        g.destroy()
+        for hx in hs:
+            assert hx.query()["device_flags"] == 0
+
+
 def test_node_data_after_rebuild(hq):
     """Centroids and T22 are refreshed by hq_rebuild only for handles built
     with keep_node_data; otherwise hq_node_data refuses them."""
