@@ -440,7 +440,7 @@ def main():
                                 if npipe > 1 else "one handle, one stream")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_up_wide<float, 32, 32, 6, 3, 3, 1, {str(lay == 'triples').lower()}>: "
+                     "kernel": f"k_up_wide<float, 32, 32, 6, 3, 3, 1, {str(lay == 'triples').lower()}, false>: "
                                "first tile phase of the upward FP32 sweep",
                      "bytes": int(pbytes[1]), "ms": t_p1,
                      "copy_ceiling": {"achieved": copy_gbs, "unit": "GB/s", "frac": copy_gbs / HBM_PEAK_GBS,
