@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--bodies", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--first-waves-per-cu", type=int, default=0,
+                    help="cap of the first tile phase's sweep grid (waves per CU; 0: uncapped)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="one handle and one stream: step i+1's rebuild waits for step i's sweeps")
     ap.add_argument("--apply-reps", type=int, default=20)
@@ -230,7 +232,7 @@ def main():
         t0 = time.perf_counter()
         # the step applies in FP32, so only the FP32 copy of the FP64-generated
         # transforms is kept; the FP64 sweep is timed on its own handle below
-        h = hq.build(pos, wl.offsets, store=2, stream=stream, **opts)
+        h = hq.build(pos, wl.offsets, store=2, stream=stream, first_waves_per_cu=args.first_waves_per_cu, **opts)
         torch.cuda.synchronize()
         log(f"first build {1e3 * (time.perf_counter() - t0):.1f} ms; {h.query()}")
         h.reserve(R, torch.float32)
@@ -246,7 +248,8 @@ def main():
         npipe = 1 if args.no_pipeline else 2
         hs, ss, tmps, outs = [h], [stream], [tmp], [out]
         for _ in range(1, npipe):
-            hs.append(hq.build(pos, wl.offsets, store=2, stream=stream, **opts))
+            hs.append(hq.build(pos, wl.offsets, store=2, stream=stream, first_waves_per_cu=args.first_waves_per_cu,
+                               **opts))
             hs[-1].reserve(R, torch.float32)
             ss.append(torch.cuda.Stream())
             tmps.append(torch.empty_like(tmp))
@@ -435,6 +438,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bd_step_m{m}_lognormal500_R{R}", "bodies": m, "beads": N, "nrhs": R,
                    "rows": wl.rows, **effective(opts), "autotuned": autotuned, "layout": lay,
+                   "first_waves_per_cu": args.first_waves_per_cu,
                    "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps",
                    "pipeline": (f"{npipe} handles on {npipe} streams: step i+1's rebuild overlaps step i's sweeps"
                                 if npipe > 1 else "one handle, one stream")},

@@ -109,6 +109,12 @@ typedef struct {
                               whose units are the roots of earlier tiles; smaller tiles give
                               those short phases more parallel work at the cost of more
                               phases; 0 = tile_units; <= 1024 */
+    int32_t first_waves_per_cu; /* grid of the first tile phase's wide sweeps (>= 32 RHS), in
+                              waves per compute unit, grid-strided over the runs; 0 = one wave
+                              per run pair (uncapped, fastest for a sweep on its own); 1..64.
+                              A cap leaves compute-unit slots and LDS to work running
+                              concurrently on another stream, e.g. the next step's hq_rebuild
+                              on a second handle; results are the same bit for bit */
 } hq_options;
 
 typedef struct {

@@ -350,12 +350,12 @@ def _offsets(positions, offsets):
 
 
 def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max_phases=0, run_nodes=0,
-          waves_per_cu=0, keep_node_data=0, later_tile_units=0, stream=None):
+          waves_per_cu=0, keep_node_data=0, later_tile_units=0, first_waves_per_cu=0, stream=None):
     """Build the tree and FP64 transforms for bodies given by ``offsets``
     (host, m + 1 int64) over ``positions`` (device, N x 3 float64)."""
     off = _offsets(positions, offsets)
     opt = Options(int(tile_units), int(store), int(explicit_dense_max_n), int(max_phases), int(run_nodes),
-                  int(waves_per_cu), int(keep_node_data), int(later_tile_units))
+                  int(waves_per_cu), int(keep_node_data), int(later_tile_units), int(first_waves_per_cu))
     raw = ctypes.c_void_p()
     lib = _lib.load()
     _check(lib.hq_build(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, ctypes.byref(opt),

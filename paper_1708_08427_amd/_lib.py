@@ -24,7 +24,7 @@ HQ_BODY_ILLCOND, HQ_BODY_DEGENERATE = 1, 2
 class Options(ctypes.Structure):
     _fields_ = [("tile_units", c_i32), ("store", c_i32), ("explicit_dense_max_n", c_i32), ("max_phases", c_i32),
                 ("run_nodes", c_i32), ("waves_per_cu", c_i32), ("keep_node_data", c_i32),
-                ("later_tile_units", c_i32)]
+                ("later_tile_units", c_i32), ("first_waves_per_cu", c_i32)]
 
 
 class KrylovInfo(ctypes.Structure):

@@ -82,6 +82,7 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     P.S2 = (opt && opt->later_tile_units) ? opt->later_tile_units : P.S;
     if (opt && opt->run_nodes) P.run_nodes = opt->run_nodes;
     if (opt && opt->waves_per_cu) P.waves_per_cu = opt->waves_per_cu;
+    if (opt) P.first_wpc = opt->first_waves_per_cu;
     P.keep_node_data = opt && opt->keep_node_data != 0;
     {
         int dev = 0, ncu = 0;
@@ -374,6 +375,10 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
         }
         if (opt->keep_node_data != 0 && opt->keep_node_data != 1) {
             set_error("keep_node_data must be 0 or 1");
+            return HQ_E_INVALID;
+        }
+        if (opt->first_waves_per_cu < 0 || opt->first_waves_per_cu > 64) {
+            set_error("first_waves_per_cu must be 0 or in [1, 64]");
             return HQ_E_INVALID;
         }
         if (opt->waves_per_cu != 0 && (opt->waves_per_cu < 1 || opt->waves_per_cu > 64)) {

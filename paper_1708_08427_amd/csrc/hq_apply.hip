@@ -1271,8 +1271,10 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     const int64_t nrun_max = std::max<int64_t>(P.NI / P.run_nodes + 2, kRunTarget + 2);
     const int64_t items = ((nrun_max + TPW - 1) / TPW) * (int64_t)C.nchunks;
     // later phases hold few runs (often none, for phases reserved for a
-    // rebuild): a grid of waves_per_cu waves per CU loops over them
-    const int64_t g = (phase == 1) ? items : std::min<int64_t>(items, (int64_t)P.waves_per_cu * P.ncu);
+    // rebuild): a grid of waves_per_cu waves per CU loops over them; the
+    // first phase takes one wave per item unless the handle caps its grid
+    const int64_t cap = (phase == 1) ? (int64_t)P.first_wpc : (int64_t)P.waves_per_cu;
+    const int64_t g = (phase == 1 && cap == 0) ? items : std::min<int64_t>(items, cap * P.ncu);
     const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
 #define HQ_WIDE(RT, PRU1, NRU1, PRU, NRU, PRD1, NRD1, PRD, NRD)                                              \
     do {                                                                                                     \

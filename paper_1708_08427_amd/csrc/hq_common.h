@@ -142,6 +142,7 @@ struct Plan {
     int max_n = 0;
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int waves_per_cu = 16;    // grid of the later phases' sweeps, waves per CU
+    int first_wpc = 0;        // grid cap of the first phase's wide sweeps, waves per CU (0: none)
     int ncu = 256;            // compute units of the device
     bool keep_node_data = false;  // hq_rebuild writes per-node centroids and T22
     bool node_data_fresh = false; // they describe the last (re)build

@@ -75,7 +75,8 @@ def test_bad_options_rejected(lib):
     h = ctypes.c_void_p()
     bad = [Options(1, 0, 0, 0), Options(4096, 0, 0, 0), Options(0, 7, 0, 0), Options(0, 0, 0, 99),
            Options(run_nodes=4), Options(waves_per_cu=65), Options(keep_node_data=2),
-           Options(later_tile_units=1), Options(later_tile_units=2048)]
+           Options(later_tile_units=1), Options(later_tile_units=2048), Options(first_waves_per_cu=-1),
+           Options(first_waves_per_cu=65)]
     for opt in bad:
         st = lib.hq_build(ctypes.c_void_p(1), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1,
                           ctypes.byref(opt), None, ctypes.byref(h))

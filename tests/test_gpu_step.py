@@ -205,6 +205,30 @@ def test_two_handle_pipeline_matches_sequence(hq):
             assert hx.query()["device_flags"] == 0
 
 
+def test_first_phase_grid_cap_matches_uncapped(hq):
+    """A capped first-phase grid (one wave per compute unit, grid-strided
+    over more run pairs than it has waves) gives the uncapped sweeps' results
+    bit for bit, both directions, both layouts."""
+    w = W.small_batch(23, [2, 5, 700, 3000, 9000, 6100, 480], nrhs=32)
+    rng = np.random.default_rng(23)
+    f = torch.from_numpy(rng.standard_normal((3 * w.N, 32))).float().cuda()
+    g = torch.from_numpy(rng.standard_normal((w.rows, 32))).float().cuda()
+    pos = torch.from_numpy(w.pos).cuda()
+    h0 = hq.build(pos, w.offsets, tile_units=16, run_nodes=8)
+    h1 = hq.build(pos, w.offsets, tile_units=16, run_nodes=8, first_waves_per_cu=1)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert (w.N - w.m) // 8 // 2 > 2 * ncu  # more run pairs than the capped grid has waves
+    for lay in ("rows", "triples"):
+        fv = f if lay == "rows" else f.view(w.N, 3, 32).transpose(1, 2).contiguous()
+        gv = g if lay == "rows" else g.view(w.rows // 3, 3, 32).transpose(1, 2).contiguous()
+        for tr, v in ((False, fv), (True, gv)):
+            a = h0.apply(v, transpose=tr, layout=lay)
+            b = h1.apply(v, transpose=tr, layout=lay)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), (lay, tr)
+    assert h0.query()["device_flags"] == 0 and h1.query()["device_flags"] == 0
+
+
 def test_node_data_after_rebuild(hq):
     """Centroids and T22 are refreshed by hq_rebuild only for handles built
     with keep_node_data; otherwise hq_node_data refuses them."""
