@@ -187,7 +187,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bodies of this workload "
-              "shard across GPUs with no communication, which this build does not run.", file=sys.stderr)
+              "would shard across GPUs with no communication, but the library runs one GPU per process and "
+              "the benchmark drives one.", file=sys.stderr)
         sys.exit(2)
 
     import torch
