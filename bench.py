@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "bead-vectors/s for batched Q̃v+Q̃ᵀv; % HBM peak; FP32 err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
 PROBE_SWEEPS = 3  # must match paper_1708_08427_amd.traffic
-TRAFFIC_FILE = "traffic_up_sweep_bd_m4096_R32.json"
+TRAFFIC_GLOB = "traffic_up_sweep_bd_m4096_R32*.json"  # one counter summary per launch configuration
 
 
 def phase_bytes(h, nrhs, elem=4):
@@ -149,17 +149,23 @@ def traffic_from_profile(opts, layout):
     """HBM bytes of one first-phase upward launch from the committed counter
     summary, if it was taken on the current sweep sources in the same launch
     configuration (else None)."""
+    import glob
+
     from paper_1708_08427_amd.traffic import sweep_source_hash
-    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
-    if not os.path.exists(path):
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", TRAFFIC_GLOB)))
+    if not paths:
         return None, "no counter summary"
-    with open(path) as fh:
-        prof = json.load(fh)
-    if prof.get("source_sha256") != sweep_source_hash():
-        return None, "sweep sources changed since the counters were taken"
-    if prof.get("options") != options_tag(opts, layout):
-        return None, f"counters taken with {prof.get('options')}, bench runs {options_tag(opts, layout)}"
-    return prof["up_phase1"]["hbm_bytes"], prof["command"]
+    src, tag, seen = sweep_source_hash(), options_tag(opts, layout), []
+    for path in paths:
+        with open(path) as fh:
+            prof = json.load(fh)
+        if prof.get("source_sha256") != src:
+            seen.append(f"{os.path.basename(path)}: sweep sources changed since the counters were taken")
+        elif prof.get("options") != tag:
+            seen.append(f"{os.path.basename(path)}: counters taken with {prof.get('options')}")
+        else:
+            return prof["up_phase1"]["hbm_bytes"], prof["command"]
+    return None, f"bench runs {tag}; " + "; ".join(seen)
 
 
 def main():
