@@ -115,6 +115,18 @@ typedef struct {
                               A cap leaves compute-unit slots and LDS to work running
                               concurrently on another stream, e.g. the next step's hq_rebuild
                               on a second handle; results are the same bit for bit */
+    int32_t max_nrhs;      /* hq_build_into: right-hand sides the sweeps' exchange entries in the
+                              workspace hold (in the largest precision kept); 0 = 32.  Calls
+                              with more fail with HQ_E_UNSUPPORTED.  Ignored by hq_build, whose
+                              handle grows its own buffer */
+    int32_t max_tiles;     /* hq_build_into: tiles the tile-indexed tables hold (plus 64); 0 =
+                              one per internal node, a bound every tree meets (tiles are
+                              disjoint and hold at least one node).  A smaller value saves
+                              workspace; a tree with more tiles fails hq_build_into with
+                              HQ_E_UNSUPPORTED and raises HQ_FLAG_BOUNDS on hq_rebuild */
+    int32_t krylov_nrhs;   /* hq_build_into: right-hand sides of hq_constrained_solve whose
+                              work vectors the workspace holds; 0 = none (the solve then fails
+                              on the handle with HQ_E_UNSUPPORTED) */
 } hq_options;
 
 typedef struct {
@@ -154,28 +166,57 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
                       hq_precision prec, hq_layout layout, int include_rebuild, const hq_options *base, hq_stream stream,
                       hq_options *best, double *best_ms);
 
-/* Build the tree and the FP64 local transforms of m bodies.
+/* Build the tree and the FP64 local transforms of m bodies: Section 1's
+ * Problem Statement (construct Q~), with Section 2.1's nested boxes and
+ * Section 3's per-node factorisations (Eqs. 3.4-3.13; Algorithm 1 without
+ * forming Q~).
  *   positions     device, N x 3 FP64, x,y,z interleaved, caller's bead order.
  *   body_offsets  host, m + 1 entries: [0] = 0, strictly increasing, so that
  *                 body j holds beads [off_j, off_{j+1}); every n_j >= 2.
  *   opt           host, may be NULL for the defaults.
  *   out           receives the handle, which owns all device memory it uses
  *                 (allocated here with hipMalloc).
- * Synchronises the stream once (to size the tile phases).  Errors:
+ * Synchronises the stream once (to size the tile phases); the stream is the
+ * handle's: the calls below that read device state synchronise it.  Errors:
  * HQ_E_INVALID for bad offsets, n_j < 2, NULL pointers or non-finite
  * positions (found on the device); HQ_E_NOMEM; HQ_E_DEVICE. */
 hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t m,
                    const hq_options *opt, hq_stream stream, hq_handle *out);
 
-/* Rebuild the same bodies (same offsets) from new positions: device,
- * N x 3 FP64.  No allocation and no host synchronisation, so a stream
- * capture may record it; tile phases beyond the reserved count raise
- * HQ_FLAG_PHASES. */
+/* Device bytes hq_build_into needs for these bodies and options (the
+ * Problem Statement's Q~ construction, as hq_build, in caller memory): the
+ * tree, tile and node tables, the transforms of the precisions kept, the
+ * tile-root table and exchange entries (hq_options.max_tiles, max_nrhs), the
+ * explicit-block offsets of the largest body and the Krylov vectors
+ * (krylov_nrhs).  Host only: no device memory is touched.  Errors as for
+ * hq_build's argument checks. */
+hq_status hq_workspace_bytes(const int64_t *body_offsets, int64_t m, const hq_options *opt, size_t *bytes);
+
+/* hq_build into caller-owned device memory: workspace (device, 256-byte
+ * aligned, at least hq_workspace_bytes bytes, e.g. a torch tensor) holds
+ * every piece of the handle's device state; the handle allocates no device
+ * memory, now or in any later call on it (hq_apply* beyond max_nrhs and
+ * hq_constrained_solve beyond krylov_nrhs fail with HQ_E_UNSUPPORTED instead
+ * of allocating).  The caller keeps the workspace alive until hq_destroy,
+ * which frees nothing on the device.  Results are bit for bit those of
+ * hq_build.  Errors as for hq_build; HQ_E_INVALID for a NULL, misaligned or
+ * too small workspace. */
+hq_status hq_build_into(const double *positions, const int64_t *body_offsets, int64_t m,
+                        const hq_options *opt, void *workspace, size_t bytes, hq_stream stream,
+                        hq_handle *out);
+
+/* Rebuild the same bodies (same offsets) from new positions (Section 2.1's
+ * tree and Section 3's factorisations again, as after a Brownian-dynamics
+ * step, Section 1): device, N x 3 FP64.  No allocation and no host
+ * synchronisation, so a stream capture may record it; tile phases beyond the
+ * reserved count raise HQ_FLAG_PHASES. */
 hq_status hq_rebuild(hq_handle h, const double *positions, hq_stream stream);
 
-/* Pre-allocate the per-tile exchange buffers for up to nrhs right-hand sides
- * of precision prec, so that later hq_apply calls allocate nothing (needed
- * before a stream capture).  Synchronous. */
+/* Pre-allocate the per-tile exchange buffers of the sweeps (Algorithms 2-3
+ * across tiles) for up to nrhs right-hand sides of precision prec, so that
+ * later hq_apply calls allocate nothing (needed before a stream capture).
+ * Synchronises the handle's stream.  On a workspace handle it allocates
+ * nothing and fails with HQ_E_UNSUPPORTED beyond max_nrhs. */
 hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec);
 
 /* Apply Q~ or Q~^T to nrhs right-hand sides.
@@ -277,8 +318,20 @@ hq_status hq_apply_timed(hq_handle h, const void *v, void *out, int transpose, i
                          hq_precision prec, hq_layout layout, hq_stream stream, float *phase_ms, int32_t max_phases,
                          int32_t *nphases);
 
-/* Tile phase of every internal node (host, N - m entries, the handle's node
- * order; 1 = first phase).  Synchronises. */
+/* Measurement helper for the sweeps' HBM roofline (Algorithms 2-3 stream
+ * their vectors and node records once): one launch of a streaming kernel
+ * that reads read_bytes from src and writes write_bytes to dst (a copy of
+ * the first write_bytes; the rest is only read), 16 bytes per access with
+ * the sweeps' non-temporal cache policy, blocks x 256 threads.  src, dst
+ * device (distinct), sink device (4 bytes, written only if the data holds a
+ * marker value).  Byte counts multiples of 16, write_bytes <= read_bytes.
+ * Stream-ordered; the caller times it. */
+hq_status hq_stream_ceiling(const void *src, size_t read_bytes, void *dst, size_t write_bytes, int32_t blocks,
+                            void *sink, hq_stream stream);
+
+/* Tile phase of every internal node of Section 2.1's tree (host, N - m
+ * entries, the handle's node order; 1 = first phase): the launch that sweeps
+ * it in Algorithms 2-3.  Synchronises the handle's stream. */
 hq_status hq_node_phase(hq_handle h, int32_t *phase);
 
 /* Dense Q~ of one body (Algorithm 1): out device FP64, (3n_j - 6) rows with
@@ -302,9 +355,9 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
                              int64_t *val_off, int64_t *row_off, int64_t *bead_first,
                              int32_t *rows, int32_t *cols, hq_stream stream);
 
-/* The tree order of one body's beads: host, n_j entries, the caller's bead
- * index (0-based within the body) of each tree leaf left to right.
- * Synchronises. */
+/* The tree order of one body's beads (the leaves of Section 2.1's nested
+ * boxes): host, n_j entries, the caller's bead index (0-based within the
+ * body) of each tree leaf left to right.  Synchronises the handle's stream. */
 hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index);
 
 /* Rigid motion of every body (a Brownian-dynamics step's position update):
@@ -316,36 +369,44 @@ hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index);
 hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot,
                           const double *trans, hq_stream stream);
 
-/* Sizes, phase/tile counts and device flags (synchronises the handle's
- * device state). */
+/* Sizes (Section 1: Q~ of body j has 3n_j - 6 rows), phase and tile counts,
+ * conditioning of the per-node factorisations (Section 3) and device flags.
+ * Synchronises the handle's stream (work queued on other streams must be
+ * complete). */
 hq_status hq_query(hq_handle h, hq_info *info);
 
-/* Per-body flags and largest kappa(T22): host arrays of m entries (either may
- * be NULL).  Synchronises. */
+/* Per-body flags and largest kappa(T22) over the nodes of Section 3's
+ * factorisation (rank-5 bodies, Section 2.2): host arrays of m entries
+ * (either may be NULL).  Synchronises the handle's stream. */
 hq_status hq_body_info(hq_handle h, int32_t *flags, double *kappa);
 
-/* Per-node data for tests, host arrays of N - m entries in the handle's node
- * order (any may be NULL): first/last sorted bead position within the body,
+/* Per-node data of Section 3's factorisation for tests, host arrays of N - m
+ * entries in the handle's node order (any may be NULL): first/last sorted bead position within the body,
  * the children (>= 0: node index; < 0: -(sorted position within body) - 1),
  * body index, beads below, centroid (3, body-local: relative to the body's
  * lower corner), T22 (9, row-major), G (81, row-major k x k in the top-left),
  * k, and the first residue row within the body.  Synchronises.  Centroids and
- * T22 after an hq_rebuild need hq_options.keep_node_data (else HQ_E_INVALID). */
+ * T22 after an hq_rebuild need hq_options.keep_node_data (else HQ_E_INVALID).  Synchronises the handle's stream. */
 hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchild,
                        int32_t *ychild, int32_t *body, int32_t *nbeads, double *centroid,
                        double *T22, double *G, int32_t *k, int32_t *row);
 
-/* Stream capture helpers (hipStreamBeginCapture / EndCapture /
- * hipGraphInstantiate / hipGraphLaunch): everything enqueued between begin
+/* Stream capture helpers for repeated Brownian-dynamics steps (Section 1:
+ * Q~ v and Q~^T v once per step): hipStreamBeginCapture / EndCapture /
+ * hipGraphInstantiate / hipGraphLaunch; everything enqueued between begin
  * and end on the stream is recorded into *graph_exec, which replays it. */
 hq_status hq_capture_begin(hq_stream stream);
 hq_status hq_capture_end(hq_stream stream, void **graph_exec);
 hq_status hq_graph_launch(void *graph_exec, hq_stream stream);
 void hq_graph_destroy(void *graph_exec);
 
-/* Destroy a handle and free what it allocated (NULL is accepted). */
+/* Destroy a handle (the end of Section 1's Q~ object): synchronise its
+ * stream and free what it allocated (nothing on the device for a workspace
+ * handle; NULL is accepted). */
 void hq_destroy(hq_handle h);
 
+/* The name of a status, and the thread's message of its last failing call
+ * (the error behaviour stated at the top of this header). */
 const char *hq_status_string(hq_status s);
 const char *hq_last_error(void);
 

@@ -31,7 +31,9 @@
  *   - x = lower-half child, y = upper-half child; a box whose beads fall in
  *     one half is replaced by that half (single-child chains collapse).
  *   - beads that share all 63 code bits are split by the highest differing
- *     bit of their body-local sorted position (ties keep user order).
+ *     bit of their body-local sorted position (ties keep user order).  No
+ *     passage fixes this split: parity unpinned beyond the basis-free pins
+ *     (rows orthonormal and orthogonal to Z, the projector of LAPACK's QR).
  *   - one tree per body, coordinates relative to the body's lower corner.
  *   - QR by Householder reflections in LAPACK's convention:
  *     beta = -sign(alpha) * ||(alpha, x)|| with sign(alpha) = +1 for
@@ -387,6 +389,20 @@ int64_t or_num_internal(const or_body *B) { return B->nint; }
 void or_perm(const or_body *B, int64_t *perm)
 {
     memcpy(perm, B->perm, sizeof(int64_t) * B->n);
+}
+
+/* The tree as sorted-position ranges: for internal node id, its range
+   [first, last] and the last sorted position of its x child (x covers
+   [first, split], y covers [split + 1, last]).  A binary tree over sorted
+   positions is fixed by these triples. */
+void or_tree(const or_body *B, int64_t *first, int64_t *last, int64_t *split)
+{
+    for (int64_t i = 0; i < B->nint; ++i) {
+        const onode *p = &B->nodes[i];
+        first[i] = p->first;
+        last[i] = p->last;
+        split[i] = (p->x >= 0) ? B->nodes[p->x].last : -(p->x + 1);
+    }
 }
 
 double or_max_kappa(const or_body *B)

@@ -53,6 +53,8 @@ def load(path: str | None = None):
     lib.or_max_kappa.argtypes = [ctypes.c_void_p]
     lib.or_perm.argtypes = [ctypes.c_void_p, _i64p]
     lib.or_perm.restype = None
+    lib.or_tree.argtypes = [ctypes.c_void_p, _i64p, _i64p, _i64p]
+    lib.or_tree.restype = None
     lib.or_codes.argtypes = [_dp, _i64, _u64p]
     lib.or_codes.restype = None
     lib.or_node.argtypes = [ctypes.c_void_p, _i64, _i64p, _dp]
@@ -125,6 +127,14 @@ class Body:
         out = np.zeros(self.n, dtype=np.int64)
         self.lib.or_perm(self._h, _ptr(out, _i64p))
         return out
+
+    def tree(self):
+        """(first, last, split) of every internal node: its sorted-position
+        range and the last position of its x child."""
+        k = self.num_internal
+        f, l, s = (np.zeros(k, dtype=np.int64) for _ in range(3))
+        self.lib.or_tree(self._h, _ptr(f, _i64p), _ptr(l, _i64p), _ptr(s, _i64p))
+        return f, l, s
 
     def node(self, i) -> Node:
         ints = np.zeros(8, dtype=np.int64)

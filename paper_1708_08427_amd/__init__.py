@@ -24,7 +24,7 @@ from . import _lib
 from ._lib import (HQ_BODY_DEGENERATE, HQ_BODY_ILLCOND, HQ_FLAG_BOUNDS, HQ_FLAG_NONFINITE, HQ_FLAG_PHASES,
                    HQ_FLAG_STACK, HQ_FP32, HQ_FP64, Info, Options)
 
-__all__ = ["HQError", "Handle", "build", "load", "HQ_FP64", "HQ_FP32"]
+__all__ = ["HQError", "Handle", "build", "build_into", "workspace_bytes", "load", "HQ_FP64", "HQ_FP32"]
 
 
 class HQError(RuntimeError):
@@ -80,6 +80,17 @@ def _check_dev(t, name):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _check_f64(t, name, count, shape=None):
+    """A contiguous float64 device tensor of ``count`` values (and ``shape``)."""
+    torch = _torch()
+    _check_dev(t, name)
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.numel() != count or (shape is not None and tuple(t.shape) != shape):
+        want = shape if shape is not None else f"{count} values"
+        raise ValueError(f"{name} must hold {want}, got {tuple(t.shape)}")
 
 
 class Handle:
@@ -164,8 +175,8 @@ class Handle:
                                       lay, _stream(stream), ms, 64, ctypes.byref(nph)), "hq_apply_timed")
             res = out.reshape(nout) if squeeze else out
             return res, [ms[i] for i in range(nph.value)]
-        _check(lib.hq_apply_layout(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype),
-                                   lay, _stream(stream)), "hq_apply_layout")
+        _check(lib.hq_apply_layout(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype), lay,
+                                   _stream(stream)), "hq_apply_layout")
         return out.reshape(nout) if squeeze else out
 
     def apply_full(self, v, transpose=False, root=None, out=None, stream=None, layout="rows"):
@@ -198,8 +209,10 @@ class Handle:
                 raise ValueError(f"root must be a contiguous {rshape} tensor of v's dtype")
         if out is None:
             out = torch.empty(oshape, dtype=v.dtype, device=v.device)
-        elif tuple(out.shape) != oshape or out.dtype != v.dtype or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
+        else:
+            _check_dev(out, "out")
+            if tuple(out.shape) != oshape or out.dtype != v.dtype:
+                raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
         if not v.is_contiguous():
             raise ValueError("v must be contiguous")
         _check(_lib.load().hq_apply_full(self._h(), _ptr(v), _ptr(out), _ptr(root), int(bool(transpose)), R,
@@ -234,14 +247,18 @@ class Handle:
             raise ValueError("v must be contiguous")
         if out is None:
             out = torch.empty(oshape, dtype=v.dtype, device=v.device)
-        elif tuple(out.shape) != oshape or out.dtype != v.dtype or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
+        else:
+            _check_dev(out, "out")
+            if tuple(out.shape) != oshape or out.dtype != v.dtype:
+                raise ValueError(f"out must be a contiguous {oshape} tensor of v's dtype")
         wp = None
         if not transpose:
             if work is None:
                 work = torch.empty_like(v)
-            elif work.shape != v.shape or work.dtype != v.dtype or not work.is_contiguous():
-                raise ValueError("work must be a contiguous tensor like v")
+            else:
+                _check_dev(work, "work")
+                if work.shape != v.shape or work.dtype != v.dtype:
+                    raise ValueError("work must be a contiguous tensor like v")
             wp = _ptr(work)
         _check(_lib.load().hq_apply_rotated(self._h(), _ptr(rot), _ptr(v), _ptr(out), wp, int(bool(transpose)), R,
                                             _prec(v.dtype), LAYOUTS[layout], _stream(stream)), "hq_apply_rotated")
@@ -257,12 +274,15 @@ class Handle:
         _check(_lib.load().hq_reserve(self._h(), int(nrhs), _prec(dtype)), "hq_reserve")
 
     def rebuild(self, positions, stream=None):
-        _check_dev(positions, "positions")
+        _check_f64(positions, "positions", 3 * self.N, (self.N, 3))
         _check(_lib.load().hq_rebuild(self._h(), _ptr(positions), _stream(stream)), "hq_rebuild")
 
     def rigid_update(self, positions, rot, trans, stream=None):
-        for t, nm in ((positions, "positions"), (rot, "rot"), (trans, "trans")):
-            _check_dev(t, nm)
+        """Positions (N, 3) float64 in place; rot m x 9 (or m x 3 x 3) and
+        trans m x 3 float64, all on the device."""
+        _check_f64(positions, "positions", 3 * self.N, (self.N, 3))
+        _check_f64(rot, "rot", 9 * self.m)
+        _check_f64(trans, "trans", 3 * self.m)
         _check(_lib.load().hq_rigid_update(self._h(), _ptr(positions), _ptr(rot), _ptr(trans), _stream(stream)),
                "hq_rigid_update")
 
@@ -274,6 +294,13 @@ class Handle:
         out = torch.empty((max(3 * n - 6, 0), 3 * n), dtype=torch.float64, device="cuda")
         _check(_lib.load().hq_explicit(self._h(), int(body), _ptr(out), 3 * n, _stream(stream)), "hq_explicit")
         return out
+
+    def explicit_blocks_size(self, body=0):
+        """(blocks, values) of the block-sparse Q~ of one body."""
+        nb, nv = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib.load().hq_explicit_blocks_size(self._h(), int(body), ctypes.byref(nb), ctypes.byref(nv)),
+               "hq_explicit_blocks_size")
+        return nb.value, nv.value
 
     def explicit_blocks(self, body=0, dtype=None, stream=None):
         """Block-sparse Q~ of one body: (values, val_off, row_off, bead_first,
@@ -349,18 +376,59 @@ def _offsets(positions, offsets):
     return off
 
 
-def build(positions, offsets, tile_units=0, store=0, explicit_dense_max_n=0, max_phases=0, run_nodes=0,
-          waves_per_cu=0, keep_node_data=0, later_tile_units=0, first_waves_per_cu=0, stream=None):
+def _options(kw):
+    names = [f for f, _ in Options._fields_]
+    unknown = set(kw) - set(names)
+    if unknown:
+        raise TypeError(f"unknown options {sorted(unknown)}")
+    return Options(*[int(kw.get(f, 0)) for f in names])
+
+
+def build(positions, offsets, stream=None, **options):
     """Build the tree and FP64 transforms for bodies given by ``offsets``
-    (host, m + 1 int64) over ``positions`` (device, N x 3 float64)."""
+    (host, m + 1 int64) over ``positions`` (device, N x 3 float64).
+    ``options``: hq_options fields (tile_units, store, run_nodes, ...)."""
     off = _offsets(positions, offsets)
-    opt = Options(int(tile_units), int(store), int(explicit_dense_max_n), int(max_phases), int(run_nodes),
-                  int(waves_per_cu), int(keep_node_data), int(later_tile_units), int(first_waves_per_cu))
+    opt = _options(options)
     raw = ctypes.c_void_p()
     lib = _lib.load()
     _check(lib.hq_build(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, ctypes.byref(opt),
                         _stream(stream), ctypes.byref(raw)), "hq_build")
     return Handle(raw, off)
+
+
+def workspace_bytes(offsets, **options):
+    """hq_workspace_bytes: device bytes of a handle built by build_into."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or len(off) < 2:
+        raise ValueError("offsets must hold m + 1 entries")
+    opt = _options(options)
+    n = ctypes.c_size_t(0)
+    _check(_lib.load().hq_workspace_bytes(off.ctypes.data_as(_lib.P_i64), len(off) - 1, ctypes.byref(opt),
+                                          ctypes.byref(n)), "hq_workspace_bytes")
+    return int(n.value)
+
+
+def build_into(positions, offsets, workspace=None, stream=None, **options):
+    """hq_build_into: build with every piece of device state in ``workspace``
+    (a 256-byte aligned torch uint8 tensor of at least workspace_bytes bytes;
+    allocated here with torch when None).  The handle keeps a reference to it
+    and the library allocates no device memory for this handle."""
+    torch = _torch()
+    off = _offsets(positions, offsets)
+    opt = _options(options)
+    need = workspace_bytes(off, **options)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=positions.device)
+    _check_dev(workspace, "workspace")
+    nbytes = workspace.numel() * workspace.element_size()
+    raw = ctypes.c_void_p()
+    _check(_lib.load().hq_build_into(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1,
+                                     ctypes.byref(opt), _ptr(workspace), nbytes, _stream(stream), ctypes.byref(raw)),
+           "hq_build_into")
+    h = Handle(raw, off)
+    h.workspace = workspace
+    return h
 
 
 def constrained_solve(h, dapply, F, layout="rows", rtol=1e-8, max_iter=500, stream=None):
@@ -430,10 +498,7 @@ def autotune(positions, offsets, nrhs, dtype=None, include_rebuild=True, stream=
     if key in _TUNED:
         return dict(_TUNED[key])
     names = [f for f, _ in Options._fields_]
-    unknown = set(base) - set(names)
-    if unknown:
-        raise TypeError(f"unknown options {sorted(unknown)}")
-    b = Options(*[int(base.get(f, 0)) for f in names])
+    b = _options(base)
     best = Options()
     ms = ctypes.c_double()
     _check(_lib.load().hq_autotune(_ptr(positions), off.ctypes.data_as(_lib.P_i64), len(off) - 1, int(nrhs),

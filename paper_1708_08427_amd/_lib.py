@@ -24,7 +24,8 @@ HQ_BODY_ILLCOND, HQ_BODY_DEGENERATE = 1, 2
 class Options(ctypes.Structure):
     _fields_ = [("tile_units", c_i32), ("store", c_i32), ("explicit_dense_max_n", c_i32), ("max_phases", c_i32),
                 ("run_nodes", c_i32), ("waves_per_cu", c_i32), ("keep_node_data", c_i32),
-                ("later_tile_units", c_i32), ("first_waves_per_cu", c_i32)]
+                ("later_tile_units", c_i32), ("first_waves_per_cu", c_i32), ("max_nrhs", c_i32),
+                ("max_tiles", c_i32), ("krylov_nrhs", c_i32)]
 
 
 class KrylovInfo(ctypes.Structure):
@@ -45,6 +46,9 @@ class Info(ctypes.Structure):
 # (name, restype, argtypes) of every exported function
 SIGNATURES = [
     ("hq_build", c_i32, [c_vp, P_i64, c_i64, ctypes.POINTER(Options), c_vp, ctypes.POINTER(c_vp)]),
+    ("hq_workspace_bytes", c_i32, [P_i64, c_i64, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]),
+    ("hq_build_into", c_i32, [c_vp, P_i64, c_i64, ctypes.POINTER(Options), c_vp, ctypes.c_size_t, c_vp,
+                              ctypes.POINTER(c_vp)]),
     ("hq_autotune", c_i32, [c_vp, P_i64, c_i64, c_i64, c_i32, c_i32, ctypes.c_int, ctypes.POINTER(Options), c_vp,
                             ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)]),
     ("hq_rebuild", c_i32, [c_vp, c_vp, c_vp]),
@@ -57,6 +61,7 @@ SIGNATURES = [
                                      ctypes.POINTER(KrylovInfo), c_vp]),
     ("hq_apply_timed", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp,
                                ctypes.POINTER(ctypes.c_float), c_i32, P_i32]),
+    ("hq_stream_ceiling", c_i32, [c_vp, ctypes.c_size_t, c_vp, ctypes.c_size_t, c_i32, c_vp, c_vp]),
     ("hq_node_phase", c_i32, [c_vp, P_i32]),
     ("hq_explicit", c_i32, [c_vp, c_i64, c_vp, c_i64, c_vp]),
     ("hq_explicit_blocks_size", c_i32, [c_vp, c_i64, P_i64, P_i64]),

@@ -16,42 +16,7 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-namespace {
-
-template <typename T>
-hq_status dalloc(Plan &P, T **p, int64_t count) {
-    *p = nullptr;
-    if (count < 1) count = 1;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
-    if (e != hipSuccess) {
-        set_error(std::string("hipMalloc of ") + std::to_string((size_t)count * sizeof(T)) +
-                  " bytes: " + hipGetErrorString(e));
-        return HQ_E_NOMEM;
-    }
-    P.allocs.push_back(q);
-    *p = reinterpret_cast<T *>(q);
-    return HQ_OK;
-}
-
-template <typename T>
-hq_status upload(Plan &P, T **dst, const std::vector<T> &src) {
-    HQ_TRY(dalloc(P, dst, (int64_t)src.size()));
-    if (!src.empty()) HQ_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-    return HQ_OK;
-}
-
-void free_plan(Plan *P) {
-    if (!P) return;
-    // teardown: errors of earlier work were reported by the calls that queued it
-    (void)hipDeviceSynchronize();
-    for (void *p : P->allocs) (void)hipFree(p);
-    if (P->d_xch) (void)hipFree(P->d_xch);
-    P->magic = 0;
-    delete P;
-}
-
-Plan *get_plan(hq_handle h) {
+Plan *plan_of(hq_handle h) {
     Plan *P = reinterpret_cast<Plan *>(h);
     if (!P || P->magic != kPlanMagic) {
         set_error("invalid or destroyed handle");
@@ -59,6 +24,66 @@ Plan *get_plan(hq_handle h) {
     }
     return P;
 }
+
+// Workspace pieces start on 256-byte boundaries.
+constexpr size_t kWsAlign = 256;
+
+hq_status plan_alloc(Plan &P, void **p, size_t bytes) {
+    *p = nullptr;
+    bytes = std::max<size_t>(bytes, 1);
+    if (P.sizing || P.ws) {
+        const size_t b = (bytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+        if (P.ws) {
+            if (P.ws_used + b > P.ws_bytes) {
+                set_error("the workspace is too small (hq_workspace_bytes gives the size)");
+                return HQ_E_INVALID;
+            }
+            *p = P.ws + P.ws_used;
+        }
+        P.ws_used += b;
+        return HQ_OK;
+    }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+        return HQ_E_NOMEM;
+    }
+    P.allocs.push_back(q);
+    *p = q;
+    return HQ_OK;
+}
+
+namespace {
+
+template <typename T>
+hq_status dalloc(Plan &P, T **p, int64_t count) {
+    void *q = nullptr;
+    HQ_TRY(plan_alloc(P, &q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+    *p = reinterpret_cast<T *>(q);
+    return HQ_OK;
+}
+
+template <typename T>
+hq_status upload(Plan &P, T **dst, const std::vector<T> &src) {
+    HQ_TRY(dalloc(P, dst, (int64_t)src.size()));
+    if (!P.sizing && !src.empty())
+        HQ_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HQ_OK;
+}
+
+void free_plan(Plan *P) {
+    if (!P) return;
+    // teardown: work queued on the handle's stream may still read its memory
+    // (errors of earlier work were reported by the calls that queued it)
+    if (!P->sizing) (void)hipStreamSynchronize(P->stream);
+    for (void *p : P->allocs) (void)hipFree(p);
+    if (P->d_xch && !P->ws) (void)hipFree(P->d_xch);
+    P->magic = 0;
+    delete P;
+}
+
+Plan *get_plan(hq_handle h) { return plan_of(h); }
 
 int next_pow2(int v) {
     int p = 1;
@@ -219,14 +244,47 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_run, P.run_cap));
     HQ_TRY(dalloc(P, &P.d_cnt, kCntNum));
     HQ_TRY(dalloc(P, &P.d_err, 1));
-    HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
+    if (!P.sizing) HQ_HIP(hipMemset(P.d_err, 0, sizeof(int32_t)));
     P.scan_blk_cap = scan_blocks_needed(std::max(std::max(N, NI), (int64_t)P.S * 256)) + 8;
     HQ_TRY(dalloc(P, &P.d_scan_blk, P.scan_blk_cap));
     return HQ_OK;
 }
 
+// Elements of the largest precision a handle keeps.
+size_t store_elem(const Plan &P) { return (P.store & 1) ? sizeof(double) : sizeof(float); }
+
+// The rest of a workspace handle's memory, which a library-allocated handle
+// sizes after its first build or on demand: the tile-root table and the
+// sweeps' exchange entries for (max_tiles or, without it, every internal
+// node: tiles are disjoint and hold at least one) tiles plus 64, the
+// exchange entries for max_nrhs right-hand sides, the explicit-block offsets
+// of the largest body, and the Krylov solve's vectors for krylov_nrhs
+// right-hand sides.
+hq_status reserve_workspace_extras(Plan &P, const hq_options *opt) {
+    const int64_t tiles = ((opt && opt->max_tiles > 0) ? (int64_t)opt->max_tiles : P.NI) + 64;
+    HQ_TRY(dalloc(P, &P.d_troot, tiles * kGenWords));
+    P.troot_cap = tiles;
+    const int64_t nrhs = (opt && opt->max_nrhs > 0) ? opt->max_nrhs : 32;
+    P.xch_bytes = (size_t)tiles * 6 * (size_t)nrhs * store_elem(P);
+    HQ_TRY(plan_alloc(P, &P.d_xch, P.xch_bytes));
+    HQ_TRY(dalloc(P, &P.d_blk, P.max_n));
+    if (opt && opt->krylov_nrhs > 0) {
+        P.kry_bytes = krylov_bytes(P.rows, opt->krylov_nrhs, store_elem(P));
+        HQ_TRY(plan_alloc(P, &P.d_kry, P.kry_bytes));
+    }
+    return HQ_OK;
+}
+
 hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
+    if (P.ws) {
+        // the workspace holds entries for troot_cap tiles
+        if (P.xch_bytes < (size_t)P.troot_cap * 6 * (size_t)nrhs * elem) {
+            set_error("nrhs beyond the workspace's exchange entries (hq_options.max_nrhs)");
+            return HQ_E_UNSUPPORTED;
+        }
+        return HQ_OK;
+    }
     const int64_t cap_tiles = 2 * P.tiles_built + 64;
     const size_t need = (size_t)cap_tiles * 6 * (size_t)nrhs * elem;
     if (P.xch_bytes >= need) return HQ_OK;
@@ -235,7 +293,8 @@ hq_status ensure_xch(Plan &P, int64_t nrhs, hq_precision prec, hipStream_t s) {
         set_error("exchange buffer too small during stream capture: call hq_reserve first");
         return HQ_E_INVALID;
     }
-    HQ_HIP(hipDeviceSynchronize());
+    // the old buffer may still be in use by work queued on this stream
+    HQ_HIP(hipStreamSynchronize(s));
     if (P.d_xch) {
         (void)hipFree(P.d_xch);
         P.d_xch = nullptr;
@@ -319,15 +378,15 @@ const char *hq_status_string(hq_status s) {
     return "unknown status";
 }
 
-hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t m, const hq_options *opt,
-                   hq_stream stream, hq_handle *out) {
-    if (!out) {
-        set_error("out is NULL");
-        return HQ_E_INVALID;
-    }
-    *out = nullptr;
-    if (!positions || !body_offsets) {
-        set_error("positions or body_offsets is NULL");
+}  // extern "C"
+
+namespace hq {
+namespace {
+
+// Argument checks shared by hq_build, hq_build_into and hq_workspace_bytes.
+hq_status check_build_args(const int64_t *body_offsets, int64_t m, const hq_options *opt) {
+    if (!body_offsets) {
+        set_error("body_offsets is NULL");
         return HQ_E_INVALID;
     }
     if (m < 1 || m > (1 << 26)) {
@@ -385,6 +444,51 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
             set_error("waves_per_cu must be 0 or in [1, 64]");
             return HQ_E_INVALID;
         }
+        if (opt->max_nrhs < 0 || opt->max_nrhs > (1 << 20) || opt->max_tiles < 0 || opt->krylov_nrhs < 0 ||
+            opt->krylov_nrhs > (1 << 20)) {
+            set_error("max_nrhs, max_tiles and krylov_nrhs must be >= 0 (nrhs <= 2^20)");
+            return HQ_E_INVALID;
+        }
+    }
+    return HQ_OK;
+}
+
+// Device bytes of a workspace handle (the plan, then the pieces a
+// library-allocated handle sizes later).
+hq_status workspace_size(const int64_t *off, int64_t m, const hq_options *opt, size_t *bytes) {
+    Plan P;
+    P.sizing = true;
+    HQ_TRY(create_plan(P, off, m, opt));
+    HQ_TRY(reserve_workspace_extras(P, opt));
+    *bytes = P.ws_used;
+    return HQ_OK;
+}
+
+// hq_build (ws = nullptr: the handle allocates its memory) and hq_build_into.
+hq_status build_handle(const double *positions, const int64_t *body_offsets, int64_t m, const hq_options *opt,
+                       void *ws, size_t ws_bytes, hipStream_t s, hq_handle *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return HQ_E_INVALID;
+    }
+    *out = nullptr;
+    if (!positions) {
+        set_error("positions is NULL");
+        return HQ_E_INVALID;
+    }
+    HQ_TRY(check_build_args(body_offsets, m, opt));
+    if (ws) {
+        size_t need = 0;
+        HQ_TRY(workspace_size(body_offsets, m, opt, &need));
+        if (ws_bytes < need) {
+            set_error("the workspace holds " + std::to_string(ws_bytes) + " bytes, the handle needs " +
+                      std::to_string(need) + " (hq_workspace_bytes)");
+            return HQ_E_INVALID;
+        }
+        if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+            set_error("the workspace must be 256-byte aligned");
+            return HQ_E_INVALID;
+        }
     }
     Plan *P = new (std::nothrow) Plan;
     if (!P) {
@@ -392,8 +496,11 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
         return HQ_E_NOMEM;
     }
     P->magic = kPlanMagic;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    P->stream = s;
+    P->ws = reinterpret_cast<char *>(ws);
+    P->ws_bytes = ws_bytes;
     hq_status st = create_plan(*P, body_offsets, m, opt);
+    if (st == HQ_OK && ws) st = reserve_workspace_extras(*P, opt);
     if (st == HQ_OK) st = build_device(*P, positions, s, true);
     if (st == HQ_OK) {
         if (P->phases_reserved == 0) P->phases_reserved = std::min(kMaxPhases - 1, P->phases_built + 2);
@@ -418,6 +525,37 @@ hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t
     }
     *out = reinterpret_cast<hq_handle>(P);
     return HQ_OK;
+}
+
+}  // namespace
+}  // namespace hq
+
+extern "C" {
+
+hq_status hq_build(const double *positions, const int64_t *body_offsets, int64_t m, const hq_options *opt,
+                   hq_stream stream, hq_handle *out) {
+    return build_handle(positions, body_offsets, m, opt, nullptr, 0, reinterpret_cast<hipStream_t>(stream), out);
+}
+
+hq_status hq_workspace_bytes(const int64_t *body_offsets, int64_t m, const hq_options *opt, size_t *bytes) {
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return HQ_E_INVALID;
+    }
+    *bytes = 0;
+    HQ_TRY(check_build_args(body_offsets, m, opt));
+    return workspace_size(body_offsets, m, opt, bytes);
+}
+
+hq_status hq_build_into(const double *positions, const int64_t *body_offsets, int64_t m, const hq_options *opt,
+                        void *workspace, size_t bytes, hq_stream stream, hq_handle *out) {
+    if (!workspace) {
+        if (out) *out = nullptr;
+        set_error("workspace is NULL");
+        return HQ_E_INVALID;
+    }
+    return build_handle(positions, body_offsets, m, opt, workspace, bytes, reinterpret_cast<hipStream_t>(stream),
+                        out);
 }
 
 hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int64_t m, int64_t nrhs,
@@ -555,8 +693,8 @@ hq_status hq_reserve(hq_handle h, int64_t nrhs, hq_precision prec) {
         set_error("nrhs must be >= 1 and prec HQ_FP64 or HQ_FP32");
         return HQ_E_INVALID;
     }
-    HQ_TRY(ensure_xch(*P, nrhs, prec, nullptr));
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_TRY(ensure_xch(*P, nrhs, prec, P->stream));
+    HQ_HIP(hipStreamSynchronize(P->stream));
     return HQ_OK;
 }
 
@@ -609,7 +747,7 @@ hq_status hq_node_phase(hq_handle h, int32_t *phase) {
         set_error("phase is NULL");
         return HQ_E_INVALID;
     }
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P->stream));
     HQ_HIP(hipMemcpy(phase, P->d_cov, P->NI * sizeof(int32_t), hipMemcpyDeviceToHost));
     return HQ_OK;
 }
@@ -710,7 +848,7 @@ hq_status read_body_nodes(Plan &P, int64_t body, BodyNodes &B, int64_t &nb, int6
     const int64_t n = P.offsets[body + 1] - nb;
     nin = n - 1;
     const int64_t g0 = nb - body;
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P.stream));
     B.lc.resize(nin);
     B.rc.resize(nin);
     B.nn.resize(nin);
@@ -781,8 +919,8 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
         ++b;
         val_off[b] = acc;
     }
-    int64_t *d_blk = nullptr;
-    HQ_HIP(hipMalloc(&d_blk, std::max<int64_t>(1, nin) * sizeof(int64_t)));
+    int64_t *d_blk = P->d_blk;  // the workspace's piece, else allocated for the call
+    if (!d_blk) HQ_HIP(hipMalloc(&d_blk, std::max<int64_t>(1, nin) * sizeof(int64_t)));
     hipError_t e = hipMemcpy(d_blk, blk_off.data(), nin * sizeof(int64_t), hipMemcpyHostToDevice);
     hq_status st = HQ_OK;
     if (e != hipSuccess) {
@@ -792,7 +930,7 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (st == HQ_OK) st = explicit_blocks_launch(*P, body, prec == HQ_FP64 ? 0 : 1, values, d_blk, s);
     const hipError_t se = hipStreamSynchronize(s);
-    (void)hipFree(d_blk);
+    if (d_blk != P->d_blk) (void)hipFree(d_blk);
     if (st == HQ_OK && se != hipSuccess) {
         set_error(std::string("hq_explicit_blocks: ") + hipGetErrorString(se));
         st = HQ_E_DEVICE;
@@ -809,7 +947,7 @@ hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index) {
     }
     const int64_t b0 = P->offsets[body], n = P->offsets[body + 1] - b0;
     std::vector<int32_t> tmp(n);
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P->stream));
     HQ_HIP(hipMemcpy(tmp.data(), P->d_perm + b0, n * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) bead_index[i] = tmp[i] - b0;
     return HQ_OK;
@@ -832,7 +970,7 @@ hq_status hq_query(hq_handle h, hq_info *info) {
         set_error("info is NULL");
         return HQ_E_INVALID;
     }
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P->stream));
     int32_t err = 0, cnt[kCntNum];
     HQ_HIP(hipMemcpy(&err, P->d_err, sizeof err, hipMemcpyDeviceToHost));
     HQ_HIP(hipMemcpy(cnt, P->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
@@ -865,7 +1003,7 @@ hq_status hq_query(hq_handle h, hq_info *info) {
 hq_status hq_body_info(hq_handle h, int32_t *flags, double *kappa) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P->stream));
     if (flags) HQ_HIP(hipMemcpy(flags, P->d_bflags, P->m * 4, hipMemcpyDeviceToHost));
     if (kappa) HQ_HIP(hipMemcpy(kappa, P->d_kappa, P->m * 8, hipMemcpyDeviceToHost));
     return HQ_OK;
@@ -880,7 +1018,7 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
         return HQ_E_INVALID;
     }
     const int64_t NI = P->NI;
-    HQ_HIP(hipDeviceSynchronize());
+    HQ_HIP(hipStreamSynchronize(P->stream));
     std::vector<int32_t> lc(NI), rc(NI), nbody(NI), fst(NI), lst(NI), nn(NI), sched(NI);
     HQ_HIP(hipMemcpy(lc.data(), P->d_lc, NI * 4, hipMemcpyDeviceToHost));
     HQ_HIP(hipMemcpy(rc.data(), P->d_rc, NI * 4, hipMemcpyDeviceToHost));

@@ -1417,7 +1417,11 @@ __global__ void k_rot_to_float(int64_t n, const double *__restrict__ in, float *
 }
 
 hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
-                       int layout, hipStream_t s, hipEvent_t *ev, const double *rot) {
+                       int layout, hipStream_t s, hipEvent_t *ev, const double *rot, void *xch, size_t xch_bytes) {
+    if (!xch) {
+        xch = P.d_xch;
+        xch_bytes = P.xch_bytes;
+    }
     Ctx C;
     C.m = (int)P.m;
     C.N = P.N;
@@ -1428,7 +1432,7 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     C.vcomp = (layout == HQ_TRIPLES) ? 1 : C.R;
     C.root_in = (root && transpose) ? 1 : 0;
     const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
-    C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(P.xch_bytes / (6 * elem * (size_t)nrhs)));
+    C.xch_cap = (int)std::min<int64_t>(INT32_MAX, (int64_t)(xch_bytes / (6 * elem * (size_t)nrhs)));
     // the wide sweeps address each buffer with 32-bit byte offsets below 2 GiB
     const int64_t vin = (transpose ? P.rows : 3 * P.N) * nrhs * (int64_t)elem;
     const int64_t vout = (transpose ? 3 * P.N : P.rows) * nrhs * (int64_t)elem;
@@ -1459,10 +1463,10 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     // turns the vectors in separate passes for the narrow ones
     if (rot && !wide) return HQ_E_UNSUPPORTED;
     if (prec == HQ_FP64) {
-        if (root && transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 1, C, s);
-        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)P.d_xch, rot, C,
+        if (root && transpose) launch_root_io<double>(P, wide, (double *)xch, (double *)root, 1, C, s);
+        launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)xch, rot, C,
                            s, ev);
-        if (root && !transpose) launch_root_io<double>(P, wide, (double *)P.d_xch, (double *)root, 0, C, s);
+        if (root && !transpose) launch_root_io<double>(P, wide, (double *)xch, (double *)root, 0, C, s);
     } else {
         const float *rotf = nullptr;
         if (rot) {
@@ -1470,10 +1474,10 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
                                9 * P.m, rot, P.d_rotf);
             rotf = P.d_rotf;
         }
-        if (root && transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 1, C, s);
-        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)P.d_xch, rotf, C, s,
+        if (root && transpose) launch_root_io<float>(P, wide, (float *)xch, (float *)root, 1, C, s);
+        launch_all<float>(P, transpose, kind, P.d_rec32, (const float *)v, (float *)out, (float *)xch, rotf, C, s,
                           ev);
-        if (root && !transpose) launch_root_io<float>(P, wide, (float *)P.d_xch, (float *)root, 0, C, s);
+        if (root && !transpose) launch_root_io<float>(P, wide, (float *)xch, (float *)root, 0, C, s);
     }
     HQ_HIP(hipGetLastError());
     return HQ_OK;

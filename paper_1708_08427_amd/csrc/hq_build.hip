@@ -878,7 +878,6 @@ __global__ void __launch_bounds__(256) k_len_scatter(int phase, const int32_t *p
 // node is computed, the children of the next node and the links of the one
 // after it are in flight.
 // ---------------------------------------------------------------------------
-constexpr int kGenWords = 10;  // n, c[3], T22[6] per LDS slot and lane, and per tile root
 constexpr int kStageStride = 36;  // words per lane row of the record staging area (144 B)
 constexpr size_t kStageBytes = (size_t)64 * kStageStride * 4 + 64 * 4;  // rows + schedule offsets
 
@@ -1372,7 +1371,11 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     // --- 5. transforms, one launch per tile phase; later phases read the
     // roots of earlier phases' tiles from the tile-root table (sized after
     // the first build: twice its tiles, the capacity of the exchange buffer)
-    if (probe_phases && P.troot_cap < 2 * P.tiles_built + 64) {
+    if (probe_phases && P.ws && P.troot_cap < P.tiles_built + 64) {
+        set_error("the tree has more tiles than the workspace holds (hq_options.max_tiles)");
+        return HQ_E_UNSUPPORTED;
+    }
+    if (probe_phases && !P.ws && P.troot_cap < 2 * P.tiles_built + 64) {
         const int64_t cap = 2 * P.tiles_built + 64;
         void *q = nullptr;
         hipError_t e = hipMalloc(&q, (size_t)cap * kGenWords * sizeof(double));

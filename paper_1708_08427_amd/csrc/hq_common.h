@@ -20,6 +20,7 @@ constexpr int kMaxTileUnits = 1024;     // largest tile (units) supported
 constexpr int kMaxPhases = 64;          // phase table capacity
 constexpr int kRecWords = 32;           // elements (float or double) per node record
 constexpr int kMaxDepth = 256;          // bound on tree depth walks (63 code bits + 32 index bits)
+constexpr int kGenWords = 10;           // n, c[3], T22[6] per LDS slot and lane, and per tile root
 
 // A node record (one per internal node, in schedule order) holds the three
 // Householder reflectors of G in a zero-padded length-9 layout, the two
@@ -227,8 +228,26 @@ struct Plan {
     float *d_rotf = nullptr;  // m x 9: the FP32 copy of a rigid-motion rotation table
     size_t xch_bytes = 0;
 
+    // Device memory comes either from hipMalloc, one allocation per buffer
+    // (hq_build; the handle frees them), or from one caller-owned workspace
+    // carved into aligned pieces (hq_build_into; nothing is allocated, and
+    // requests beyond the reserved sizes fail instead of growing a buffer).
+    // sizing: only count the bytes the pieces take (hq_workspace_bytes).
+    bool sizing = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
+    int64_t *d_blk = nullptr;        // workspace: explicit-block offsets (max_n entries)
+    void *d_kry = nullptr;           // workspace: Krylov vectors and scalars
+    size_t kry_bytes = 0;
+    hipStream_t stream = nullptr;    // the stream of hq_build / hq_build_into
+
     std::vector<void *> allocs;
 };
+
+// The plan behind a handle (nullptr, with the error set, for an invalid one).
+Plan *plan_of(hq_handle h);
+// Device memory of a handle: count elements from its workspace, or allocate.
+hq_status plan_alloc(Plan &P, void **p, size_t bytes);
 
 constexpr uint32_t kPlanMagic = 0x48514c42u;  // "HQLB"
 
@@ -263,12 +282,16 @@ hq_status scan_i64_exclusive(Plan &P, const long long *in, long long *out, int64
 hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_phases);
 // rot: each body's rigid-motion rotation (m x 9 FP64, device) fused into the
 // wide sweeps; HQ_E_UNSUPPORTED (nothing launched) when the sweeps are narrow
+// xch, xch_bytes: the exchange buffer of the sweeps (nullptr: the handle's own)
 hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transpose, int64_t nrhs, int prec,
-                       int layout, hipStream_t s, hipEvent_t *ev = nullptr, const double *rot = nullptr);
+                       int layout, hipStream_t s, hipEvent_t *ev = nullptr, const double *rot = nullptr,
+                       void *xch = nullptr, size_t xch_bytes = 0);
 hq_status explicit_dense(Plan &P, int64_t body, double *out, int64_t ld, hipStream_t s);
 hq_status explicit_blocks_launch(Plan &P, int64_t body, int prec, void *values, const int64_t *d_blk_off,
                                  hipStream_t s);
 int64_t scan_blocks_needed(int64_t n);
+// device bytes of the Krylov solve's work vectors and scalars
+size_t krylov_bytes(int64_t rows, int64_t nrhs, size_t elem);
 int lanes_per_tile(int64_t nrhs);
 hq_status rigid_update(Plan &P, double *pos, const double *rot, const double *trans, hipStream_t s);
 // in or out times blockdiag(Rot_j^T) (transpose = 1) or blockdiag(Rot_j) per body; in may equal out

@@ -89,15 +89,26 @@ __global__ void k_neg(int64_t n, const T *__restrict__ x, T *y) {
 
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kKThreads - 1) / kKThreads, 8192)); }
 
+// Work vectors: carved from a piece of the handle's workspace (hq_build_into
+// with krylov_nrhs), else allocated for the call and freed at its end.
 struct Work {
     std::vector<void *> bufs;
+    char *base = nullptr;
+    size_t used = 0, cap = 0;
     ~Work() {
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
     void *get(size_t bytes) {
+        bytes = (std::max<size_t>(bytes, 16) + 255) / 256 * 256;
+        if (base) {
+            if (used + bytes > cap) return nullptr;
+            void *p = base + used;
+            used += bytes;
+            return p;
+        }
         void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) return nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
         bufs.push_back(p);
         return p;
     }
@@ -115,6 +126,17 @@ hq_status solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, voi
     const int max_iter = info->max_iter > 0 ? info->max_iter : 500;
     const double rtol = info->rtol > 0 ? info->rtol : 1e-8;
     Work w;
+    Plan *P = plan_of(h);
+    if (!P) return HQ_E_INVALID;
+    if (P->ws) {
+        if (!P->d_kry || P->kry_bytes < krylov_bytes(q.rows, nrhs, sizeof(T))) {
+            set_error("the handle's workspace holds no Krylov vectors for nrhs right-hand sides "
+                      "(hq_options.krylov_nrhs)");
+            return HQ_E_UNSUPPORTED;
+        }
+        w.base = (char *)P->d_kry;
+        w.cap = P->kry_bytes;
+    }
     T *r = (T *)w.get(nr * sizeof(T)), *p = (T *)w.get(nr * sizeof(T)), *Ap = (T *)w.get(nr * sizeof(T));
     T *zr = (T *)w.get(nr * sizeof(T));
     double *dots = (double *)w.get(2 * (size_t)R * sizeof(double)), *coef = (double *)w.get((size_t)R * sizeof(double));
@@ -205,6 +227,13 @@ hq_status solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, voi
 }
 
 }  // namespace
+
+// four vectors of rows x nrhs and 3 nrhs FP64 scalars, each piece 256-byte aligned
+size_t krylov_bytes(int64_t rows, int64_t nrhs, size_t elem) {
+    auto a = [](size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; };
+    return 4 * a((size_t)rows * nrhs * elem) + a(2 * (size_t)nrhs * sizeof(double)) + a((size_t)nrhs * sizeof(double));
+}
+
 }  // namespace hq
 
 using namespace hq;

@@ -81,3 +81,21 @@ def test_bad_options_rejected(lib):
         st = lib.hq_build(ctypes.c_void_p(1), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1,
                           ctypes.byref(opt), None, ctypes.byref(h))
         assert st == 1
+
+
+def test_workspace_bytes_host_only():
+    """hq_workspace_bytes needs no device: it only sizes the pieces."""
+    import paper_1708_08427_amd as hq
+    off = np.array([0, 500, 1700, 1702], dtype=np.int64)
+    base = hq.workspace_bytes(off)
+    assert base > 0 and base % 256 == 0
+    # exchange entries grow with max_nrhs and the tile bound, Krylov vectors
+    # appear with krylov_nrhs, a smaller tile bound shrinks the tables
+    assert hq.workspace_bytes(off, max_nrhs=64) > base
+    assert hq.workspace_bytes(off, krylov_nrhs=4) > base
+    assert hq.workspace_bytes(off, max_tiles=16) < base
+    assert hq.workspace_bytes(off, store=2) < hq.workspace_bytes(off, store=3)
+    with pytest.raises(hq.HQError):
+        hq.workspace_bytes([0, 1])
+    with pytest.raises(hq.HQError):
+        hq.workspace_bytes(off, max_nrhs=-1)

@@ -135,13 +135,22 @@ def test_bd_step_workload_sampled_bodies(hq):
     out32 = h.apply(h.apply(_dev(f, torch.float32)), transpose=True).cpu().numpy().astype(np.float64)
     assert h.query()["device_flags"] == 0
     sample = np.random.default_rng(7).choice(w.m, 24, replace=False)
+    checked = 0
     for j in sample:
         b0, b1 = w.offsets[j], w.offsets[j + 1]
         bo = hier.Body(p[b0:b1])
         ref = bo.apply(bo.apply(f[3 * b0:3 * b1]), transpose=True)
-        assert _rel(out64[3 * b0:3 * b1], ref) <= 1e-12 or bo.max_kappa > 1e4
+        if bo.max_kappa <= 1e4:
+            assert _rel(out64[3 * b0:3 * b1], ref) <= 1e-12
+            checked += 1
+        else:
+            # basis not unique beyond rounding: the projector is
+            want = dense.project(p[b0:b1], f[3 * b0:3 * b1])
+            assert np.abs(out64[3 * b0:3 * b1] - want).max() <= 1e-12 * np.abs(f[3 * b0:3 * b1]).max()
         e32 = np.linalg.norm(out32[3 * b0:3 * b1] - ref, axis=0) / np.linalg.norm(f[3 * b0:3 * b1], axis=0)
         assert e32.max() <= 1e-5
+    print(f"[gpu] element-wise parity on {checked} of {len(sample)} sampled bodies", flush=True)
+    assert checked >= 20
     for j in range(0, w.m, 97):
         b0, b1 = w.offsets[j], w.offsets[j + 1]
         assert dense.leak_large(p[b0:b1], out32[3 * b0:3 * b1]).max() <= 1e-5

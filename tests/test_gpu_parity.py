@@ -59,7 +59,7 @@ def oracle_products(w, v, wv):
     return bt, bt.apply(v), bt.apply(wv, transpose=True)
 
 
-def check_fp64(hq, w, S=0, nrhs=None, S2=0):
+def check_fp64(hq, w, S=0, nrhs=None, S2=0, min_checked=None):
     rng = np.random.default_rng(123)
     R = nrhs or w.nrhs
     v = rng.standard_normal((3 * w.N, R))
@@ -71,10 +71,20 @@ def check_fp64(hq, w, S=0, nrhs=None, S2=0):
     assert h.query()["device_flags"] == 0
     rows = h.row_offsets
     beads3 = 3 * w.offsets
-    ill = np.array([b.max_kappa > 1e4 for b in bt.bodies])
-    if not ill.any():
-        assert rel_per_body(up, up_o, w.offsets, rows) <= 1e-12
-        assert rel_per_body(dn, dn_o, w.offsets, beads3) <= 1e-12
+    # element-wise parity body by body; a body with an ill-conditioned node
+    # (its basis is fixed only up to rounding) is compared on the projector
+    # below instead
+    checked = 0
+    for j, b in enumerate(bt.bodies):
+        if b.max_kappa > 1e4:
+            continue
+        r0, r1, b0, b1 = rows[j], rows[j + 1], beads3[j], beads3[j + 1]
+        if r1 > r0:
+            assert rel_per_body(up[r0:r1], up_o[r0:r1], [0, 1], [0, r1 - r0]) <= 1e-12, j
+            assert rel_per_body(dn[b0:b1], dn_o[b0:b1], [0, 1], [0, b1 - b0]) <= 1e-12, j
+        checked += 1
+    print(f"[gpu] element-wise parity on {checked} of {w.m} bodies", flush=True)
+    assert checked >= min_checked if min_checked is not None else checked == w.m
     # projector round trip per body is basis-free
     pr = h.apply(h.apply(_dev(v)), transpose=True).cpu().numpy()
     for j in range(w.m):

@@ -211,3 +211,54 @@ def small_batch(seed, sizes, axes_lo=10.0, axes_hi=50.0, box=100.0, nrhs=1):
         parts.append(ellipsoid_body(rng, int(n), axes, center=off))
     pos = np.concatenate(parts, axis=0) if parts else np.zeros((0, 3))
     return Workload(f"small_batch_{seed}", pos, offsets_from_sizes(sizes), nrhs, rng)
+
+
+# --------------------------------------------------------------------------
+# degenerate and edge-case bodies (Section 2.2: collinear beads make Z rank 5;
+# coincident beads share their finest box)
+# --------------------------------------------------------------------------
+
+
+def collinear_body(rng, n, length=30.0, center=(0.0, 0.0, 0.0)):
+    """n beads at uniform positions along a random line segment."""
+    d = unit_vectors(rng, 1)[0]
+    t = rng.uniform(0.0, length, n)
+    return np.asarray(center, dtype=np.float64) + t[:, None] * d[None, :]
+
+
+def with_duplicates(rng, pos, ndup, group=1):
+    """``pos`` plus ``ndup`` groups of ``group`` exact copies of randomly
+    chosen beads, the whole body in a random bead order."""
+    src = rng.choice(len(pos), ndup, replace=False)
+    extra = np.repeat(pos[src], group, axis=0)
+    allp = np.concatenate([pos, extra], axis=0)
+    return allp[rng.permutation(len(allp))]
+
+
+def mixed_batch(seed, parts, nrhs=1):
+    """A batch of bodies from (kind, n) parts: "ellipsoid" (batched geometry),
+    "collinear", "duplicates" (an ellipsoid body of n beads of which n // 5 are
+    exact copies of others), "cluster" (an ellipsoid body with one point
+    holding n // 10 coincident beads), "point" (all n beads at one point)."""
+    rng = np.random.default_rng(seed)
+    out, sizes = [], []
+    for kind, n in parts:
+        off = rng.uniform(0.0, 100.0, 3)
+        if kind == "ellipsoid":
+            p = ellipsoid_body(rng, n, rng.uniform(10.0, 50.0, 3), center=off)
+        elif kind == "collinear":
+            p = collinear_body(rng, n, center=off)
+        elif kind == "duplicates":
+            base = ellipsoid_body(rng, n - n // 5, rng.uniform(10.0, 50.0, 3), center=off)
+            p = with_duplicates(rng, base, n // 5)
+        elif kind == "cluster":
+            base = ellipsoid_body(rng, n - n // 10 + 1, rng.uniform(10.0, 50.0, 3), center=off)
+            p = with_duplicates(rng, base, 1, group=n // 10 - 1)
+        elif kind == "point":
+            p = np.repeat(off[None, :], n, axis=0)
+        else:
+            raise ValueError(kind)
+        assert len(p) == n
+        out.append(p)
+        sizes.append(n)
+    return Workload(f"mixed_{seed}", np.concatenate(out, axis=0), offsets_from_sizes(sizes), nrhs, rng)
