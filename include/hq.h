@@ -236,6 +236,24 @@ hq_status hq_apply(hq_handle h, const void *v, void *out, int transpose, int64_t
 hq_status hq_apply_layout(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
                           hq_precision prec, hq_layout layout, hq_stream stream);
 
+/* hq_apply_layout for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same products from the same kernels, with the sweeps' exchange buffer
+ * (one entry of 6 x nrhs values per tile, passing Info-sets and
+ * Velocity-sets between tile phases) in a static device array of 128 MiB
+ * instead of the handle's own, growable buffer.  No hipMalloc, hipFree or
+ * other allocation; each GPU the library runs on holds its array until the
+ * process ends.  Nothing in the array needs clearing between calls (every
+ * entry a sweep reads was written earlier in the same call), but all calls on
+ * one GPU share it: calls that overlap in time on one GPU (other streams,
+ * other handles, other threads) race and give wrong results.
+ * HQ_E_UNSUPPORTED when (tiles of the handle's hq_build + 64) x 6 x nrhs
+ * elements exceed 128 MiB (e.g. beyond 174,000 tiles at 32 FP32 right-hand
+ * sides); a rebuilt tree with more tiles than that raises HQ_FLAG_BOUNDS.
+ * Other errors as for hq_apply_layout. */
+hq_status hq_apply_noalloc(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs,
+                           hq_precision prec, hq_layout layout, hq_stream stream);
+
 /* The full orthogonal Q = [Q_Z; Q~] of every body (Algorithms 2 and 3 with
  * the root kept; Q_Z's six rows span the row space of Z, Eq. 1.2).
  *   transpose = 0: out = Q~ v as hq_apply_layout, and root receives Q_Z v,

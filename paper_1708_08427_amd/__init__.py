@@ -131,11 +131,13 @@ class Handle:
             pass
 
     # -- products ---------------------------------------------------------
-    def apply(self, v, transpose=False, out=None, stream=None, timed=False, layout="rows"):
+    def apply(self, v, transpose=False, out=None, stream=None, timed=False, layout="rows", noalloc=False):
         """Q~ v (v: 3N x R) or Q~^T w (w: rows x R); R = 1 for a 1-D v.
         layout="triples": v and out are (rows / 3, R, 3) tensors, row triple
         t's right-hand side r at [t, r, :] (hq_apply_layout, HQ_TRIPLES).
-        With timed=True returns (out, per-phase launch ms) via hq_apply_timed."""
+        With timed=True returns (out, per-phase launch ms) via hq_apply_timed.
+        noalloc=True calls hq_apply_noalloc (the library allocates nothing;
+        pass ``out`` to allocate nothing here either)."""
         torch = _torch()
         _check_dev(v, "v")
         if layout not in LAYOUTS:
@@ -175,8 +177,8 @@ class Handle:
                                       lay, _stream(stream), ms, 64, ctypes.byref(nph)), "hq_apply_timed")
             res = out.reshape(nout) if squeeze else out
             return res, [ms[i] for i in range(nph.value)]
-        _check(lib.hq_apply_layout(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype), lay,
-                                   _stream(stream)), "hq_apply_layout")
+        fn, name = (lib.hq_apply_noalloc, "hq_apply_noalloc") if noalloc else (lib.hq_apply_layout, "hq_apply_layout")
+        _check(fn(self._h(), _ptr(v2), _ptr(out), int(bool(transpose)), R, _prec(v.dtype), lay, _stream(stream)), name)
         return out.reshape(nout) if squeeze else out
 
     def apply_full(self, v, transpose=False, root=None, out=None, stream=None, layout="rows"):

@@ -55,6 +55,7 @@ SIGNATURES = [
     ("hq_reserve", c_i32, [c_vp, c_i64, c_i32]),
     ("hq_apply", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_vp]),
     ("hq_apply_layout", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
+    ("hq_apply_noalloc", c_i32, [c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
     ("hq_apply_full", c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
     ("hq_apply_rotated", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_int, c_i64, c_i32, c_i32, c_vp]),
     ("hq_constrained_solve", c_i32, [c_vp, DAPPLY_FN, c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "hq_common.h"
@@ -357,12 +358,69 @@ hq_status hq_apply_checked(Plan &P, const void *v, void *out, void *root, int tr
     return apply_device(P, v, out, root, transpose, nrhs, prec, layout, s, ev);
 }
 
+// ---------------------------------------------------------------------------
+// The exchange buffer of hq_apply_noalloc: one static array per device, so
+// that the call allocates nothing.  In host code the name `scratch` is only a
+// stand-in for the symbol; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hq_status scratch_address(void **out) {
+    int dev = 0;
+    HQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the static exchange table");
+        return HQ_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress of the static exchange buffer: ") + hipGetErrorString(e));
+            return HQ_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HQ_OK;
+}
+
 }  // namespace
 }  // namespace hq
 
 using namespace hq;
 
 extern "C" {
+
+hq_status hq_apply_noalloc(hq_handle h, const void *v, void *out, int transpose, int64_t nrhs, hq_precision prec,
+                           hq_layout layout, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    HQ_TRY(check_apply(*P, v, out, nullptr, transpose, nrhs, prec, layout));
+    // one exchange entry (6 nrhs values) per tile, with the same margin of 64
+    // entries as the handle's own buffer for trees rebuilt with more tiles
+    const size_t elem = (prec == HQ_FP64) ? sizeof(double) : sizeof(float);
+    const double need = (double)(P->tiles_built + 64) * 6.0 * (double)nrhs * (double)elem;
+    if (need > (double)kScratchBytes) {
+        set_error("hq_apply_noalloc: the exchange buffer needs " + std::to_string((long long)need) +
+                  " bytes (tiles x 6 x nrhs values), above the static limit of " + std::to_string(kScratchBytes) +
+                  "; use hq_apply_layout");
+        return HQ_E_UNSUPPORTED;
+    }
+    void *xch = nullptr;
+    HQ_TRY(scratch_address(&xch));
+    return apply_device(*P, v, out, nullptr, transpose, nrhs, prec, layout, reinterpret_cast<hipStream_t>(stream),
+                        nullptr, nullptr, xch, kScratchBytes);
+}
 
 const char *hq_last_error(void) { return g_last_error.c_str(); }
 
