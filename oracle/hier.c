@@ -14,7 +14,7 @@
  *
  *   tree      Section 2.1 and its binary-tree comment: nested cubical boxes,
  *             split at midpoints in z, then y, then x, empty halves pruned,
- *             leaves hold one bead (s = 1).
+ *             until a box holds at most s beads (a leaf; s = 1 by default).
  *   Q_gen     Algorithm 1 with Eqs. 3.4-3.8: per internal node p with children
  *             x, y the 3 x k matrix K = [R22 | S22 | sqrt(n_x n/n_y) R21] is
  *             factored K = [T22 | 0] G with G orthogonal (a QR of K^T); the
@@ -66,11 +66,15 @@ typedef struct {
     double G[9][9];        /* k x k orthogonal */
     double sx, sy;         /* sqrt(n_x/n), sqrt(n_y/n) */
     int64_t off;           /* first residue row of this node in Q~ */
-    double kappa;          /* sigma_1 / sigma_3 of T22 (k > 3 nodes) */
+    double kappa;          /* sigma_1 / sigma_3 of T22 (k > 3 nodes, buckets of 3 or more) */
+    int bucket;            /* 1: a leaf box of 2..s beads (no children) */
+    double *hv;            /* bucket: the 6 Householder vectors, 3n x 6, column-major */
+    double htau[6];        /* bucket: their taus */
 } onode;
 
 typedef struct or_body {
     int64_t n;
+    int64_t s;             /* leaf size: boxes of at most s beads are leaves */
     double *r;             /* body-local positions, user order, n x 3 */
     uint64_t *code;        /* user order */
     int64_t *perm;         /* sorted position -> user index */
@@ -166,9 +170,15 @@ static int64_t build_rec(or_body *B, int64_t lo, int64_t hi)
 {
     if (lo == hi) return -(lo + 1);
     int64_t id = B->nint++;
-    int64_t s = split_of(B, lo, hi);
     B->nodes[id].first = lo;
     B->nodes[id].last = hi;
+    if (hi - lo + 1 <= B->s) {
+        /* a box of 2..s beads is a leaf (a bucket) */
+        B->nodes[id].bucket = 1;
+        B->nodes[id].x = B->nodes[id].y = -1;
+        return id;
+    }
+    int64_t s = split_of(B, lo, hi);
     int64_t x = build_rec(B, lo, s);
     int64_t y = build_rec(B, s + 1, hi);
     B->nodes[id].x = x;
@@ -270,10 +280,110 @@ static double cond3(double T[3][3])
     return sqrt(mx / mn);
 }
 
+/* A leaf box of n = 2..s beads (Section 2.1 allows leaves of more than one
+   bead; the paper leaves their processing open).  Reading: the leaf's Z about
+   its centroid c has the translation rows U_t = [I ... I] / sqrt(n) and the
+   rotation rows Z_r = [A_1 ... A_n] with A_k = [r_k - c]x, orthogonal to U_t.
+   A Householder QR (the convention above) of the 3n x 6 matrix
+   X = [U_t^T | Z_r^T] gives X = Q [R; 0] with R(1:3,1:3) = -I (U_t^T has
+   orthonormal columns, and each pivot is positive) and R(1:3,4:6) = 0.
+   The leaf's orthogonal transform is G = diag(-1,-1,-1,1,...,1) Q^T: its rows
+   1-3 are U_t, its rows 4-6 the rotation rows with Z_r = R(4:6,4:6)^T G(4:6,:),
+   so T22 = R(4:6,4:6)^T (lower triangular) as for a node, and its rows 7..3n
+   are the leaf's 3n - 6 residue rows.  A two-bead leaf has a rank-2 Z_r: its
+   T22(3,3) is set to the exact 0 (as Eq. 3.9 for two beads). */
+static void gen_bucket(or_body *B, onode *p)
+{
+    int64_t n = p->last - p->first + 1, m = 3 * n;
+    p->n = n;
+    for (int d = 0; d < 3; ++d) p->c[d] = 0.0;
+    for (int64_t b = 0; b < n; ++b)
+        for (int d = 0; d < 3; ++d) p->c[d] += B->r[3 * B->perm[p->first + b] + d];
+    for (int d = 0; d < 3; ++d) p->c[d] /= (double)n;
+    double *X = (double *)calloc((size_t)(m * 6), sizeof(double));   /* column-major m x 6 */
+    double rs = 1.0 / sqrt((double)n);
+    for (int64_t b = 0; b < n; ++b) {
+        double u[3], A[3][3];
+        for (int d = 0; d < 3; ++d) u[d] = B->r[3 * B->perm[p->first + b] + d] - p->c[d];
+        cross_matrix(u, A);
+        for (int d = 0; d < 3; ++d) {
+            X[d * m + 3 * b + d] = rs;                            /* U_t^T */
+            for (int e = 0; e < 3; ++e) X[(3 + e) * m + 3 * b + d] = A[e][d];   /* Z_r^T = A_b^T */
+        }
+    }
+    for (int j = 0; j < 6; ++j) {
+        double *col = X + j * m;
+        double alpha = col[j], xs = 0.0;
+        for (int64_t i = j + 1; i < m; ++i) xs += col[i] * col[i];
+        double xnorm = sqrt(xs);
+        if (xnorm == 0.0 || j >= m - 1) {
+            p->htau[j] = 0.0;
+            for (int64_t i = j + 1; i < m; ++i) col[i] = 0.0;
+            continue;
+        }
+        const double nrm = sqrt(alpha * alpha + xnorm * xnorm);
+        const double beta = (alpha >= 0.0) ? -nrm : nrm;
+        p->htau[j] = (beta - alpha) / beta;
+        double scal = 1.0 / (alpha - beta);
+        for (int64_t i = j + 1; i < m; ++i) col[i] *= scal;   /* v = [1; x / (alpha - beta)] */
+        col[j] = beta;
+        for (int l = j + 1; l < 6; ++l) {
+            double *cl = X + l * m, w = cl[j];
+            for (int64_t i = j + 1; i < m; ++i) w += col[i] * cl[i];
+            w *= p->htau[j];
+            cl[j] -= w;
+            for (int64_t i = j + 1; i < m; ++i) cl[i] -= w * col[i];
+        }
+    }
+    /* T22 = R(4:6,4:6)^T */
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) p->T22[i][j] = (j <= i) ? X[(3 + i) * m + 3 + j] : 0.0;
+    if (n == 2) p->T22[2][2] = 0.0;
+    p->hv = X;
+    p->k = 0;
+    p->dim = (int)(m - 6);
+    p->sx = p->sy = 0.0;
+    p->kappa = (n >= 3) ? cond3(p->T22) : 0.0;
+}
+
+/* t <- Q^T t = H_6 ... H_1 t for a bucket (t: 3n values) */
+static void bucket_qt(const onode *p, double *t)
+{
+    int64_t m = 3 * p->n;
+    for (int j = 0; j < 6; ++j) {
+        if (p->htau[j] == 0.0) continue;
+        const double *v = p->hv + j * m;
+        double w = t[j];
+        for (int64_t i = j + 1; i < m; ++i) w += v[i] * t[i];
+        w *= p->htau[j];
+        t[j] -= w;
+        for (int64_t i = j + 1; i < m; ++i) t[i] -= w * v[i];
+    }
+}
+
+/* t <- Q t = H_1 ... H_6 t */
+static void bucket_q(const onode *p, double *t)
+{
+    int64_t m = 3 * p->n;
+    for (int j = 5; j >= 0; --j) {
+        if (p->htau[j] == 0.0) continue;
+        const double *v = p->hv + j * m;
+        double w = t[j];
+        for (int64_t i = j + 1; i < m; ++i) w += v[i] * t[i];
+        w *= p->htau[j];
+        t[j] -= w;
+        for (int64_t i = j + 1; i < m; ++i) t[i] -= w * v[i];
+    }
+}
+
 /* Algorithm 1 (generation part): post-order over the tree. */
 static void gen_rec(or_body *B, int64_t id)
 {
     onode *p = &B->nodes[id];
+    if (p->bucket) {
+        gen_bucket(B, p);
+        return;
+    }
     int64_t nx, ny;
     double cx[3], cy[3];
     int xin = p->x >= 0, yin = p->y >= 0;
@@ -337,6 +447,7 @@ static int64_t offsets_rec(or_body *B, int64_t id, int64_t off)
     onode *p = &B->nodes[id];
     p->off = off;
     off += p->dim;
+    if (p->bucket) return off;
     if (p->x >= 0) off = offsets_rec(B, p->x, off);
     if (p->y >= 0) off = offsets_rec(B, p->y, off);
     return off;
@@ -349,16 +460,19 @@ static int64_t offsets_rec(or_body *B, int64_t id, int64_t off)
 void or_free(or_body *B)
 {
     if (!B) return;
+    for (int64_t i = 0; i < B->nint; ++i) free(B->nodes[i].hv);
     free(B->r); free(B->code); free(B->perm); free(B->scode); free(B->nodes);
     free(B);
 }
 
-/* pos: n x 3 FP64 positions of one body in user order.  NULL when n < 2. */
-or_body *or_build(const double *pos, int64_t n)
+/* pos: n x 3 FP64 positions of one body in user order; leaves of at most s
+   beads (s >= 1).  NULL when n < 2 or s < 1. */
+or_body *or_build_s(const double *pos, int64_t n, int64_t s)
 {
-    if (n < 2) return NULL;
+    if (n < 2 || s < 1) return NULL;
     or_body *B = (or_body *)calloc(1, sizeof *B);
     B->n = n;
+    B->s = s;
     B->r = (double *)malloc(sizeof(double) * 3 * n);
     B->code = (uint64_t *)malloc(sizeof(uint64_t) * n);
     B->perm = (int64_t *)malloc(sizeof(int64_t) * n);
@@ -382,6 +496,8 @@ or_body *or_build(const double *pos, int64_t n)
     return B;
 }
 
+or_body *or_build(const double *pos, int64_t n) { return or_build_s(pos, n, 1); }
+
 int64_t or_n(const or_body *B) { return B->n; }
 int64_t or_rows(const or_body *B) { return 3 * B->n - 6; }
 int64_t or_num_internal(const or_body *B) { return B->nint; }
@@ -401,7 +517,7 @@ void or_tree(const or_body *B, int64_t *first, int64_t *last, int64_t *split)
         const onode *p = &B->nodes[i];
         first[i] = p->first;
         last[i] = p->last;
-        split[i] = (p->x >= 0) ? B->nodes[p->x].last : -(p->x + 1);
+        split[i] = p->bucket ? -1 : ((p->x >= 0) ? B->nodes[p->x].last : -(p->x + 1));
     }
 }
 
@@ -413,14 +529,14 @@ double or_max_kappa(const or_body *B)
     return m;
 }
 
-/* Per-node record for tests: ints = {first, last, x, y, n, k, dim, off},
+/* Per-node record for tests: ints = {first, last, x, y, n, k, dim, off, bucket},
    dbl = {c[3], T22[9] row-major, sx, sy, kappa, G[81] row-major (k x k in the
    top-left corner)} = 96 doubles. */
 void or_node(const or_body *B, int64_t id, int64_t *ints, double *dbl)
 {
     const onode *p = &B->nodes[id];
     ints[0] = p->first; ints[1] = p->last; ints[2] = p->x; ints[3] = p->y;
-    ints[4] = p->n; ints[5] = p->k; ints[6] = p->dim; ints[7] = p->off;
+    ints[4] = p->n; ints[5] = p->k; ints[6] = p->dim; ints[7] = p->off; ints[8] = p->bucket;
     for (int d = 0; d < 3; ++d) dbl[d] = p->c[d];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) dbl[3 + 3 * i + j] = p->T22[i][j];
     dbl[12] = p->sx; dbl[13] = p->sy; dbl[14] = p->kappa;
@@ -436,6 +552,19 @@ static void up_rec(const or_body *B, int64_t id, const double *v, double *out,
                    double *Mall, double M[6])
 {
     const onode *p = &B->nodes[id];
+    if (p->bucket) {
+        /* [M; eps] = G f with G = diag(-1,-1,-1,1,...) Q^T over the leaf's beads */
+        int64_t m = 3 * p->n;
+        double *t = (double *)malloc(sizeof(double) * (size_t)m);
+        for (int64_t b = 0; b < p->n; ++b)
+            for (int d = 0; d < 3; ++d) t[3 * b + d] = v[3 * B->perm[p->first + b] + d];
+        bucket_qt(p, t);
+        for (int d = 0; d < 3; ++d) { M[d] = -t[d]; M[3 + d] = t[3 + d]; }
+        for (int64_t i = 0; i < p->dim; ++i) out[p->off + i] = t[6 + i];
+        free(t);
+        if (Mall) for (int d = 0; d < 6; ++d) Mall[6 * id + d] = M[d];
+        return;
+    }
     double Mx[6] = {0}, My[6] = {0};
     if (p->x >= 0) up_rec(B, p->x, v, out, Mall, Mx);
     else { int64_t u = B->perm[-(p->x + 1)]; for (int d = 0; d < 3; ++d) Mx[d] = v[3 * u + d]; }
@@ -468,6 +597,18 @@ static void up_rec(const or_body *B, int64_t id, const double *v, double *out,
 static void down_rec(const or_body *B, int64_t id, const double L[6], const double *w, double *out)
 {
     const onode *p = &B->nodes[id];
+    if (p->bucket) {
+        /* f = G^T [L; w_p] = Q diag(-1,-1,-1,1,...) [L; w_p] */
+        int64_t m = 3 * p->n;
+        double *t = (double *)malloc(sizeof(double) * (size_t)m);
+        for (int d = 0; d < 3; ++d) { t[d] = -L[d]; t[3 + d] = L[3 + d]; }
+        for (int64_t i = 0; i < p->dim; ++i) t[6 + i] = w[p->off + i];
+        bucket_q(p, t);
+        for (int64_t b = 0; b < p->n; ++b)
+            for (int d = 0; d < 3; ++d) out[3 * B->perm[p->first + b] + d] = t[3 * b + d];
+        free(t);
+        return;
+    }
     int k = p->k;
     double in[9], s[9];
     for (int d = 0; d < 3; ++d) in[d] = L[3 + d];
@@ -546,6 +687,20 @@ static void expl_rec(const or_body *B, int64_t id, double *U, double *Qs)
 {
     const onode *p = &B->nodes[id];
     int64_t np = p->n, ncol = 3 * np;
+    if (p->bucket) {
+        /* rows of G = diag(-1,-1,-1,1,...) Q^T: column c is Q^T e_c; rows
+           4-6 are U, rows 7.. the residue rows */
+        int64_t ncolQ = 3 * B->n;
+        double *t = (double *)malloc(sizeof(double) * (size_t)ncol);
+        for (int64_t c = 0; c < ncol; ++c) {
+            for (int64_t i = 0; i < ncol; ++i) t[i] = (i == c) ? 1.0 : 0.0;
+            bucket_qt(p, t);
+            for (int i = 0; i < 3; ++i) U[i * ncol + c] = t[3 + i];
+            for (int64_t i = 0; i < p->dim; ++i) Qs[(p->off + i) * ncolQ + 3 * p->first + c] = t[6 + i];
+        }
+        free(t);
+        return;
+    }
     int64_t nx = (p->x >= 0) ? B->nodes[p->x].n : 1;
     int64_t ny = np - nx;
     int k = p->k;

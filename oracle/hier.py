@@ -44,6 +44,8 @@ def load(path: str | None = None):
     lib = ctypes.CDLL(path)
     lib.or_build.restype = ctypes.c_void_p
     lib.or_build.argtypes = [_dp, _i64]
+    lib.or_build_s.restype = ctypes.c_void_p
+    lib.or_build_s.argtypes = [_dp, _i64, _i64]
     lib.or_free.argtypes = [ctypes.c_void_p]
     lib.or_free.restype = None
     for f in ("or_n", "or_rows", "or_num_internal"):
@@ -88,20 +90,24 @@ def codes(pos) -> np.ndarray:
 
 
 class Node:
-    __slots__ = ("first", "last", "x", "y", "n", "k", "dim", "off", "c", "T22",
+    __slots__ = ("first", "last", "x", "y", "n", "k", "dim", "off", "bucket", "c", "T22",
                  "sx", "sy", "kappa", "G")
 
 
 class Body:
-    """One rigid body: the oracle's tree, transforms and products."""
+    """One rigid body: the oracle's tree, transforms and products.  Leaves
+    hold at most ``s`` beads (s = 1: one bead per leaf)."""
 
-    def __init__(self, pos, lib=None):
+    def __init__(self, pos, lib=None, s=1):
         self.lib = lib if lib is not None else load()
         self.pos = np.ascontiguousarray(pos, dtype=np.float64)
         self.n = len(self.pos)
+        self.s = int(s)
         if self.n < 2:
             raise ValueError("a body needs at least 2 beads")
-        self._h = self.lib.or_build(_ptr(self.pos), self.n)
+        if self.s < 1:
+            raise ValueError("s must be >= 1")
+        self._h = self.lib.or_build_s(_ptr(self.pos), self.n, self.s)
         if not self._h:
             raise RuntimeError("oracle build failed")
 
@@ -137,11 +143,11 @@ class Body:
         return f, l, s
 
     def node(self, i) -> Node:
-        ints = np.zeros(8, dtype=np.int64)
+        ints = np.zeros(9, dtype=np.int64)
         dbl = np.zeros(96, dtype=np.float64)
         self.lib.or_node(self._h, int(i), _ptr(ints, _i64p), _ptr(dbl))
         nd = Node()
-        (nd.first, nd.last, nd.x, nd.y, nd.n, nd.k, nd.dim, nd.off) = (int(t) for t in ints)
+        (nd.first, nd.last, nd.x, nd.y, nd.n, nd.k, nd.dim, nd.off, nd.bucket) = (int(t) for t in ints)
         nd.c = dbl[0:3].copy()
         nd.T22 = dbl[3:12].reshape(3, 3).copy()
         nd.sx, nd.sy, nd.kappa = float(dbl[12]), float(dbl[13]), float(dbl[14])
@@ -194,10 +200,10 @@ class Body:
 class Batch:
     """Block-diagonal Q~ = diag(Q~^1, ..., Q~^m) over bodies given by offsets."""
 
-    def __init__(self, pos, offsets):
+    def __init__(self, pos, offsets, s=1):
         self.pos = np.ascontiguousarray(pos, dtype=np.float64)
         self.offsets = np.asarray(offsets, dtype=np.int64)
-        self.bodies = [Body(self.pos[self.offsets[j]:self.offsets[j + 1]])
+        self.bodies = [Body(self.pos[self.offsets[j]:self.offsets[j + 1]], s=s)
                        for j in range(len(self.offsets) - 1)]
         sizes = np.diff(self.offsets)
         self.row_off = np.zeros(len(sizes) + 1, dtype=np.int64)

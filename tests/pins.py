@@ -269,6 +269,41 @@ def block_structure_error(body, tol=1e-13):
     return worst
 
 
+def bucket_lapack_error(body):
+    """Every leaf box of 2..s beads against LAPACK: its transform is
+    G = diag(-1,-1,-1,1,...,1) Q^T from numpy's Householder QR of the 3n x 6
+    matrix X = [U_t^T | Z_r^T] (U_t = [I ... I] / sqrt(n); Z_r = [A_1 ... A_n],
+    A_k = [r_k - c]x about the leaf's centroid), beads in the tree's order.
+    Checks the leaf's residue rows of the explicit Q~ (G's rows 7..3n) and
+    T22 = R(4:6,4:6)^T, skipping ill-conditioned leaves (whose last
+    reflectors are fixed only up to rounding).  Returns the worst deviation."""
+    Q = body.explicit()
+    perm = body.perm()
+    worst = 0.0
+    for nd in body.nodes():
+        if not nd.bucket:
+            continue
+        ids = perm[nd.first:nd.last + 1]
+        n = len(ids)
+        r = body.pos[ids] - body.pos[ids].mean(axis=0)
+        X = np.zeros((3 * n, 6))
+        for b in range(n):
+            X[3 * b:3 * b + 3, 0:3] = np.eye(3) / np.sqrt(n)
+            X[3 * b:3 * b + 3, 3:6] = cross(r[b]).T
+        Qn, Rn = np.linalg.qr(X, mode="complete")
+        if n >= 3 and nd.kappa > 1e6:
+            continue
+        T = Rn[3:6, 3:6].T.copy()
+        if n == 2:
+            T[2, 2] = 0.0
+        worst = max(worst, np.abs(nd.T22 - T).max() / max(np.abs(T).max(), 1e-300))
+        cols = (3 * ids[:, None] + np.arange(3)[None, :]).reshape(-1)
+        got = Q[nd.off:nd.off + nd.dim][:, cols]
+        if got.size:
+            worst = max(worst, np.abs(got - Qn.T[6:]).max())
+    return worst
+
+
 def case1_closed_form(a, b, c):
     """T22 and U printed for two beads at (a,b,c) and (-a,-b,-c) (Eqs.
     3.9-3.10, valid as printed for b > 0, c > 0)."""

@@ -320,3 +320,67 @@ def test_large_body_helpers_match_dense_definitions():
         px = dense.project_large(p, x)
         assert np.abs(dense.zmul(p, px)).max() <= 1e-9 * np.abs(Z).max() * np.abs(x).max() * n
         assert np.abs(dense.project_large(p, px) - px).max() <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# leaf boxes of up to s beads (Section 2.1 allows s > 1)
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("s", [2, 3, 5, 8, 16])
+@pytest.mark.parametrize("seed,n,kind", [(60, 300, "ellipsoid"), (61, 97, "sphere"), (62, 500, "cube")])
+def test_leaf_buckets_basis_free(s, seed, n, kind):
+    """Buckets keep every basis-free fact: rows orthonormal and orthogonal to
+    Z, the LAPACK projector, the full Q orthogonal with Q_Z spanning row(Z),
+    explicit = implicit, and the pre-order block layout."""
+    b = hier.Body(rand_body(seed, n, kind), s=s)
+    rng = np.random.default_rng(seed)
+    assert sum(nd.bucket for nd in b.nodes()) > 0
+    assert pins.projector_error(b, rng) < 1e-12
+    assert pins.roundtrip_error(b, rng) < 1e-12
+    assert pins.leak_error(b, rng) < 1e-14
+    assert pins.full_q_inverse_error(b, rng) < 1e-12
+    assert pins.root_rows_error(b) < 1e-12
+    assert pins.explicit_error(b, rng) < 1e-13
+    assert pins.block_structure_error(b) == 0.0
+
+
+@pytest.mark.parametrize("s", [2, 4, 16])
+def test_leaf_buckets_pinned_to_lapack(s):
+    """Each bucket's transform against numpy's Householder QR of its 3n x 6
+    matrix [U_t^T | Z_r^T], and its Info-set identities (Definition 4.1)."""
+    b = hier.Body(rand_body(63, 400), s=s)
+    assert pins.bucket_lapack_error(b) < 1e-12
+    assert pins.infoset_identity_error(b, np.random.default_rng(63)) < 1e-13
+
+
+def test_leaf_bucket_whole_body():
+    """A body of n <= s beads is one leaf: Q~ is LAPACK's complement rows of
+    [U_t^T | Z_r^T] (beads in tree order) and the rest of the tree is empty."""
+    pos = rand_body(64, 12)
+    b = hier.Body(pos, s=12)
+    assert b.num_internal == 1 and b.node(0).bucket == 1
+    assert pins.bucket_lapack_error(b) < 1e-13
+    assert pins.projector_error(b, np.random.default_rng(64)) < 1e-13
+
+
+def test_leaf_buckets_leave_s1_unchanged():
+    """s = 1 is the one-bead-leaf tree, bit for bit."""
+    pos = rand_body(65, 200)
+    v = np.random.default_rng(65).standard_normal((600, 2))
+    assert np.array_equal(hier.Body(pos).apply(v), hier.Body(pos, s=1).apply(v))
+
+
+def test_leaf_bucket_degenerate_cases():
+    """Two-bead leaves (rank-2 rotation rows, T22(3,3) = 0) and a collinear
+    leaf keep the rows orthonormal and orthogonal to Z."""
+    rng = np.random.default_rng(66)
+    pos = np.concatenate([rand_body(66, 40), 50 + np.outer(rng.uniform(0, 1, 6), [1.0, 2.0, -0.5])])
+    b = hier.Body(pos, s=6)
+    for nd in b.nodes():
+        if nd.bucket and nd.n == 2:
+            assert nd.T22[2, 2] == 0.0
+    Q = b.explicit()
+    assert np.abs(Q @ Q.T - np.eye(b.rows)).max() < 1e-12
+    Z = dense.zmatrix_centroid(pos)
+    assert np.abs(Z @ Q.T).max() / np.linalg.norm(Z, 2) < 1e-12

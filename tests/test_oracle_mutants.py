@@ -33,8 +33,8 @@ MUTANTS = [
     ("cross-product sign", "A[0][0] = 0.0;   A[0][1] = -u[2];", "A[0][0] = 0.0;   A[0][1] = u[2];"),
     ("centroid weight", "((double)nx * cx[d] + (double)ny * cy[d]) / n",
      "((double)nx * cx[d] + (double)nx * cy[d]) / n"),
-    ("Householder sign convention", "double beta = (alpha >= 0.0) ? -nrm : nrm;",
-     "double beta = (alpha >= 0.0) ? nrm : -nrm;"),
+    ("Householder sign convention", "xnorm * xnorm);\n        double beta = (alpha >= 0.0) ? -nrm : nrm;",
+     "xnorm * xnorm);\n        double beta = (alpha >= 0.0) ? nrm : -nrm;"),
     ("T22 not transposed", "p->T22[i][j] = (j <= i) ? A[j][i] : 0.0;", "p->T22[i][j] = (j <= i) ? A[i][j] : 0.0;"),
     ("G = Q instead of Q^T", "p->G[i][j] = Q[j][i];", "p->G[i][j] = Q[i][j];"),
     ("x is the upper half", "int64_t x = build_rec(B, lo, s);\n    int64_t y = build_rec(B, s + 1, hi);",
@@ -52,6 +52,23 @@ MUTANTS = [
      "if (root) for (int d = 0; d < 6; ++d) root[d * nrhs + r] = M[(d + 3) % 6];"),
     ("explicit last block sign", "J[(q + d) * ncol + 3 * (nx + b) + d] = -p->sx / sqrt((double)ny);",
      "J[(q + d) * ncol + 3 * (nx + b) + d] = p->sx / sqrt((double)ny);"),
+    # leaf boxes of up to s beads
+    ("bucket translation sign not flipped (up)", "for (int d = 0; d < 3; ++d) { M[d] = -t[d]; M[3 + d] = t[3 + d]; }",
+     "for (int d = 0; d < 3; ++d) { M[d] = t[d]; M[3 + d] = t[3 + d]; }"),
+    ("bucket translation sign not flipped (down)", "for (int d = 0; d < 3; ++d) { t[d] = -L[d]; t[3 + d] = L[3 + d]; }",
+     "for (int d = 0; d < 3; ++d) { t[d] = L[d]; t[3 + d] = L[3 + d]; }"),
+    ("bucket rotation rows transposed", "for (int e = 0; e < 3; ++e) X[(3 + e) * m + 3 * b + d] = A[e][d];",
+     "for (int e = 0; e < 3; ++e) X[(3 + e) * m + 3 * b + d] = A[d][e];"),
+    ("bucket centroid weight", "for (int d = 0; d < 3; ++d) p->c[d] /= (double)n;",
+     "for (int d = 0; d < 3; ++d) p->c[d] /= (double)(n + 1);"),
+    ("bucket T22 not transposed", "p->T22[i][j] = (j <= i) ? X[(3 + i) * m + 3 + j] : 0.0;",
+     "p->T22[i][j] = (j <= i) ? X[(3 + j) * m + 3 + i] : 0.0;"),
+    ("bucket reflectors applied in reverse upward", "    for (int j = 0; j < 6; ++j) {\n        if (p->htau[j] == 0.0) continue;",
+     "    for (int j = 5; j >= 0; --j) {\n        if (p->htau[j] == 0.0) continue;"),
+    ("bucket Householder sign convention", "const double beta = (alpha >= 0.0) ? -nrm : nrm;",
+     "const double beta = (alpha >= 0.0) ? nrm : -nrm;"),
+    ("bucket residue rows shifted", "for (int64_t i = 0; i < p->dim; ++i) out[p->off + i] = t[6 + i];",
+     "for (int64_t i = 0; i < p->dim; ++i) out[p->off + i] = t[5 + i];"),
 ]
 
 BATTERY = r"""
@@ -91,6 +108,14 @@ pos = np.random.default_rng(30).uniform(-2, 7, (150, 3))
 tr = W.ellipsoid_body(np.random.default_rng(30), 150, (20, 12, 8), jitter=0.3)
 q0 = B(tr).explicit(); q1 = B(tr + np.array([0.25, -0.5, 2.0])).explicit()
 check('translation', np.abs(q0 - q1).max() < 1e-12)
+# leaf boxes of up to s beads
+for sb in (3, 8):
+    bb = hier.Body(ell, lib=lib, s=sb)
+    check(f'bucket-infoset-{{sb}}', pins.infoset_identity_error(bb, rng) < 1e-12)
+    check(f'bucket-lapack-{{sb}}', pins.bucket_lapack_error(bb) < 1e-11)
+    check(f'bucket-projector-{{sb}}', pins.projector_error(bb, rng) < 1e-12)
+    check(f'bucket-fullq-{{sb}}', pins.full_q_inverse_error(bb, rng) < 1e-12)
+    check(f'bucket-explicit-{{sb}}', pins.explicit_error(bb, rng) < 1e-12)
 print('FAILS', fails)
 sys.exit(1 if fails else 0)
 """
