@@ -56,30 +56,135 @@ def algorithmic_bytes(h, nrhs, elem=4):
     return (elem * 3 * h.N * nrhs + elem * h.rows * nrhs + elem * int(w) + 16 * (h.N - h.m) + 4 * h.N)
 
 
-def cpu_baseline(wl, rng_seed, budget_s=15.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same bodies:
-    per body a rebuild plus Q~ f and Q~^T (Q~ f) for all R right-hand sides."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_workers():
+    """Host threads this process may use (at most 16, the GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+_CPU_WL = None  # the workload, inherited by the forked oracle workers
+
+
+def _oracle_body(j):
+    """The oracle's rebuild + Q~ f + Q~^T (Q~ f) for body j (all R right-hand
+    sides, f drawn from a per-body seed): (beads, seconds)."""
     from oracle import hier
-    rng = np.random.default_rng(rng_seed)
+    wl = _CPU_WL
+    p = wl.pos[wl.offsets[j]:wl.offsets[j + 1]]
+    f = np.random.default_rng(1000 + int(j)).standard_normal((3 * len(p), wl.nrhs))
+    ts = time.perf_counter()
+    b = hier.Body(p)
+    y = b.apply(f)
+    b.apply(y, transpose=True)
+    return len(p), time.perf_counter() - ts
+
+
+def cpu_baseline(wl, rng_seed, budget_s=8.0):
+    """The FP64 oracle as it stands (plain C recursion, one body per call) on
+    bounded samples of the same bodies: one thread, then every host core (a
+    process pool over bodies).  Runs before the GPU is touched, so the pool's
+    processes are forked from a process without GPU state."""
+    import multiprocessing as mp
+    global _CPU_WL
+    _CPU_WL = wl
     R = wl.nrhs
-    order = rng.permutation(wl.m)
-    beads, t_total, nb = 0, 0.0, 0
-    t0 = time.perf_counter()
+    order = np.random.default_rng(rng_seed).permutation(wl.m)
+    beads1, t1, n1 = 0, 0.0, 0
     for j in order:
-        p = wl.pos[wl.offsets[j]:wl.offsets[j + 1]]
-        f = rng.standard_normal((3 * len(p), R))
-        ts = time.perf_counter()
-        b = hier.Body(p)
-        y = b.apply(f)
-        b.apply(y, transpose=True)
-        t_total += time.perf_counter() - ts
-        beads += len(p)
-        nb += 1
-        if time.perf_counter() - t0 > budget_s:
+        b, t = _oracle_body(j)
+        beads1, t1, n1 = beads1 + b, t1 + t, n1 + 1
+        if t1 > budget_s:
             break
-    return {"value": beads * R / t_total, "unit": "bead-vectors/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nb} of {wl.m} bodies ({beads} beads, R={R}), FP64 plain C recursion, one thread, "
-                      f"rebuild + Q~f + Q~^T(Q~f) per body, {t_total:.1f} s"}
+    workers = host_workers()
+    # the all-core sample: about budget_s of wall time on every worker
+    sample = order[:min(wl.m, n1 * workers)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_body, [int(j) for j in sample], chunksize=4)
+    wall = time.perf_counter() - t0
+    beads = sum(b for b, _ in res)
+    return {"value": beads * R / wall, "unit": "bead-vectors/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{len(sample)} of {wl.m} bodies ({beads} beads, R={R}) over {workers} processes, "
+                      f"FP64 plain C recursion, rebuild + Q~f + Q~^T(Q~f) per body, {wall:.1f} s wall",
+            "one_core": {"value": beads1 * R / t1, "unit": "bead-vectors/s", "cores": 1,
+                         "sample": f"{n1} bodies ({beads1} beads), {t1:.1f} s"}}
+
+
+def sweep_kernel(nrhs, layout, dtype, transpose=False, phase=1):
+    """The kernel the library launches for a tile phase of a sweep with this
+    many right-hand sides, when its buffers fit the wide sweeps' 2 GiB range
+    (its dispatch: runs of 32 or 64 lanes above 16 right-hand sides, 32-lane
+    ones specialised for exactly 32; for 8 to 16, 16-lane runs in FP32 and
+    32-lane runs in FP64; below 8, narrow sweeps of one lane group per tile)."""
+    lpt = 1
+    while lpt < nrhs and lpt < 64:
+        lpt *= 2
+    if nrhs < 8:
+        return f"k_{'down' if transpose else 'up'}<{dtype}, {lpt}>"
+    if lpt < 32:
+        lpt = 16 if dtype == "float" else 32
+    rt = 32 if nrhs == 32 else 0
+    tri = str(layout == "triples").lower()
+    if transpose:
+        return f"k_down_wide<{dtype}, {lpt}, {rt}, 6, 3, {str(phase > 1).lower()}, 1, {tri}, false>"
+    return f"k_up_wide<{dtype}, {lpt}, {rt}, 6, 3, {3 if phase == 1 else 6}, 1, {tri}, false>"
+
+
+def stream_ceiling(hq, torch, read_bytes, write_bytes, stream, reps=10):
+    """The library's streaming kernel (hq_stream_ceiling: non-temporal 16-byte
+    accesses, the sweeps' cache policy) with a given read:write mix; the best
+    median over a few grid sizes, in GB/s of bytes moved."""
+    import ctypes
+    from paper_1708_08427_amd import _lib
+    lib = _lib.load()
+    rb = (int(read_bytes) // 4096) * 4096
+    wb = min(rb, (int(write_bytes) // 4096) * 4096)
+    src = torch.ones(rb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(wb // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        def run():
+            st = lib.hq_stream_ceiling(ctypes.c_void_p(src.data_ptr()), rb, ctypes.c_void_p(dst.data_ptr()), wb,
+                                       blocks, ctypes.c_void_p(sink.data_ptr()), sp)
+            if st != 0:
+                raise RuntimeError(lib.hq_last_error().decode())
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        run()
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream)
+            run()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        gbs = (rb + wb) / (ms * 1e-3) / 1e9
+        if best is None or gbs > best["achieved"]:
+            best = {"achieved": gbs, "unit": "GB/s", "ms": ms, "read_bytes": rb, "write_bytes": wb,
+                    "blocks": blocks}
+    del src, dst
+    best["frac"] = best["achieved"] / HBM_PEAK_GBS
+    best["what"] = ("hq_stream_ceiling: one launch reading and writing the dominant launch's HBM traffic mix "
+                    "(non-temporal 16-byte accesses, 256 threads per block, best of 1024-8192 blocks)")
+    return best
 
 
 def to_layout(a, layout):
@@ -126,7 +231,7 @@ def probe(hq, torch, wl, f, args):
 
 def fixed_options(args):
     return {"tile_units": args.tile_units, "run_nodes": args.run_nodes, "waves_per_cu": args.waves_per_cu,
-            "later_tile_units": args.later_tile_units}
+            "later_tile_units": args.later_tile_units, "leaf_size": args.leaf_size}
 
 
 DEFAULT_OPTIONS = {"tile_units": 32, "run_nodes": 48, "waves_per_cu": 16}  # the library's defaults for 0
@@ -135,6 +240,7 @@ DEFAULT_OPTIONS = {"tile_units": 32, "run_nodes": 48, "waves_per_cu": 16}  # the
 def effective(opts):
     e = {k: int(opts.get(k) or v) for k, v in DEFAULT_OPTIONS.items()}
     e["later_tile_units"] = int(opts.get("later_tile_units") or e["tile_units"])
+    e["leaf_size"] = max(1, int(opts.get("leaf_size") or 1))
     return e
 
 
@@ -168,6 +274,147 @@ def traffic_from_profile(opts, layout):
     return None, f"bench runs {tag}; " + "; ".join(seen)
 
 
+def timed_ms(torch, stream, fn, reps, before=None):
+    """Median over reps of fn's duration (HIP events on ``stream``); ``before``
+    runs ahead of each rep, outside the timed interval (e.g. a cache flush)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    fn()
+    torch.cuda.synchronize()
+    for a, b in evs:
+        if before is not None:
+            before()
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def first_phase_ms(torch, h, v, out, stream, reps, transpose=False):
+    """Median duration of the first tile phase's launch (hq_apply_timed)."""
+    ms = []
+    for _ in range(reps):
+        h.apply(v, out=out, stream=stream, transpose=transpose)
+        _, ph = h.apply(v, out=out, stream=stream, timed=True, transpose=transpose)
+        ms.append(ph[0])
+    torch.cuda.synchronize()
+    return float(np.median(ms))
+
+
+def config_leg(hq, torch, W, name, stream, reps=10, log=print):
+    """One of the other target configurations, timed like the sweeps of the
+    BD step: FP32 Q~v and Q~^T w (and FP64 where the configuration asks for
+    it), algorithmic bytes and fraction of the HBM peak per direction, the
+    first tile phase's launch, the FP32 error against the FP64 oracle and the
+    leak.  Inputs are N(0,1) in the rows layout."""
+    from oracle import dense, hier
+    dev = torch.device("cuda:0")
+    flush = None
+    if name == "C2":
+        wl, R, fp64 = W.ellipsoid_n65536(), 16, True
+        # the whole working set fits the 256 MB Infinity Cache: time it after a
+        # 1 GiB write evicts it, as well as warm
+        fbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        flush = lambda: fbuf.fill_(1.0)
+    elif name == "C3":
+        wl, R, fp64 = W.batched_m1000(), 1, False
+    else:
+        wl, R, fp64 = W.large_clustered(), 1, False
+    assert wl.nrhs == R
+    v, w = wl.draw_vectors()
+    log(f"leg {name}: {wl.name} N={wl.N} m={wl.m} R={R}")
+    pos = torch.from_numpy(wl.pos).to(dev)
+    # C5 also generates its explicit block-sparse Q~, which needs the FP64
+    # transforms
+    h = hq.build(pos, wl.offsets, store=3 if (fp64 or name == "C5") else 2, stream=stream)
+    res = {"workload": wl.name, "beads": wl.N, "bodies": wl.m, "nrhs": R, "rows": wl.rows,
+           "tiles": h.query()["tiles"], "phases": h.query()["phases"]}
+    precs = [("fp32", torch.float32, 4)] + ([("fp64", torch.float64, 8)] if fp64 else [])
+    outs = {}
+    for tag, dt, elem in precs:
+        vd = torch.from_numpy(v).to(dt).to(dev)
+        wd = torch.from_numpy(w).to(dt).to(dev)
+        up = torch.empty((wl.rows, R), dtype=dt, device=dev)
+        dn = torch.empty((3 * wl.N, R), dtype=dt, device=dev)
+        nbytes = algorithmic_bytes(h, R, elem)
+        t_up = timed_ms(torch, stream, lambda: h.apply(vd, out=up, stream=stream), reps)
+        t_dn = timed_ms(torch, stream, lambda: h.apply(wd, transpose=True, out=dn, stream=stream), reps)
+        t_p1 = first_phase_ms(torch, h, vd, up, stream, reps)
+        pb = phase_bytes(h, R, elem)
+        leg = {"up_ms": t_up, "down_ms": t_dn, "bytes_per_sweep": int(nbytes),
+               "bead_vectors_per_s": wl.N * R / ((t_up + t_dn) * 1e-3),
+               "frac_up": nbytes / (t_up * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "frac_down": nbytes / (t_dn * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "first_phase": {"kernel": sweep_kernel(R, "rows", "float" if elem == 4 else "double"),
+                               "ms": t_p1, "bytes": int(pb[1]),
+                               "frac": pb[1] / (t_p1 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+        if flush is not None:
+            c_up = timed_ms(torch, stream, lambda: h.apply(vd, out=up, stream=stream), reps, before=flush)
+            c_dn = timed_ms(torch, stream, lambda: h.apply(wd, transpose=True, out=dn, stream=stream), reps,
+                            before=flush)
+            leg["after_1gib_flush"] = {"up_ms": c_up, "down_ms": c_dn,
+                                       "frac_up": nbytes / (c_up * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       "frac_down": nbytes / (c_dn * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        torch.cuda.synchronize()
+        outs[tag] = (up.double().cpu().numpy(), dn.double().cpu().numpy())
+        res[tag] = leg
+        del vd, wd, up, dn
+    assert h.query()["device_flags"] == 0
+    up32, dn32 = outs["fp32"]
+    # accuracy: FP32 against the FP64 oracle (element-wise where the bodies'
+    # nodes are well conditioned), and the leak of Q~^T w
+    if name == "C5":
+        # one body of 4.2M beads with near-collinear clusters: its basis is
+        # fixed only up to rounding, so the comparison is basis-free (the
+        # projector and the leak, Z applied in O(n) on the host)
+        pr = h.apply(h.apply(torch.from_numpy(v).float().to(dev)), transpose=True).double().cpu().numpy()
+        want = dense.project_large(wl.pos, v)
+        res["fp32_projector_rel_err"] = float(np.linalg.norm(pr - want) / np.linalg.norm(v))
+        res["fp32_leak"] = float(dense.leak_large(wl.pos, dn32).max())
+        res["accuracy_note"] = "FP32 Q~^T(Q~ v) against the FP64 dense projector; leak of FP32 Q~^T w"
+        # explicit block-sparse Q~ in FP32: generation time and bytes written
+        nb, nv = h.explicit_blocks_size(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vals = h.explicit_blocks(0, dtype=torch.float32, stream=stream)[0]
+        torch.cuda.synchronize()
+        t_ex = (time.perf_counter() - t0) * 1e3
+        res["explicit_blocks"] = {"blocks": nb, "values": nv, "bytes_written": 4 * nv, "ms_incl_host": t_ex,
+                                  "what": "hq_explicit_blocks (FP32), wall time including its host-side tables"}
+        del vals
+    else:
+        sample = np.arange(wl.m) if wl.m <= 100 else np.random.default_rng(8).choice(wl.m, 100, replace=False)
+        err = leak = 0.0
+        rows = np.concatenate([[0], np.cumsum(3 * np.diff(wl.offsets) - 6)])
+        for j in sample:
+            b0, b1 = wl.offsets[j], wl.offsets[j + 1]
+            p = wl.pos[b0:b1]
+            bo = hier.Body(p)
+            r0, r1 = rows[j], rows[j + 1]
+            ref_up = bo.apply(v[3 * b0:3 * b1])
+            ref_dn = bo.apply(w[r0:r1], transpose=True)
+            e1 = np.linalg.norm(up32[r0:r1] - ref_up, axis=0) / np.linalg.norm(v[3 * b0:3 * b1], axis=0)
+            e2 = np.linalg.norm(dn32[3 * b0:3 * b1] - ref_dn, axis=0) / np.linalg.norm(w[r0:r1], axis=0)
+            err = max(err, float(e1.max()), float(e2.max()))
+            leak = max(leak, float(dense.leak_large(p, dn32[3 * b0:3 * b1]).max()))
+            if "fp64" in outs:
+                u64, d64 = outs["fp64"]
+                res.setdefault("fp64_rel_err_vs_oracle", 0.0)
+                e64 = max(float((np.linalg.norm(u64[r0:r1] - ref_up, axis=0) /
+                                 np.linalg.norm(ref_up, axis=0)).max()),
+                          float((np.linalg.norm(d64[3 * b0:3 * b1] - ref_dn, axis=0) /
+                                 np.linalg.norm(ref_dn, axis=0)).max()))
+                res["fp64_rel_err_vs_oracle"] = max(res["fp64_rel_err_vs_oracle"], e64)
+        res["fp32_rel_err_vs_fp64_oracle"] = err
+        res["fp32_leak"] = leak
+        res["accuracy_bodies"] = int(len(sample))
+    h.destroy()
+    if flush is not None:
+        del fbuf
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +424,8 @@ def main():
     ap.add_argument("--run-nodes", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--later-tile-units", type=int, default=0, help="0: tile size of the first phase")
+    ap.add_argument("--leaf-size", type=int, default=0, help="leaf boxes of up to this many beads (0: autotuned "
+                    "with the tile sizes, or 1 bead without the autotuner)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults for options left at 0")
     ap.add_argument("--layout", choices=("triples", "rows"), default="triples",
                     help="vector layout of the force and residue vectors (hq_layout)")
@@ -190,6 +439,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--probe", action="store_true",
                     help="only build, copy 512 MiB once and run 3 sweeps per direction (for rocprofv3 --pmc)")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other configurations (C2, C3, C5)")
+    ap.add_argument("--legs-only", action="store_true", help="only the other configurations (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bodies of this workload "
@@ -203,6 +454,19 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.legs_only:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            for name in ("C2", "C3", "C5"):
+                log(json.dumps({name: config_leg(hq, torch, W, name, stream, log=log)}))
+        return
+    # the CPU baseline first: its process pool forks before the GPU is touched
+    cpu = None
+    if not args.no_cpu and not args.probe:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(W.bd_m4096(m=args.bodies, nrhs=args.nrhs), 5)
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu}")
 
     wl = W.bd_m4096(m=args.bodies, nrhs=args.nrhs)
     N, m, R = wl.N, wl.m, wl.nrhs
@@ -396,12 +660,45 @@ def main():
         k_iter = (t_k - t_k1) / max(kinfo["iters"] - 1, 1)
         log(f"Krylov solve: {kinfo['iters']} CG iterations to {kinfo['max_rel_residual']:.1e} in {t_k:.1f} ms "
             f"({k_iter:.2f} ms per iteration)")
+        # the FP64 path beside it: the same workload at the final positions,
+        # FP64 transforms and FP64 vectors (a handle keeping only FP64)
         f64 = f32.double()
         tmp64 = torch.empty(vec_shape(wl.rows, R, lay), dtype=torch.float64, device=dev)
+        out64 = torch.empty(vec_shape(3 * N, R, lay), dtype=torch.float64, device=dev)
         h64 = hq.build(pos, wl.offsets, store=1, stream=stream, **opts)
-        t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream, layout=lay), 5)
+        t_up64 = timed(lambda: h64.apply(f64, out=tmp64, stream=stream, layout=lay), 10)
+        t_dn64 = timed(lambda: h64.apply(tmp64, transpose=True, out=out64, stream=stream, layout=lay), 10)
+        t_rb64 = timed(lambda: h64.rebuild(pos, stream=stream), 5)
+
+        def step64():
+            h64.rebuild(pos, stream=stream)
+            h64.apply(f64, out=tmp64, stream=stream, layout=lay)
+            h64.apply(tmp64, transpose=True, out=out64, stream=stream, layout=lay)
+
+        t_step64 = timed(step64, 5)
+        p1_64 = []
+        for _ in range(5):
+            h64.apply(f64, out=tmp64, stream=stream, layout=lay)
+            _, ms_ph = h64.apply(f64, out=tmp64, stream=stream, timed=True, layout=lay)
+            p1_64.append(ms_ph[0])
+        t_p1_64 = float(np.median(p1_64))
+        pb64 = phase_bytes(h64, R, 8)
+        nbytes64 = algorithmic_bytes(h64, R, 8)
+        assert h64.query()["device_flags"] == 0
         h64.destroy()
-        log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms, up FP64 {t_up64:.3f} ms")
+        del f64, tmp64, out64
+        fp64 = {"up_ms": t_up64, "down_ms": t_dn64, "rebuild_ms": t_rb64, "step_ms": t_step64,
+                "bead_vectors_per_s": N * R / (t_step64 * 1e-3),
+                "apply_only_bead_vectors_per_s": N * R / ((t_up64 + t_dn64) * 1e-3),
+                "roofline": {"bound": "hbm", "kernel": sweep_kernel(R, lay, "double"), "bytes": int(pb64[1]),
+                             "ms": t_p1_64, "achieved": pb64[1] / (t_p1_64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": pb64[1] / (t_p1_64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "whole_sweep_up": {"bytes": int(nbytes64), "ms": t_up64,
+                                                "frac": nbytes64 / (t_up64 * 1e-3) / 1e9 / HBM_PEAK_GBS}},
+                "what": "FP64 transforms and vectors on the same workload (final positions): rebuild + Q~f + "
+                        "Q~^T(Q~f) per step, eager launches on one stream, no pipelining"}
+        log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms; FP64 up {t_up64:.3f} "
+            f"down {t_dn64:.3f} step {t_step64:.3f} ms")
         nbytes = algorithmic_bytes(h, R)
         # the dominant kernel: the first tile phase's upward launch, timed with
         # HIP events around that launch on the stream it runs on
@@ -418,17 +715,24 @@ def main():
         achieved = pbytes[1] / (t_p1 * 1e-3) / 1e9
         log(f"first-phase upward launch: {t_p1:.3f} ms, {pbytes[1] / 1e9:.3f} GB -> {achieved:.0f} GB/s; "
             f"whole sweep {nbytes / (t_up * 1e-3) / 1e9:.0f} GB/s")
-        # the measured device-copy ceiling beside the published peak: 1 GiB
-        # read + 1 GiB written by a plain copy on the same stream
-        ca = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        cb = torch.empty_like(ca)
-        t_copy = timed(lambda: cb.copy_(ca), 10)
-        copy_gbs = 2 * ca.numel() * 4 / (t_copy * 1e-3) / 1e9
-        del ca, cb
-        log(f"device copy 1 GiB: {t_copy:.3f} ms -> {copy_gbs:.0f} GB/s read + write")
+        # the measured streaming ceiling beside the published peak: the
+        # library's streaming kernel with the dominant launch's read:write mix
+        # (its algorithmic reads: vectors in, records, permutation; writes:
+        # residue rows), the sweeps' non-temporal policy
+        nd_k = h.node_data(with_G=False, with_geometry=False)
+        ph1 = h.node_phase() == 1
+        wbytes = 4 * R * int((nd_k["k"][ph1].astype(np.int64) - 3).sum())
+        ceiling = stream_ceiling(hq, torch, pbytes[1] - wbytes, wbytes, stream)
+        log(f"streaming ceiling {ceiling['achieved']:.0f} GB/s ({ceiling['read_bytes'] / 1e9:.2f} GB read, "
+            f"{ceiling['write_bytes'] / 1e9:.2f} GB written in {ceiling['ms']:.3f} ms)")
         traffic, traffic_src = traffic_from_profile(opts, lay)
         log(f"traffic: {traffic} ({traffic_src})")
         q = h.query()
+        legs = {}
+        if not args.no_legs:
+            for name in ("C2", "C3", "C5"):
+                legs[name] = config_leg(hq, torch, W, name, stream, log=log)
+                log(f"{name}: {json.dumps(legs[name])}")
 
     result = {
         "metric": METRIC,
@@ -451,15 +755,14 @@ def main():
                                 if npipe > 1 else "one handle, one stream")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_up_wide<float, 32, 32, 6, 3, 3, 1, {str(lay == 'triples').lower()}, false>: "
-                               "first tile phase of the upward FP32 sweep",
+                     "kernel": f"{sweep_kernel(R, lay, 'float')}: first tile phase of the upward FP32 sweep",
                      "bytes": int(pbytes[1]), "ms": t_p1,
-                     "copy_ceiling": {"achieved": copy_gbs, "unit": "GB/s", "frac": copy_gbs / HBM_PEAK_GBS,
-                                      "kernel_frac_of_copy": achieved / copy_gbs,
-                                      "what": "torch device copy of 1 GiB (read + write bytes / time)"},
+                     "stream_ceiling": dict(ceiling, kernel_frac_of_ceiling=achieved / ceiling["achieved"]),
                      "whole_sweep": {"bytes": int(nbytes), "ms": t_up,
                                      "achieved": nbytes / (t_up * 1e-3) / 1e9}},
-        "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64},
+        "sweeps_ms": {"up_fp32": t_up, "down_fp32": t_dn, "rebuild_fp64": t_rb, "up_fp64": t_up64,
+                      "down_fp64": t_dn64},
+        "fp64": fp64,
         "apply_only_bead_vectors_per_s": N * R / ((t_up + t_dn) * 1e-3),
         "krylov": {"iters": kinfo["iters"], "max_rel_residual": kinfo["max_rel_residual"], "ms_total": t_k,
                    "ms_per_iter": k_iter,
@@ -476,9 +779,10 @@ def main():
         "fp32_leak": leak,
         "tiles": q["tiles"], "phases": q["phases"],
     }
-    if not args.no_cpu:
-        wl0 = W.bd_m4096(m=args.bodies, nrhs=args.nrhs)
-        result["cpu_baseline"] = cpu_baseline(wl0, 5)
+    if legs:
+        result["configs"] = legs
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

@@ -127,6 +127,28 @@ typedef struct {
     int32_t krylov_nrhs;   /* hq_build_into: right-hand sides of hq_constrained_solve whose
                               work vectors the workspace holds; 0 = none (the solve then fails
                               on the handle with HQ_E_UNSUPPORTED) */
+    int32_t sweep_kernel;  /* 0: wide sweeps (a lane group per run of whole tiles, node
+                              records read once per group and broadcast) for 8 or more
+                              right-hand sides when every vector buffer stays below 2 GiB,
+                              else narrow ones; 1: narrow sweeps (a lane group per tile,
+                              lanes reading whole records).  Results agree to rounding */
+    int32_t fused_upward;  /* 0: one launch per tile phase; 1: the wide upward sweep
+                              (Algorithm 2) of up to 64 right-hand sides in one launch, each
+                              later-phase tile swept by the workgroup whose child tile
+                              finished last (arrival counters, no waiting).  Same results
+                              bit for bit; measured slower on 4,096 bodies (the last tiles'
+                              chains of later-phase nodes trail the launch).  The downward
+                              sweep, leaf boxes and sweeps of more than 64 right-hand sides
+                              take one launch per phase either way */
+    int32_t leaf_size;     /* 0 or 1: leaves of one bead (the paper's s = 1); 2..16: the
+                              bisection of Section 2.1 stops at boxes of at most leaf_size
+                              beads, each factored densely as one leaf: the Householder QR
+                              of its 3n x 6 matrix [U_t^T | Z_r^T] (translation rows
+                              [I..I]/sqrt(n), rotation rows [A_1..A_n] about its centroid)
+                              gives G = diag(-1,-1,-1,1,..,1) Q^T, whose rows 7..3n are the
+                              leaf's residue rows.  tile_units then sizes the tiles above
+                              the leaves.  hq_explicit, hq_explicit_blocks and the
+                              geometry of hq_node_data are unavailable (HQ_E_UNSUPPORTED) */
 } hq_options;
 
 typedef struct {
@@ -144,7 +166,7 @@ typedef struct {
     int64_t degenerate_bodies;
 } hq_info;
 
-/* Pick tile_units, later_tile_units, run_nodes and waves_per_cu for a workload
+/* Pick tile_units, later_tile_units, run_nodes, waves_per_cu and leaf_size for a workload
  * by measurement: the subtree sizes of Section 2's tree cut into tiles, and
  * the launch shape of the sweeps (Algorithms 2 and 3).  For every candidate,
  * builds a handle on the given positions, then times (median of 5 after 2
@@ -155,9 +177,12 @@ typedef struct {
  * 16, 32 (later_tile_units = tile_units).
  * Stage 2, on the winner: later_tile_units 4, 8, 16 (those below its
  * tile_units) x waves_per_cu 8, 16, 32; kept only if faster.
+ * Stage 3, on that winner (unless base fixes leaf_size): leaf_size 4, 8, 16
+ * (Section 2.1's leaves of up to s beads) x waves_per_cu; kept only if
+ * faster.
  *   positions, body_offsets, m  as for hq_build.
  *   base          host, may be NULL: the other options of the trial builds.
- *   best          host: receives base with the four chosen fields set
+ *   best          host: receives base with the chosen fields set
  *                 (later_tile_units 0 when stage 2 kept tile_units).
  *   best_ms       host, may be NULL: the chosen candidate's time per round.
  * Allocates (and frees) trial handles and two vector buffers; synchronises

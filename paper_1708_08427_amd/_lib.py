@@ -25,7 +25,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tile_units", c_i32), ("store", c_i32), ("explicit_dense_max_n", c_i32), ("max_phases", c_i32),
                 ("run_nodes", c_i32), ("waves_per_cu", c_i32), ("keep_node_data", c_i32),
                 ("later_tile_units", c_i32), ("first_waves_per_cu", c_i32), ("max_nrhs", c_i32),
-                ("max_tiles", c_i32), ("krylov_nrhs", c_i32)]
+                ("max_tiles", c_i32), ("krylov_nrhs", c_i32),
+                ("sweep_kernel", c_i32), ("fused_upward", c_i32), ("leaf_size", c_i32)]
 
 
 class KrylovInfo(ctypes.Structure):

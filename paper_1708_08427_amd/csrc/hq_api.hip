@@ -106,9 +106,16 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     P.rows = P.row_off[m];
     P.S = (opt && opt->tile_units) ? opt->tile_units : 32;
     P.S2 = (opt && opt->later_tile_units) ? opt->later_tile_units : P.S;
+    if (opt && opt->leaf_size > 1) {
+        // the first tile phase holds the leaf boxes; tile_units sizes the rest
+        P.leaf_s = opt->leaf_size;
+        P.S = P.leaf_s;
+    }
     if (opt && opt->run_nodes) P.run_nodes = opt->run_nodes;
     if (opt && opt->waves_per_cu) P.waves_per_cu = opt->waves_per_cu;
     if (opt) P.first_wpc = opt->first_waves_per_cu;
+    if (opt) P.sweep_kernel = opt->sweep_kernel;
+    if (opt) P.fused_up = opt->fused_upward;
     P.keep_node_data = opt && opt->keep_node_data != 0;
     {
         int dev = 0, ncu = 0;
@@ -234,6 +241,9 @@ hq_status create_plan(Plan &P, const int64_t *off, int64_t m, const hq_options *
     HQ_TRY(dalloc(P, &P.d_tile_base, NI));
     HQ_TRY(dalloc(P, &P.d_tile_len, NI));
     HQ_TRY(dalloc(P, &P.d_sched_node, NI));
+    HQ_TRY(dalloc(P, &P.d_ptile, NI));
+    HQ_TRY(dalloc(P, &P.d_tcnt, NI));
+    HQ_TRY(dalloc(P, &P.d_tcnt0, NI));
     HQ_TRY(dalloc(P, &P.d_links, (int64_t)kLinkInts * NI));
     if (P.store & 2) HQ_TRY(dalloc(P, &P.d_rec32, (int64_t)kRecWords * NI));
     if (P.store & 1) HQ_TRY(dalloc(P, &P.d_rec64, (int64_t)kRecWords * NI));
@@ -269,6 +279,13 @@ hq_status reserve_workspace_extras(Plan &P, const hq_options *opt) {
     P.xch_bytes = (size_t)tiles * 6 * (size_t)nrhs * store_elem(P);
     HQ_TRY(plan_alloc(P, &P.d_xch, P.xch_bytes));
     HQ_TRY(dalloc(P, &P.d_blk, P.max_n));
+    if (P.leaf_s > 1) {
+        // leaf boxes hold two or more beads each
+        P.bucket_cap = P.N / 2 + 64;
+        const int64_t vals = P.bucket_cap * (int64_t)bucket_stride(P.leaf_smax());
+        if (P.store & 1) HQ_TRY(dalloc(P, &P.d_brec64, vals));
+        if (P.store & 2) HQ_TRY(dalloc(P, &P.d_brec32, vals));
+    }
     if (opt && opt->krylov_nrhs > 0) {
         P.kry_bytes = krylov_bytes(P.rows, opt->krylov_nrhs, store_elem(P));
         HQ_TRY(plan_alloc(P, &P.d_kry, P.kry_bytes));
@@ -502,6 +519,18 @@ hq_status check_build_args(const int64_t *body_offsets, int64_t m, const hq_opti
             set_error("waves_per_cu must be 0 or in [1, 64]");
             return HQ_E_INVALID;
         }
+        if (opt->leaf_size < 0 || opt->leaf_size > kMaxLeaf) {
+            set_error("leaf_size must be in [0, 16]");
+            return HQ_E_INVALID;
+        }
+        if (opt->fused_upward < 0 || opt->fused_upward > 1) {
+            set_error("fused_upward must be 0 (one launch per tile phase) or 1 (one upward launch)");
+            return HQ_E_INVALID;
+        }
+        if (opt->sweep_kernel < 0 || opt->sweep_kernel > 1) {
+            set_error("sweep_kernel must be 0 (wide sweeps where they fit) or 1 (narrow sweeps)");
+            return HQ_E_INVALID;
+        }
         if (opt->max_nrhs < 0 || opt->max_nrhs > (1 << 20) || opt->max_tiles < 0 || opt->krylov_nrhs < 0 ||
             opt->krylov_nrhs > (1 << 20)) {
             set_error("max_nrhs, max_tiles and krylov_nrhs must be >= 0 (nrhs <= 2^20)");
@@ -723,6 +752,19 @@ hq_status hq_autotune(const double *positions, const int64_t *body_offsets, int6
         o.later_tile_units = s2_cand[k];
         trial(o);
     }
+    // stage 3: leaf boxes of 4, 8 or 16 beads under the chosen tiles (their
+    // tile_units then sizes the tiles above the leaves), unless the caller
+    // fixed the leaf size
+    if (!(base && base->leaf_size)) {
+        const hq_options second = chosen;
+        const int leaf_cand[] = {4, 8, 16};
+        for (int k = 0; k < 3 && st == HQ_OK; ++k) {
+            hq_options o = second;
+            o.leaf_size = leaf_cand[k];
+            o.later_tile_units = 0;
+            trial(o);
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (va) (void)hipFree(va);
@@ -884,6 +926,10 @@ hq_status hq_explicit(hq_handle h, int64_t body, double *out, int64_t ld, hq_str
         set_error("body larger than explicit_dense_max_n");
         return HQ_E_UNSUPPORTED;
     }
+    if (P->leaf_s > 1) {
+        set_error("explicit Q~ is not available for leaf boxes of more than one bead (hq_options.leaf_size)");
+        return HQ_E_UNSUPPORTED;
+    }
     if (ld < 3 * n) {
         set_error("ld must be >= 3 n_j");
         return HQ_E_INVALID;
@@ -925,6 +971,10 @@ hq_status read_body_nodes(Plan &P, int64_t body, BodyNodes &B, int64_t &nb, int6
 hq_status hq_explicit_blocks_size(hq_handle h, int64_t body, int64_t *nblocks, int64_t *nvalues) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
+    if (P->leaf_s > 1) {
+        set_error("explicit Q~ is not available for leaf boxes of more than one bead (hq_options.leaf_size)");
+        return HQ_E_UNSUPPORTED;
+    }
     if (!nblocks || !nvalues || body < 0 || body >= P->m) {
         set_error("NULL output or body out of range");
         return HQ_E_INVALID;
@@ -948,6 +998,10 @@ hq_status hq_explicit_blocks(hq_handle h, int64_t body, hq_precision prec, void 
                              int64_t *row_off, int64_t *bead_first, int32_t *rows, int32_t *cols, hq_stream stream) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
+    if (P->leaf_s > 1) {
+        set_error("explicit Q~ is not available for leaf boxes of more than one bead (hq_options.leaf_size)");
+        return HQ_E_UNSUPPORTED;
+    }
     if (!values || !val_off || !row_off || !bead_first || !rows || !cols || body < 0 || body >= P->m ||
         (prec != HQ_FP64 && prec != HQ_FP32)) {
         set_error("NULL argument, bad precision or body out of range");
@@ -1071,6 +1125,10 @@ hq_status hq_node_data(hq_handle h, int32_t *first, int32_t *last, int32_t *xchi
                        int32_t *nbeads, double *centroid, double *T22, double *G, int32_t *k, int32_t *row) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;
+    if ((centroid || T22 || G) && P->leaf_s > 1) {
+        set_error("per-node centroids, T22 and G are not kept inside leaf boxes (hq_options.leaf_size)");
+        return HQ_E_UNSUPPORTED;
+    }
     if ((centroid || T22) && !P->node_data_fresh) {
         set_error("centroids and T22 after hq_rebuild need hq_options.keep_node_data = 1");
         return HQ_E_INVALID;

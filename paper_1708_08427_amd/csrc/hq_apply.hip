@@ -490,6 +490,11 @@ __global__ void __launch_bounds__(64) k_down(int phase, const int32_t *__restric
 
 constexpr int kNT = 2;  // cache-policy operand of the streaming buffer accesses: nt
 
+// Ring depths of the wide sweeps: records kPR nodes ahead, memory inputs
+// kNR - 1 nodes ahead, in the first tile phase (1) and the later ones (L).
+constexpr int kPR1 = 6, kNR1 = 3, kPRL = 6, kNRL = 3;
+constexpr int kPR1d = 6, kNR1d = 3, kPRLd = 6, kNRLd = 3;
+
 template <typename T>
 __device__ __forceinline__ T bld(rsrc_t r, uint32_t vo, uint32_t so);
 template <>
@@ -512,10 +517,17 @@ __device__ __forceinline__ void bst<double>(double v, rsrc_t r, uint32_t vo, uin
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, kNT);
 }
 
+// Cache policy of the exchange accesses: the default, or (kSC1) the bit
+// that agent-scope relaxed atomics carry, which makes each access coherent
+// across the L2 caches of the device's compute dies.  The fused upward sweep
+// uses it, because there the entries pass between workgroups of one launch.
+constexpr int kSC1 = 16;
+
 // The six values of one exchange entry (slot, rhs) are contiguous.
+template <int XP = 0>
 __device__ __forceinline__ void bld6(rsrc_t r, uint32_t vo, float (&m)[6]) {
-    const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 0, 0);
-    const u32x3 b = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 12, 0);
+    const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 0, XP);
+    const u32x3 b = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 12, XP);
     m[0] = __uint_as_float(a.x);
     m[1] = __uint_as_float(a.y);
     m[2] = __uint_as_float(a.z);
@@ -523,25 +535,28 @@ __device__ __forceinline__ void bld6(rsrc_t r, uint32_t vo, float (&m)[6]) {
     m[4] = __uint_as_float(b.y);
     m[5] = __uint_as_float(b.z);
 }
+template <int XP = 0>
 __device__ __forceinline__ void bld6(rsrc_t r, uint32_t vo, double (&m)[6]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 16 * k, 0);
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 16 * k, XP);
         m[2 * k] = __builtin_bit_cast(double, u32x2{a.x, a.y});
         m[2 * k + 1] = __builtin_bit_cast(double, u32x2{a.z, a.w});
     }
 }
+template <int XP = 0>
 __device__ __forceinline__ void bst6(rsrc_t r, uint32_t vo, const float (&m)[6]) {
     __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(m[0]), __float_as_uint(m[1]), __float_as_uint(m[2])},
-                                          r, vo, 0, 0);
+                                          r, vo, 0, XP);
     __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(m[3]), __float_as_uint(m[4]), __float_as_uint(m[5])},
-                                          r, vo, 12, 0);
+                                          r, vo, 12, XP);
 }
+template <int XP = 0>
 __device__ __forceinline__ void bst6(rsrc_t r, uint32_t vo, const double (&m)[6]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const u32x2 a = __builtin_bit_cast(u32x2, m[2 * k]), b = __builtin_bit_cast(u32x2, m[2 * k + 1]);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, 16 * k, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, 16 * k, XP);
     }
 }
 
@@ -709,11 +724,11 @@ __device__ __forceinline__ void bstn(const T (&m)[NC], rsrc_t r, uint32_t vo, ui
 
 // Exchange entries are [slot][column][6 values]: a lane's NC entries are 6 NC
 // contiguous values.
-template <typename T, int NC>
+template <typename T, int NC, int XP = 0>
 __device__ __forceinline__ void bld6n(rsrc_t r, uint32_t vo, T (&m)[6][NC]) {
     if constexpr (NC == 1) {
         T e[6];
-        bld6(r, vo, e);
+        bld6<XP>(r, vo, e);
 #pragma unroll
         for (int k = 0; k < 6; ++k) m[k][0] = e[k];
     } else {
@@ -723,7 +738,7 @@ __device__ __forceinline__ void bld6n(rsrc_t r, uint32_t vo, T (&m)[6][NC]) {
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 24 * c + 12 * h, 0);
+                const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 24 * c + 12 * h, XP);
                 m[3 * h][c] = __uint_as_float(a.x);
                 m[3 * h + 1][c] = __uint_as_float(a.y);
                 m[3 * h + 2][c] = __uint_as_float(a.z);
@@ -731,13 +746,13 @@ __device__ __forceinline__ void bld6n(rsrc_t r, uint32_t vo, T (&m)[6][NC]) {
     }
 }
 
-template <typename T, int NC>
+template <typename T, int NC, int XP = 0>
 __device__ __forceinline__ void bst6n(rsrc_t r, uint32_t vo, const T (&m)[6][NC]) {
     if constexpr (NC == 1) {
         T e[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) e[k] = m[k][0];
-        bst6(r, vo, e);
+        bst6<XP>(r, vo, e);
     } else {
         static_assert(NC == 2 && sizeof(T) == 4, "two columns per lane are float");
         // four 12-byte pieces: each column's two triples
@@ -747,7 +762,7 @@ __device__ __forceinline__ void bst6n(rsrc_t r, uint32_t vo, const T (&m)[6][NC]
             for (int h = 0; h < 2; ++h)
                 __builtin_amdgcn_raw_buffer_store_b96(
                     u32x3{__float_as_uint(m[3 * h][c]), __float_as_uint(m[3 * h + 1][c]), __float_as_uint(m[3 * h + 2][c])},
-                    r, vo, 24 * c + 12 * h, 0);
+                    r, vo, 24 * c + 12 * h, XP);
     }
 }
 
@@ -882,7 +897,7 @@ __device__ __forceinline__ uint32_t xch_off(int slot, bool on, const Ctx &C, Lan
 // tail) or, with IW = 6, an earlier tile root's Info-set.  A stack child loads
 // nothing (zeros).  IW = 3 serves the first tile phase, whose only memory
 // inputs are beads.
-template <typename T, int RT, int IW, int NC, bool TRI>
+template <typename T, int RT, int IW, int NC, bool TRI, int XP = 0>
 __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B, const Ctx &C, LaneB lb) {
     if constexpr (IW == 6) {
         // later phases: beads are rare children there, so their loads go
@@ -898,7 +913,7 @@ __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B
     }
     if constexpr (IW == 6) {
         T e[6][NC];
-        bld6n<T, NC>(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
+        bld6n<T, NC, XP>(B.xch, xch_off<T, RT>(ref_slot(ref), ref < kRefStack, C, lb), e);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
 #pragma unroll
@@ -912,7 +927,7 @@ __device__ __forceinline__ void up_input(int ref, T (&m)[IW][NC], const WBufs &B
 // One upward node step (Eqs. 4.2-4.3).  A child of the same tile is read from
 // its LDS slot; a bead or an earlier tile's root comes from the prefetched
 // registers ax / ay.  Nothing is stored unless the node is live.
-template <typename T, int RT, int IW, int NC, bool TRI, bool ROT>
+template <typename T, int RT, int IW, int NC, bool TRI, bool ROT, int XP = 0>
 __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, const T (&ax)[IW][NC],
                                         const T (&ay)[IW][NC], const T (&rm)[9], T *lds, int lane, const WBufs &B,
                                         const Ctx &C, LaneB lb, bool live, bool act) {
@@ -977,7 +992,7 @@ __device__ __forceinline__ void up_node(const T (&g)[26], const Links6 &lk, cons
     const uint32_t ob = (uint32_t)lk.off * B.row + lb.v;
     if (en && any) bst3n<T, TRI, NC, 3>(t9, B.out, ob, B.row);
     if (en && both) bst3n<T, TRI, NC, 6>(t9, B.out, ob + 3 * B.row, B.row);
-    if (en && troot) bst6n<T, NC>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, true, C, lb), mp);
+    if (en && troot) bst6n<T, NC, XP>(B.xch, xch_off<T, RT>(lk.meta >> kMetaSlotShift, true, C, lb), mp);
     if (live && !troot) lds_put6<T, NC>(lds, os, lane, mp);
 }
 
@@ -1005,6 +1020,65 @@ __device__ __forceinline__ int wave_max_len(int len) {
     return __builtin_amdgcn_readfirstlane(len);
 }
 
+// The upward sweep of one lane group over schedule indices [base, base +
+// len) (a run of whole tiles, or one tile): records PR nodes ahead, memory
+// inputs NR - 1 nodes ahead; exchange accesses with cache policy XP.
+template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC, bool TRI, bool ROT, int XP>
+__device__ __forceinline__ void up_run(int base, int len, const T *__restrict__ rec, const T *__restrict__ rot,
+                                       T *lds, int lane, const WBufs &B, const Ctx &C, LaneB lb, bool act) {
+    const int maxlen = wave_max_len<LPT>(len);
+    const int last = max(len - 1, 0);
+    const T *rp = rec + (int64_t)kRecWords * base;
+    RecReg<T> RW[PR];
+    T A[NR][IW][NC], Bv[NR][IW][NC];
+    T RM[ROT ? NR : 1][9];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) RW[k].load(rp + (int64_t)min(k, last) * kRecWords, lane);
+#pragma unroll
+    for (int k = 0; k < NR - 1; ++k) {
+        const int2 ref = bcast_refs(RW[k]);
+        up_input<T, RT, IW, NC, TRI, XP>(ref.x, A[k], B, C, lb);
+        up_input<T, RT, IW, NC, TRI, XP>(ref.y, Bv[k], B, C, lb);
+        if constexpr (ROT) load_rot(rot, bcast_body(RW[k]), C.m, RM[k]);
+    }
+#define HQ_UP_STEP(K)                                                                       \
+    {                                                                                       \
+        const int n = n0 + (K);                                                             \
+        T g[26];                                                                            \
+        bcast_g<0>(g, RW[K]);                                                               \
+        const Links6 lk = bcast_links6(RW[K]);                                              \
+        RW[K].load(rp + (int64_t)min(n + PR, last) * kRecWords, lane);                      \
+        {                                                                                   \
+            const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                           \
+            up_input<T, RT, IW, NC, TRI, XP>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);      \
+            up_input<T, RT, IW, NC, TRI, XP>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);     \
+            if constexpr (ROT)                                                              \
+                load_rot(rot, bcast_body(RW[((K) + NR - 1) % PR]), C.m, RM[((K) + NR - 1) % NR]); \
+        }                                                                                   \
+        up_node<T, RT, IW, NC, TRI, ROT, XP>(g, lk, A[(K) % NR], Bv[(K) % NR], RM[ROT ? (K) % NR : 0], lds, lane, \
+                                             B, C, lb, n < len, act);                       \
+    }
+    for (int n0 = 0; n0 < maxlen; n0 += PR) {
+        HQ_UP_STEP(0)
+        HQ_UP_STEP(1)
+        HQ_UP_STEP(2)
+        if constexpr (PR >= 4) HQ_UP_STEP(3)
+        if constexpr (PR >= 6) {
+            HQ_UP_STEP(4)
+            HQ_UP_STEP(5)
+        }
+        if constexpr (PR >= 12) {
+            HQ_UP_STEP(6)
+            HQ_UP_STEP(7)
+            HQ_UP_STEP(8)
+            HQ_UP_STEP(9)
+            HQ_UP_STEP(10)
+            HQ_UP_STEP(11)
+        }
+    }
+#undef HQ_UP_STEP
+}
+
 template <typename T, int LPT, int RT, int PR, int NR, int IW, int NC, bool TRI, bool ROT>
 __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) k_up_wide(
     int phase, const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
@@ -1029,59 +1103,131 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
         const int rr = min(col, R - NC);
         int base, len;
         run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
-        const bool act = col < R;
         const LaneB lb{(uint32_t)(rr * (TRI ? 3 : 1) * sizeof(T)), (uint32_t)(rr * 6 * sizeof(T))};
+        up_run<T, LPT, RT, PR, NR, IW, NC, TRI, ROT, 0>(base, len, rec, rot, lds, lane, B, C, lb, col < R);
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// ---------------------------------------------------------------------------
+// The fused upward sweep: the whole of Algorithm 2 in one launch.
+//
+// Lane groups sweep the first tile phase's runs as above.  Every tile whose
+// root has a parent belongs to a parent tile (of a later phase) that counts
+// its child tiles; after a run, the group waits for its stores and takes one
+// arrival per tile root of the run from that counter (a device-scope atomic).
+// The group whose arrival empties a counter sweeps the parent tile itself --
+// its children's Info-sets are all in the exchange buffer by then -- and
+// arrives at that tile's parent in turn, so the later phases run inside the
+// launch, each tile started by the last of its children to finish, and no
+// group ever waits for another.  The exchange entries travel between
+// workgroups of the launch, so their stores and loads carry the agent-scope
+// coherence bit (kSC1), and a group's stores are complete (s_waitcnt
+// vmcnt(0)) before its arrival.  The counter's last arrival restores it to
+// the tile's child count for the next sweep.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// meta word of the record at schedule index s
+template <typename T>
+__device__ __forceinline__ int rec_meta(const T *__restrict__ rec, int s) {
+    return reinterpret_cast<const int32_t *>(rec + (int64_t)kRecWords * s + kRecLinks)[3];
+}
+
+// Arrival of a finished tile at its parent tile: returns the parent tile when
+// this arrival was the last one (the caller then sweeps it), else -1.
+__device__ __forceinline__ int tile_arrive(int t, const int32_t *__restrict__ ptile, int32_t *tcnt,
+                                           const int32_t *__restrict__ tcnt0, const Ctx &C, int &bad) {
+    if ((unsigned)t >= (unsigned)C.nsched) {
+        bad |= kFlagBounds;
+        return -1;
+    }
+    const int p = ptile[t];
+    if (p < 0) return -1;
+    if ((unsigned)p >= (unsigned)C.nsched) {
+        bad |= kFlagBounds;
+        return -1;
+    }
+    if (__hip_atomic_fetch_add(&tcnt[p], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1) return -1;
+    __hip_atomic_store(&tcnt[p], tcnt0[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return p;
+}
+
+// value of lane src of this lane's group of LPT lanes
+template <int LPT>
+__device__ __forceinline__ int group_read(int v, int src, int lane) {
+    return __shfl(v, (lane & ~(LPT - 1)) | src, 64);
+}
+
+template <typename T, int LPT, int RT, int NC, bool TRI, bool ROT>
+__global__ void __launch_bounds__(64, 2) k_up_fused(
+    const int32_t *__restrict__ prun, const int32_t *__restrict__ run, const T *__restrict__ rec,
+    const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch, const T *__restrict__ rot,
+    const int32_t *__restrict__ tile_base, const int32_t *__restrict__ tile_len, const int32_t *__restrict__ ptile,
+    int32_t *tcnt, const int32_t *__restrict__ tcnt0, Ctx C, int32_t *err) {
+    static_assert(LPT == 16 || LPT == 32 || LPT == 64, "wide sweeps use 16, 32 or 64 lanes per run");
+    static_assert(sizeof(T) == 4 || LPT >= 32, "double records are broadcast inside 32-lane halves");
+    extern __shared__ unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    constexpr int TPW = 64 / LPT;
+    const int R = rhs_count<RT>(C);
+    const int lane = threadIdx.x;
+    const int tslot = lane / LPT, rl = lane % LPT;
+    const int c0 = prun[kPrunStride * 1 + 2], nrun = prun[kPrunStride * 1 + 3];
+    const int items = ((nrun + TPW - 1) / TPW) * C.nchunks;
+    const WBufs B = wide_bufs<T, RT>(v, out, xch, C);
+    int bad = 0;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
+        const int col = (chunk * LPT + rl) * NC;
+        const int rr = min(col, R - NC);
+        const bool act = col < R;
+        int base, len;
+        run_range(grp * TPW + tslot, nrun, c0, run, C, base, len, bad);
+        const LaneB lb{(uint32_t)(rr * (TRI ? 3 : 1) * sizeof(T)), (uint32_t)(rr * 6 * sizeof(T))};
+        up_run<T, LPT, RT, kPR1, kNR1, 3, NC, TRI, ROT, kSC1>(base, len, rec, rot, lds, lane, B, C, lb, act);
+        // arrivals of the run's tile roots, LPT schedule indices at a time
+        // (the lanes of a group read consecutive records' meta words)
         const int maxlen = wave_max_len<LPT>(len);
-        const int last = max(len - 1, 0);
-        const T *rp = rec + (int64_t)kRecWords * base;
-        RecReg<T> RW[PR];
-        T A[NR][IW][NC], Bv[NR][IW][NC];
-        T RM[ROT ? NR : 1][9];
-#pragma unroll
-        for (int k = 0; k < PR; ++k) RW[k].load(rp + (int64_t)min(k, last) * kRecWords, lane);
-#pragma unroll
-        for (int k = 0; k < NR - 1; ++k) {
-            const int2 ref = bcast_refs(RW[k]);
-            up_input<T, RT, IW, NC, TRI>(ref.x, A[k], B, C, lb);
-            up_input<T, RT, IW, NC, TRI>(ref.y, Bv[k], B, C, lb);
-            if constexpr (ROT) load_rot(rot, bcast_body(RW[k]), C.m, RM[k]);
-        }
-#define HQ_UP_STEP(K)                                                                       \
-        {                                                                                   \
-            const int n = n0 + (K);                                                         \
-            T g[26];                                                                        \
-            bcast_g<0>(g, RW[K]);                                                           \
-            const Links6 lk = bcast_links6(RW[K]);                                          \
-            RW[K].load(rp + (int64_t)min(n + PR, last) * kRecWords, lane);                  \
-            {                                                                               \
-                const int2 ref = bcast_refs(RW[((K) + NR - 1) % PR]);                       \
-                up_input<T, RT, IW, NC, TRI>(ref.x, A[((K) + NR - 1) % NR], B, C, lb);      \
-                up_input<T, RT, IW, NC, TRI>(ref.y, Bv[((K) + NR - 1) % NR], B, C, lb);     \
-                if constexpr (ROT)                                                          \
-                    load_rot(rot, bcast_body(RW[((K) + NR - 1) % PR]), C.m, RM[((K) + NR - 1) % NR]); \
-            }                                                                               \
-            up_node<T, RT, IW, NC, TRI, ROT>(g, lk, A[(K) % NR], Bv[(K) % NR], RM[ROT ? (K) % NR : 0], lds, lane, \
-                                             B, C, lb, n < len, act);                       \
-        }
-        for (int n0 = 0; n0 < maxlen; n0 += PR) {
-            HQ_UP_STEP(0)
-            HQ_UP_STEP(1)
-            HQ_UP_STEP(2)
-            if constexpr (PR >= 4) HQ_UP_STEP(3)
-            if constexpr (PR >= 6) {
-                HQ_UP_STEP(4)
-                HQ_UP_STEP(5)
+        bool waited = false;
+        for (int k0 = 0; k0 < maxlen; k0 += LPT) {
+            int meta = 0;
+            if (k0 + rl < len) meta = rec_meta(rec, base + k0 + rl);
+            const bool arrives = (meta & kMetaTileRoot) && !(meta & kMetaBodyRoot);
+            if (!__builtin_amdgcn_ballot_w64(arrives)) continue;
+            if (!waited) {
+                wait_vmem();  // this wave's exchange stores are complete
+                waited = true;
             }
-            if constexpr (PR >= 12) {
-                HQ_UP_STEP(6)
-                HQ_UP_STEP(7)
-                HQ_UP_STEP(8)
-                HQ_UP_STEP(9)
-                HQ_UP_STEP(10)
-                HQ_UP_STEP(11)
+            int mine = arrives ? tile_arrive(meta >> kMetaSlotShift, ptile, tcnt, tcnt0, C, bad) : -1;
+            // sweep the tiles this group completed, one at a time, each
+            // followed up its chain of last arrivals
+            uint64_t todo = __builtin_amdgcn_ballot_w64(mine >= 0) >> (tslot * LPT);
+            if constexpr (LPT < 64) todo &= (1ull << LPT) - 1;
+            int cur = -1;
+            while (true) {
+                if (cur < 0 && todo) {
+                    const int src = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    cur = group_read<LPT>(mine, src, lane);
+                }
+                if (!__builtin_amdgcn_ballot_w64(cur >= 0)) break;
+                int tb = 0, tl = 0;
+                if (cur >= 0) {
+                    tb = tile_base[cur];
+                    tl = tile_len[cur];
+                    if (tb < 0 || tl < 0 || (int64_t)tb + tl > C.nsched) {
+                        bad |= kFlagBounds;
+                        tl = 0;
+                    }
+                }
+                up_run<T, LPT, RT, kPRL, kNRL, 6, NC, TRI, ROT, kSC1>(tb, tl, rec, rot, lds, lane, B, C, lb, act);
+                wait_vmem();
+                int nxt = -1;
+                if (cur >= 0 && rl == 0) nxt = tile_arrive(cur, ptile, tcnt, tcnt0, C, bad);
+                cur = group_read<LPT>(nxt, 0, lane);
             }
         }
-#undef HQ_UP_STEP
     }
     if (bad) atomicOr(err, bad);
 }
@@ -1298,9 +1444,184 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     // (measured: a deeper input ring for the later phases, five nodes ahead,
     // was 8% slower on their upward launches; a 12-deep record ring slower
     // still)
-    if (C.R == 32) HQ_WIDE(32, 6, 3, 6, 3, 6, 3, 6, 3);
-    else HQ_WIDE(0, 6, 3, 6, 3, 6, 3, 6, 3);
+    if (C.R == 32) HQ_WIDE(32, kPR1, kNR1, kPRL, kNRL, kPR1d, kNR1d, kPRLd, kNRLd);
+    else HQ_WIDE(0, kPR1, kNR1, kPRL, kNRL, kPR1d, kNR1d, kPRLd, kNRLd);
 #undef HQ_WIDE
+}
+
+// ---------------------------------------------------------------------------
+// Leaf boxes (the first tile phase of a handle with leaf_size > 1): each leaf
+// of n beads applies its transform diag(-1,-1,-1,1,...,1) Q^T (six stored
+// reflectors) to its 3n bead values.  Upward: [M; eps] = G f, the Info-set M
+// to the leaf's exchange entry, the 3n - 6 residues to the rows from the
+// leaf's first residue row.  Downward: f = G^T [L; w] with L from the
+// exchange entry (zero at a body root unless given).  G lanes per leaf, one
+// right-hand side per lane; the exchange entry in the layout of the sweeps
+// that follow (WX: wide [slot][R][6], else [slot][6][R]).
+// ---------------------------------------------------------------------------
+template <typename T, int G, int SMAX, bool WX, bool UP>
+__global__ void __launch_bounds__(64) k_bucket(const int32_t *__restrict__ phase_tab,
+                                               const int32_t *__restrict__ tile_root,
+                                               const int32_t *__restrict__ tile_base,
+                                               const int32_t *__restrict__ tile_len,
+                                               const int32_t *__restrict__ first, const int32_t *__restrict__ last,
+                                               const int32_t *__restrict__ perm, const int32_t *__restrict__ links,
+                                               const T *__restrict__ brec, int64_t bcap, const T *__restrict__ v,
+                                               T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
+    constexpr int MS = 3 * SMAX, BS = 6 * MS + 8, LPW = 64 / G;
+    const int lane = threadIdx.x;
+    const int slotw = lane / G, rl = lane % G;
+    const int tb = phase_tab[2 * 1], te = phase_tab[2 * 1 + 1];
+    const int ngroups = (te - tb + LPW - 1) / LPW;
+    const int items = ngroups * C.nchunks;
+    int bad = 0;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
+        const int t = tb + grp * LPW + slotw;
+        const int r = chunk * G + rl;
+        const bool act = r < C.R && t < te;
+        int f = 0, n = 0, off = 0, meta = 0;
+        if (t < te) {
+            const int q = tile_root[t], sr = tile_base[t] + tile_len[t] - 1;
+            if (q < 0 || q >= C.nsched || sr < 0 || sr >= C.nsched || (int64_t)(t - tb) >= bcap) {
+                bad |= kFlagBounds;
+            } else {
+                f = first[q];
+                n = last[q] - f + 1;
+                off = links[(int64_t)kLinkInts * sr + 2];
+                meta = links[(int64_t)kLinkInts * sr + 3];
+                if (n < 2 || n > SMAX || f < 0 || (int64_t)f + n > C.N || off < 0 ||
+                    (int64_t)off + 3 * n - 6 > C.rows) {
+                    bad |= kFlagBounds;
+                    n = 0;
+                }
+            }
+        }
+        const int mrows = 3 * n;
+        const T *g = brec + (int64_t)(t - tb) * BS;
+        const int slot = meta >> kMetaSlotShift;
+        const bool xok = (meta & kMetaTileRoot) && slot < C.xch_cap;
+        if (n > 0 && !xok) bad |= kFlagBounds;
+        auto xidx = [&](int d) -> int64_t {
+            return WX ? ((int64_t)slot * C.R + r) * 6 + d : ((int64_t)slot * 6 + d) * C.R + r;
+        };
+        T x[MS];
+#pragma unroll
+        for (int i = 0; i < MS; ++i) x[i] = T(0);
+        if (UP) {
+            if (act && n > 0)
+                for (int k = 0; k < n; ++k) {
+                    const int64_t u = perm[f + k];
+#pragma unroll
+                    for (int i = 0; i < MS; ++i)
+                        if (i / 3 == k) x[i] = v[velem(3 * u, i % 3, r, C)];
+                }
+            // x <- Q^T x = H_6 ... H_1 x
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const T tau = n > 0 ? g[6 * MS + j] : T(0);
+                T w = x[j];
+#pragma unroll
+                for (int i = j + 1; i < MS; ++i)
+                    if (i < mrows) w += g[j * MS + i] * x[i];
+                w *= tau;
+                x[j] -= w;
+#pragma unroll
+                for (int i = j + 1; i < MS; ++i)
+                    if (i < mrows) x[i] -= w * g[j * MS + i];
+            }
+            if (act && n > 0) {
+                if (xok) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) xch[xidx(d)] = (d < 3) ? -x[d] : x[d];
+                }
+#pragma unroll
+                for (int i = 6; i < MS; ++i)
+                    if (i < mrows) out[velem(off + 3 * ((i - 6) / 3), (i - 6) % 3, r, C)] = x[i];
+            }
+        } else {
+            if (act && n > 0) {
+                if (xok && (!(meta & kMetaBodyRoot) || C.root_in)) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) x[d] = (d < 3) ? -xch[xidx(d)] : xch[xidx(d)];
+                }
+#pragma unroll
+                for (int i = 6; i < MS; ++i)
+                    if (i < mrows) x[i] = v[velem(off + 3 * ((i - 6) / 3), (i - 6) % 3, r, C)];
+            }
+            // x <- Q x = H_1 ... H_6 x
+#pragma unroll
+            for (int j = 5; j >= 0; --j) {
+                const T tau = n > 0 ? g[6 * MS + j] : T(0);
+                T w = x[j];
+#pragma unroll
+                for (int i = j + 1; i < MS; ++i)
+                    if (i < mrows) w += g[j * MS + i] * x[i];
+                w *= tau;
+                x[j] -= w;
+#pragma unroll
+                for (int i = j + 1; i < MS; ++i)
+                    if (i < mrows) x[i] -= w * g[j * MS + i];
+            }
+            if (act && n > 0)
+                for (int k = 0; k < n; ++k) {
+                    const int64_t u = perm[f + k];
+#pragma unroll
+                    for (int i = 0; i < MS; ++i)
+                        if (i / 3 == k) out[velem(3 * u, i % 3, r, C)] = x[i];
+                }
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+template <typename T, int G, int SMAX>
+void launch_bucket_g(const Plan &P, bool up, bool wide, const T *brec, const T *v, T *out, T *xch, const Ctx &C,
+                     hipStream_t s) {
+    constexpr int LPW = 64 / G;
+    const int64_t items = ((P.bucket_cap + LPW - 1) / LPW) * (int64_t)C.nchunks;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 1 << 20));
+#define HQ_BK(WXV, UPV)                                                                                        \
+    hipLaunchKernelGGL((k_bucket<T, G, SMAX, WXV, UPV>), dim3(grid), dim3(64), 0, s, P.d_phase, P.d_tile_root, \
+                       P.d_tile_base, P.d_tile_len, P.d_first, P.d_last, P.d_perm, P.d_links, brec, P.bucket_cap,  \
+                       v, out, xch, C, P.d_err)
+    if (wide) {
+        if (up) HQ_BK(true, true);
+        else HQ_BK(true, false);
+    } else {
+        if (up) HQ_BK(false, true);
+        else HQ_BK(false, false);
+    }
+#undef HQ_BK
+}
+
+template <typename T, int G>
+void launch_bucket(const Plan &P, bool up, bool wide, const T *brec, const T *v, T *out, T *xch, const Ctx &C,
+                   hipStream_t s) {
+    // leaves of up to 8 beads take the 24-row kernel (records laid out for 8)
+    if (P.leaf_smax() <= 8) launch_bucket_g<T, G, 8>(P, up, wide, brec, v, out, xch, C, s);
+    else launch_bucket_g<T, G, 16>(P, up, wide, brec, v, out, xch, C, s);
+}
+
+// The fused upward sweep (one launch for every tile phase), grid as the first
+// phase's wide launch.
+template <typename T, int LPT, int NC, bool TRI, bool ROT>
+void launch_up_fused(const Plan &P, const T *rec, const T *v, T *out, T *xch, const T *rot, const Ctx &C,
+                     hipStream_t s) {
+    constexpr int TPW = 64 / LPT;
+    const size_t lds_w = (size_t)C.nslot * 6 * 64 * NC * sizeof(T);
+    const int64_t nrun_max = std::max<int64_t>(P.NI / P.run_nodes + 2, kRunTarget + 2);
+    const int64_t items = ((nrun_max + TPW - 1) / TPW) * (int64_t)C.nchunks;
+    const int64_t g = (P.first_wpc == 0) ? items : std::min<int64_t>(items, (int64_t)P.first_wpc * P.ncu);
+    const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
+    if (C.R == 32)
+        hipLaunchKernelGGL((k_up_fused<T, LPT, 32, NC, TRI, ROT>), dim3(grid), dim3(64), lds_w, s, P.d_prun, P.d_run,
+                           rec, v, out, xch, rot, P.d_tile_base, P.d_tile_len, P.d_ptile, P.d_tcnt, P.d_tcnt0, C,
+                           P.d_err);
+    else
+        hipLaunchKernelGGL((k_up_fused<T, LPT, 0, NC, TRI, ROT>), dim3(grid), dim3(64), lds_w, s, P.d_prun, P.d_run,
+                           rec, v, out, xch, rot, P.d_tile_base, P.d_tile_len, P.d_ptile, P.d_tcnt, P.d_tcnt0, C,
+                           P.d_err);
 }
 
 template <typename T, int LPT>
@@ -1363,22 +1684,86 @@ void launch_root_io(const Plan &P, bool wide, T *xch, T *root, int to_xch, const
 
 // Sweep kinds: narrow (lanes per tile 1..16, tile stack in LDS) and wide
 // (runs of whole tiles, explicit slots, buffer addressing).
-enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide32, kWide64 };
+enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide16, kWide32, kWide64 };
+
+// fewest right-hand sides the wide sweeps take (sweep_kernel = 0)
+constexpr int kWideMinR = 8;
 
 template <typename T>
 void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
                 const T *rot, const Ctx &C, hipStream_t s, hipEvent_t *ev) {
     const bool tri = C.vlane == 3;
     const int nph = std::max(P.phases_built, P.phases_reserved);
+    if (!transpose && P.fused_up && C.nchunks == 1 && P.leaf_s <= 1 &&
+        (kind == kWide16 || kind == kWide32 || kind == kWide64)) {
+        // every tile phase in one launch (the arrival counters count a
+        // tile's children once, so one column chunk per sweep: up to 64
+        // right-hand sides); its time is reported as the first phase's, the
+        // later phases' as 0
+        if (ev) (void)hipEventRecord(ev[0], s);
+#define HQ_FUSED(LPT)                                                                                          \
+        do {                                                                                                   \
+            if (rot) {                                                                                         \
+                if (tri) launch_up_fused<T, LPT, 1, true, true>(P, rec, v, out, xch, rot, C, s);               \
+                else launch_up_fused<T, LPT, 1, false, true>(P, rec, v, out, xch, rot, C, s);                  \
+            } else {                                                                                           \
+                if (tri) launch_up_fused<T, LPT, 1, true, false>(P, rec, v, out, xch, rot, C, s);              \
+                else launch_up_fused<T, LPT, 1, false, false>(P, rec, v, out, xch, rot, C, s);                 \
+            }                                                                                                  \
+        } while (0)
+        if (kind == kWide16) {
+            if constexpr (sizeof(T) == 4) HQ_FUSED(16);
+        } else if (kind == kWide32) {
+            HQ_FUSED(32);
+        } else {
+            HQ_FUSED(64);
+        }
+#undef HQ_FUSED
+        if (ev)
+            for (int k = 1; k <= nph; ++k) (void)hipEventRecord(ev[k], s);
+        return;
+    }
     for (int k = 0; k < nph; ++k) {
         const int phase = transpose ? (nph - k) : (k + 1);
         if (ev) (void)hipEventRecord(ev[k], s);
+        if (phase == 1 && P.leaf_s > 1) {
+            // the first phase holds the leaf boxes
+            const T *brec = sizeof(T) == 8 ? reinterpret_cast<const T *>(P.d_brec64)
+                                           : reinterpret_cast<const T *>(P.d_brec32);
+            const bool wide = kind == kWide16 || kind == kWide32 || kind == kWide64;
+            // one lane per leaf for a single right-hand side, else groups of
+            // 16, 32 or 64 lanes (idle lanes beyond the columns)
+            switch (kind) {
+            case kNarrow1: launch_bucket<T, 1>(P, !transpose, wide, brec, v, out, xch, C, s); break;
+            case kNarrow2:
+            case kNarrow4:
+            case kNarrow8:
+            case kNarrow16:
+            case kWide16: launch_bucket<T, 16>(P, !transpose, wide, brec, v, out, xch, C, s); break;
+            case kWide32: launch_bucket<T, 32>(P, !transpose, wide, brec, v, out, xch, C, s); break;
+            case kWide64: launch_bucket<T, 64>(P, !transpose, wide, brec, v, out, xch, C, s); break;
+            }
+            continue;
+        }
         switch (kind) {
         case kNarrow1: launch_narrow<T, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow2: launch_narrow<T, 2>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow4: launch_narrow<T, 4>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow8: launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
+        case kWide16:
+            // 16-lane runs (four per wave) broadcast float records inside
+            // 16-lane rows; double records need 32-lane halves
+            if constexpr (sizeof(T) == 4) {
+                if (rot) {
+                    if (tri) launch_wide<T, 16, 1, true, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                    else launch_wide<T, 16, 1, false, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                } else {
+                    if (tri) launch_wide<T, 16, 1, true, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                    else launch_wide<T, 16, 1, false, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
+                }
+            }
+            break;
         case kWide32:
             if (rot) {
                 if (tri) launch_wide<T, 32, 1, true, true>(P, phase, transpose, rec, v, out, xch, rot, C, s);
@@ -1442,26 +1827,44 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     C.in_bytes = (uint32_t)std::min<int64_t>(vin, lim);
     C.out_bytes = (uint32_t)std::min<int64_t>(vout, lim);
     C.xch_bytes = (uint32_t)std::min<int64_t>(vx, lim);
-    // more than 16 right-hand sides: wide sweeps (one column per lane; two
-    // columns per lane measured slower: 4 runs per wave lose more to uneven
-    // run lengths and to LDS-limited occupancy than they save in VALU work);
-    // otherwise, or beyond the buffer range, narrow sweeps
+    // Wide sweeps (a lane group per run of whole tiles, one column per lane,
+    // each node record read once per group and broadcast): 32 or 64 lanes
+    // per run above 16 right-hand sides; 8 to 16 of them, 16-lane runs
+    // (FP32) or 32-lane runs (FP64, whose records need 32 lanes), the lanes
+    // beyond the columns computing alongside without storing.  (Two columns
+    // per lane measured slower: 4 runs per wave lose more to uneven run
+    // lengths and to LDS-limited occupancy than they save in VALU work.)
+    // Narrow sweeps (a lane group per tile, each lane reading whole records)
+    // below 8 right-hand sides (measured faster at one: 0.31 against 0.39 ms
+    // for both sweeps of 1,000 bodies of 200-2,000 beads, where a 16-lane run
+    // idles 15 lanes; slower at 16: 0.29 against 0.21 ms on a 65,536-bead
+    // body), beyond the wide sweeps' 2 GiB range, or on request.
     int lpt = lanes_per_tile(nrhs);
-    if (lpt >= 32 && !wide_ok) lpt = 16;
     SweepKind kind;
-    const int cols = lpt;  // right-hand sides per chunk
-    if (lpt >= 32) {
-        kind = (lpt == 32) ? kWide32 : kWide64;
+    int cols;  // right-hand sides per chunk
+    if (wide_ok && P.sweep_kernel != 1 && nrhs >= kWideMinR) {
+        if (lpt >= 32) {
+            kind = (lpt == 32) ? kWide32 : kWide64;
+            cols = lpt;
+        } else if (prec == HQ_FP32) {
+            kind = kWide16;
+            cols = 16;
+        } else {
+            kind = kWide32;
+            cols = 32;
+        }
     } else {
+        lpt = std::min(lpt, 16);
         kind = lpt == 1 ? kNarrow1 : lpt == 2 ? kNarrow2 : lpt == 4 ? kNarrow4 : lpt == 8 ? kNarrow8 : kNarrow16;
+        cols = lpt;
     }
     C.nchunks = (int)((nrhs + cols - 1) / cols);
     C.dmax = stack_depth(P.smax());
     C.nslot = stack_slots(P.smax());
-    const bool wide = kind == kWide32 || kind == kWide64;
-    // rigid-motion rotations are fused into the wide sweeps only; the caller
-    // turns the vectors in separate passes for the narrow ones
-    if (rot && !wide) return HQ_E_UNSUPPORTED;
+    const bool wide = kind == kWide16 || kind == kWide32 || kind == kWide64;
+    // rigid-motion rotations are fused into the wide sweeps only (not into
+    // leaf boxes); the caller turns the vectors in separate passes otherwise
+    if (rot && (!wide || P.leaf_s > 1)) return HQ_E_UNSUPPORTED;
     if (prec == HQ_FP64) {
         if (root && transpose) launch_root_io<double>(P, wide, (double *)xch, (double *)root, 1, C, s);
         launch_all<double>(P, transpose, kind, P.d_rec64, (const double *)v, (double *)out, (double *)xch, rot, C,

@@ -1219,6 +1219,222 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
     if (bad) raise_flag(err, kFlagBounds);
 }
 
+// ---------------------------------------------------------------------------
+// Leaf boxes of up to s beads (Section 2.1 lets the bisection stop at boxes
+// of at most s beads).  They are the first tile phase's tiles of a handle
+// with leaf_size s (a tile of at most s bead units is a maximal subtree of at
+// most s beads, a leaf box), and each is factored densely: its 3n x 6 matrix
+// X = [U_t^T | Z_r^T] (translation rows [I ... I] / sqrt(n), rotation rows
+// [A_1 ... A_n] about the leaf's centroid, beads in tree order) by six
+// Householder reflections in the convention of the nodes.  Its transform is
+// diag(-1,-1,-1,1,...,1) Q^T: rows 1-3 the translation rows, rows 4-6 the
+// rotation rows with T22 = R(4:6,4:6)^T, rows 7..3n its residue rows.  The
+// tiles above it see the leaf as an earlier tile's root: (n, c, T22) in the
+// tile-root table, its Info-set in the exchange buffer.
+//
+// Six lanes per leaf (lane j holds column j of X), ten leaves per wave; at
+// step p lane p forms reflector p and hands it to lanes p+1..5 through LDS.
+// Record of leaf b (the phase's b-th tile): column-major 3 s_max x 6 (entries
+// below the diagonal of column j are reflector j's tail), then the six taus.
+// ---------------------------------------------------------------------------
+constexpr int kBucketLanes = 6;
+constexpr int kBucketsPerWave = 10;
+
+template <int SMAX, int kStore>
+__global__ void __launch_bounds__(64) k_gen_bucket(const int32_t *__restrict__ phase_tab,
+                                                   const int32_t *__restrict__ tile_root,
+                                                   const int32_t *__restrict__ tile_base,
+                                                   const int32_t *__restrict__ tile_len,
+                                                   const int32_t *__restrict__ first, const int32_t *__restrict__ last,
+                                                   const int32_t *__restrict__ nbody, const int32_t *__restrict__ perm,
+                                                   const int32_t *__restrict__ links, const double *__restrict__ pos,
+                                                   const double *__restrict__ lo, double *troot, int64_t ntr,
+                                                   double *brec64, float *brec32, int64_t bcap, double *bcen,
+                                                   unsigned long long *kappa, int32_t *bflags, int64_t m_bodies,
+                                                   int64_t N, int64_t NI, int32_t *err) {
+    constexpr int MS = 3 * SMAX, BS = 6 * MS + 8;
+    __shared__ double vbuf[kBucketsPerWave][MS + 8];
+    __shared__ double rbuf[kBucketsPerWave][9];
+    const int lane = threadIdx.x;
+    const int bq = lane / kBucketLanes, j = lane - bq * kBucketLanes;
+    const int tb = phase_tab[2 * 1], te = phase_tab[2 * 1 + 1];
+    bool bad = false;
+    for (int t0 = tb + blockIdx.x * kBucketsPerWave; t0 < te; t0 += gridDim.x * kBucketsPerWave) {
+        const int t = t0 + bq;
+        const bool on = bq < kBucketsPerWave && t < te && (int64_t)(t - tb) < bcap;
+        int f = 0, n = 0, body = 0, meta = 0;
+        if (bq < kBucketsPerWave && t < te && !on) bad = true;
+        if (on) {
+            const int r = tile_root[t];
+            const int sr = tile_base[t] + tile_len[t] - 1;
+            if (r < 0 || r >= NI || sr < 0 || sr >= NI) {
+                bad = true;
+            } else {
+                f = first[r];
+                n = last[r] - f + 1;
+                body = nbody[r];
+                meta = links[(int64_t)kLinkInts * sr + 3];
+                if (n < 2 || n > SMAX || f < 0 || (int64_t)f + n > N || body < 0 || body >= m_bodies) {
+                    bad = true;
+                    n = 0;
+                }
+            }
+        }
+        const int mrows = 3 * n;
+        // the leaf's centroid (body-local), and column j of X
+        double c[3] = {0.0, 0.0, 0.0}, lo3[3] = {0.0, 0.0, 0.0};
+        if (n > 0)
+            for (int d = 0; d < 3; ++d) lo3[d] = lo[3 * body + d];
+        for (int k = 0; k < n; ++k) {
+            const int64_t u = perm[f + k];
+            for (int d = 0; d < 3; ++d) c[d] += pos[3 * u + d] - lo3[d];
+        }
+        for (int d = 0; d < 3; ++d) c[d] = n > 0 ? c[d] / (double)n : 0.0;
+        const double rs = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
+        double col[MS];
+#pragma unroll
+        for (int i = 0; i < MS; ++i) col[i] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double u[3];
+            const int64_t b = perm[f + k];
+            for (int d = 0; d < 3; ++d) u[d] = pos[3 * b + d] - lo3[d] - c[d];
+            // column j < 3: U_t^T; column 3 + e: Z_r^T = A_k^T, A_k = [u]x
+            const double A[3][3] = {{0.0, -u[2], u[1]}, {u[2], 0.0, -u[0]}, {-u[1], u[0], 0.0}};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double x = 0.0;
+                if (j < 3) x = (d == j) ? rs : 0.0;
+                else if (j < 6) x = A[j - 3][d];
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+                    if (i == 3 * k + d) col[i] = x;
+            }
+        }
+        double tau_j = 0.0;
+        for (int p = 0; p < 6; ++p) {
+            if (j == p && n > 0) {
+                const double alpha = col[p];
+                double xs = 0.0;
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+                    if (i > p && i < mrows) xs += col[i] * col[i];
+                const double xnorm = sqrt(xs);
+                if (xnorm == 0.0 || p >= mrows - 1) {
+                    tau_j = 0.0;
+                } else {
+                    const double nrm = sqrt(alpha * alpha + xnorm * xnorm);
+                    const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                    tau_j = (beta - alpha) / beta;
+                    const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+                    for (int i = 0; i < MS; ++i)
+                        if (i > p && i < mrows) col[i] *= scal;
+                    col[p] = beta;
+                }
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+                    if (i > p) vbuf[bq][i] = (i < mrows) ? col[i] : 0.0;
+                vbuf[bq][MS] = tau_j;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (j > p && j < 6 && n > 0) {
+                const double tp = vbuf[bq][MS];
+                if (tp != 0.0) {
+                    double w = col[p];
+#pragma unroll
+                    for (int i = 0; i < MS; ++i)
+                        if (i > p) w += vbuf[bq][i] * col[i];
+                    w *= tp;
+                    col[p] -= w;
+#pragma unroll
+                    for (int i = 0; i < MS; ++i)
+                        if (i > p) col[i] -= w * vbuf[bq][i];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // records: reflector j's tail and tau_j
+        if (j < 6 && n > 0) {
+            const int64_t base = (int64_t)(t - tb) * BS;
+#pragma unroll
+            for (int i = 0; i < MS; ++i) {
+                const double x = (i > j && i < mrows) ? col[i] : 0.0;
+                if (kStore & 1) brec64[base + j * MS + i] = x;
+                if (kStore & 2) brec32[base + j * MS + i] = (float)x;
+            }
+            if (kStore & 1) brec64[base + 6 * MS + j] = tau_j;
+            if (kStore & 2) brec32[base + 6 * MS + j] = (float)tau_j;
+        }
+        // T22 = R(4:6,4:6)^T: lane 3 + i holds R(3 .. 3 + i, 3 + i)
+        if (j >= 3 && j < 6 && n > 0)
+            for (int q = 0; q <= j - 3; ++q) rbuf[bq][(j - 3) * 3 + q] = col[3 + q];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (j == 0 && n > 0) {
+            double T[6] = {rbuf[bq][0], rbuf[bq][3], rbuf[bq][4], rbuf[bq][6], rbuf[bq][7], rbuf[bq][8]};
+            if (n == 2) T[5] = 0.0;  // rank-2 rotation rows of two beads
+            const double kap = (n >= 3) ? cond_bound3(T) : 0.0;
+            if (t < ntr) {
+                double *tr = troot + (int64_t)kGenWords * t;
+                tr[0] = (double)n;
+                for (int d = 0; d < 3; ++d) tr[1 + d] = c[d];
+                for (int d = 0; d < 6; ++d) tr[4 + d] = T[d];
+            } else {
+                bad = true;
+            }
+            const bool body_root = (meta & kMetaBodyRoot) != 0;
+            if (kap > 0.0) {
+                atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(kap));
+                if (kap > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
+            }
+            if (body_root) {
+                if (n == 2 || kap > 1e12) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+                for (int d = 0; d < 3; ++d) bcen[3 * body + d] = c[d] + lo3[d];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (bad) raise_flag(err, kFlagBounds);
+}
+
+// Tile tables of the fused upward sweep: each tile's parent tile (the tile
+// holding its root's parent node; -1 for a body root), and the child-tile
+// counts, which the sweep's arrival counters start from.
+__global__ void k_tile_zero(int64_t NI, const int32_t *__restrict__ cnt, int32_t *tcnt0) {
+    const int64_t nt = min((int64_t)cnt[kCntTiles], NI);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        tcnt0[t] = 0;
+}
+
+__global__ void k_tile_parents(int64_t NI, const int32_t *__restrict__ cnt, const int32_t *__restrict__ tile_root,
+                               const int32_t *__restrict__ par, const int32_t *__restrict__ tileof, int32_t *ptile,
+                               int32_t *tcnt0, int32_t *err) {
+    const int64_t nt = min((int64_t)cnt[kCntTiles], NI);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int r = tile_root[t];
+        if (r < 0 || r >= NI) {
+            raise_flag(err, kFlagBounds);
+            ptile[t] = -1;
+            continue;
+        }
+        const int p = par[r];
+        const int pt = (p >= 0 && p < NI) ? tileof[p] : -1;
+        ptile[t] = pt;
+        if (pt >= 0 && pt < nt) atomicAdd(&tcnt0[pt], 1);
+        else if (p >= 0) raise_flag(err, kFlagBounds);
+    }
+}
+
+__global__ void k_tile_copy(int64_t NI, const int32_t *__restrict__ cnt, const int32_t *__restrict__ tcnt0,
+                            int32_t *tcnt) {
+    const int64_t nt = min((int64_t)cnt[kCntTiles], NI);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        tcnt[t] = tcnt0[t];
+}
+
 // Rigid motion: r <- Rot (r - c) + c + t per body.
 __global__ void __launch_bounds__(kThreads) k_rigid(const int32_t *__restrict__ chunks, double *pos,
                                                     const double *__restrict__ rot, const double *__restrict__ trans,
@@ -1349,6 +1565,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             int32_t cnt[kCntNum];
             HQ_HIP(hipMemcpyAsync(cnt, P.d_cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
             HQ_HIP(hipStreamSynchronize(s));
+            if (ph == 1) P.tiles1_built = cnt[kCntTiles];
             if (cnt[kCntRemain] == 0) {
                 P.tiles_built = cnt[kCntTiles];
                 break;
@@ -1368,6 +1585,13 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm, toff,
                        P.d_slot, stack_slots(P.smax()), P.d_lw, P.d_links, P.d_err);
+    {
+        const unsigned tg = std::min(grid_for(NI), 2048u);
+        hipLaunchKernelGGL(k_tile_zero, dim3(tg), dim3(kThreads), 0, s, NI, P.d_cnt, P.d_tcnt0);
+        hipLaunchKernelGGL(k_tile_parents, dim3(tg), dim3(kThreads), 0, s, NI, P.d_cnt, P.d_tile_root, P.d_par,
+                           P.d_tileof, P.d_ptile, P.d_tcnt0, P.d_err);
+        hipLaunchKernelGGL(k_tile_copy, dim3(tg), dim3(kThreads), 0, s, NI, P.d_cnt, P.d_tcnt0, P.d_tcnt);
+    }
     // --- 5. transforms, one launch per tile phase; later phases read the
     // roots of earlier phases' tiles from the tile-root table (sized after
     // the first build: twice its tiles, the capacity of the exchange buffer)
@@ -1387,6 +1611,26 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         P.d_troot = reinterpret_cast<double *>(q);
         P.troot_cap = cap;
     }
+    // leaf-box records: twice the first build's leaves (a rebuilt tree with
+    // more raises HQ_FLAG_BOUNDS); a workspace handle has them already
+    if (probe_phases && P.leaf_s > 1 && P.bucket_cap < 2 * P.tiles1_built + 64) {
+        if (P.ws) {
+            set_error("the tree has more leaf boxes than the workspace holds");
+            return HQ_E_UNSUPPORTED;
+        }
+        const int64_t cap = 2 * P.tiles1_built + 64;
+        const size_t per = (size_t)bucket_stride(P.leaf_smax());
+        void *q = nullptr;
+        if (P.store & 1) {
+            HQ_TRY(plan_alloc(P, &q, (size_t)cap * per * sizeof(double)));
+            P.d_brec64 = reinterpret_cast<double *>(q);
+        }
+        if (P.store & 2) {
+            HQ_TRY(plan_alloc(P, &q, (size_t)cap * per * sizeof(float)));
+            P.d_brec32 = reinterpret_cast<float *>(q);
+        }
+        P.bucket_cap = cap;
+    }
     const int nslot = stack_slots(P.smax());
     const size_t gen_lds = (size_t)nslot * kGenWords * 64 * sizeof(double) + ((P.store & 2) ? kStageBytes : 0);
     const unsigned gen_grid = (unsigned)std::min<int64_t>((P.tiles_built + P.tiles_built / 4) / 64 + 1, 65535);
@@ -1404,7 +1648,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     // the first phase's tiles longest first, when every buffer the generation
     // writes can be addressed from its start with 32-bit offsets
     const int64_t lim = 0x7fffffffll;
-    const bool sort_tiles = NI * 256 < lim && P.troot_cap * 80 < lim && m * 24 < lim;
+    const bool sort_tiles = P.leaf_s <= 1 && NI * 256 < lim && P.troot_cap * 80 < lim && m * 24 < lim;
     if (sort_tiles) {
         const int nbins = P.S;
         hipLaunchKernelGGL(k_len_hist, dim3(kLenBlocks), dim3(256), 0, s, 1, P.d_phase, P.d_tile_len, nbins, P.d_lhist);
@@ -1414,6 +1658,25 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     }
     for (int ph = 1; ph <= phases; ++ph) {
         const bool later = ph > 1;
+        if (ph == 1 && P.leaf_s > 1) {
+            const unsigned bg = (unsigned)std::min<int64_t>(P.bucket_cap / kBucketsPerWave + 1, 65535);
+#define HQ_GEN_BUCKET(SM, ST)                                                                                   \
+    hipLaunchKernelGGL((k_gen_bucket<SM, ST>), dim3(bg), dim3(64), 0, s, P.d_phase, P.d_tile_root, P.d_tile_base, \
+                       P.d_tile_len, P.d_first, P.d_last, P.d_nbody, P.d_perm, P.d_links, pos, P.d_lo, P.d_troot, \
+                       P.troot_cap, P.d_brec64, P.d_brec32, P.bucket_cap, P.d_cen, P.d_kappa, P.d_bflags, m, N, NI, \
+                       P.d_err)
+#define HQ_GEN_BUCKET_S(SM)                                    \
+    do {                                                       \
+        if ((P.store & 3) == 1) HQ_GEN_BUCKET(SM, 1);          \
+        else if ((P.store & 3) == 2) HQ_GEN_BUCKET(SM, 2);     \
+        else HQ_GEN_BUCKET(SM, 3);                             \
+    } while (0)
+            if (P.leaf_smax() == 8) HQ_GEN_BUCKET_S(8);
+            else HQ_GEN_BUCKET_S(16);
+#undef HQ_GEN_BUCKET_S
+#undef HQ_GEN_BUCKET
+            continue;
+        }
         hipLaunchKernelGGL(gen_fn[later][P.store & 3][nodes ? 1 : 0], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
                            gen_lds, s, ph, P.d_phase, P.d_tile_base, P.d_tile_len, P.d_tile_root, P.d_links,
                            P.d_nbody, pos, P.d_lo, P.d_troot, P.troot_cap, nslot, P.d_ncen, P.d_T22, P.d_rec32,

@@ -120,6 +120,11 @@ inline int stack_depth(int S) { return floor_log2(S) + 2; }
 // results of a tile.
 inline int stack_slots(int S) { return floor_log2(S) + 1; }
 
+// Leaf boxes: largest leaf size, and the values of one leaf record for
+// leaves of up to smax beads (column-major 3 smax x 6 reflectors, 6 taus, pad)
+constexpr int kMaxLeaf = 16;
+inline int bucket_stride(int smax) { return 6 * 3 * smax + 8; }
+
 // Run table: per phase (node begin, node end, first entry, runs, run length)
 // at stride kPrunStride; a phase is cut into at least ~kRunTarget runs when it
 // has that many tiles.
@@ -144,6 +149,14 @@ struct Plan {
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int waves_per_cu = 16;    // grid of the later phases' sweeps, waves per CU
     int first_wpc = 0;        // grid cap of the first phase's wide sweeps, waves per CU (0: none)
+    int sweep_kernel = 0;     // 0: wide sweeps unless a buffer exceeds their range; 1: narrow sweeps
+    int fused_up = 0;         // 1: the wide upward sweep in one launch; 0: one launch per tile phase
+    int leaf_s = 1;           // leaf boxes hold up to leaf_s beads (>1: the first tile phase is leaves)
+    int leaf_smax() const { return leaf_s <= 8 ? 8 : 16; }  // leaf-record layout and kernel instance
+    int64_t tiles1_built = 0; // first-phase tiles (leaf boxes) of the last hq_build
+    int64_t bucket_cap = 0;   // leaf-box records held
+    double *d_brec64 = nullptr;  // leaf-box records (bucket_stride values each)
+    float *d_brec32 = nullptr;
     int ncu = 256;            // compute units of the device
     bool keep_node_data = false;  // hq_rebuild writes per-node centroids and T22
     bool node_data_fresh = false; // they describe the last (re)build
@@ -208,6 +221,9 @@ struct Plan {
     // tiles and schedule
     int32_t *d_tile_root = nullptr, *d_tile_base = nullptr, *d_tile_len = nullptr;
     int32_t *d_sched_node = nullptr; // schedule index -> node
+    int32_t *d_ptile = nullptr;      // tile -> tile holding its root's parent (-1 at a body root)
+    int32_t *d_tcnt = nullptr;       // tile -> child tiles yet to arrive in the fused upward sweep
+    int32_t *d_tcnt0 = nullptr;      // tile -> child tiles (the counters' value between sweeps)
     int32_t *d_links = nullptr;      // schedule index -> int32[kLinkInts] links
     float *d_rec32 = nullptr;        // NI x 32
     double *d_rec64 = nullptr;       // NI x 32

@@ -157,20 +157,27 @@ def test_bd_step_workload_sampled_bodies(hq):
 
 
 def test_bd_step_wide_and_narrow_sweeps_agree(hq):
-    """The wide sweeps (R >= 32, links read from the records) and the narrow
-    ones (R < 32, links read from the link table) on the benchmark's workload:
-    the same products column by column, for all 4,096 bodies."""
+    """The wide sweeps (links read from the records) and the narrow ones
+    (links read from the link table, forced with sweep_kernel = 1) on the
+    benchmark's workload: the same products column by column, for all 4,096
+    bodies, with 32 columns wide against 4 narrow, and 4 wide (16-lane runs
+    in FP32, 32-lane runs in FP64) against 4 narrow."""
     w = W.bd_m4096()
     rng = np.random.default_rng(5)
     f = rng.standard_normal((3 * w.N, 32))
     g = rng.standard_normal((w.rows, 32))
     h = _build(hq, w, store=3)
+    hn = _build(hq, w, store=3, sweep_kernel=1)
     for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
         up = h.apply(_dev(f, dt)).cpu().numpy().astype(np.float64)
         dn = h.apply(_dev(g, dt), transpose=True).cpu().numpy().astype(np.float64)
         for c0 in (0, 13, 28):
-            up4 = h.apply(_dev(f[:, c0:c0 + 4], dt)).cpu().numpy().astype(np.float64)
-            dn4 = h.apply(_dev(g[:, c0:c0 + 4], dt), transpose=True).cpu().numpy().astype(np.float64)
+            up4 = hn.apply(_dev(f[:, c0:c0 + 4], dt)).cpu().numpy().astype(np.float64)
+            dn4 = hn.apply(_dev(g[:, c0:c0 + 4], dt), transpose=True).cpu().numpy().astype(np.float64)
+            upw = h.apply(_dev(f[:, c0:c0 + 4], dt)).cpu().numpy().astype(np.float64)
+            dnw = h.apply(_dev(g[:, c0:c0 + 4], dt), transpose=True).cpu().numpy().astype(np.float64)
+            assert np.abs(upw - up4).max() <= tol * np.abs(f).max()
+            assert np.abs(dnw - dn4).max() <= tol * np.abs(g).max()
             assert np.abs(up[:, c0:c0 + 4] - up4).max() <= tol * np.abs(f).max()
             assert np.abs(dn[:, c0:c0 + 4] - dn4).max() <= tol * np.abs(g).max()
     assert h.query()["device_flags"] == 0

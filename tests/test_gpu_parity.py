@@ -59,12 +59,12 @@ def oracle_products(w, v, wv):
     return bt, bt.apply(v), bt.apply(wv, transpose=True)
 
 
-def check_fp64(hq, w, S=0, nrhs=None, S2=0, min_checked=None):
+def check_fp64(hq, w, S=0, nrhs=None, S2=0, min_checked=None, **opts):
     rng = np.random.default_rng(123)
     R = nrhs or w.nrhs
     v = rng.standard_normal((3 * w.N, R))
     wv = rng.standard_normal((w.rows, R))
-    h = build(hq, w, tile_units=S, later_tile_units=S2)
+    h = build(hq, w, tile_units=S, later_tile_units=S2, **opts)
     bt, up_o, dn_o = oracle_products(w, v, wv)
     up = h.apply(_dev(v)).cpu().numpy()
     dn = h.apply(_dev(wv), transpose=True).cpu().numpy()
@@ -143,10 +143,43 @@ def test_batch_fp64_later_tile_sizes(hq, S, S2):
     check_fp64(hq, w, S=S, nrhs=40, S2=S2)
 
 
-@pytest.mark.parametrize("R", [1, 5, 16, 32, 64, 70])
+@pytest.mark.parametrize("R", [1, 5, 8, 16, 32, 64, 70])
 def test_nrhs_shapes(hq, R):
     w = W.small_batch(12, [40, 700, 1200])
     check_fp64(hq, w, S=128, nrhs=R)
+
+
+@pytest.mark.parametrize("R", [1, 5, 16])
+def test_narrow_sweeps_on_request(hq, R):
+    """The narrow sweeps (a lane group per tile), which serve buffers beyond
+    the wide sweeps' range, against the oracle at small R."""
+    w = W.small_batch(12, [40, 700, 1200])
+    check_fp64(hq, w, S=64, nrhs=R, sweep_kernel=1)
+
+
+@pytest.mark.parametrize("R", [1, 3, 8, 11, 16])
+def test_small_nrhs_fp32(hq, R):
+    """FP32 at R <= 16 (narrow sweeps below 8, 16-lane runs from 8) against
+    FP64 and the leak, two tile sizes, both directions."""
+    w = W.small_batch(17, [2, 3, 90, 700, 2300, 1100], nrhs=R)
+    rng = np.random.default_rng(17)
+    v = rng.standard_normal((3 * w.N, R))
+    wv = rng.standard_normal((w.rows, R))
+    for S in (16, 64):
+        h = build(hq, w, tile_units=S)
+        up64 = h.apply(_dev(v)).cpu().numpy()
+        dn64 = h.apply(_dev(wv), transpose=True).cpu().numpy()
+        up32 = h.apply(_dev(v, torch.float32)).cpu().numpy().astype(np.float64)
+        dn32 = h.apply(_dev(wv, torch.float32), transpose=True).cpu().numpy().astype(np.float64)
+        assert h.query()["device_flags"] == 0
+        for j in range(w.m):
+            r0, r1 = h.row_offsets[j], h.row_offsets[j + 1]
+            b0, b1 = 3 * w.offsets[j], 3 * w.offsets[j + 1]
+            if r1 == r0:
+                continue
+            assert (np.linalg.norm(up32[r0:r1] - up64[r0:r1], axis=0) / np.linalg.norm(v[b0:b1], axis=0)).max() <= 1e-5
+            assert (np.linalg.norm(dn32[b0:b1] - dn64[b0:b1], axis=0) / np.linalg.norm(wv[r0:r1], axis=0)).max() <= 1e-5
+            assert dense.leak(w.pos[w.offsets[j]:w.offsets[j + 1]], dn32[b0:b1]).max() <= 1e-5
 
 
 def test_results_independent_of_tile_size(hq):
