@@ -127,11 +127,20 @@ typedef struct {
     int32_t krylov_nrhs;   /* hq_build_into: right-hand sides of hq_constrained_solve whose
                               work vectors the workspace holds; 0 = none (the solve then fails
                               on the handle with HQ_E_UNSUPPORTED) */
-    int32_t sweep_kernel;  /* 0: wide sweeps (a lane group per run of whole tiles, node
-                              records read once per group and broadcast) for 8 or more
-                              right-hand sides when every vector buffer stays below 2 GiB,
-                              else narrow ones; 1: narrow sweeps (a lane group per tile,
-                              lanes reading whole records).  Results agree to rounding */
+    int32_t sweep_kernel;  /* Which sweep kernels run; results agree to rounding.
+                              0 (automatic): the first tile phase with the wide sweeps (a
+                              lane group per run of whole tiles, node records read once per
+                              group and broadcast) for 8 or more right-hand sides when every
+                              vector buffer stays below 2 GiB, else with a lane group per
+                              tile; the later phases node-parallel (a lane per node and
+                              right-hand side, a tile's levels resolved in LDS) where their
+                              tiles fit a workgroup, else as the first.
+                              1: a lane group per tile (lanes reading whole records) in
+                              every phase.
+                              2: node-parallel in every phase whose tiles hold at most 64
+                              units (up to 8 right-hand sides per pass).
+                              3: the wide sweeps in every phase, for any number of
+                              right-hand sides (buffers below 2 GiB). */
     int32_t fused_upward;  /* 0: one launch per tile phase; 1: the wide upward sweep
                               (Algorithm 2) of up to 64 right-hand sides in one launch, each
                               later-phase tile swept by the workgroup whose child tile
@@ -304,8 +313,10 @@ typedef int (*hq_dapply_fn)(const void *x, void *y, int64_t nrhs, void *user, hq
 typedef struct {
     int32_t max_iter;          /* in: CG iteration limit; 0 = 500 */
     double rtol;               /* in: relative residual target per RHS; 0 = 1e-8 */
-    int32_t iters;             /* out: iterations done */
+    int32_t iters;             /* out: most iterations taken by one RHS */
     double max_rel_residual;   /* out: largest ||r|| / ||b|| over the RHS */
+    int32_t check_every;       /* in: iterations between the host's convergence checks
+                                  (1..64; 0 = 4) */
 } hq_krylov_info;
 
 /* The constrained Brownian-dynamics solve of Section 1: the constraint forces
@@ -320,10 +331,16 @@ typedef struct {
  *   dx, dy  device workspace, 3N x nrhs elements each (caller-owned): the
  *       solve writes D's input into dx and calls dapply(dx, dy, ...).
  *   info  host, in/out (limits and results).
- * Synchronises the stream every iteration (host-side CG scalars); allocates
- * and frees its own workspace (four vectors of rows x nrhs).  HQ_E_INVALID if an argument
- * is NULL, the callback fails or Q~ D Q~^T is not positive definite; other
- * errors as for hq_apply_full. */
+ * The CG scalars (one CG per right-hand side, FP64) stay on the device: a
+ * column that has converged takes zero steps while others go on, and the host
+ * synchronises the stream once every check_every iterations to read how many
+ * columns are still active (so the loop may run up to check_every - 1
+ * iterations past convergence without changing the results).  Allocates and
+ * frees its own workspace (four vectors of rows x nrhs and the scalars),
+ * unless the handle was built into a workspace with krylov_nrhs.
+ * HQ_E_INVALID if an argument is NULL, the callback fails or Q~ D Q~^T is
+ * not positive definite (reported at the next check); other errors as for
+ * hq_apply_full. */
 hq_status hq_constrained_solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, void *V, void *g,
                                int64_t nrhs, hq_precision prec, hq_layout layout, void *dx, void *dy,
                                hq_krylov_info *info, hq_stream stream);

@@ -433,12 +433,13 @@ def build_into(positions, offsets, workspace=None, stream=None, **options):
     return h
 
 
-def constrained_solve(h, dapply, F, layout="rows", rtol=1e-8, max_iter=500, stream=None):
+def constrained_solve(h, dapply, F, layout="rows", rtol=1e-8, max_iter=500, stream=None, check_every=4):
     """hq_constrained_solve: the constraint forces g of Eq. 1.5 by conjugate
     gradients on Q~ D Q~^T and the rigid-body velocities V of Eq. 1.6.
     ``dapply(x, y)`` writes D x into y (torch tensors of the vector shape
     (3N, R), or (N, R, 3) in the triples layout) on the current stream.
-    ``F``: (6m, R) or (2m, R, 3).  Returns (V, g, info dict)."""
+    ``F``: (6m, R) or (2m, R, 3).  The host checks convergence every
+    ``check_every`` iterations.  Returns (V, g, info dict)."""
     torch = _torch()
     _check_dev(F, "F")
     if layout not in LAYOUTS:
@@ -472,7 +473,9 @@ def constrained_solve(h, dapply, F, layout="rows", rtol=1e-8, max_iter=500, stre
             return 1
 
     fn = _lib.DAPPLY_FN(cb)
-    info = _lib.KrylovInfo(int(max_iter), float(rtol), 0, 0.0)
+    if not 1 <= int(check_every) <= 64:
+        raise ValueError("check_every must be in [1, 64]")
+    info = _lib.KrylovInfo(int(max_iter), float(rtol), 0, 0.0, int(check_every))
     st = _lib.load().hq_constrained_solve(h._h(), fn, None, _ptr(F), _ptr(V), _ptr(g), R, _prec(F.dtype),
                                           LAYOUTS[layout], _ptr(dx), _ptr(dy), ctypes.byref(info), _stream(ts))
     if errors:

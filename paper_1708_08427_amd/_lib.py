@@ -31,7 +31,7 @@ class Options(ctypes.Structure):
 
 class KrylovInfo(ctypes.Structure):
     _fields_ = [("max_iter", c_i32), ("rtol", ctypes.c_double), ("iters", c_i32),
-                ("max_rel_residual", ctypes.c_double)]
+                ("max_rel_residual", ctypes.c_double), ("check_every", c_i32)]
 
 
 # int (*)(const void *x, void *y, int64_t nrhs, void *user, hq_stream stream)

@@ -527,8 +527,9 @@ hq_status check_build_args(const int64_t *body_offsets, int64_t m, const hq_opti
             set_error("fused_upward must be 0 (one launch per tile phase) or 1 (one upward launch)");
             return HQ_E_INVALID;
         }
-        if (opt->sweep_kernel < 0 || opt->sweep_kernel > 1) {
-            set_error("sweep_kernel must be 0 (wide sweeps where they fit) or 1 (narrow sweeps)");
+        if (opt->sweep_kernel < 0 || opt->sweep_kernel > 3) {
+            set_error("sweep_kernel must be 0 (automatic), 1 (a lane group per tile), 2 (node-parallel sweeps) "
+                      "or 3 (wide sweeps in every phase)");
             return HQ_E_INVALID;
         }
         if (opt->max_nrhs < 0 || opt->max_nrhs > (1 << 20) || opt->max_tiles < 0 || opt->krylov_nrhs < 0 ||

@@ -465,6 +465,407 @@ __global__ void __launch_bounds__(64) k_down(int phase, const int32_t *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Node-parallel sweeps (few right-hand sides): one lane per (node, column).
+// A workgroup takes whole tiles of at most TS - 1 nodes, lane slot i of a
+// tile holding the tile's i-th node in schedule order.  Every lane issues its
+// node's record and memory inputs at once; the tile's dependencies are then
+// resolved in LDS, one tree level per round, so no round waits on HBM.
+//
+// The schedule is a post-order that takes one child's subtree before the
+// other's (yfirst in the links), so a node with two children in its own tile
+// finds the child taken second in the slot just before its own, and the one
+// taken first before that child's subtree; a node with one such child finds
+// it in the slot before its own.  Subtree sizes (in nodes of the tile) are
+// therefore all the upward sweep needs, and it computes them as it goes; the
+// downward sweep finds them in a first, integer-only round.
+//
+// Every case of k (3, 6, 9) runs the length-9 reflectors on a zero-padded
+// vector: the stored tails are zero beyond k, so the results equal the
+// length-k products, and the lanes of a round do not diverge on k.
+// ---------------------------------------------------------------------------
+
+// Index of value k of exchange entry (slot, column r): [slot][R][6] (the
+// layout of the wide sweeps) or [slot][6][R].
+template <bool WX>
+__device__ __forceinline__ int64_t xidx(int slot, int k, int r, const Ctx &C) {
+    return WX ? ((int64_t)slot * C.R + r) * 6 + k : ((int64_t)slot * 6 + k) * C.R + r;
+}
+
+template <typename T, bool WX>
+__device__ __forceinline__ void np_fetch(int ref, T (&m)[6], const T *__restrict__ v, const T *__restrict__ xch,
+                                         const Ctx &C, int r, bool act, int32_t *err) {
+    if (ref >= 0) {
+        if (ref >= C.N) {
+            atomicOr(err, kFlagBounds);
+        } else if (act) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m[c] = v[velem((int64_t)3 * ref, c, r, C)];
+        }
+    } else if (ref != kRefStack) {
+        const int slot = ref_slot(ref);
+        if (slot < 0 || slot >= C.xch_cap) {
+            atomicOr(err, kFlagBounds);
+        } else if (act) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) m[c] = xch[xidx<WX>(slot, c, r, C)];
+        }
+    }
+}
+
+// The node's record (reflectors, weights) and its links, which the record
+// carries from element kRecLinks on.
+template <typename T>
+__device__ __forceinline__ int4 np_record(const T *__restrict__ rec, int s, T (&g)[26]) {
+    const T *p = rec + (int64_t)kRecWords * s;
+    load_g(g, p);
+    const int2 *lk = reinterpret_cast<const int2 *>(p + kRecLinks);
+    const int2 a = lk[0], b = lk[1];
+    return make_int4(a.x, a.y, b.x, b.y);
+}
+
+// Slots of the children in the node's own tile (-1: elsewhere) from the
+// subtree size z2 of the slot before q: (x slot, y slot).
+__device__ __forceinline__ int2 np_children(int q, int xref, int yref, int meta, int z2) {
+    const bool xs = xref == kRefStack, ys = yref == kRefStack;
+    int xq = -1, yq = -1;
+    if (xs && ys) {
+        // the child taken second sits just before the node
+        if (meta & kMetaYFirst) {
+            xq = q - 1;
+            yq = q - 1 - z2;
+        } else {
+            yq = q - 1;
+            xq = q - 1 - z2;
+        }
+    } else if (xs) {
+        xq = q - 1;
+    } else if (ys) {
+        yq = q - 1;
+    }
+    return make_int2(xq, yq);
+}
+
+// Work item geometry shared by both directions.
+template <int NB, int CW, int TS>
+struct NpGeom {
+    static constexpr int TPB = NB / (TS * CW);  // tiles per workgroup
+    int q, c, tl, i;
+    __device__ NpGeom() {
+        const int tid = threadIdx.x;
+        q = tid / CW;
+        c = tid - q * CW;
+        tl = q / TS;
+        i = q - tl * TS;
+    }
+};
+
+// Upward (Algorithm 2) for one tile phase.
+template <typename T, int NB, int CW, int TS, bool WX>
+__global__ void __launch_bounds__(NB) k_up_np(int phase, const int32_t *__restrict__ phase_tab,
+                                              const int32_t *__restrict__ tile_base,
+                                              const int32_t *__restrict__ tile_len, const T *__restrict__ rec,
+                                              const T *__restrict__ v, T *__restrict__ out, T *__restrict__ xch,
+                                              Ctx C, int32_t *err) {
+    __shared__ T sv[NB * 6];
+    __shared__ int ssz[NB / CW];
+    const NpGeom<NB, CW, TS> G;
+    constexpr int TPB = NpGeom<NB, CW, TS>::TPB;
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    const int items = ((te - tb + TPB - 1) / TPB) * C.nchunks;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
+        const int t = tb + grp * TPB + G.tl;
+        const int r = chunk * CW + G.c;
+        int base = 0, len = 0;
+        if (t < te) {
+            base = tile_base[t];
+            len = tile_len[t];
+            if (base < 0 || len < 0 || len > TS || (int64_t)base + len > C.nsched) {
+                atomicOr(err, kFlagBounds);
+                len = 0;
+            }
+        }
+        const bool valid = G.i < len;
+        const bool act = valid && r < C.R;
+        T g[26];
+        T ma[6], mb[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ma[k] = mb[k] = T(0);
+        int4 lk = make_int4(0, 0, 0, 0);
+        if (valid) {
+            lk = np_record(rec, base + G.i, g);
+            np_fetch<T, WX>(lk.x, ma, v, xch, C, r, act, err);
+            np_fetch<T, WX>(lk.y, mb, v, xch, C, r, act, err);
+        }
+        const int xref = lk.x, yref = lk.y, off = lk.z, meta = lk.w;
+        const int nst = (int)(xref == kRefStack) + (int)(yref == kRefStack);
+        if (valid && nst > 0 && G.i == 0) {
+            // a tile's first node has no node of its own tile before it
+            atomicOr(err, kFlagStack);
+        }
+        const int q0 = G.tl * TS;  // the tile's first slot
+        bool done = !valid || (nst > 0 && G.i == 0);
+        __syncthreads();  // the previous item's rounds are over
+        if (G.c == 0) ssz[G.q] = 0;
+        for (int round = 0; round <= TS; ++round) {
+            if (!__syncthreads_or(!done)) break;
+            // read the subtree sizes published by earlier rounds
+            int z2 = 0, z1 = 0;
+            int2 ch = make_int2(-1, -1);
+            bool ready = false;
+            if (!done) {
+                if (nst == 0) {
+                    ready = true;
+                } else {
+                    z2 = ssz[G.q - 1];
+                    if (z2 > 0) {
+                        ch = np_children(G.q, xref, yref, meta, z2);
+                        if (nst == 1) {
+                            ready = true;
+                        } else {
+                            const int q1 = G.q - 1 - z2;
+                            if (q1 < q0) {
+                                atomicOr(err, kFlagStack);
+                                done = true;
+                            } else {
+                                z1 = ssz[q1];
+                                ready = z1 > 0;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (ready) {
+                T mx[6], my[6];
+                const int cx = ch.x >= 0 ? ch.x : 0, cy = ch.y >= 0 ? ch.y : 0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    mx[k] = ch.x >= 0 ? sv[(cx * 6 + k) * CW + G.c] : ma[k];
+                    my[k] = ch.y >= 0 ? sv[(cy * 6 + k) * CW + G.c] : mb[k];
+                }
+                const T sx = g[kRecSx], sy = g[kRecSy];
+                const bool xi = xref < 0, yi = yref < 0;
+                T mp[6], sh[3], t9[9];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    mp[k] = sx * mx[k] + sy * my[k];
+                    sh[k] = sy * mx[k] - sx * my[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    t9[k] = xi ? mx[3 + k] : (yi ? my[3 + k] : sh[k]);
+                    t9[3 + k] = (xi && yi) ? my[3 + k] : ((xi || yi) ? sh[k] : T(0));
+                    t9[6 + k] = (xi && yi) ? sh[k] : T(0);
+                }
+                house_fwd<9>(t9, g);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) mp[3 + k] = t9[k];
+                const int dim = 3 * ((int)xi + (int)yi);
+                if (dim > 0) {
+                    if (off < 0 || (int64_t)off + dim > C.rows) {
+                        atomicOr(err, kFlagBounds);
+                    } else if (act) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) out[velem(off, k, r, C)] = t9[3 + k];
+                        if (dim == 6) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) out[velem(off + 3, k, r, C)] = t9[6 + k];
+                        }
+                    }
+                }
+                if (meta & kMetaTileRoot) {
+                    const int slot = meta >> kMetaSlotShift;
+                    if (slot >= C.xch_cap) {
+                        atomicOr(err, kFlagBounds);
+                    } else if (act) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) xch[xidx<WX>(slot, k, r, C)] = mp[k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) sv[(G.q * 6 + k) * CW + G.c] = mp[k];
+                }
+                if (G.c == 0) ssz[G.q] = 1 + z2 + z1;
+                done = true;
+            }
+        }
+        if (!done) atomicOr(err, kFlagStack);
+    }
+}
+
+// Downward (Algorithm 3) for one tile phase.  The node's own Velocity-set
+// arrives in its LDS slot from its parent (a tile root: from the exchange
+// buffer, zero at a body root unless given).
+template <typename T, int NB, int CW, int TS, bool WX>
+__global__ void __launch_bounds__(NB) k_down_np(int phase, const int32_t *__restrict__ phase_tab,
+                                                const int32_t *__restrict__ tile_base,
+                                                const int32_t *__restrict__ tile_len, const T *__restrict__ rec,
+                                                const T *__restrict__ w, T *__restrict__ out, T *__restrict__ xch,
+                                                Ctx C, int32_t *err) {
+    __shared__ T sv[NB * 6];
+    __shared__ int ssz[NB / CW];
+    __shared__ int sready[NB / CW];
+    const NpGeom<NB, CW, TS> G;
+    constexpr int TPB = NpGeom<NB, CW, TS>::TPB;
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    const int items = ((te - tb + TPB - 1) / TPB) * C.nchunks;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
+        const int t = tb + grp * TPB + G.tl;
+        const int r = chunk * CW + G.c;
+        int base = 0, len = 0;
+        if (t < te) {
+            base = tile_base[t];
+            len = tile_len[t];
+            if (base < 0 || len < 0 || len > TS || (int64_t)base + len > C.nsched) {
+                atomicOr(err, kFlagBounds);
+                len = 0;
+            }
+        }
+        const bool valid = G.i < len;
+        const bool act = valid && r < C.R;
+        T g[26];
+        T a[6], lin[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a[k] = lin[k] = T(0);
+        int4 lk = make_int4(0, 0, 0, 0);
+        if (valid) {
+            lk = np_record(rec, base + G.i, g);
+            const int off = lk.z;
+            const int dim = 3 * (int)(lk.x < 0) + 3 * (int)(lk.y < 0);
+            if (dim > 0) {
+                if (off < 0 || (int64_t)off + dim > C.rows) {
+                    atomicOr(err, kFlagBounds);
+                } else if (act) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) a[k] = w[velem(off, k, r, C)];
+                    if (dim == 6) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) a[3 + k] = w[velem(off + 3, k, r, C)];
+                    }
+                }
+            }
+            if ((lk.w & kMetaTileRoot) && (!(lk.w & kMetaBodyRoot) || C.root_in)) {
+                const int slot = lk.w >> kMetaSlotShift;
+                if (slot >= C.xch_cap) {
+                    atomicOr(err, kFlagBounds);
+                } else if (act) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) lin[k] = xch[xidx<WX>(slot, k, r, C)];
+                }
+            }
+        }
+        const int xref = lk.x, yref = lk.y, meta = lk.w;
+        const int nst = (int)(xref == kRefStack) + (int)(yref == kRefStack);
+        const int q0 = G.tl * TS;
+        bool bad = valid && nst > 0 && G.i == 0;
+        if (bad) atomicOr(err, kFlagStack);
+        // round 0: subtree sizes, bottom up (integers only)
+        bool sized = !valid || bad;
+        __syncthreads();  // the previous item's rounds are over
+        if (G.c == 0) {
+            ssz[G.q] = (valid && nst == 0) ? 1 : 0;
+            sready[G.q] = 0;
+        }
+        if (valid && nst == 0) sized = true;
+        for (int round = 0; round <= TS; ++round) {
+            if (!__syncthreads_or(!sized)) break;
+            int nz = 0;
+            if (!sized) {
+                const int z2 = ssz[G.q - 1];
+                if (z2 > 0) {
+                    if (nst == 1) {
+                        nz = 1 + z2;
+                    } else if (G.q - 1 - z2 < q0) {
+                        atomicOr(err, kFlagStack);
+                        sized = true;
+                        bad = true;
+                    } else {
+                        const int z1 = ssz[G.q - 1 - z2];
+                        if (z1 > 0) nz = 1 + z2 + z1;
+                    }
+                }
+            }
+            __syncthreads();
+            if (nz > 0) {
+                if (G.c == 0) ssz[G.q] = nz;
+                sized = true;
+            }
+        }
+        if (!sized) {
+            atomicOr(err, kFlagStack);
+            bad = true;
+        }
+        __syncthreads();
+        int2 ch = make_int2(-1, -1);
+        if (valid && !bad && nst > 0) ch = np_children(G.q, xref, yref, meta, ssz[G.q - 1]);
+        // rounds 1..: Velocity-sets, top down
+        bool done = !valid || bad;
+        for (int round = 0; round <= TS; ++round) {
+            if (!__syncthreads_or(!done)) break;
+            const bool ready = !done && ((meta & kMetaTileRoot) || sready[G.q] != 0);
+            __syncthreads();
+            if (ready) {
+                T L[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) L[k] = (meta & kMetaTileRoot) ? lin[k] : sv[(G.q * 6 + k) * CW + G.c];
+                const T sx = g[kRecSx], sy = g[kRecSy];
+                const bool xi = xref < 0, yi = yref < 0;
+                T x9[9];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) x9[k] = L[3 + k];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) x9[3 + k] = a[k];
+                house_bwd<9>(x9, g);
+                T st[3], Lx[6], Ly[6];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Lx[3 + k] = xi ? x9[k] : T(0);
+                    Ly[3 + k] = (xi && yi) ? x9[3 + k] : (yi ? x9[k] : T(0));
+                    st[k] = (xi && yi) ? x9[6 + k] : ((xi || yi) ? x9[3 + k] : x9[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Lx[k] = sx * L[k] + sy * st[k];
+                    Ly[k] = sy * L[k] - sx * st[k];
+                }
+                auto emit = [&](int ref, int cq, const T (&Lc)[6]) {
+                    if (ref >= 0) {
+                        if (ref >= C.N) {
+                            atomicOr(err, kFlagBounds);
+                        } else if (act) {
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) out[velem((int64_t)3 * ref, k, r, C)] = Lc[k];
+                        }
+                    } else if (ref == kRefStack) {
+                        if (cq < q0 || cq >= G.q) {
+                            atomicOr(err, kFlagStack);
+                            return;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) sv[(cq * 6 + k) * CW + G.c] = Lc[k];
+                        if (G.c == 0) sready[cq] = 1;
+                    } else {
+                        const int slot = ref_slot(ref);
+                        if (slot < 0 || slot >= C.xch_cap) {
+                            atomicOr(err, kFlagBounds);
+                        } else if (act) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) xch[xidx<WX>(slot, k, r, C)] = Lc[k];
+                        }
+                    }
+                };
+                emit(xref, ch.x, Lx);
+                emit(yref, ch.y, Ly);
+                done = true;
+            }
+        }
+        if (!done) atomicOr(err, kFlagStack);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Wide sweeps: a lane group of 32 or 64 lanes (one right-hand side per lane)
 // sweeps a run of whole tiles; a wave holds two groups of 32 or one of 64.
 //
@@ -1641,6 +2042,64 @@ void launch_narrow(const Plan &P, int phase, int transpose, const T *rec, const 
                            P.d_tile_len, P.d_links, rec, v, out, xch, C, P.d_err);
 }
 
+// Node-parallel sweeps of one tile phase: TS slots per tile (a power of two
+// above the phase's tile size), CW columns per node.
+template <typename T, int CW, int TS, bool WX>
+void launch_np_ts(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
+                  hipStream_t s) {
+    constexpr int NB = TS * CW > 256 ? TS * CW : 256;
+    constexpr int TPB = NB / (TS * CW);
+    // the first phase: a workgroup per tile group of the largest first phase a
+    // rebuild can make; later phases hold few tiles and stride over them
+    const int64_t groups = (2 * (int64_t)P.tiles_built + 64 + TPB - 1) / TPB;
+    const int64_t items = groups * (int64_t)C.nchunks;
+    const unsigned grid = (unsigned)std::min<int64_t>(items, phase == 1 ? (1 << 20) : 4096);
+    if (!transpose)
+        hipLaunchKernelGGL((k_up_np<T, NB, CW, TS, WX>), dim3(grid), dim3(NB), 0, s, phase, P.d_phase, P.d_tile_base,
+                           P.d_tile_len, rec, v, out, xch, C, P.d_err);
+    else
+        hipLaunchKernelGGL((k_down_np<T, NB, CW, TS, WX>), dim3(grid), dim3(NB), 0, s, phase, P.d_phase,
+                           P.d_tile_base, P.d_tile_len, rec, v, out, xch, C, P.d_err);
+}
+
+// Slots per tile for the node-parallel sweeps of a phase (0: its tiles are
+// too large for them).
+int np_slots(const Plan &P, int phase) {
+    const int S = phase == 1 ? P.S : P.S2;
+    return S <= 16 ? 16 : S <= 32 ? 32 : S <= 64 ? 64 : 0;
+}
+
+template <typename T, int CW>
+void launch_np(const Plan &P, int phase, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
+               hipStream_t s) {
+    switch (np_slots(P, phase)) {
+    case 16: launch_np_ts<T, CW, 16, false>(P, phase, transpose, rec, v, out, xch, C, s); break;
+    case 32: launch_np_ts<T, CW, 32, false>(P, phase, transpose, rec, v, out, xch, C, s); break;
+    default: launch_np_ts<T, CW, 64, false>(P, phase, transpose, rec, v, out, xch, C, s); break;
+    }
+}
+
+enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide16, kWide32, kWide64 };
+
+// Node-parallel launch of a later phase of a 16-column FP32 wide sweep;
+// false where it does not apply.  (At 32 columns a workgroup of a whole tile
+// holds 1,024 lanes that each load the node's record; on the bench workload
+// that made the second phase 2.8 times slower than the wide sweep, so wider
+// sweeps keep the wide kernel in every phase.)
+template <typename T>
+bool launch_np_wide(const Plan &P, int phase, int transpose, SweepKind kind, const T *rec, const T *v, T *out, T *xch,
+                    const Ctx &C, hipStream_t s) {
+    const int ts = np_slots(P, phase);
+    if (ts == 0 || kind != kWide16) return false;
+    if constexpr (sizeof(T) == 4) {
+        if (ts == 16) launch_np_ts<T, 16, 16, true>(P, phase, transpose, rec, v, out, xch, C, s);
+        else if (ts == 32) launch_np_ts<T, 16, 32, true>(P, phase, transpose, rec, v, out, xch, C, s);
+        else launch_np_ts<T, 16, 64, true>(P, phase, transpose, rec, v, out, xch, C, s);
+        return true;
+    }
+    return false;
+}
+
 // The full Q = [Q_Z; Q~] (Algorithms 2 and 3 with the root kept): every body
 // root is the root of a tile, whose exchange entry holds the root's Info-set
 // after the upward sweep and supplies its Velocity-set to the downward one.
@@ -1684,7 +2143,6 @@ void launch_root_io(const Plan &P, bool wide, T *xch, T *root, int to_xch, const
 
 // Sweep kinds: narrow (lanes per tile 1..16, tile stack in LDS) and wide
 // (runs of whole tiles, explicit slots, buffer addressing).
-enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide16, kWide32, kWide64 };
 
 // fewest right-hand sides the wide sweeps take (sweep_kernel = 0)
 constexpr int kWideMinR = 8;
@@ -1745,12 +2203,46 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
             }
             continue;
         }
+        // node-parallel sweeps (up to 8 columns per pass) where the phase's
+        // tiles fit them: in the later phases of 16 units or more by default,
+        // in every phase on request.  (The first phase stays with the lane
+        // group per tile: there every lane is busy already, and a
+        // node-parallel round issues the node arithmetic across all the
+        // tile's lanes, once per level; tiles of 8 units are short chains
+        // for a lane group, and fill half a node-parallel tile's lanes.)
+        const bool np = np_slots(P, phase) > 0 &&
+                        (P.sweep_kernel == 2 || (P.sweep_kernel == 0 && phase > 1 && P.S2 >= 16));
+        if (kind != kWide16 && kind != kWide32 && kind != kWide64) {
+            switch (kind) {
+            case kNarrow1:
+                if (np) launch_np<T, 1>(P, phase, transpose, rec, v, out, xch, C, s);
+                else launch_narrow<T, 1>(P, phase, transpose, rec, v, out, xch, C, s);
+                break;
+            case kNarrow2:
+                if (np) launch_np<T, 2>(P, phase, transpose, rec, v, out, xch, C, s);
+                else launch_narrow<T, 2>(P, phase, transpose, rec, v, out, xch, C, s);
+                break;
+            case kNarrow4:
+                if (np) launch_np<T, 4>(P, phase, transpose, rec, v, out, xch, C, s);
+                else launch_narrow<T, 4>(P, phase, transpose, rec, v, out, xch, C, s);
+                break;
+            case kNarrow8:
+                if (np) launch_np<T, 8>(P, phase, transpose, rec, v, out, xch, C, s);
+                else launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s);
+                break;
+            case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
+            default: break;
+            }
+            continue;
+        }
+        // the later phases of a wide sweep, node-parallel (one lane per node
+        // and column, the wide sweeps' exchange layout) where those phases
+        // hold few tiles, so that the wide sweep's chains would leave the
+        // device idle
+        if (!rot && phase > 1 && P.sweep_kernel == 0 && P.tiles_built - P.tiles1_built <= 4 * (int64_t)P.ncu &&
+            launch_np_wide(P, phase, transpose, kind, rec, v, out, xch, C, s))
+            continue;
         switch (kind) {
-        case kNarrow1: launch_narrow<T, 1>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kNarrow2: launch_narrow<T, 2>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kNarrow4: launch_narrow<T, 4>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kNarrow8: launch_narrow<T, 8>(P, phase, transpose, rec, v, out, xch, C, s); break;
-        case kNarrow16: launch_narrow<T, 16>(P, phase, transpose, rec, v, out, xch, C, s); break;
         case kWide16:
             // 16-lane runs (four per wave) broadcast float records inside
             // 16-lane rows; double records need 32-lane halves
@@ -1842,7 +2334,7 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     int lpt = lanes_per_tile(nrhs);
     SweepKind kind;
     int cols;  // right-hand sides per chunk
-    if (wide_ok && P.sweep_kernel != 1 && nrhs >= kWideMinR) {
+    if (wide_ok && (P.sweep_kernel == 3 || (P.sweep_kernel == 0 && nrhs >= kWideMinR))) {
         if (lpt >= 32) {
             kind = (lpt == 32) ? kWide32 : kWide64;
             cols = lpt;
@@ -1854,7 +2346,9 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
             cols = 32;
         }
     } else {
-        lpt = std::min(lpt, 16);
+        // node-parallel sweeps take up to 8 columns per pass, the
+        // lane-group-per-tile ones up to 16
+        lpt = std::min(lpt, P.sweep_kernel == 1 ? 16 : 8);
         kind = lpt == 1 ? kNarrow1 : lpt == 2 ? kNarrow2 : lpt == 4 ? kNarrow4 : lpt == 8 ? kNarrow8 : kNarrow16;
         cols = lpt;
     }

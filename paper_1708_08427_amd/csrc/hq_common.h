@@ -149,7 +149,7 @@ struct Plan {
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int waves_per_cu = 16;    // grid of the later phases' sweeps, waves per CU
     int first_wpc = 0;        // grid cap of the first phase's wide sweeps, waves per CU (0: none)
-    int sweep_kernel = 0;     // 0: wide sweeps unless a buffer exceeds their range; 1: narrow sweeps
+    int sweep_kernel = 0;     // 0: automatic; 1: a lane group per tile; 2: node-parallel; 3: wide
     int fused_up = 0;         // 1: the wide upward sweep in one launch; 0: one launch per tile phase
     int leaf_s = 1;           // leaf boxes hold up to leaf_s beads (>1: the first tile phase is leaves)
     int leaf_smax() const { return leaf_s <= 8 ? 8 : 16; }  // leaf-record layout and kernel instance

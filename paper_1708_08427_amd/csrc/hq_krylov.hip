@@ -53,18 +53,17 @@ __global__ void __launch_bounds__(kKThreads) k_dot_cols(int64_t n, int R, int tr
     col_reduce(acc, e0 < S ? col_of(e0, R, tri) : 0, R, sh, out);
 }
 
-// x += alpha p; r -= alpha Ap (per column alpha), and out[col] = ||r||^2
+// r -= alpha Ap (per column alpha), and out[col] = ||r||^2
 template <typename T>
-__global__ void __launch_bounds__(kKThreads) k_cg_xr(int64_t n, int R, int tri, int64_t S,
-                                                     const double *__restrict__ alpha, const T *__restrict__ p,
-                                                     const T *__restrict__ Ap, T *x, T *r, double *out) {
+__global__ void __launch_bounds__(kKThreads) k_cg_r(int64_t n, int R, int tri, int64_t S,
+                                                    const double *__restrict__ alpha, const T *__restrict__ Ap, T *r,
+                                                    double *out) {
     __shared__ double sh[kLdsCols];
     const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
     if (e0 < S) {
         const double a = alpha[col_of(e0, R, tri)];
         for (int64_t e = e0; e < n; e += S) {
-            x[e] = (T)((double)x[e] + a * (double)p[e]);
             const T rn = (T)((double)r[e] - a * (double)Ap[e]);
             r[e] = rn;
             acc += (double)rn * (double)rn;
@@ -73,11 +72,70 @@ __global__ void __launch_bounds__(kKThreads) k_cg_xr(int64_t n, int R, int tri, 
     col_reduce(acc, e0 < S ? col_of(e0, R, tri) : 0, R, sh, out);
 }
 
-// p = r + beta p (per column beta)
+// x += alpha p, then p = r + beta p (per column alpha, beta), in one pass
 template <typename T>
-__global__ void k_cg_p(int64_t n, int R, int tri, const double *__restrict__ beta, const T *__restrict__ r, T *p) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        p[e] = (T)((double)r[e] + beta[col_of(e, R, tri)] * (double)p[e]);
+__global__ void k_cg_xp(int64_t n, int R, int tri, const double *__restrict__ alpha, const double *__restrict__ beta,
+                        const T *__restrict__ r, T *x, T *p) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = col_of(e, R, tri);
+        const double pe = (double)p[e];
+        x[e] = (T)((double)x[e] + alpha[c] * pe);
+        p[e] = (T)((double)r[e] + beta[c] * pe);
+    }
+}
+
+// The CG scalars of every column on the device.  State per column k:
+// rr[k] = ||r||^2, bb[k] = ||b||^2, act[k] = 1 while the column iterates.
+// Step 1 (after p^T A p is in pap): alpha = rr / pap for active columns
+// (0 otherwise; a non-positive p^T A p of an active column is reported and
+// ends that column), and the accumulator of ||r_new||^2 is cleared.
+__global__ void k_cg_alpha(int R, const double *__restrict__ pap, const double *__restrict__ rr, int32_t *act,
+                           double *alpha, double *rn, int32_t *bad) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R; k += gridDim.x * blockDim.x) {
+        double a = 0.0;
+        if (act[k]) {
+            if (pap[k] > 0.0) {
+                a = rr[k] / pap[k];
+            } else {
+                atomicOr(bad, 1);
+                act[k] = 0;
+            }
+        }
+        alpha[k] = a;
+        rn[k] = 0.0;
+    }
+}
+
+// Step 2 (after ||r_new||^2 is in rn): beta = rn / rr, rr = rn, and a column
+// whose relative residual reached rtol stops; iters counts the iterations of
+// each column; the accumulator of the next p^T A p is cleared.
+__global__ void k_cg_beta(int R, double rtol2, const double *__restrict__ rn, const double *__restrict__ bb,
+                          double *rr, int32_t *act, double *beta, int32_t *iters, int32_t *nact, double *pap) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R; k += gridDim.x * blockDim.x) {
+        double b = 0.0;
+        if (act[k]) {
+            b = rr[k] > 0.0 ? rn[k] / rr[k] : 0.0;
+            rr[k] = rn[k];
+            iters[k] += 1;
+            if (!(rn[k] > rtol2 * bb[k])) act[k] = 0;
+        }
+        beta[k] = b;
+        pap[k] = 0.0;
+        if (act[k]) atomicAdd(nact, 1);
+    }
+}
+
+// Initial state: rr = bb = ||b||^2 (in rr), act = 1 unless already within
+// rtol, iterations 0, p^T A p accumulator cleared.
+__global__ void k_cg_init(int R, double rtol2, double *rr, double *bb, int32_t *act, int32_t *iters,
+                          double *pap, int32_t *nact) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R; k += gridDim.x * blockDim.x) {
+        bb[k] = rr[k];
+        act[k] = rr[k] > rtol2 * bb[k] ? 1 : 0;
+        iters[k] = 0;
+        pap[k] = 0.0;
+        if (act[k]) atomicAdd(nact, 1);
+    }
 }
 
 // y = -x
@@ -139,23 +197,24 @@ hq_status solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, voi
     }
     T *r = (T *)w.get(nr * sizeof(T)), *p = (T *)w.get(nr * sizeof(T)), *Ap = (T *)w.get(nr * sizeof(T));
     T *zr = (T *)w.get(nr * sizeof(T));
-    double *dots = (double *)w.get(2 * (size_t)R * sizeof(double)), *coef = (double *)w.get((size_t)R * sizeof(double));
-    if (!r || !p || !Ap || !zr || !dots || !coef) {
+    // per-column FP64 scalars: rr, bb, pap, rn, alpha, beta; int32 act, iters;
+    // and two int32 counters (active columns, a bad p^T A p)
+    double *sc = (double *)w.get(6 * (size_t)R * sizeof(double));
+    int32_t *ic = (int32_t *)w.get((2 * (size_t)R + 2) * sizeof(int32_t));
+    if (!r || !p || !Ap || !zr || !sc || !ic) {
         set_error("hipMalloc of the Krylov workspace");
         return HQ_E_NOMEM;
     }
+    double *rr = sc, *bb = sc + R, *pap = sc + 2 * R, *rn = sc + 3 * R, *alpha = sc + 4 * R, *beta = sc + 5 * R;
+    int32_t *act = ic, *iters = ic + R, *nact = ic + 2 * R, *bad = ic + 2 * R + 1;
     T *x = (T *)g, *u = (T *)dx, *y = (T *)dy;
     // column-fixed grid: stride S a multiple of the column period, about
     // 1024 blocks
     const int64_t per = tri ? 3 * (int64_t)R : (int64_t)R;
     const int64_t S = std::max<int64_t>(per, ((int64_t)1024 * kKThreads / per) * per);
     const unsigned gd = (unsigned)((S + kKThreads - 1) / kKThreads);
-    auto dot = [&](const T *a, const T *b, double *out) -> hq_status {
-        HQ_HIP(hipMemsetAsync(out, 0, (size_t)R * sizeof(double), s));
-        hipLaunchKernelGGL(k_dot_cols<T>, dim3(gd), dim3(kKThreads), 0, s, nr, R, tri, S, a, b, out);
-        HQ_HIP(hipGetLastError());
-        return HQ_OK;
-    };
+    const unsigned gs = (unsigned)std::min<int64_t>((R + kKThreads - 1) / kKThreads, 1024);
+    const double rtol2 = rtol * rtol;
     auto dprod = [&]() -> hq_status {  // y = D u
         if (dapply(u, y, nrhs, user, stream) != 0) {
             set_error("the mobility callback failed");
@@ -177,61 +236,70 @@ hq_status solve(hq_handle h, hq_dapply_fn dapply, void *user, const void *F, voi
     hipLaunchKernelGGL(k_neg<T>, dim3(grid_of(nr)), dim3(kKThreads), 0, s, nr, Ap, r);
     HQ_HIP(hipMemsetAsync(x, 0, nr * sizeof(T), s));
     HQ_HIP(hipMemcpyAsync(p, r, nr * sizeof(T), hipMemcpyDeviceToDevice, s));
-    std::vector<double> rr(R), bb(R), pap(R), c(R);
-    HQ_TRY(dot(r, r, dots));
-    HQ_HIP(hipMemcpyAsync(bb.data(), dots, R * sizeof(double), hipMemcpyDeviceToHost, s));
-    HQ_HIP(hipStreamSynchronize(s));
-    rr = bb;
-    std::vector<char> active(R);
-    auto converged = [&](int k) { return !(rr[k] > rtol * rtol * bb[k]); };
-    int it = 0;
-    for (int k = 0; k < R; ++k) active[k] = !converged(k);
-    while (it < max_iter && std::any_of(active.begin(), active.end(), [](char a) { return a != 0; })) {
+    HQ_HIP(hipMemsetAsync(sc, 0, 6 * (size_t)R * sizeof(double), s));
+    HQ_HIP(hipMemsetAsync(ic, 0, (2 * (size_t)R + 2) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_dot_cols<T>, dim3(gd), dim3(kKThreads), 0, s, nr, R, tri, S, r, r, rr);
+    hipLaunchKernelGGL(k_cg_init, dim3(gs), dim3(kKThreads), 0, s, R, rtol2, rr, bb, act, iters, pap, nact);
+    HQ_HIP(hipGetLastError());
+    // The iterations run without the host: the scalars stay on the device and
+    // converged columns take zero steps.  The host reads the count of active
+    // columns every few iterations (one synchronisation) to stop the loop.
+    int it = 0, live = 1;
+    int32_t hc[2] = {0, 0};
+    const int check = std::max(1, std::min(info->check_every > 0 ? info->check_every : 4, 64));
+    auto poll = [&]() -> hq_status {
+        HQ_HIP(hipMemcpyAsync(hc, nact, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HQ_HIP(hipStreamSynchronize(s));
+        live = hc[0];
+        if (hc[1]) {
+            set_error("Q~ D Q~^T is not positive definite (p^T A p <= 0): D must be symmetric positive definite");
+            return HQ_E_INVALID;
+        }
+        return HQ_OK;
+    };
+    HQ_TRY(poll());
+    while (it < max_iter && live > 0) {
+        HQ_HIP(hipMemsetAsync(nact, 0, sizeof(int32_t), s));
         HQ_TRY(apply_A(p, Ap));
-        HQ_TRY(dot(p, Ap, dots));
-        HQ_HIP(hipMemcpyAsync(pap.data(), dots, R * sizeof(double), hipMemcpyDeviceToHost, s));
-        HQ_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < R; ++k) {
-            if (active[k] && !(pap[k] > 0.0)) {
-                set_error("Q~ D Q~^T is not positive definite (p^T A p <= 0): D must be symmetric positive definite");
-                return HQ_E_INVALID;
-            }
-            c[k] = active[k] ? rr[k] / pap[k] : 0.0;
-        }
-        HQ_HIP(hipMemcpyAsync(coef, c.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
-        HQ_HIP(hipMemsetAsync(dots, 0, (size_t)R * sizeof(double), s));
-        hipLaunchKernelGGL(k_cg_xr<T>, dim3(gd), dim3(kKThreads), 0, s, nr, R, tri, S, coef, p, Ap, x, r, dots);
+        hipLaunchKernelGGL(k_dot_cols<T>, dim3(gd), dim3(kKThreads), 0, s, nr, R, tri, S, p, Ap, pap);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(gs), dim3(kKThreads), 0, s, R, pap, rr, act, alpha, rn, bad);
+        hipLaunchKernelGGL(k_cg_r<T>, dim3(gd), dim3(kKThreads), 0, s, nr, R, tri, S, alpha, Ap, r, rn);
+        hipLaunchKernelGGL(k_cg_beta, dim3(gs), dim3(kKThreads), 0, s, R, rtol2, rn, bb, rr, act, beta, iters, nact,
+                           pap);
+        hipLaunchKernelGGL(k_cg_xp<T>, dim3(grid_of(nr)), dim3(kKThreads), 0, s, nr, R, tri, alpha, beta, r, x, p);
         HQ_HIP(hipGetLastError());
-        std::vector<double> rn(R);
-        HQ_HIP(hipMemcpyAsync(rn.data(), dots, R * sizeof(double), hipMemcpyDeviceToHost, s));
-        HQ_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < R; ++k) {
-            c[k] = (active[k] && rr[k] > 0.0) ? rn[k] / rr[k] : 0.0;
-            if (active[k]) rr[k] = rn[k];
-            if (active[k] && converged(k)) active[k] = 0;
-        }
-        HQ_HIP(hipMemcpyAsync(coef, c.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_cg_p<T>, dim3(grid_of(nr)), dim3(kKThreads), 0, s, nr, R, tri, coef, r, p);
         ++it;
+        if (it % check == 0 || it == max_iter) HQ_TRY(poll());
     }
     // V = Q_Z D (Q_Z^T F + Q~^T g)
     HQ_TRY(hq_apply_full(h, x, u, const_cast<void *>(F), 1, nrhs, prec, layout, stream));
     HQ_TRY(dprod());
     HQ_TRY(hq_apply_full(h, y, Ap, V, 0, nrhs, prec, layout, stream));
+    std::vector<double> hrr(R), hbb(R);
+    std::vector<int32_t> hit(R);
+    HQ_HIP(hipMemcpyAsync(hrr.data(), rr, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    HQ_HIP(hipMemcpyAsync(hbb.data(), bb, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    HQ_HIP(hipMemcpyAsync(hit.data(), iters, R * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HQ_HIP(hipStreamSynchronize(s));
     double worst = 0.0;
-    for (int k = 0; k < R; ++k) worst = std::max(worst, bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0);
-    info->iters = it;
+    int most = 0;
+    for (int k = 0; k < R; ++k) {
+        worst = std::max(worst, hbb[k] > 0 ? std::sqrt(hrr[k] / hbb[k]) : 0.0);
+        most = std::max(most, (int)hit[k]);
+    }
+    info->iters = most;
     info->max_rel_residual = worst;
     return HQ_OK;
 }
 
 }  // namespace
 
-// four vectors of rows x nrhs and 3 nrhs FP64 scalars, each piece 256-byte aligned
+// four vectors of rows x nrhs, 6 nrhs FP64 scalars and 2 nrhs + 2 int32
+// ones, each piece 256-byte aligned
 size_t krylov_bytes(int64_t rows, int64_t nrhs, size_t elem) {
     auto a = [](size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; };
-    return 4 * a((size_t)rows * nrhs * elem) + a(2 * (size_t)nrhs * sizeof(double)) + a((size_t)nrhs * sizeof(double));
+    return 4 * a((size_t)rows * nrhs * elem) + a(6 * (size_t)nrhs * sizeof(double)) +
+           a((2 * (size_t)nrhs + 2) * sizeof(int32_t));
 }
 
 }  // namespace hq

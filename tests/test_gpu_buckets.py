@@ -9,7 +9,7 @@ per-phase one.
 * FP32 against FP64 <= 1e-5 and the leak; the full Q against the oracle's.
 * A rebuild after a rigid motion equals a fresh build bit for bit.
 * The fused upward sweep (one launch, arrival counters) equals the per-phase
-  launches bit for bit.
+  launches of the wide sweeps bit for bit.
 """
 import numpy as np
 import pytest
@@ -147,7 +147,7 @@ def test_fused_upward_equals_phase_launches(hq, R, layout):
         f = f.reshape(w.N, 3, R).transpose(1, 2).contiguous()
     for S, S2 in ((32, 0), (16, 4), (64, 8)):
         pos = _dev(w.pos)
-        a = hq.build(pos, w.offsets, tile_units=S, later_tile_units=S2)
+        a = hq.build(pos, w.offsets, tile_units=S, later_tile_units=S2, sweep_kernel=3)
         b = hq.build(pos, w.offsets, tile_units=S, later_tile_units=S2, fused_upward=1)
         ya, yb = a.apply(f, layout=layout), b.apply(f, layout=layout)
         assert torch.equal(ya, yb)

@@ -104,3 +104,26 @@ def test_constrained_solve_errors(hq):
     with pytest.raises(ValueError):
         hq.constrained_solve(h, dense_dapply(torch.from_numpy(D).cuda(), "rows"), Fd[:5])
     assert h.query()["device_flags"] == 0
+
+
+def test_constrained_solve_check_interval(hq):
+    """The CG scalars live on the device and converged columns take zero
+    steps, so the host's check interval changes neither the iterations each
+    column takes nor the solution (beyond the order of the dot products'
+    atomic partial sums)."""
+    w, D, F = problem(54, [15, 60, 150], 5)
+    # columns of very different size converge at different iterations
+    F = F * np.array([1.0, 1e3, 1e-3, 1.0, 10.0])
+    h = hq.build(torch.from_numpy(w.pos).cuda(), w.offsets)
+    Dd = torch.from_numpy(D).cuda()
+    Fd = torch.from_numpy(F).cuda()
+    res = [hq.constrained_solve(h, dense_dapply(Dd, "rows"), Fd, rtol=1e-10, check_every=c) for c in (1, 3, 16)]
+    V0, g0, i0 = res[0]
+    for V, g, info in res[1:]:
+        assert info["iters"] == i0["iters"]
+        assert float((V - V0).norm() / V0.norm()) <= 1e-12
+        assert float((g - g0).norm() / g0.norm()) <= 1e-12
+    V_o, g_o = bd.constrained_solve(w.pos, w.offsets, D, F)
+    assert np.abs(V0.cpu().numpy() - V_o).max() <= 1e-8 * np.abs(V_o).max()
+    with pytest.raises(ValueError):
+        hq.constrained_solve(h, dense_dapply(Dd, "rows"), Fd, check_every=0)

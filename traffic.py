@@ -8,7 +8,7 @@ scaled by what it reads for the probe's device copy of 512 MiB (bytes it
 must read and write), and the summary records a hash of the sweep sources so
 that a reader can tell whether it still describes the current kernels.
 
-    python -m paper_1708_08427_amd.traffic FETCH_DIR WRITE_DIR OUT.json --command "..."
+    python traffic.py FETCH_DIR WRITE_DIR OUT.json --command "..."
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ import hashlib
 import json
 import os
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1708_08427_amd")
 COPY_BYTES = 128 * 1024 * 1024 * 4  # the probe's float32 copy
 PROBE_SWEEPS = 3
 
