@@ -130,14 +130,19 @@ def cpu_baseline(wl, rng_seed, budget_s=8.0):
 def sweep_kernel(nrhs, layout, dtype, transpose=False, phase=1):
     """The kernel the library launches for a tile phase of a sweep with this
     many right-hand sides, when its buffers fit the wide sweeps' 2 GiB range
-    (its dispatch: runs of 32 or 64 lanes above 16 right-hand sides, 32-lane
-    ones specialised for exactly 32; for 8 to 16, 16-lane runs in FP32 and
-    32-lane runs in FP64; below 8, narrow sweeps of one lane group per tile)."""
+    and the tiles hold 32 units (its dispatch: runs of 32 or 64 lanes above 16
+    right-hand sides, 32-lane ones specialised for exactly 32; for 8 to 16,
+    16-lane runs in FP32 and 32-lane runs in FP64; below 8, a lane group per
+    tile in the first phase and node-parallel sweeps in the later ones)."""
     lpt = 1
     while lpt < nrhs and lpt < 64:
         lpt *= 2
     if nrhs < 8:
-        return f"k_{'down' if transpose else 'up'}<{dtype}, {lpt}>"
+        # first phase: a lane group per tile with exact wait counts; later
+        # phases node-parallel
+        if phase == 1:
+            return f"k_{'down' if transpose else 'up'}_lane<{dtype}, {lpt}>"
+        return f"k_{'down' if transpose else 'up'}_np<{dtype}, 256, {lpt}, 32, false>"
     if lpt < 32:
         lpt = 16 if dtype == "float" else 32
     rt = 32 if nrhs == 32 else 0

@@ -39,6 +39,7 @@ struct Ctx {
     int root_in;  // downward: body roots take their Velocity-set from the exchange buffer (full Q)
     int m;        // bodies (rows of the rotation table of the fused rigid-motion products)
     uint32_t in_bytes, out_bytes, xch_bytes;  // buffer sizes of the wide sweeps (each < 2 GiB)
+    int bufs_ok;  // every vector buffer lies below 2 GiB (the sizes above are exact)
 };
 
 // Index of element (row0 + k, r) of a vector, row0 a multiple of 3.
@@ -916,6 +917,345 @@ __device__ __forceinline__ void bst<float>(float v, rsrc_t r, uint32_t vo, uint3
 template <>
 __device__ __forceinline__ void bst<double>(double v, rsrc_t r, uint32_t vo, uint32_t so) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, kNT);
+}
+
+// ---------------------------------------------------------------------------
+// Lane-per-tile sweeps of the first tile phase for few right-hand sides: a
+// group of LPT lanes (one column each) walks one tile's nodes in schedule
+// order (reverse order downward).  Every memory access is issued whether or
+// not the node needs it, with an out-of-range offset where it does not, so
+// that the compiler's wait counts are exact and no node waits for the stores
+// of the nodes before it.  Three streams run ahead of the node being
+// computed: its link words four nodes ahead, then (with two nodes of slack
+// for the links to arrive) its reflectors and the vectors the links address
+// two nodes ahead.  Pending results sit in the fixed LDS slots the links name
+// (as in the wide sweeps), plus one sink slot for the writes of absent
+// values.  In the first phase every child is a bead or a node of the same
+// tile, and only the tile root touches the exchange buffer.
+// ---------------------------------------------------------------------------
+constexpr int kLaneRing = 5;  // ring slots: links 4 nodes ahead, the rest 2
+
+// Buffer accesses of the lane kernels with the default cache policy: a lane
+// touches parts of a line in several instructions (a record in eight loads, a
+// bead's three values in three), which the non-temporal policy of the wide
+// sweeps would send to memory once per instruction.
+template <typename T>
+__device__ __forceinline__ T bldc(rsrc_t r, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstc(T v, rsrc_t r, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+}
+
+struct LaneLk {
+    int xref, yref, off, meta, slots;
+};
+
+// The link words of the record at byte offset bo (kOOB: all zero).
+template <typename T>
+__device__ __forceinline__ void lane_links(rsrc_t rr, uint32_t bo, LaneLk &l) {
+    constexpr uint32_t L0 = kRecLinks * sizeof(T);
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rr, bo + L0, 0, 0);
+    const unsigned b = __builtin_amdgcn_raw_buffer_load_b32(rr, bo + L0 + 16, 0, 0);
+    l.xref = (int)a.x;
+    l.yref = (int)a.y;
+    l.off = (int)a.z;
+    l.meta = (int)a.w;
+    l.slots = (int)b;
+}
+
+// The reflectors and weights (elements 0..25) of the record at byte offset bo.
+template <typename T>
+__device__ __forceinline__ void lane_g(rsrc_t rr, uint32_t bo, T (&g)[26]) {
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rr, bo + 16 * q, 0, 0);
+            g[4 * q] = __uint_as_float(w.x);
+            g[4 * q + 1] = __uint_as_float(w.y);
+            g[4 * q + 2] = __uint_as_float(w.z);
+            g[4 * q + 3] = __uint_as_float(w.w);
+        }
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rr, bo + 96, 0, 0);
+        g[24] = __uint_as_float(w.x);
+        g[25] = __uint_as_float(w.y);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 13; ++q) {
+            const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rr, bo + 16 * q, 0, 0);
+            g[2 * q] = __hiloint2double((int)w.y, (int)w.x);
+            g[2 * q + 1] = __hiloint2double((int)w.w, (int)w.z);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void lane_get6(const T *lds, int slot, int lane, T (&m)[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m[k] = lds[(slot * 6 + k) * 64 + lane];
+}
+
+template <typename T>
+__device__ __forceinline__ void lane_put6(T *lds, int slot, int lane, const T (&m)[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lds[(slot * 6 + k) * 64 + lane] = m[k];
+}
+
+// Byte offset of element (row0 + k, r) of a vector, or kOOB unless en.
+template <typename T>
+__device__ __forceinline__ uint32_t lane_vo(bool en, int64_t row0, int k, int r, const Ctx &C) {
+    return en ? (uint32_t)(velem(row0, k, r, C) * (int64_t)sizeof(T)) : kOOB;
+}
+
+// The tile of lane group tslot in work item `item`: (base, len, column r).
+__device__ __forceinline__ void lane_tile(int item, int tslot, int rl, int LPT, int TPW, int tb, int te,
+                                          const int32_t *__restrict__ tile_base,
+                                          const int32_t *__restrict__ tile_len, const Ctx &C, int &base, int &len,
+                                          int &r, int &bad) {
+    const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
+    const int t = tb + grp * TPW + tslot;
+    r = chunk * LPT + rl;
+    base = 0;
+    len = 0;
+    if (t < te) {
+        base = tile_base[t];
+        len = tile_len[t];
+        if (base < 0 || len < 0 || (int64_t)base + len > C.nsched) {
+            bad |= kFlagBounds;
+            base = 0;
+            len = 0;
+        }
+    }
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) v = max(v, __shfl_xor(v, sh, 64));
+    return v;
+}
+
+template <typename T, int LPT>
+__global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phase_tab,
+                                                const int32_t *__restrict__ tile_base,
+                                                const int32_t *__restrict__ tile_len, const T *__restrict__ rec,
+                                                uint32_t rec_bytes, const T *__restrict__ v, T *__restrict__ out,
+                                                T *__restrict__ xch, Ctx C, int32_t *err) {
+    extern __shared__ unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    constexpr int TPW = 64 / LPT, RD = kLaneRing;
+    constexpr uint32_t RB = kRecWords * sizeof(T);
+    const int lane = threadIdx.x;
+    const int tslot = lane / LPT, rl = lane % LPT;
+    const int sink = C.nslot;
+    const rsrc_t rr = make_rsrc(rec, rec_bytes), rv = make_rsrc(v, C.in_bytes), ro = make_rsrc(out, C.out_bytes),
+                 rx = make_rsrc(xch, C.xch_bytes);
+    const int tb = phase_tab[2], te = phase_tab[3];
+    const int items = ((te - tb + TPW - 1) / TPW) * C.nchunks;
+    int bad = 0;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        int base, len, r;
+        lane_tile(item, tslot, rl, LPT, TPW, tb, te, tile_base, tile_len, C, base, len, r, bad);
+        const bool act = r < C.R;
+        const int lmax = wave_max(len);
+        auto bo = [&](int i) -> uint32_t { return i < len ? (uint32_t)(base + i) * RB : kOOB; };
+        // the bead children's vectors of node i (links l)
+        auto in_of = [&](int i, const LaneLk &l, T (&a)[3], T (&b)[3]) {
+            const bool live = i < len && act;
+            const bool xb = live && l.xref >= 0 && l.xref < C.N, yb = live && l.yref >= 0 && l.yref < C.N;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                a[k] = bldc<T>(rv, lane_vo<T>(xb, 3 * (int64_t)l.xref, k, r, C), 0);
+                b[k] = bldc<T>(rv, lane_vo<T>(yb, 3 * (int64_t)l.yref, k, r, C), 0);
+            }
+        };
+        LaneLk lq[RD];
+        T gq[RD][26], ia[RD][3], ib[RD][3];
+#pragma unroll
+        for (int u = 0; u < RD - 1; ++u) lane_links<T>(rr, bo(u), lq[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            lane_g<T>(rr, bo(u), gq[u]);
+            in_of(u, lq[u], ia[u], ib[u]);
+        }
+        for (int i0 = 0; i0 < lmax; i0 += RD) {
+#pragma unroll
+            for (int u = 0; u < RD; ++u) {
+                const int i = i0 + u;
+                lane_links<T>(rr, bo(i + 4), lq[(u + 4) % RD]);
+                lane_g<T>(rr, bo(i + 2), gq[(u + 2) % RD]);
+                in_of(i + 2, lq[(u + 2) % RD], ia[(u + 2) % RD], ib[(u + 2) % RD]);
+                // node i (Eqs. 4.2-4.3)
+                const LaneLk &n = lq[u];
+                const T(&g)[26] = gq[u];
+                const bool live = i < len;
+                const bool xst = n.xref == kRefStack, yst = n.yref == kRefStack;
+                const int xs = min(n.slots & 0xff, sink), ys = min((n.slots >> 8) & 0xff, sink);
+                T mx[6], my[6];
+                lane_get6<T>(lds, xs, lane, mx);
+                lane_get6<T>(lds, ys, lane, my);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    mx[k] = xst ? mx[k] : (k < 3 ? ia[u][k] : T(0));
+                    my[k] = yst ? my[k] : (k < 3 ? ib[u][k] : T(0));
+                }
+                const T sx = g[kRecSx], sy = g[kRecSy];
+                const bool xi = n.xref < 0, yi = n.yref < 0;
+                const bool both = xi && yi, any = xi || yi;
+                T mp[6], tt[3], t9[9];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    mp[k] = sx * mx[k] + sy * my[k];
+                    tt[k] = sy * mx[k] - sx * my[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    t9[k] = xi ? mx[3 + k] : (yi ? my[3 + k] : tt[k]);
+                    t9[3 + k] = both ? my[3 + k] : (any ? tt[k] : T(0));
+                    t9[6 + k] = both ? tt[k] : T(0);
+                }
+                house_fwd<9>(t9, g);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) mp[3 + k] = t9[k];
+                const bool troot = (n.meta & kMetaTileRoot) != 0;
+                const int dim = 3 * ((int)xi + (int)yi);
+                const bool rok = n.off >= 0 && (int64_t)n.off + dim <= C.rows;
+                const int slot = n.meta >> kMetaSlotShift;
+                const bool xok = slot < C.xch_cap;
+                if (live && ((dim > 0 && !rok) || (troot && !xok) || (!xst && n.xref < 0) || (!yst && n.yref < 0) ||
+                             n.xref >= C.N || n.yref >= C.N))
+                    bad |= kFlagBounds;
+                const bool en = live && act && rok;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    bstc<T>(t9[3 + k], ro, lane_vo<T>(en && any, n.off, k, r, C), 0);
+                    bstc<T>(t9[6 + k], ro, lane_vo<T>(en && both, (int64_t)n.off + 3, k, r, C), 0);
+                }
+                const bool xen = live && act && troot && xok;
+                const uint32_t xb0 = xen ? (uint32_t)(xidx<false>(slot, 0, r, C) * (int64_t)sizeof(T)) : kOOB;
+                const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+#pragma unroll
+                for (int k = 0; k < 6; ++k) bstc<T>(mp[k], rx, xb0 + (xen ? k * xstep : 0), 0);
+                lane_put6<T>(lds, (live && !troot) ? min((n.slots >> 16) & 0xff, sink) : sink, lane, mp);
+            }
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+template <typename T, int LPT>
+__global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ phase_tab,
+                                                  const int32_t *__restrict__ tile_base,
+                                                  const int32_t *__restrict__ tile_len, const T *__restrict__ rec,
+                                                  uint32_t rec_bytes, const T *__restrict__ w, T *__restrict__ out,
+                                                  const T *__restrict__ xch, Ctx C, int32_t *err) {
+    extern __shared__ unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    constexpr int TPW = 64 / LPT, RD = kLaneRing;
+    constexpr uint32_t RB = kRecWords * sizeof(T);
+    const int lane = threadIdx.x;
+    const int tslot = lane / LPT, rl = lane % LPT;
+    const int sink = C.nslot;
+    const rsrc_t rr = make_rsrc(rec, rec_bytes), rw = make_rsrc(w, C.in_bytes), ro = make_rsrc(out, C.out_bytes),
+                 rx = make_rsrc(xch, C.xch_bytes);
+    const int tb = phase_tab[2], te = phase_tab[3];
+    const int items = ((te - tb + TPW - 1) / TPW) * C.nchunks;
+    int bad = 0;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        int base, len, r;
+        lane_tile(item, tslot, rl, LPT, TPW, tb, te, tile_base, tile_len, C, base, len, r, bad);
+        const bool act = r < C.R;
+        const int lmax = wave_max(len);
+        const int last = base + len - 1;  // node j of the sweep is schedule index last - j
+        auto bo = [&](int j) -> uint32_t { return j < len ? (uint32_t)(last - j) * RB : kOOB; };
+        // the node's residue coefficients and, at a tile root, its
+        // Velocity-set from the exchange buffer (zero at a body root unless
+        // given)
+        auto in_of = [&](int j, const LaneLk &l, T (&a)[6], T (&lv)[6]) {
+            const bool live = j < len && act;
+            const int dim = 3 * (int)(l.xref < 0) + 3 * (int)(l.yref < 0);
+            const bool rok = l.off >= 0 && (int64_t)l.off + dim <= C.rows;
+            const int slot = l.meta >> kMetaSlotShift;
+            const bool xin = live && (l.meta & kMetaTileRoot) && (!(l.meta & kMetaBodyRoot) || C.root_in) &&
+                             slot < C.xch_cap;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                a[k] = bldc<T>(rw, lane_vo<T>(live && rok && dim >= 3, l.off, k, r, C), 0);
+                a[3 + k] = bldc<T>(rw, lane_vo<T>(live && rok && dim == 6, (int64_t)l.off + 3, k, r, C), 0);
+            }
+            const uint32_t xb0 = xin ? (uint32_t)(xidx<false>(slot, 0, r, C) * (int64_t)sizeof(T)) : kOOB;
+            const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lv[k] = bldc<T>(rx, xb0 + (xin ? k * xstep : 0), 0);
+        };
+        LaneLk lq[RD];
+        T gq[RD][26], ia[RD][6], il[RD][6];
+#pragma unroll
+        for (int u = 0; u < RD - 1; ++u) lane_links<T>(rr, bo(u), lq[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            lane_g<T>(rr, bo(u), gq[u]);
+            in_of(u, lq[u], ia[u], il[u]);
+        }
+        for (int j0 = 0; j0 < lmax; j0 += RD) {
+#pragma unroll
+            for (int u = 0; u < RD; ++u) {
+                const int j = j0 + u;
+                lane_links<T>(rr, bo(j + 4), lq[(u + 4) % RD]);
+                lane_g<T>(rr, bo(j + 2), gq[(u + 2) % RD]);
+                in_of(j + 2, lq[(u + 2) % RD], ia[(u + 2) % RD], il[(u + 2) % RD]);
+                // node j (Algorithm 3)
+                const LaneLk &n = lq[u];
+                const T(&g)[26] = gq[u];
+                const bool live = j < len;
+                const bool troot = (n.meta & kMetaTileRoot) != 0;
+                const int os = min((n.slots >> 16) & 0xff, sink);
+                T L[6];
+                lane_get6<T>(lds, os, lane, L);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) L[k] = troot ? il[u][k] : L[k];
+                const T sx = g[kRecSx], sy = g[kRecSy];
+                const bool xi = n.xref < 0, yi = n.yref < 0;
+                const bool both = xi && yi, any = xi || yi;
+                T x9[9];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) x9[k] = L[3 + k];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) x9[3 + k] = ia[u][k];
+                house_bwd<9>(x9, g);
+                T st[3], Lx[6], Ly[6];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Lx[3 + k] = xi ? x9[k] : T(0);
+                    Ly[3 + k] = both ? x9[3 + k] : (yi ? x9[k] : T(0));
+                    st[k] = both ? x9[6 + k] : (any ? x9[3 + k] : x9[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Lx[k] = sx * L[k] + sy * st[k];
+                    Ly[k] = sy * L[k] - sx * st[k];
+                }
+                const bool xst = n.xref == kRefStack, yst = n.yref == kRefStack;
+                if (live && ((!xst && n.xref < 0) || (!yst && n.yref < 0) || n.xref >= C.N || n.yref >= C.N))
+                    bad |= kFlagBounds;
+                const bool en = live && act;
+                const bool xb = en && n.xref >= 0 && n.xref < C.N, yb = en && n.yref >= 0 && n.yref < C.N;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    bstc<T>(Lx[k], ro, lane_vo<T>(xb, 3 * (int64_t)n.xref, k, r, C), 0);
+                    bstc<T>(Ly[k], ro, lane_vo<T>(yb, 3 * (int64_t)n.yref, k, r, C), 0);
+                }
+                lane_put6<T>(lds, (live && xst) ? min(n.slots & 0xff, sink) : sink, lane, Lx);
+                lane_put6<T>(lds, (live && yst) ? min((n.slots >> 8) & 0xff, sink) : sink, lane, Ly);
+            }
+        }
+    }
+    if (bad) atomicOr(err, bad);
 }
 
 // Cache policy of the exchange accesses: the default, or (kSC1) the bit
@@ -2081,6 +2421,26 @@ void launch_np(const Plan &P, int phase, int transpose, const T *rec, const T *v
 
 enum SweepKind { kNarrow1, kNarrow2, kNarrow4, kNarrow8, kNarrow16, kWide16, kWide32, kWide64 };
 
+// Lane-per-tile sweep of the first tile phase (false where a buffer lies
+// beyond the range of 32-bit offsets).
+template <typename T, int LPT>
+bool launch_lane(const Plan &P, int transpose, const T *rec, const T *v, T *out, T *xch, const Ctx &C,
+                 hipStream_t s) {
+    const int64_t rb = P.NI * (int64_t)kRecWords * (int64_t)sizeof(T);
+    if (!C.bufs_ok || rb >= (int64_t)kOOB - (int64_t)(1 << 20)) return false;
+    constexpr int TPW = 64 / LPT;
+    const size_t lds = (size_t)(C.nslot + 1) * 6 * 64 * sizeof(T);
+    const int64_t items = ((2 * P.tiles_built + 64 + TPW - 1) / TPW) * (int64_t)C.nchunks;
+    const unsigned grid = (unsigned)std::min<int64_t>(items, 1 << 20);
+    if (!transpose)
+        hipLaunchKernelGGL((k_up_lane<T, LPT>), dim3(grid), dim3(64), lds, s, P.d_phase, P.d_tile_base,
+                           P.d_tile_len, rec, (uint32_t)rb, v, out, xch, C, P.d_err);
+    else
+        hipLaunchKernelGGL((k_down_lane<T, LPT>), dim3(grid), dim3(64), lds, s, P.d_phase, P.d_tile_base,
+                           P.d_tile_len, rec, (uint32_t)rb, v, out, xch, C, P.d_err);
+    return true;
+}
+
 // Node-parallel launch of a later phase of a 16-column FP32 wide sweep;
 // false where it does not apply.  (At 32 columns a workgroup of a whole tile
 // holds 1,024 lanes that each load the node's record; on the bench workload
@@ -2213,6 +2573,20 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
         const bool np = np_slots(P, phase) > 0 &&
                         (P.sweep_kernel == 2 || (P.sweep_kernel == 0 && phase > 1 && P.S2 >= 16));
         if (kind != kWide16 && kind != kWide32 && kind != kWide64) {
+            // the first phase: lane group per tile with exact wait counts
+            // (every access issued, absent ones out of range)
+            const bool lane = phase == 1 && P.sweep_kernel == 0;
+            if (lane) {
+                bool done = false;
+                switch (kind) {
+                case kNarrow1: done = launch_lane<T, 1>(P, transpose, rec, v, out, xch, C, s); break;
+                case kNarrow2: done = launch_lane<T, 2>(P, transpose, rec, v, out, xch, C, s); break;
+                case kNarrow4: done = launch_lane<T, 4>(P, transpose, rec, v, out, xch, C, s); break;
+                case kNarrow8: done = launch_lane<T, 8>(P, transpose, rec, v, out, xch, C, s); break;
+                default: break;
+                }
+                if (done) continue;
+            }
             switch (kind) {
             case kNarrow1:
                 if (np) launch_np<T, 1>(P, phase, transpose, rec, v, out, xch, C, s);
@@ -2274,6 +2648,7 @@ void launch_all(const Plan &P, int transpose, SweepKind kind, const T *rec, cons
                 else launch_wide<T, 64, 1, false, false>(P, phase, transpose, rec, v, out, xch, rot, C, s);
             }
             break;
+        default: break;
         }
     }
     if (ev) (void)hipEventRecord(ev[nph], s);
@@ -2316,6 +2691,7 @@ hq_status apply_device(Plan &P, const void *v, void *out, void *root, int transp
     const int64_t vx = (int64_t)C.xch_cap * 6 * nrhs * (int64_t)elem;
     const int64_t lim = (int64_t)kOOB - (int64_t)(1 << 20);
     const bool wide_ok = vin < lim && vout < lim && vx < lim;
+    C.bufs_ok = wide_ok ? 1 : 0;
     C.in_bytes = (uint32_t)std::min<int64_t>(vin, lim);
     C.out_bytes = (uint32_t)std::min<int64_t>(vout, lim);
     C.xch_bytes = (uint32_t)std::min<int64_t>(vx, lim);

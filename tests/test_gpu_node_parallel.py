@@ -127,13 +127,18 @@ def test_np_against_other_kernels_bd(hq):
         a = hn.apply(_dev(g, dt), transpose=True).double().cpu().numpy()
         b = hl.apply(_dev(g, dt), transpose=True).double().cpu().numpy()
         assert np.abs(a - b).max() <= tol * np.abs(g).max()
-    # the automatic choice at R = 1 (a lane group per tile in the first phase,
-    # node-parallel later) against both
+    # the automatic choice (the first phase with the lane-per-tile kernels of
+    # exact wait counts, node-parallel later phases) against both, at 1 and 3
+    # right-hand sides, in both precisions and directions
     ha = hq.build(pos, w.offsets, store=3)
-    f1 = _dev(f[:, :1])
-    a = ha.apply(f1)
-    assert float((a - hn.apply(f1)).abs().max()) <= 1e-13 * float(f1.abs().max())
-    assert float((a - hl.apply(f1)).abs().max()) <= 1e-13 * float(f1.abs().max())
+    for R in (1, 3):
+        for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+            fr, gr = _dev(f[:, :R], dt), _dev(g[:, :R], dt)
+            a, b = ha.apply(fr), ha.apply(gr, transpose=True)
+            for hx in (hn, hl):
+                assert float((a - hx.apply(fr)).abs().max()) <= tol * float(fr.abs().max()), (R, dt)
+                assert float((b - hx.apply(gr, transpose=True)).abs().max()) <= tol * float(gr.abs().max()), (R, dt)
+    assert ha.query()["device_flags"] == 0
     assert hn.query()["device_flags"] == 0 and hl.query()["device_flags"] == 0
 
 
