@@ -2210,6 +2210,11 @@ __global__ void __launch_bounds__(64) k_bucket(const int32_t *__restrict__ phase
                                                const T *__restrict__ brec, int64_t bcap, const T *__restrict__ v,
                                                T *__restrict__ out, T *__restrict__ xch, Ctx C, int32_t *err) {
     constexpr int MS = 3 * SMAX, BS = 6 * MS + 8, LPW = 64 / G;
+    // groups of 16 or more lanes stage their leaf's record in LDS (one
+    // coalesced pass, then broadcast reads); a lane that is a leaf of its own
+    // reads the record itself
+    constexpr bool kStage = G >= 16;
+    __shared__ T sg[kStage ? LPW : 1][kStage ? BS : 1];
     const int lane = threadIdx.x;
     const int slotw = lane / G, rl = lane % G;
     const int tb = phase_tab[2 * 1], te = phase_tab[2 * 1 + 1];
@@ -2220,7 +2225,7 @@ __global__ void __launch_bounds__(64) k_bucket(const int32_t *__restrict__ phase
         const int grp = item / C.nchunks, chunk = item - grp * C.nchunks;
         const int t = tb + grp * LPW + slotw;
         const int r = chunk * G + rl;
-        const bool act = r < C.R && t < te;
+        const int rc = min(r, C.R - 1);  // a column to address for lanes beyond the right-hand sides
         int f = 0, n = 0, off = 0, meta = 0;
         if (t < te) {
             const int q = tile_root[t], sr = tile_base[t] + tile_len[t] - 1;
@@ -2238,40 +2243,54 @@ __global__ void __launch_bounds__(64) k_bucket(const int32_t *__restrict__ phase
                 }
             }
         }
+        if (n == 0) f = off = 0;
+        const bool act = r < C.R && n > 0;
         const int mrows = 3 * n;
-        const T *g = brec + (int64_t)(t - tb) * BS;
-        const int slot = meta >> kMetaSlotShift;
+        const T *g = brec + (n > 0 ? (int64_t)(t - tb) : 0) * BS;
+        if constexpr (kStage) {
+            __syncthreads();  // the previous item's reads of the staging rows are over
+            for (int e = rl; e < BS; e += G) sg[slotw][e] = g[e];
+            __syncthreads();
+        }
+        auto gv = [&](int e) -> T {
+            if constexpr (kStage) return sg[slotw][e];
+            else return g[e];
+        };
+        int slot = meta >> kMetaSlotShift;
         const bool xok = (meta & kMetaTileRoot) && slot < C.xch_cap;
         if (n > 0 && !xok) bad |= kFlagBounds;
+        if (!xok) slot = 0;
         auto xidx = [&](int d) -> int64_t {
-            return WX ? ((int64_t)slot * C.R + r) * 6 + d : ((int64_t)slot * 6 + d) * C.R + r;
+            return WX ? ((int64_t)slot * C.R + rc) * 6 + d : ((int64_t)slot * 6 + d) * C.R + rc;
         };
+        // the record is zero beyond the leaf's 3n rows, so the reflectors run
+        // over all rows; absent values load from valid addresses and are
+        // replaced by zeros
         T x[MS];
-#pragma unroll
-        for (int i = 0; i < MS; ++i) x[i] = T(0);
         if (UP) {
-            if (act && n > 0)
-                for (int k = 0; k < n; ++k) {
-                    const int64_t u = perm[f + k];
 #pragma unroll
-                    for (int i = 0; i < MS; ++i)
-                        if (i / 3 == k) x[i] = v[velem(3 * u, i % 3, r, C)];
+            for (int k = 0; k < SMAX; ++k) {
+                const bool ok = act && k < n;
+                const int64_t u = perm[f + (k < n ? k : 0)];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const T val = v[velem(3 * u, d, rc, C)];
+                    x[3 * k + d] = ok ? val : T(0);
                 }
+            }
             // x <- Q^T x = H_6 ... H_1 x
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                const T tau = n > 0 ? g[6 * MS + j] : T(0);
+                const T tau = gv(6 * MS + j);
                 T w = x[j];
 #pragma unroll
-                for (int i = j + 1; i < MS; ++i)
-                    if (i < mrows) w += g[j * MS + i] * x[i];
+                for (int i = j + 1; i < MS; ++i) w += gv(j * MS + i) * x[i];
                 w *= tau;
                 x[j] -= w;
 #pragma unroll
-                for (int i = j + 1; i < MS; ++i)
-                    if (i < mrows) x[i] -= w * g[j * MS + i];
+                for (int i = j + 1; i < MS; ++i) x[i] -= w * gv(j * MS + i);
             }
-            if (act && n > 0) {
+            if (act) {
                 if (xok) {
 #pragma unroll
                     for (int d = 0; d < 6; ++d) xch[xidx(d)] = (d < 3) ? -x[d] : x[d];
@@ -2281,36 +2300,41 @@ __global__ void __launch_bounds__(64) k_bucket(const int32_t *__restrict__ phase
                     if (i < mrows) out[velem(off + 3 * ((i - 6) / 3), (i - 6) % 3, r, C)] = x[i];
             }
         } else {
-            if (act && n > 0) {
-                if (xok && (!(meta & kMetaBodyRoot) || C.root_in)) {
+            const bool lin = act && xok && (!(meta & kMetaBodyRoot) || C.root_in);
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) x[d] = (d < 3) ? -xch[xidx(d)] : xch[xidx(d)];
-                }
+            for (int d = 0; d < 6; ++d) {
+                const T val = xch[xidx(d)];
+                x[d] = lin ? ((d < 3) ? -val : val) : T(0);
+            }
 #pragma unroll
-                for (int i = 6; i < MS; ++i)
-                    if (i < mrows) x[i] = v[velem(off + 3 * ((i - 6) / 3), (i - 6) % 3, r, C)];
+            for (int i = 6; i < MS; ++i) {
+                const bool ok = act && i < mrows;
+                const int row = ok ? off + (i - 6) : 0;
+                const T val = v[velem(row - row % 3, row % 3, rc, C)];
+                x[i] = ok ? val : T(0);
             }
             // x <- Q x = H_1 ... H_6 x
 #pragma unroll
             for (int j = 5; j >= 0; --j) {
-                const T tau = n > 0 ? g[6 * MS + j] : T(0);
+                const T tau = gv(6 * MS + j);
                 T w = x[j];
 #pragma unroll
-                for (int i = j + 1; i < MS; ++i)
-                    if (i < mrows) w += g[j * MS + i] * x[i];
+                for (int i = j + 1; i < MS; ++i) w += gv(j * MS + i) * x[i];
                 w *= tau;
                 x[j] -= w;
 #pragma unroll
-                for (int i = j + 1; i < MS; ++i)
-                    if (i < mrows) x[i] -= w * g[j * MS + i];
+                for (int i = j + 1; i < MS; ++i) x[i] -= w * gv(j * MS + i);
             }
-            if (act && n > 0)
-                for (int k = 0; k < n; ++k) {
-                    const int64_t u = perm[f + k];
+            if (act) {
 #pragma unroll
-                    for (int i = 0; i < MS; ++i)
-                        if (i / 3 == k) out[velem(3 * u, i % 3, r, C)] = x[i];
+                for (int k = 0; k < SMAX; ++k) {
+                    if (k < n) {
+                        const int64_t u = perm[f + k];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) out[velem(3 * u, d, r, C)] = x[3 * k + d];
+                    }
                 }
+            }
         }
     }
     if (bad) atomicOr(err, bad);

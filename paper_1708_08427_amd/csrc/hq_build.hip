@@ -1281,36 +1281,46 @@ __global__ void __launch_bounds__(64) k_gen_bucket(const int32_t *__restrict__ p
             }
         }
         const int mrows = 3 * n;
-        // the leaf's centroid (body-local), and column j of X
+        // the leaf's bead positions (body-local; zeros beyond n, loaded from
+        // valid addresses), its centroid, and column j of X
         double c[3] = {0.0, 0.0, 0.0}, lo3[3] = {0.0, 0.0, 0.0};
         if (n > 0)
             for (int d = 0; d < 3; ++d) lo3[d] = lo[3 * body + d];
-        for (int k = 0; k < n; ++k) {
-            const int64_t u = perm[f + k];
-            for (int d = 0; d < 3; ++d) c[d] += pos[3 * u + d] - lo3[d];
+        double pb[SMAX][3];
+#pragma unroll
+        for (int k = 0; k < SMAX; ++k) {
+            const bool ok = k < n;
+            const int64_t u = perm[f + (ok ? k : 0)];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double x = pos[3 * u + d];
+                pb[k][d] = ok ? x - lo3[d] : 0.0;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < SMAX; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c[d] += pb[k][d];
         for (int d = 0; d < 3; ++d) c[d] = n > 0 ? c[d] / (double)n : 0.0;
         const double rs = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
         double col[MS];
 #pragma unroll
-        for (int i = 0; i < MS; ++i) col[i] = 0.0;
-        for (int k = 0; k < n; ++k) {
-            double u[3];
-            const int64_t b = perm[f + k];
-            for (int d = 0; d < 3; ++d) u[d] = pos[3 * b + d] - lo3[d] - c[d];
+        for (int k = 0; k < SMAX; ++k) {
+            const bool ok = k < n;
+            const double u0 = pb[k][0] - c[0], u1 = pb[k][1] - c[1], u2 = pb[k][2] - c[2];
             // column j < 3: U_t^T; column 3 + e: Z_r^T = A_k^T, A_k = [u]x
-            const double A[3][3] = {{0.0, -u[2], u[1]}, {u[2], 0.0, -u[0]}, {-u[1], u[0], 0.0}};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                double x = 0.0;
-                if (j < 3) x = (d == j) ? rs : 0.0;
-                else if (j < 6) x = A[j - 3][d];
-#pragma unroll
-                for (int i = 0; i < MS; ++i)
-                    if (i == 3 * k + d) col[i] = x;
-            }
+            // (rows {0, -u2, u1}, {u2, 0, -u0}, {-u1, u0, 0})
+            const double e0 = j == 0 ? rs : (j == 4 ? u2 : (j == 5 ? -u1 : 0.0));
+            const double e1 = j == 1 ? rs : (j == 3 ? -u2 : (j == 5 ? u0 : 0.0));
+            const double e2 = j == 2 ? rs : (j == 3 ? u1 : (j == 4 ? -u0 : 0.0));
+            col[3 * k] = ok ? e0 : 0.0;
+            col[3 * k + 1] = ok ? e1 : 0.0;
+            col[3 * k + 2] = ok ? e2 : 0.0;
         }
         double tau_j = 0.0;
+        // unrolled, so that col[] is indexed by constants (a runtime index
+        // would put the array in scratch memory)
+#pragma unroll
         for (int p = 0; p < 6; ++p) {
             if (j == p && n > 0) {
                 const double alpha = col[p];
@@ -1368,8 +1378,11 @@ __global__ void __launch_bounds__(64) k_gen_bucket(const int32_t *__restrict__ p
             if (kStore & 2) brec32[base + 6 * MS + j] = (float)tau_j;
         }
         // T22 = R(4:6,4:6)^T: lane 3 + i holds R(3 .. 3 + i, 3 + i)
-        if (j >= 3 && j < 6 && n > 0)
-            for (int q = 0; q <= j - 3; ++q) rbuf[bq][(j - 3) * 3 + q] = col[3 + q];
+        if (j >= 3 && j < 6 && n > 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (q <= j - 3) rbuf[bq][(j - 3) * 3 + q] = col[3 + q];
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (j == 0 && n > 0) {
