@@ -437,27 +437,49 @@ __global__ void k_rem_scatter(int64_t NI, const int32_t *cov, const int32_t *pos
 // Units of the uncovered nodes after the first phase (beads and roots of
 // earlier tiles count one each): every uncovered node adds the units among its
 // own children to itself and to all its ancestors, which are uncovered too.
+__device__ __forceinline__ void units_walk_at(int64_t i, int64_t NI, const int32_t *rem, const int32_t *cov,
+                                              const int32_t *lc, const int32_t *rc, const int32_t *par,
+                                              int32_t *units, int32_t *err) {
+    const int g = node_at(i, rem);
+    if (cov[g] != 0) return;
+    const int x = lc[g], y = rc[g];
+    const int c = ((x < 0 || cov[x] != 0) ? 1 : 0) + ((y < 0 || cov[y] != 0) ? 1 : 0);
+    if (c == 0) return;
+    int q = g;
+    for (int guard = 0; q >= 0; ++guard) {
+        if (guard == kMaxDepth || q >= NI) {
+            raise_flag(err, kFlagBounds);
+            break;
+        }
+        atomicAdd(&units[q], c);
+        q = par[q];
+    }
+}
+
 __global__ void k_units_walk(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
                              const int32_t *lc, const int32_t *rc, const int32_t *par, int32_t *units,
                              int32_t *err, const int32_t *gate) {
     if (gate && *gate == 0) return;
     const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] != 0) continue;
-        const int x = lc[g], y = rc[g];
-        const int c = ((x < 0 || cov[x] != 0) ? 1 : 0) + ((y < 0 || cov[y] != 0) ? 1 : 0);
-        if (c == 0) continue;
-        int q = g;
-        for (int guard = 0; q >= 0; ++guard) {
-            if (guard == kMaxDepth || q >= NI) {
-                raise_flag(err, kFlagBounds);
-                break;
-            }
-            atomicAdd(&units[q], c);
-            q = par[q];
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        units_walk_at(i, NI, rem, cov, lc, rc, par, units, err);
+}
+
+__device__ __forceinline__ void tile_roots_at(int64_t i, const int32_t *rem, int phase, int S, const int32_t *cov,
+                                              const int32_t *par, const int32_t *nn, int32_t *units,
+                                              long long *trval) {
+    const int g = node_at(i, rem);
+    if (cov[g] != 0) {
+        trval[i] = 0;
+        return;
     }
+    // first phase: every bead is a unit; later: counted by k_units_walk
+    const int u = (phase == 1) ? nn[g] : units[g];
+    const int p = par[g];
+    const int up = (p < 0) ? INT_MAX : ((phase == 1) ? nn[p] : units[p]);
+    if (phase == 1) units[g] = u;
+    const bool root = (u <= S) && (up > S);
+    trval[i] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
 }
 
 __global__ void k_tile_roots(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int S,
@@ -465,20 +487,8 @@ __global__ void k_tile_roots(int64_t NI, const int32_t *rem, const int32_t *dn, 
                              long long *trval, const int32_t *gate) {
     if (gate && *gate == 0) return;
     const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] != 0) {
-            trval[i] = 0;
-            continue;
-        }
-        // first phase: every bead is a unit; later: counted by k_units_walk
-        const int u = (phase == 1) ? nn[g] : units[g];
-        const int p = par[g];
-        const int up = (p < 0) ? INT_MAX : ((phase == 1) ? nn[p] : units[p]);
-        if (phase == 1) units[g] = u;
-        const bool root = (u <= S) && (up > S);
-        trval[i] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        tile_roots_at(i, rem, phase, S, cov, par, nn, units, trval);
 }
 
 // Per uncovered node: evaluation order of its children (the one with more
@@ -493,6 +503,41 @@ constexpr int kAwPend = 1 << 29, kAwRoot = 1 << 30, kAwSkip = (1 << 29) - 1;
 
 // A tile root also enters its tile in the tile tables: root, node count and
 // first schedule index (from the scan of the root flags and node counts).
+__device__ __forceinline__ void assign_prep_at(int64_t i, const int32_t *rem, const int32_t *cov,
+                                               const int32_t *par, const int32_t *lc, const int32_t *rc,
+                                               const int32_t *units, const long long *trval,
+                                               const long long *trscan, int tiles0, int nodes0, int32_t *tile_root,
+                                               int32_t *tile_len, int32_t *tile_base, int32_t *tileof,
+                                               int32_t *yfirst, int2 *aw) {
+    const int g = node_at(i, rem);
+    if (cov[g] != 0) return;
+    const long long tv = trval[i];
+    if (tv != 0) {
+        const long long sc = trscan[i];
+        const int t = tiles0 + (int)(sc >> 32);
+        tile_root[t] = g;
+        tile_len[t] = (int)(tv & 0xffffffffll);
+        tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
+        tileof[g] = t;
+    }
+    {
+        const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
+        yfirst[g] = (uy > ux) ? 1 : 0;
+    }
+    const int p = par[g];
+    int word = (tv != 0) ? kAwRoot : 0;
+    if (p >= 0) {
+        const int x = lc[p], y = rc[p];
+        const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
+        const bool y_first = uy > ux;
+        if (g == (y_first ? x : y)) {
+            const int ufirst = y_first ? uy : ux;
+            word |= min(ufirst - 1, kAwSkip) | ((ufirst > 1) ? kAwPend : 0);
+        }
+    }
+    aw[g] = make_int2(p, word);
+}
+
 __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn, const int32_t *cov,
                               const int32_t *par, const int32_t *lc, const int32_t *rc, const int32_t *units,
                               const long long *trval, const long long *trscan, const int32_t *cnt,
@@ -501,27 +546,34 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn,
     if (gate && *gate == 0) return;
     const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
     const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] != 0) continue;
-        const long long tv = trval[i];
-        if (tv != 0) {
-            const long long sc = trscan[i];
-            const int t = tiles0 + (int)(sc >> 32);
-            tile_root[t] = g;
-            tile_len[t] = (int)(tv & 0xffffffffll);
-            tile_base[t] = nodes0 + (int)(sc & 0xffffffffll);
-            tileof[g] = t;
-        }
-        {
-            const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
-            yfirst[g] = (uy > ux) ? 1 : 0;
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        assign_prep_at(i, rem, cov, par, lc, rc, units, trval, trscan, tiles0, nodes0, tile_root, tile_len, tile_base,
+                       tileof, yfirst, aw);
+}
+
+// The first phase in two passes instead of three.  With every node still
+// uncovered, a node's units are its bead count (nn), so the per-node steps of
+// k_assign_prep (child order, the walk word) need no earlier pass and join
+// k_tile_roots; and k_assign finds a tile's index and first schedule slot in
+// the scan of the root flags at the root itself (the list of nodes is the
+// identity in the first phase), where the root also enters its tile.
+__device__ __forceinline__ int first_units(int c, const int32_t *nn) { return c < 0 ? 1 : nn[c]; }
+
+__global__ void k_tile_roots1(int64_t NI, int S, const int32_t *par, const int32_t *lc, const int32_t *rc,
+                              const int32_t *nn, int32_t *units, long long *trval, int32_t *yfirst, int2 *aw) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)i;
+        const int u = nn[g];
         const int p = par[g];
-        int word = (tv != 0) ? kAwRoot : 0;
+        const int up = (p < 0) ? INT_MAX : nn[p];
+        units[g] = u;
+        const bool root = (u <= S) && (up > S);
+        trval[i] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
+        yfirst[g] = (first_units(rc[g], nn) > first_units(lc[g], nn)) ? 1 : 0;
+        int word = root ? kAwRoot : 0;
         if (p >= 0) {
             const int x = lc[p], y = rc[p];
-            const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
+            const int ux = first_units(x, nn), uy = first_units(y, nn);
             const bool y_first = uy > ux;
             if (g == (y_first ? x : y)) {
                 const int ufirst = y_first ? uy : ux;
@@ -532,20 +584,13 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn,
     }
 }
 
-// Post-order position of every uncovered node inside the tile whose root it
-// reaches first going up (the child with more units is evaluated first), and
-// the stack slot that receives its result (results of the tile pending while
-// its subtree is swept).  A node placed in a tile is covered by this phase; a
-// node left over gets its unit count cleared for the next phase's count.
-__global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
-                         int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
-                         int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int32_t *err, int64_t sched_cap,
-                         const int32_t *gate) {
-    if (gate && *gate == 0) return;
-    const int64_t n = node_count(NI, dn);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = node_at(i, rem);
-        if (cov[g] != 0) continue;
+__global__ void k_assign1(int64_t NI, int32_t *cov, int32_t *units, const int2 *aw, const long long *trval,
+                          const long long *trscan, const int32_t *cnt, int32_t *tile_root, int32_t *tile_len,
+                          int32_t *tile_base, int32_t *tileof, int32_t *sched, int32_t *sched_node,
+                          int32_t *depth_slot, int32_t *err, int64_t sched_cap) {
+    const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)i;
         int pos = units[g] - 2, pend = 0;
         int q = g;
         bool found = false;
@@ -559,30 +604,89 @@ __global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, int 
             q = w.x;
         }
         if (too_deep) raise_flag(err, kFlagBounds);
-        bool placed = false;
-        if (found) {
-            const int t = tileof[q];
-            const int64_t s = (t >= 0 && t < NI) ? (int64_t)tile_base[t] + pos : -1;
-            if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
-                raise_flag(err, kFlagBounds);
-            } else {
-                tileof[g] = t;
-                depth_slot[g] = pend;
-                sched[g] = (int)s;
-                sched_node[s] = g;
-                cov[g] = phase;
-                placed = true;
-            }
+        // a node above every tile root is left for the next phase, which
+        // counts its units afresh
+        if (!found) {
+            units[g] = 0;
+            continue;
         }
-        if (!placed) units[g] = 0;
+        const long long sc = trscan[q];
+        const int t = tiles0 + (int)(sc >> 32);
+        const int64_t base = (int64_t)nodes0 + (int)(sc & 0xffffffffll);
+        const int64_t s = base + pos;
+        if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
+            raise_flag(err, kFlagBounds);
+            units[g] = 0;
+            continue;
+        }
+        if (q == g) {
+            tile_root[t] = g;
+            tile_len[t] = (int)(trval[g] & 0xffffffffll);
+            tile_base[t] = (int)base;
+        }
+        tileof[g] = t;
+        depth_slot[g] = pend;
+        sched[g] = (int)s;
+        sched_node[s] = g;
+        cov[g] = 1;
     }
 }
 
-__global__ void k_phase_close(int64_t NI, const int32_t *dn, int phase, const long long *trval,
-                              const long long *trscan, int32_t *cnt, int32_t *phase_tab, int run_nodes,
-                              int32_t *prun, int64_t run_cap, int32_t *err, const int32_t *gate) {
+// Post-order position of every uncovered node inside the tile whose root it
+// reaches first going up (the child with more units is evaluated first), and
+// the stack slot that receives its result (results of the tile pending while
+// its subtree is swept).  A node placed in a tile is covered by this phase; a
+// node left over gets its unit count cleared for the next phase's count.
+__device__ __forceinline__ void assign_at(int64_t i, int64_t NI, const int32_t *rem, int phase, int32_t *cov,
+                                          int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
+                                          int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int32_t *err,
+                                          int64_t sched_cap) {
+    const int g = node_at(i, rem);
+    if (cov[g] != 0) return;
+    int pos = units[g] - 2, pend = 0;
+    int q = g;
+    bool found = false;
+    bool too_deep = true;
+    for (int guard = 0; guard < kMaxDepth; ++guard) {
+        const int2 w = aw[q];
+        if (w.y & kAwRoot) { found = true; too_deep = false; break; }
+        if (w.x < 0) { too_deep = false; break; }
+        pos += w.y & kAwSkip;
+        pend += (w.y & kAwPend) ? 1 : 0;
+        q = w.x;
+    }
+    if (too_deep) raise_flag(err, kFlagBounds);
+    bool placed = false;
+    if (found) {
+        const int t = tileof[q];
+        const int64_t s = (t >= 0 && t < NI) ? (int64_t)tile_base[t] + pos : -1;
+        if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
+            raise_flag(err, kFlagBounds);
+        } else {
+            tileof[g] = t;
+            depth_slot[g] = pend;
+            sched[g] = (int)s;
+            sched_node[s] = g;
+            cov[g] = phase;
+            placed = true;
+        }
+    }
+    if (!placed) units[g] = 0;
+}
+
+__global__ void k_assign(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
+                         int32_t *units, const int2 *aw, const int32_t *tile_base, int32_t *tileof,
+                         int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int32_t *err, int64_t sched_cap,
+                         const int32_t *gate) {
     if (gate && *gate == 0) return;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        assign_at(i, NI, rem, phase, cov, units, aw, tile_base, tileof, sched, sched_node, depth_slot, err, sched_cap);
+}
+
+__device__ __forceinline__ void phase_close_one(int64_t NI, const int32_t *dn, int phase, const long long *trval,
+                                                const long long *trscan, int32_t *cnt, int32_t *phase_tab,
+                                                int run_nodes, int32_t *prun, int64_t run_cap, int32_t *err) {
     const int64_t n = node_count(NI, dn);
     const long long tot = (n > 0) ? trscan[n - 1] + trval[n - 1] : 0;
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
@@ -610,18 +714,24 @@ __global__ void k_phase_close(int64_t NI, const int32_t *dn, int phase, const lo
     cnt[kCntRemain] = (int)(NI - cnt[kCntNodes]);
 }
 
+__global__ void k_phase_close(int64_t NI, const int32_t *dn, int phase, const long long *trval,
+                              const long long *trscan, int32_t *cnt, int32_t *phase_tab, int run_nodes,
+                              int32_t *prun, int64_t run_cap, int32_t *err, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    phase_close_one(NI, dn, phase, trval, trscan, cnt, phase_tab, run_nodes, prun, run_cap, err);
+}
+
 // Run starts of one phase: run c begins at the first tile that starts at or
 // after node c * tp of the phase (phase end if none), so every run holds
 // whole tiles and a lane group can sweep it as one node stream.
-__global__ void k_runs(int phase, const int32_t *phase_tab, const int32_t *tile_base, const int32_t *prun,
-                       int32_t *run, const int32_t *gate) {
-    if (gate && *gate == 0) return;
+__device__ __forceinline__ void runs_range(int phase, const int32_t *phase_tab, const int32_t *tile_base,
+                                           const int32_t *prun, int32_t *run, int64_t first, int64_t stride) {
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
     const int *pr = prun + kPrunStride * phase;
     const int p0 = pr[0], p1 = pr[1], c0 = pr[2], nrun = pr[3], tp = max(pr[4], 1);
     if (nrun == 0 && p1 > p0) return;  // table full: flagged by k_phase_close
-    for (int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tt <= te - tb;
-         tt += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t tt = first; tt <= te - tb; tt += stride) {
         const int t = tb + (int)tt;
         const int st = (t < te) ? tile_base[t] - p0 : p1 - p0;
         const int lo = (t == tb) ? 0 : (tile_base[t - 1] - p0) / tp + 1;
@@ -630,8 +740,76 @@ __global__ void k_runs(int phase, const int32_t *phase_tab, const int32_t *tile_
     }
 }
 
-__global__ void k_check_phases(int32_t *cnt, int32_t *err) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[kCntRemain] != 0) raise_flag(err, kFlagPhases);
+__global__ void k_runs(int phase, const int32_t *phase_tab, const int32_t *tile_base, const int32_t *prun,
+                       int32_t *run, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    runs_range(phase, phase_tab, tile_base, prun, run, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+               (int64_t)gridDim.x * blockDim.x);
+}
+
+// Exclusive scan of in[0, n) into out by one workgroup (every thread calls
+// it): a contiguous chunk per thread, the chunk sums scanned in LDS.
+__device__ void block_exscan_i64(const long long *in, long long *out, int64_t n, long long *part) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t chunk = (n + nt - 1) / nt;
+    const int64_t b = tid * chunk, e = min(n, b + chunk);
+    long long sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += in[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const long long v = (tid >= off) ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    long long run = (tid > 0) ? part[tid - 1] : 0;
+    for (int64_t i = b; i < e; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+}
+
+// Tile phases ph0..ph1 of a rebuild in one workgroup (one launch instead of
+// about nine per phase), for the reserved phases: a phase without nodes ends
+// at once.  The same per-node steps as the multi-workgroup kernels, separated
+// by workgroup barriers; the phase loop stops when no node is left.
+constexpr int kTailThreads = 1024;
+
+__global__ void __launch_bounds__(kTailThreads) k_tail_phases(
+    int ph0, int ph1, int64_t NI, const int32_t *rem, const int32_t *dn, int S, int32_t *cov, const int32_t *par,
+    const int32_t *lc, const int32_t *rc, const int32_t *nn, int32_t *units, long long *trval, long long *trscan,
+    int32_t *cnt, int32_t *tile_root, int32_t *tile_len, int32_t *tile_base, int32_t *tileof, int32_t *yfirst,
+    int2 *aw, int32_t *sched, int32_t *sched_node, int32_t *depth_slot, int64_t sched_cap, int32_t *phase_tab,
+    int run_nodes, int32_t *prun, int64_t run_cap, int32_t *run, int32_t *err) {
+    __shared__ long long part[kTailThreads];
+    __shared__ int live;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int ph = ph0; ph <= ph1; ++ph) {
+        __syncthreads();
+        if (tid == 0) live = cnt[kCntRemain];
+        __syncthreads();
+        if (live == 0) break;
+        const int64_t n = node_count(NI, dn);
+        for (int64_t i = tid; i < n; i += nt) units_walk_at(i, NI, rem, cov, lc, rc, par, units, err);
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += nt) tile_roots_at(i, rem, ph, S, cov, par, nn, units, trval);
+        __syncthreads();
+        block_exscan_i64(trval, trscan, n, part);
+        __syncthreads();
+        const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
+        for (int64_t i = tid; i < n; i += nt)
+            assign_prep_at(i, rem, cov, par, lc, rc, units, trval, trscan, tiles0, nodes0, tile_root, tile_len,
+                           tile_base, tileof, yfirst, aw);
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += nt)
+            assign_at(i, NI, rem, ph, cov, units, aw, tile_base, tileof, sched, sched_node, depth_slot, err,
+                      sched_cap);
+        __syncthreads();
+        if (tid == 0) phase_close_one(NI, dn, ph, trval, trscan, cnt, phase_tab, run_nodes, prun, run_cap, err);
+        __syncthreads();
+        if (prun[kPrunStride * ph + 1] != 0) runs_range(ph, phase_tab, tile_base, prun, run, tid, nt);
+    }
 }
 
 // First residue row of every tile root (pre-order rows, Section 3's
@@ -639,6 +817,8 @@ __global__ void k_check_phases(int32_t *cnt, int32_t *err) {
 // nodes then only walk up to their own tile root.
 __global__ void k_troot_off(int64_t NI, const int32_t *cnt, const int32_t *tile_root, const int2 *lw,
                             const int32_t *nbody, const int32_t *row_off, int32_t *toff, int32_t *err) {
+    // (also the check that the phases covered every node)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt[kCntRemain] != 0) raise_flag(err, kFlagPhases);
     const int nt = cnt[kCntTiles];
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
         const int r = tile_root[t];
@@ -1540,6 +1720,22 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     int phases = 0;
     const int max_ph = probe_phases ? (kMaxPhases - 1) : P.phases_reserved;
     for (int ph = 1; ph <= max_ph; ++ph) {
+        if (!probe_phases && ph > std::max(P.phases_built, 2)) {
+            // a rebuild's reserved phases (beyond those the first build
+            // needed) in one single-workgroup launch: they are normally empty,
+            // and about nine launches each cost their dispatch latency on the
+            // rebuild's critical path.  (Taking a real phase this way is
+            // slower than its multi-workgroup launches: a rebuild that needs
+            // one more phase than the first build pays that, correctly.)
+            hipLaunchKernelGGL(k_tail_phases, dim3(1), dim3(kTailThreads), 0, s, ph, max_ph, NI, P.d_rem,
+                               P.d_cnt + kCntRemList, P.S2, P.d_cov, P.d_par, P.d_lc, P.d_rc, P.d_nn, P.d_units,
+                               P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base,
+                               P.d_tileof, P.d_yfirst, P.d_aw, P.d_sched, P.d_sched_node, P.d_slot, NI, P.d_phase,
+                               P.run_nodes, P.d_prun, P.run_cap, P.d_run, P.d_err);
+            HQ_HIP(hipGetLastError());
+            phases = max_ph;
+            break;
+        }
         // a phase after the one that covered the last node is a no-op on the
         // device (reserved phases of a rebuild cost a few launches only)
         const int32_t *gate = (ph >= 2) ? P.d_cnt + kCntRemain : nullptr;
@@ -1558,15 +1754,24 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             hipLaunchKernelGGL(k_units_walk, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_lc, P.d_rc,
                                P.d_par, P.d_units, P.d_err, gate);
         }
-        hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, (ph == 1) ? P.S : P.S2,
-                           P.d_cov, P.d_par,
-                           P.d_nn, P.d_units, P.d_trval, gate);
-        HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
-        hipLaunchKernelGGL(k_assign_prep, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_par, P.d_lc,
-                           P.d_rc, P.d_units, P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root, P.d_tile_len,
-                           P.d_tile_base, P.d_tileof, P.d_yfirst, P.d_aw, gate);
-        hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_units, P.d_aw,
-                           P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI, gate);
+        if (ph == 1) {
+            hipLaunchKernelGGL(k_tile_roots1, dim3(grid), dim3(kThreads), 0, s, NI, P.S, P.d_par, P.d_lc, P.d_rc,
+                               P.d_nn, P.d_units, P.d_trval, P.d_yfirst, P.d_aw);
+            HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
+            hipLaunchKernelGGL(k_assign1, dim3(grid), dim3(kThreads), 0, s, NI, P.d_cov, P.d_units, P.d_aw,
+                               P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base,
+                               P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI);
+        } else {
+            hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.S2, P.d_cov,
+                               P.d_par, P.d_nn, P.d_units, P.d_trval, gate);
+            HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
+            hipLaunchKernelGGL(k_assign_prep, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_par,
+                               P.d_lc, P.d_rc, P.d_units, P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root,
+                               P.d_tile_len, P.d_tile_base, P.d_tileof, P.d_yfirst, P.d_aw, gate);
+            hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_units,
+                               P.d_aw, P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI,
+                               gate);
+        }
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, dn, ph, P.d_trval, P.d_trscan, P.d_cnt,
                            P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
         // the run table of a phase is built when the phase holds nodes
@@ -1590,7 +1795,6 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         }
     }
     if (probe_phases) P.phases_built = phases;
-    hipLaunchKernelGGL(k_check_phases, dim3(1), dim3(64), 0, s, P.d_cnt, P.d_err);
     // the compaction flags are free again: they hold the tile roots' offsets
     int32_t *toff = P.d_mark;
     hipLaunchKernelGGL(k_troot_off, dim3(std::min(grid_for(NI), 2048u)), dim3(kThreads), 0, s, NI, P.d_cnt,
@@ -1598,7 +1802,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     hipLaunchKernelGGL(k_links, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_tileof, P.d_sched,
                        P.d_lc, P.d_rc, P.d_par, P.d_nn, P.d_nbody, P.d_yfirst, P.d_tile_root, P.d_perm, toff,
                        P.d_slot, stack_slots(P.smax()), P.d_lw, P.d_links, P.d_err);
-    {
+    if (P.fused_up) {
+        // the fused upward sweep's tile tables (no other sweep reads them)
         const unsigned tg = std::min(grid_for(NI), 2048u);
         hipLaunchKernelGGL(k_tile_zero, dim3(tg), dim3(kThreads), 0, s, NI, P.d_cnt, P.d_tcnt0);
         hipLaunchKernelGGL(k_tile_parents, dim3(tg), dim3(kThreads), 0, s, NI, P.d_cnt, P.d_tile_root, P.d_par,
