@@ -419,12 +419,6 @@ __device__ __forceinline__ int64_t node_count(int64_t NI, const int32_t *dn) {
 }
 __device__ __forceinline__ int node_at(int64_t i, const int32_t *rem) { return rem ? rem[i] : (int)i; }
 
-__global__ void k_rem_flags(int64_t NI, const int32_t *cov, int32_t *flag, const int32_t *gate) {
-    if (gate && *gate == 0) return;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < NI; g += (int64_t)gridDim.x * blockDim.x)
-        flag[g] = (cov[g] == 0) ? 1 : 0;
-}
-
 __global__ void k_rem_scatter(int64_t NI, const int32_t *cov, const int32_t *pos, int32_t *rem, int32_t *cnt,
                               const int32_t *gate) {
     if (gate && *gate == 0) return;
@@ -556,7 +550,9 @@ __global__ void k_assign_prep(int64_t NI, const int32_t *rem, const int32_t *dn,
 // k_assign_prep (child order, the walk word) need no earlier pass and join
 // k_tile_roots; and k_assign finds a tile's index and first schedule slot in
 // the scan of the root flags at the root itself (the list of nodes is the
-// identity in the first phase), where the root also enters its tile.
+// identity in the first phase), where the root also enters its tile.  It
+// also flags the nodes it leaves for the later phases (left), the input of
+// their list.
 __device__ __forceinline__ int first_units(int c, const int32_t *nn) { return c < 0 ? 1 : nn[c]; }
 
 __global__ void k_tile_roots1(int64_t NI, int S, const int32_t *par, const int32_t *lc, const int32_t *rc,
@@ -587,7 +583,7 @@ __global__ void k_tile_roots1(int64_t NI, int S, const int32_t *par, const int32
 __global__ void k_assign1(int64_t NI, int32_t *cov, int32_t *units, const int2 *aw, const long long *trval,
                           const long long *trscan, const int32_t *cnt, int32_t *tile_root, int32_t *tile_len,
                           int32_t *tile_base, int32_t *tileof, int32_t *sched, int32_t *sched_node,
-                          int32_t *depth_slot, int32_t *err, int64_t sched_cap) {
+                          int32_t *depth_slot, int32_t *left, int32_t *err, int64_t sched_cap) {
     const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI; i += (int64_t)gridDim.x * blockDim.x) {
         const int g = (int)i;
@@ -608,6 +604,7 @@ __global__ void k_assign1(int64_t NI, int32_t *cov, int32_t *units, const int2 *
         // counts its units afresh
         if (!found) {
             units[g] = 0;
+            left[g] = 1;
             continue;
         }
         const long long sc = trscan[q];
@@ -617,8 +614,10 @@ __global__ void k_assign1(int64_t NI, int32_t *cov, int32_t *units, const int2 *
         if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
             raise_flag(err, kFlagBounds);
             units[g] = 0;
+            left[g] = 1;
             continue;
         }
+        left[g] = 0;
         if (q == g) {
             tile_root[t] = g;
             tile_len[t] = (int)(trval[g] & 0xffffffffll);
@@ -629,6 +628,97 @@ __global__ void k_assign1(int64_t NI, int32_t *cov, int32_t *units, const int2 *
         sched[g] = (int)s;
         sched_node[s] = g;
         cov[g] = 1;
+    }
+}
+
+// The later phases likewise (after k_units_walk, every unit count is
+// final): k_tile_roots_l adds the per-node steps of k_assign_prep and records
+// each root's place in the node list (ridx), and k_assign_l reads the root's
+// tile index and base from the scan there.
+__global__ void k_tile_roots_l(int64_t NI, const int32_t *rem, const int32_t *dn, int S, const int32_t *cov,
+                               const int32_t *par, const int32_t *lc, const int32_t *rc, const int32_t *units,
+                               long long *trval, int32_t *yfirst, int2 *aw, int32_t *ridx, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
+        if (cov[g] != 0) {
+            trval[i] = 0;
+            continue;
+        }
+        const int u = units[g];
+        const int p = par[g];
+        const int up = (p < 0) ? INT_MAX : units[p];
+        const bool root = (u <= S) && (up > S);
+        trval[i] = root ? ((1ll << 32) | (long long)(u - 1)) : 0ll;
+        if (root) ridx[g] = (int)i;
+        {
+            const int ux = child_units(lc[g], cov, units), uy = child_units(rc[g], cov, units);
+            yfirst[g] = (uy > ux) ? 1 : 0;
+        }
+        int word = root ? kAwRoot : 0;
+        if (p >= 0) {
+            const int x = lc[p], y = rc[p];
+            const int ux = child_units(x, cov, units), uy = child_units(y, cov, units);
+            const bool y_first = uy > ux;
+            if (g == (y_first ? x : y)) {
+                const int ufirst = y_first ? uy : ux;
+                word |= min(ufirst - 1, kAwSkip) | ((ufirst > 1) ? kAwPend : 0);
+            }
+        }
+        aw[g] = make_int2(p, word);
+    }
+}
+
+__global__ void k_assign_l(int64_t NI, const int32_t *rem, const int32_t *dn, int phase, int32_t *cov,
+                           int32_t *units, const int2 *aw, const long long *trval, const long long *trscan,
+                           const int32_t *ridx, const int32_t *cnt, int32_t *tile_root, int32_t *tile_len,
+                           int32_t *tile_base, int32_t *tileof, int32_t *sched, int32_t *sched_node,
+                           int32_t *depth_slot, int32_t *err, int64_t sched_cap, const int32_t *gate) {
+    if (gate && *gate == 0) return;
+    const int tiles0 = cnt[kCntTiles], nodes0 = cnt[kCntNodes];
+    const int64_t n = node_count(NI, dn);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = node_at(i, rem);
+        if (cov[g] != 0) continue;
+        int pos = units[g] - 2, pend = 0;
+        int q = g;
+        bool found = false;
+        bool too_deep = true;
+        for (int guard = 0; guard < kMaxDepth; ++guard) {
+            const int2 w = aw[q];
+            if (w.y & kAwRoot) { found = true; too_deep = false; break; }
+            if (w.x < 0) { too_deep = false; break; }
+            pos += w.y & kAwSkip;
+            pend += (w.y & kAwPend) ? 1 : 0;
+            q = w.x;
+        }
+        if (too_deep) raise_flag(err, kFlagBounds);
+        const int iq = found ? ridx[q] : -1;
+        if (!found || iq < 0 || iq >= n) {
+            if (found) raise_flag(err, kFlagBounds);
+            units[g] = 0;
+            continue;
+        }
+        const long long sc = trscan[iq];
+        const int t = tiles0 + (int)(sc >> 32);
+        const int64_t base = (int64_t)nodes0 + (int)(sc & 0xffffffffll);
+        const int64_t s = base + pos;
+        if (t < 0 || t >= NI || pos < 0 || s < 0 || s >= sched_cap) {
+            raise_flag(err, kFlagBounds);
+            units[g] = 0;
+            continue;
+        }
+        if (q == g) {
+            tile_root[t] = g;
+            tile_len[t] = (int)(trval[i] & 0xffffffffll);
+            tile_base[t] = (int)base;
+        }
+        tileof[g] = t;
+        depth_slot[g] = pend;
+        sched[g] = (int)s;
+        sched_node[s] = g;
+        cov[g] = phase;
     }
 }
 
@@ -1744,7 +1834,7 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
         const int32_t *dn = (ph >= 2) ? P.d_cnt + kCntRemList : nullptr;
         const unsigned grid = (ph >= 2) ? std::min(grid_for(NI), 1024u) : grid_for(NI);
         if (ph == 2) {
-            hipLaunchKernelGGL(k_rem_flags, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_mark, gate);
+            // the first phase's k_assign1 flagged the nodes it left (P.d_mark)
             HQ_TRY(scan_i32_inclusive(P, P.d_mark, P.d_msum, NI, s, gate));
             hipLaunchKernelGGL(k_rem_scatter, dim3(grid_for(NI)), dim3(kThreads), 0, s, NI, P.d_cov, P.d_msum,
                                P.d_rem, P.d_cnt, gate);
@@ -1760,17 +1850,16 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
             hipLaunchKernelGGL(k_assign1, dim3(grid), dim3(kThreads), 0, s, NI, P.d_cov, P.d_units, P.d_aw,
                                P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root, P.d_tile_len, P.d_tile_base,
-                               P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI);
+                               P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_mark, P.d_err, NI);
         } else {
-            hipLaunchKernelGGL(k_tile_roots, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.S2, P.d_cov,
-                               P.d_par, P.d_nn, P.d_units, P.d_trval, gate);
+            // (P.d_msum, the list's scan, is free once the list is built: it
+            // holds the roots' places in the list)
+            hipLaunchKernelGGL(k_tile_roots_l, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.S2, P.d_cov, P.d_par,
+                               P.d_lc, P.d_rc, P.d_units, P.d_trval, P.d_yfirst, P.d_aw, P.d_msum, gate);
             HQ_TRY(scan_i64_exclusive(P, P.d_trval, P.d_trscan, NI, s, gate, dn));
-            hipLaunchKernelGGL(k_assign_prep, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, P.d_cov, P.d_par,
-                               P.d_lc, P.d_rc, P.d_units, P.d_trval, P.d_trscan, P.d_cnt, P.d_tile_root,
-                               P.d_tile_len, P.d_tile_base, P.d_tileof, P.d_yfirst, P.d_aw, gate);
-            hipLaunchKernelGGL(k_assign, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_units,
-                               P.d_aw, P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI,
-                               gate);
+            hipLaunchKernelGGL(k_assign_l, dim3(grid), dim3(kThreads), 0, s, NI, rem, dn, ph, P.d_cov, P.d_units,
+                               P.d_aw, P.d_trval, P.d_trscan, P.d_msum, P.d_cnt, P.d_tile_root, P.d_tile_len,
+                               P.d_tile_base, P.d_tileof, P.d_sched, P.d_sched_node, P.d_slot, P.d_err, NI, gate);
         }
         hipLaunchKernelGGL(k_phase_close, dim3(1), dim3(64), 0, s, NI, dn, ph, P.d_trval, P.d_trscan, P.d_cnt,
                            P.d_phase, P.run_nodes, P.d_prun, P.run_cap, P.d_err, gate);
