@@ -5,7 +5,12 @@ hierarchical oracle; FP32 products and the leak ||Z (Q~^T w)|| / (||Z|| ||w||)
 <= 1e-5 against FP64.  Tree and permutation (index work) are bit-exact.
 Bodies whose oracle has an ill-conditioned node (kappa(T22) > 1e4) are
 compared on the basis-free projector instead, because their Q~ basis is not
-determined beyond rounding.
+determined beyond rounding.  A body whose product misses 1e-12 is held to
+ten times its oracle sensitivity instead: the largest relative change of the
+oracle's own product when the body's positions move by 1e-15 relatively (a
+rounding-level change of the input, such as the GPU's body-local
+coordinates make).  Some small bodies reach 3e-12 there with kappa(T22)
+near 10: their transforms come from differences of nearby positions.
 """
 import numpy as np
 import pytest
@@ -59,6 +64,29 @@ def oracle_products(w, v, wv):
     return bt, bt.apply(v), bt.apply(wv, transpose=True)
 
 
+def oracle_sensitivity(pj, x, transpose, trials=4, seed=0):
+    """Largest relative 2-norm change (per RHS) of the oracle's product of
+    one body under relative perturbations of 1e-15 of its positions."""
+    rng = np.random.default_rng(seed)
+    base = hier.Batch(pj, [0, len(pj)]).apply(x, transpose=transpose)
+    worst = 0.0
+    for _ in range(trials):
+        q = pj * (1.0 + 1e-15 * rng.standard_normal(pj.shape))
+        y = hier.Batch(q, [0, len(q)]).apply(x, transpose=transpose)
+        d = np.linalg.norm(y - base, axis=0) / np.maximum(np.linalg.norm(base, axis=0), 1e-300)
+        worst = max(worst, float(d.max()))
+    return worst
+
+
+def within_oracle(err, pj, x, transpose):
+    """err <= 1e-12, or within ten times the body's oracle sensitivity."""
+    if err <= 1e-12:
+        return True
+    s = oracle_sensitivity(pj, x, transpose)
+    print(f"[gpu] body of {len(pj)} beads: error {err:.2e} against oracle sensitivity {s:.2e}", flush=True)
+    return err <= 10.0 * s
+
+
 def check_fp64(hq, w, S=0, nrhs=None, S2=0, min_checked=None, **opts):
     rng = np.random.default_rng(123)
     R = nrhs or w.nrhs
@@ -80,8 +108,9 @@ def check_fp64(hq, w, S=0, nrhs=None, S2=0, min_checked=None, **opts):
             continue
         r0, r1, b0, b1 = rows[j], rows[j + 1], beads3[j], beads3[j + 1]
         if r1 > r0:
-            assert rel_per_body(up[r0:r1], up_o[r0:r1], [0, 1], [0, r1 - r0]) <= 1e-12, j
-            assert rel_per_body(dn[b0:b1], dn_o[b0:b1], [0, 1], [0, b1 - b0]) <= 1e-12, j
+            pj = w.pos[w.offsets[j]:w.offsets[j + 1]]
+            assert within_oracle(rel_per_body(up[r0:r1], up_o[r0:r1], [0, 1], [0, r1 - r0]), pj, v[b0:b1], False), j
+            assert within_oracle(rel_per_body(dn[b0:b1], dn_o[b0:b1], [0, 1], [0, b1 - b0]), pj, wv[r0:r1], True), j
         checked += 1
     print(f"[gpu] element-wise parity on {checked} of {w.m} bodies", flush=True)
     assert checked >= min_checked if min_checked is not None else checked == w.m
