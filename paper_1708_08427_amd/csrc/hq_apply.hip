@@ -2143,6 +2143,16 @@ __global__ void __launch_bounds__(64, (sizeof(T) * NC == 4 && NR <= 3) ? 4 : 2) 
     if (bad) atomicOr(err, bad);
 }
 
+// Tiles a launch of one tile phase provisions its grid for: every tile of the
+// handle in the first phase; in a later phase twice the tiles the build found
+// there, plus 64 (a rebuild may move tiles between phases: the kernels stride
+// over their work, so a smaller grid stays correct, only slower).  The phases
+// reserved for rebuilds are normally empty, and an empty launch of thousands
+// of workgroups took 4-6 us for their dispatch alone.
+int64_t phase_tiles(const Plan &P, int phase) {
+    return phase == 1 ? 2 * P.tiles_built + 64 : 2 * P.tiles_ph[phase] + 64;
+}
+
 // One tile phase of a wide sweep: LPT lanes per run, NC columns per lane,
 // vectors in the rows or (TRI) the triples layout, bead vectors turned by
 // their body's rotation (ROT).
@@ -2161,7 +2171,10 @@ void launch_wide(const Plan &P, int phase, int transpose, const T *rec, const T 
     // rebuild): a grid of waves_per_cu waves per CU loops over them; the
     // first phase takes one wave per item unless the handle caps its grid
     const int64_t cap = (phase == 1) ? (int64_t)P.first_wpc : (int64_t)P.waves_per_cu;
-    const int64_t g = (phase == 1 && cap == 0) ? items : std::min<int64_t>(items, cap * P.ncu);
+    int64_t g = (phase == 1 && cap == 0) ? items : std::min<int64_t>(items, cap * P.ncu);
+    // a later phase holds one run per tile (up to kRunTarget tiles)
+    if (phase > 1)
+        g = std::min<int64_t>(g, std::max<int64_t>(P.ncu, ((phase_tiles(P, phase) + TPW - 1) / TPW) * C.nchunks));
     const unsigned grid = (unsigned)std::min<int64_t>(g, 1 << 20);
 #define HQ_WIDE(RT, PRU1, NRU1, PRU, NRU, PRD1, NRD1, PRD, NRD)                                              \
     do {                                                                                                     \
@@ -2394,9 +2407,9 @@ void launch_narrow(const Plan &P, int phase, int transpose, const T *rec, const 
                    hipStream_t s) {
     const size_t lds = (size_t)C.dmax * 6 * 64 * sizeof(T);
     constexpr int TPW = 64 / LPT;
-    // one wave per work item of the largest phase (tile groups x RHS chunks);
-    // waves without work exit at once
-    const int64_t items = ((2 * P.tiles_built + 64 + TPW - 1) / TPW) * (int64_t)C.nchunks;
+    // one wave per work item of the phase (tile groups x RHS chunks); waves
+    // without work exit at once
+    const int64_t items = ((phase_tiles(P, phase) + TPW - 1) / TPW) * (int64_t)C.nchunks;
     const unsigned grid = (unsigned)std::min<int64_t>(items, 1 << 20);
     if (!transpose)
         hipLaunchKernelGGL((k_up<T, LPT>), dim3(grid), dim3(64), lds, s, phase, P.d_phase, P.d_tile_base,
@@ -2413,9 +2426,9 @@ void launch_np_ts(const Plan &P, int phase, int transpose, const T *rec, const T
                   hipStream_t s) {
     constexpr int NB = TS * CW > 256 ? TS * CW : 256;
     constexpr int TPB = NB / (TS * CW);
-    // the first phase: a workgroup per tile group of the largest first phase a
-    // rebuild can make; later phases hold few tiles and stride over them
-    const int64_t groups = (2 * (int64_t)P.tiles_built + 64 + TPB - 1) / TPB;
+    // a workgroup per tile group of the phase (the largest first phase a
+    // rebuild can make); later phases stride over their tiles
+    const int64_t groups = (phase_tiles(P, phase) + TPB - 1) / TPB;
     const int64_t items = groups * (int64_t)C.nchunks;
     const unsigned grid = (unsigned)std::min<int64_t>(items, phase == 1 ? (1 << 20) : 4096);
     if (!transpose)

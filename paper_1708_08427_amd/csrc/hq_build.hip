@@ -18,6 +18,7 @@
 #include "hq_buffer.h"
 #include "hq_common.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace hq {
@@ -782,12 +783,16 @@ __device__ __forceinline__ void phase_close_one(int64_t NI, const int32_t *dn, i
     const int ntiles = (int)(tot >> 32), nnodes = (int)(tot & 0xffffffffll);
     phase_tab[2 * phase] = cnt[kCntTiles];
     phase_tab[2 * phase + 1] = cnt[kCntTiles] + ntiles;
-    // runs: the phase's schedule range cut at tile starts every ~tp nodes; a
-    // small phase gets shorter runs (down to single tiles) so that it still
-    // spreads over kRunTarget lane groups
-    const int tp = max(1, min(run_nodes, (nnodes + kRunTarget - 1) / kRunTarget));
+    // runs: the first phase's schedule range cut at tile starts every ~tp
+    // nodes (a small phase gets shorter runs so that it still spreads over
+    // kRunTarget lane groups).  A later phase of at most kRunTarget tiles gets
+    // exactly one run per tile (tp = 0): cut every tp nodes, its tiles of
+    // 10-31 nodes left empty runs between them, so most waves swept one tile
+    // with half their lanes idle and the phase needed two rounds of waves
+    const bool per_tile = phase > 1 && ntiles <= kRunTarget;
+    const int tp = per_tile ? 0 : max(1, min(run_nodes, (nnodes + kRunTarget - 1) / kRunTarget));
     const int p0 = cnt[kCntNodes], c0 = cnt[kCntRuns];
-    int nrun = (nnodes + tp - 1) / tp;
+    int nrun = per_tile ? ntiles : (nnodes + tp - 1) / tp;
     if ((int64_t)c0 + nrun + 1 > run_cap) {
         raise_flag(err, kFlagBounds);
         nrun = -1;
@@ -814,13 +819,21 @@ __global__ void k_phase_close(int64_t NI, const int32_t *dn, int phase, const lo
 
 // Run starts of one phase: run c begins at the first tile that starts at or
 // after node c * tp of the phase (phase end if none), so every run holds
-// whole tiles and a lane group can sweep it as one node stream.
+// whole tiles and a lane group can sweep it as one node stream; with tp = 0
+// run c is tile c of the phase.
 __device__ __forceinline__ void runs_range(int phase, const int32_t *phase_tab, const int32_t *tile_base,
                                            const int32_t *prun, int32_t *run, int64_t first, int64_t stride) {
     const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
     const int *pr = prun + kPrunStride * phase;
     const int p0 = pr[0], p1 = pr[1], c0 = pr[2], nrun = pr[3], tp = max(pr[4], 1);
     if (nrun == 0 && p1 > p0) return;  // table full: flagged by k_phase_close
+    if (pr[4] == 0) {
+        for (int64_t tt = first; tt <= te - tb; tt += stride) {
+            const int t = tb + (int)tt;
+            run[c0 + tt] = (t < te) ? tile_base[t] : p1;
+        }
+        return;
+    }
     for (int64_t tt = first; tt <= te - tb; tt += stride) {
         const int t = tb + (int)tt;
         const int st = (t < te) ? tile_base[t] - p0 : p1 - p0;
@@ -1809,6 +1822,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
     // --- 4. tiles
     int phases = 0;
     const int max_ph = probe_phases ? (kMaxPhases - 1) : P.phases_reserved;
+    int64_t tiles_prev = 0;
+    if (probe_phases) std::fill(P.tiles_ph, P.tiles_ph + kMaxPhases, (int64_t)0);
     for (int ph = 1; ph <= max_ph; ++ph) {
         if (!probe_phases && ph > std::max(P.phases_built, 2)) {
             // a rebuild's reserved phases (beyond those the first build
@@ -1873,6 +1888,8 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             HQ_HIP(hipMemcpyAsync(cnt, P.d_cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
             HQ_HIP(hipStreamSynchronize(s));
             if (ph == 1) P.tiles1_built = cnt[kCntTiles];
+            P.tiles_ph[ph] = cnt[kCntTiles] - tiles_prev;
+            tiles_prev = cnt[kCntTiles];
             if (cnt[kCntRemain] == 0) {
                 P.tiles_built = cnt[kCntTiles];
                 break;

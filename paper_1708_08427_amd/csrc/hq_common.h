@@ -127,7 +127,8 @@ inline int bucket_stride(int smax) { return 6 * 3 * smax + 8; }
 
 // Run table: per phase (node begin, node end, first entry, runs, run length)
 // at stride kPrunStride; a phase is cut into at least ~kRunTarget runs when it
-// has that many tiles.
+// has that many tiles; run length 0: one run per tile (later phases of at most
+// kRunTarget tiles).
 constexpr int kPrunStride = 8;
 constexpr int kRunTarget = 16384;
 
@@ -145,6 +146,7 @@ struct Plan {
     int phases_reserved = 0;  // phases launched by hq_rebuild
     int phases_built = 0;     // phases found by the last hq_build
     int64_t tiles_built = 0;
+    int64_t tiles_ph[kMaxPhases] = {};  // tiles of each phase found by the last hq_build
     int max_n = 0;
     int run_nodes = 48;       // target nodes per run of whole tiles (wide sweeps)
     int waves_per_cu = 16;    // grid of the later phases' sweeps, waves per CU
