@@ -1246,6 +1246,59 @@ __device__ __forceinline__ void load_links(const int32_t *links, int64_t s, int3
     li[5] = b.y;
 }
 
+// One node's transform from its two children (Eqs. 3.4-3.13): its bead
+// count and body-local centroid, the Householder QR of its k x 3 block K
+// (the children's T22 blocks, or nothing for a bead, above the scaled
+// centroid difference), its T22, the 26 record words (reflectors below the
+// diagonal, tau, the two child weights sqrt(n_x / n) and sqrt(n_y / n)) and
+// a bound on the condition number of T22.
+__device__ __forceinline__ void gen_node(const GenIn &cx, const GenIn &cy, bool xi, bool yi, double &n,
+                                         double (&cp)[3], double (&T)[6], double (&w64)[26], double &kap, int &k) {
+    n = cx.n + cy.n;
+    const double rn = rcp_nr(n);
+    double dv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        cp[d] = (cx.n * cx.c[d] + cy.n * cy.c[d]) * rn;
+        dv[d] = cx.c[d] - cy.c[d];
+    }
+    const double sc = sqrt_nr(cx.n * cy.n * rn);
+    double A[9][3];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
+    if (xi && yi) {
+        put_lower(A, 0, cx.T);
+        put_lower(A, 3, cy.T);
+        put_shift(A, 6, sc, dv);
+        k = 9;
+    } else if (xi) {
+        put_lower(A, 0, cx.T);
+        put_shift(A, 3, sc, dv);
+        k = 6;
+    } else if (yi) {
+        put_lower(A, 0, cy.T);
+        put_shift(A, 3, sc, dv);
+        k = 6;
+    } else {
+        put_shift(A, 0, sc, dv);
+        k = 3;
+    }
+    double tau[3];
+    householder_qr(A, tau, T, k);
+    const double sx = sqrt_nr(cx.n * rn), sy = sqrt_nr(cy.n * rn);
+    kap = (k > 3) ? cond_bound3(T) : 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w64[e] = A[1 + e][0];
+#pragma unroll
+    for (int e = 8; e < 15; ++e) w64[e] = A[2 + (e - 8)][1];
+#pragma unroll
+    for (int e = 15; e < 21; ++e) w64[e] = A[3 + (e - 15)][2];
+#pragma unroll
+    for (int e = 21; e < 24; ++e) w64[e] = tau[e - 21];
+    w64[24] = sx;
+    w64[25] = sy;
+}
+
 // The stores of one node; an index of kOOB switches a group off.  The
 // prologue of the node loop issues the same stores switched off, so that the
 // compiler sees the same number of stores in flight on entry to the loop as
@@ -1418,46 +1471,9 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
             gen_child_fix(li[0], xs, lds, lane, lo3, cx);
             gen_child_fix(li[1], ys, lds, lane, lo3, cy);
             const bool xi = li[0] < 0, yi = li[1] < 0;
-            const double n = cx.n + cy.n, rn = rcp_nr(n);
-            double cp[3], dv[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                cp[d] = (cx.n * cx.c[d] + cy.n * cy.c[d]) * rn;
-                dv[d] = cx.c[d] - cy.c[d];
-            }
-            const double sc = sqrt_nr(cx.n * cy.n * rn);
-            double A[9][3];
-#pragma unroll
-            for (int r = 0; r < 9; ++r) A[r][0] = A[r][1] = A[r][2] = 0.0;
+            double n, cp[3], T[6], w64[26], kap;
             int k;
-            if (xi && yi) {
-                put_lower(A, 0, cx.T);
-                put_lower(A, 3, cy.T);
-                put_shift(A, 6, sc, dv);
-                k = 9;
-            } else if (xi) {
-                put_lower(A, 0, cx.T);
-                put_shift(A, 3, sc, dv);
-                k = 6;
-            } else if (yi) {
-                put_lower(A, 0, cy.T);
-                put_shift(A, 3, sc, dv);
-                k = 6;
-            } else {
-                put_shift(A, 0, sc, dv);
-                k = 3;
-            }
-            double tau[3], T[6];
-            householder_qr(A, tau, T, k);
-            const double sx = sqrt_nr(cx.n * rn), sy = sqrt_nr(cy.n * rn);
-            const double kap = (k > 3) ? cond_bound3(T) : 0.0;
-            auto word = [&](int e) -> double {
-                if (e < 8) return A[1 + e][0];
-                if (e < 15) return A[2 + (e - 8)][1];
-                if (e < 21) return A[3 + (e - 15)][2];
-                if (e < 24) return tau[e - 21];
-                return e == 24 ? sx : sy;
-            };
+            gen_node(cx, cy, xi, yi, n, cp, T, w64, kap, k);
             const bool troot_node = (li[3] & kMetaTileRoot) != 0, body_root = (li[3] & kMetaBodyRoot) != 0;
             // the result waits in the node's slot for its parent (a tile
             // root's slot is never read again, nor is an idle lane's)
@@ -1469,12 +1485,8 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
             // --- stores of this node
             {
                 float w32[26];
-                double w64[26];
 #pragma unroll
-                for (int e = 0; e < 26; ++e) {
-                    w64[e] = word(e);
-                    w32[e] = (float)w64[e];
-                }
+                for (int e = 0; e < 26; ++e) w32[e] = (float)w64[e];
                 const int64_t tr = li[3] >> kMetaSlotShift;
                 const bool wr = act && troot_node && tr == t && t < ntr;
                 bad |= act && troot_node && (tr != t || t >= ntr);
@@ -1498,6 +1510,202 @@ __global__ void __launch_bounds__(64) k_gen_tile(int phase, const int32_t *phase
             if (kmax > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
         }
         if (deg) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+    }
+    if (bad) raise_flag(err, kFlagBounds);
+}
+
+// Slots of a node's same-tile children in the post-order schedule, from the
+// subtree size z2 of the slot before the node (-1: a child elsewhere): the
+// child taken second sits just before the node, the other one just before
+// that child's subtree.
+__device__ __forceinline__ int2 gen_children(int q, int xref, int yref, int meta, int z2) {
+    const bool xs = xref == kRefStack, ys = yref == kRefStack;
+    int xq = -1, yq = -1;
+    if (xs && ys) {
+        if (meta & kMetaYFirst) {
+            xq = q - 1;
+            yq = q - 1 - z2;
+        } else {
+            yq = q - 1;
+            xq = q - 1 - z2;
+        }
+    } else if (xs) {
+        xq = q - 1;
+    } else if (ys) {
+        yq = q - 1;
+    }
+    return make_int2(xq, yq);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The later tile phases, node-parallel: a lane per node, TS lanes per tile
+// and 64 / TS tiles per wave.  A later phase holds few nodes, in tiles that
+// are chains of up to S2 - 1 dependent nodes; one lane per tile walked them
+// at about 4 us per node (FP64 dependency latency), so the phase took as long
+// as its longest tile.  Here every node of a tile loads its links and its
+// children from HBM at once, and the tile resolves level by level: a node
+// computes in the round after its same-tile children have published their
+// (n, centroid, T22) in LDS and the sizes of their subtrees, which locate
+// the children in the post-order schedule.  A tile takes one round per
+// level (at most TS rounds; a node left over is flagged).  The stores leave
+// once, after the rounds, as in k_gen_tile.
+template <int kStore, bool kNodes, int TS>
+__global__ void __launch_bounds__(64) k_gen_np(int phase, const int32_t *phase_tab, const int32_t *tile_base,
+                                               const int32_t *tile_len, const int32_t *tile_root,
+                                               const int32_t *links, const int32_t *nbody, const double *pos,
+                                               const double *lo, double *troot, int64_t ntr, double *ncen,
+                                               double *T22, float *rec32, double *rec64, double *bcen,
+                                               unsigned long long *kappa, int32_t *bflags, int64_t m, int64_t N,
+                                               int64_t NI, int32_t *err) {
+    static_assert(TS == 32 || TS == 64, "tiles of 32 or 64 lanes");
+    constexpr int TPW = 64 / TS;
+    extern __shared__ unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);  // [word][lane]: each node's (n, c, T22)
+    int *ssz = reinterpret_cast<int *>(smem_raw + (size_t)kGenWords * 64 * sizeof(double));
+    uint32_t *stage = reinterpret_cast<uint32_t *>(ssz + 64);
+    uint32_t *srel = stage + 64 * kStageStride;
+    const int lane = threadIdx.x, tl = lane / TS, i = lane - tl * TS, q0 = tl * TS;
+    const int tb = phase_tab[2 * phase], te = phase_tab[2 * phase + 1];
+    bool bad = false;
+    for (int t0 = tb + blockIdx.x * TPW; t0 < te; t0 += gridDim.x * TPW) {
+        const int t = t0 + tl;
+        int base = 0, len = 0, body = 0;
+        if (t < te) {
+            const int b = tile_base[t], l = tile_len[t], r = tile_root[t];
+            if (b < 0 || l < 1 || l > TS || (int64_t)b + l > NI || r < 0 || r >= NI) {
+                bad = true;
+            } else {
+                base = b;
+                len = l;
+                body = nbody[r];
+            }
+        }
+        if (body < 0 || body >= m) {
+            bad = true;
+            base = len = body = 0;
+        }
+        // wave-uniform bases: tile t0's (the wave's tiles follow it in
+        // schedule, tile and body order); offsets from them stay below 2 GiB
+        const int s0 = __builtin_amdgcn_readfirstlane(base);
+        const int b0 = __builtin_amdgcn_readfirstlane(body);
+        if (len > 0 && (base < s0 || base + len - s0 > (1 << 23) || body < b0 || body - b0 > (1 << 24))) {
+            bad = true;
+            len = 0;
+        }
+        const bool act = i < len;
+        const int s = base + (act ? i : 0);
+        auto cap = [](int64_t bytes) -> uint32_t {
+            return bytes <= 0 ? 0u : (bytes >= 0x7fffffffll ? 0x7fffffffu : (uint32_t)bytes);
+        };
+        const int64_t t0c = t0 < ntr ? t0 : ntr;
+        const rsrc_t r32 = make_rsrc_uniform(rec32 + (int64_t)kRecWords * s0, cap((NI - s0) * 128));
+        const rsrc_t r64 = make_rsrc_uniform(rec64 + (int64_t)kRecWords * s0, cap((NI - s0) * 256));
+        const rsrc_t rcen = make_rsrc_uniform(ncen + 3 * (int64_t)s0, cap((NI - s0) * 24));
+        const rsrc_t rt22 = make_rsrc_uniform(T22 + 6 * (int64_t)s0, cap((NI - s0) * 48));
+        const rsrc_t rtr = make_rsrc_uniform(troot + kGenWords * t0c, cap((ntr - t0c) * 80));
+        const rsrc_t rbc = make_rsrc_uniform(bcen + 3 * (int64_t)b0, cap((m - b0) * 24));
+        double lo3[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lo3[d] = lo[3 * body + d];
+        // links and the children held in HBM, for every node at once
+        int32_t li[kLinkInts];
+        load_links(links, min((int64_t)s, NI - 1), li);
+        GenIn cx, cy;
+        bool fbad = false;
+        gen_fetch<true>(li[0], pos, troot, N, ntr, cx, fbad);
+        gen_fetch<true>(li[1], pos, troot, N, ntr, cy, fbad);
+        bad |= act && fbad;
+        const int xref = li[0], yref = li[1], meta = li[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            cx.c[d] = xref >= 0 ? cx.c[d] - lo3[d] : cx.c[d];
+            cy.c[d] = yref >= 0 ? cy.c[d] - lo3[d] : cy.c[d];
+        }
+        const int nst = (int)(xref == kRefStack) + (int)(yref == kRefStack);
+        // a tile's first node has no node of its own tile before it
+        const bool first_bad = act && nst > 0 && i == 0;
+        bad |= first_bad;
+        bool done = !act || first_bad, fin = false;
+        double n = 0.0, cp[3] = {0.0, 0.0, 0.0}, T[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, w64[26], kap = 0.0;
+        int k = 3;
+#pragma unroll
+        for (int e = 0; e < 26; ++e) w64[e] = 0.0;
+        wave_sync();  // the previous group's reads of ssz and the slots are over
+        ssz[lane] = 0;
+        for (int round = 0; round <= TS; ++round) {
+            wave_sync();
+            if (!__ballot(!done)) break;
+            int z2 = 0, z1 = 0;
+            int2 ch = make_int2(-1, -1);
+            bool ready = false;
+            if (!done) {
+                if (nst == 0) {
+                    ready = true;
+                } else {
+                    z2 = ssz[lane - 1];
+                    if (z2 > 0) {
+                        ch = gen_children(lane, xref, yref, meta, z2);
+                        if (nst == 1) {
+                            ready = true;
+                        } else {
+                            const int q1 = lane - 1 - z2;
+                            if (q1 < q0) {
+                                bad = true;
+                                done = true;
+                            } else {
+                                z1 = ssz[q1];
+                                ready = z1 > 0;
+                            }
+                        }
+                    }
+                }
+            }
+            wave_sync();  // this round's reads before its writes
+            if (ready) {
+                GenIn ax = cx, ay = cy;
+                if (ch.x >= 0) gen_slot_get(lds, 0, ch.x, ax);
+                if (ch.y >= 0) gen_slot_get(lds, 0, ch.y, ay);
+                gen_node(ax, ay, xref < 0, yref < 0, n, cp, T, w64, kap, k);
+                gen_slot_put(lds, 0, lane, n, cp, T);
+                ssz[lane] = 1 + z2 + z1;
+                done = true;
+                fin = true;
+            }
+        }
+        bad |= act && !fin;
+        // --- stores
+        const bool troot_node = (meta & kMetaTileRoot) != 0, body_root = (meta & kMetaBodyRoot) != 0;
+        {
+            float w32[26];
+#pragma unroll
+            for (int e = 0; e < 26; ++e) w32[e] = (float)w64[e];
+            const int64_t tr = meta >> kMetaSlotShift;
+            const bool wr = fin && troot_node && tr == t && t < ntr;
+            bad |= fin && troot_node && (tr != t || t >= ntr);
+            const uint32_t rel = (uint32_t)(s - s0);
+            const double tv[kGenWords] = {n, cp[0], cp[1], cp[2], T[0], T[1], T[2], T[3], T[4], T[5]};
+            const double bc[3] = {cp[0] + lo3[0], cp[1] + lo3[1], cp[2] + lo3[2]};
+            gen_store<kStore, kNodes>(r32, r64, rcen, rt22, rtr, rbc, stage, srel, lane, fin ? rel : kOOB,
+                                      wr ? (uint32_t)(t - t0) : kOOB, (fin && body_root) ? (uint32_t)(body - b0) : kOOB,
+                                      w32, w64, li, cp, T, tv, bc);
+        }
+        // the tile's largest condition bound and its degeneracy, once per tile
+        double km = fin ? kap : 0.0;
+#pragma unroll
+        for (int o = 1; o < TS; o <<= 1) km = fmax(km, __shfl_xor(km, o, 64));
+        const unsigned long long dm = __ballot(fin && body_root && (k == 3 || kap > 1e12));
+        const bool tdeg = TS == 64 ? dm != 0 : ((dm >> q0) & 0xffffffffull) != 0;
+        if (i == 0 && len > 0) {
+            if (km > 0.0) {
+                atomicMax(&kappa[body], (unsigned long long)__double_as_longlong(km));
+                if (km > 1e4) atomicOr(&bflags[body], HQ_BODY_ILLCOND);
+            }
+            if (tdeg) atomicOr(&bflags[body], HQ_BODY_DEGENERATE);
+        }
     }
     if (bad) raise_flag(err, kFlagBounds);
 }
@@ -1999,6 +2207,36 @@ hq_status build_device(Plan &P, const double *pos, hipStream_t s, bool probe_pha
             else HQ_GEN_BUCKET_S(16);
 #undef HQ_GEN_BUCKET_S
 #undef HQ_GEN_BUCKET
+            continue;
+        }
+        if (later && P.S2 <= 64) {
+            // later phases node-parallel: tiles of up to 32 (two per wave) or
+            // 64 lanes, a grid from the build's tiles in the phase
+            const int ts = P.S2 <= 32 ? 32 : 64;
+            const size_t lds_np = (size_t)kGenWords * 64 * sizeof(double) + 64 * sizeof(int) +
+                                  ((P.store & 2) ? kStageBytes : 0);
+            const int64_t groups = (2 * P.tiles_ph[ph] + 64 + 64 / ts - 1) / (64 / ts);
+            const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(groups, P.ncu), 65535);
+#define HQ_GEN_NP(ST, ND, TS)                                                                                     \
+    hipLaunchKernelGGL((k_gen_np<ST, ND, TS>), dim3(g), dim3(64), lds_np, s, ph, P.d_phase, P.d_tile_base,        \
+                       P.d_tile_len, P.d_tile_root, P.d_links, P.d_nbody, pos, P.d_lo, P.d_troot, P.troot_cap,   \
+                       P.d_ncen, P.d_T22, P.d_rec32, P.d_rec64, P.d_cen, P.d_kappa, P.d_bflags, m, N, NI, P.d_err)
+#define HQ_GEN_NP_S(TS)                                                  \
+    do {                                                                 \
+        switch ((P.store & 3) * 2 + (nodes ? 1 : 0)) {                   \
+        case 2: HQ_GEN_NP(1, false, TS); break;                          \
+        case 3: HQ_GEN_NP(1, true, TS); break;                           \
+        case 4: HQ_GEN_NP(2, false, TS); break;                          \
+        case 5: HQ_GEN_NP(2, true, TS); break;                           \
+        case 6: HQ_GEN_NP(3, false, TS); break;                          \
+        case 7: HQ_GEN_NP(3, true, TS); break;                           \
+        default: HQ_GEN_NP(3, true, TS); break;                          \
+        }                                                                \
+    } while (0)
+            if (ts == 32) HQ_GEN_NP_S(32);
+            else HQ_GEN_NP_S(64);
+#undef HQ_GEN_NP_S
+#undef HQ_GEN_NP
             continue;
         }
         hipLaunchKernelGGL(gen_fn[later][P.store & 3][nodes ? 1 : 0], dim3(later ? std::min(gen_grid, 1024u) : gen_grid), dim3(64),
