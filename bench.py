@@ -7,8 +7,9 @@ rotation about its centroid + translation in [-1,1]^3), rebuild of the tree and
 FP64 transforms, then Q~^T (Q~ f) in FP32 for the 32 right-hand sides.  K steps
 are captured in one hipGraph and replayed; the timed region is bracketed by
 synchronisations.  By default consecutive steps alternate between two handles
-of the same bodies on two streams, so one step's rebuild overlaps the previous
-step's sweeps (--no-pipeline: one handle, one stream).  Force vectors are held as [bead][system][xyz] (the
+of the same bodies on two streams and two position buffers, so a step's
+rebuild and sweeps overlap the previous step's (--no-pipeline: one handle, one
+stream, positions moved in place).  Force vectors are held as [bead][system][xyz] (the
 library's triples layout) unless --layout rows is given.
 
 value = bead-vectors per second = N * R / (time per step).  The roofline row
@@ -513,15 +514,23 @@ def main():
         log(f"first build {1e3 * (time.perf_counter() - t0):.1f} ms; {h.query()}")
         h.reserve(R, torch.float32)
         # software pipeline over two handles of the same bodies, each with its
-        # own stream and vectors: step i runs on handle i % 2, so the rebuild
-        # of step i + 1 (latency-bound launches) overlaps the sweeps of step i
-        # (bandwidth-bound).  Step i + 1's rigid motion waits for step i's
-        # rebuild (both touch the positions) and turns each body about the
-        # centroid that rebuild found (the motion is issued through step i's
-        # handle); a handle's rebuild follows its previous sweeps on its own
-        # stream.  Positions and products are those of the plain one-handle
-        # sequence, bit for bit.
+        # own stream and vectors: step i runs on handle i % 2.  Positions
+        # alternate between two buffers: step i moves the bodies of buffer
+        # (i - 1) % 2 into buffer i % 2, turning each body about c_i, its
+        # centroid (c_0 from the first positions, c_{i+1} = c_i + t_i: a turn
+        # about the centroid keeps it in place).  So a step's motion waits
+        # only for the previous step's motion, and the rebuilds and sweeps of
+        # consecutive steps run concurrently on the two streams; a handle's
+        # next motion follows its previous sweeps on its own stream.
+        # Positions and products are those of the plain one-handle sequence,
+        # bit for bit.
         npipe = 1 if args.no_pipeline else 2
+        sizes = np.diff(np.asarray(wl.offsets))
+        c0 = np.add.reduceat(wl.pos, np.asarray(wl.offsets[:-1]), axis=0) / sizes[:, None]
+        tr3 = trans.reshape(total_steps, m, 3)
+        cen = c0[None] + np.concatenate([np.zeros((1, m, 3)), np.cumsum(tr3, axis=0)[:-1]], axis=0)
+        cen_d = torch.from_numpy(np.ascontiguousarray(cen)).to(dev)
+        posb = [pos] + [pos.clone() for _ in range(1, npipe)]
         hs, ss, tmps, outs = [h], [stream], [tmp], [out]
         for _ in range(1, npipe):
             hs.append(hq.build(pos, wl.offsets, store=2, stream=stream, first_waves_per_cu=args.first_waves_per_cu,
@@ -543,15 +552,15 @@ def main():
             fork = event(stream)
             for s in ss[1:]:
                 s.wait_event(fork)
-            rebuilt = None
+            moved = None
             for i in range(i0, i1):
                 x = i % npipe
                 hx, sx = hs[x], ss[x]
-                if rebuilt is not None and npipe > 1:
-                    sx.wait_event(rebuilt)
-                hs[(i - 1) % npipe].rigid_update(pos, rot_d[i], trans_d[i], stream=sx)
-                hx.rebuild(pos, stream=sx)
-                rebuilt = event(sx)
+                if moved is not None and npipe > 1:
+                    sx.wait_event(moved)
+                hx.rigid_motion(posb[(i - 1) % npipe], posb[x], rot_d[i], trans_d[i], cen_d[i], stream=sx)
+                moved = event(sx)
+                hx.rebuild(posb[x], stream=sx)
                 hx.apply(f32, out=tmps[x], stream=sx, layout=lay)
                 hx.apply(tmps[x], transpose=True, out=outs[x], stream=sx, layout=lay)
             for s in ss[1:]:
@@ -581,6 +590,7 @@ def main():
             if q["device_flags"] != 0:
                 raise RuntimeError(f"device flags raised: {q}")
         out_last = outs[(total_steps - 1) % npipe]
+        pos = posb[(total_steps - 1) % npipe]  # the final positions
 
         # accuracy on the final positions: FP32 sweep pair against the FP64 oracle
         pos_host = pos.cpu().numpy()
@@ -766,7 +776,7 @@ def main():
                    "rows": wl.rows, **effective(opts), "autotuned": autotuned, "layout": lay,
                    "first_waves_per_cu": args.first_waves_per_cu,
                    "step": "rigid motion + FP64 rebuild + FP32 Q~f + FP32 Q~^T(Q~f), hipGraph of K steps",
-                   "pipeline": (f"{npipe} handles on {npipe} streams: step i+1's rebuild overlaps step i's sweeps"
+                   "pipeline": (f"{npipe} handles on {npipe} streams and position buffers: step i+1's rebuild and sweeps overlap step i's"
                                 if npipe > 1 else "one handle, one stream")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

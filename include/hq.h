@@ -429,6 +429,17 @@ hq_status hq_sorted_beads(hq_handle h, int64_t body, int64_t *bead_index);
 hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot,
                           const double *trans, hq_stream stream);
 
+/* The same rigid motion about given centres, into another buffer:
+ * out_k <- Rot_j (r_k - c_j) + c_j + t_j for the beads of body j.
+ * positions device N x 3 FP64 (read), out device N x 3 FP64 (written; may be
+ * positions itself), rot device m x 9 FP64 row-major, trans and centers device
+ * m x 3 FP64.  It reads no state of the handle's last rebuild (only its body
+ * ranges), so the motion of one step need not wait for the previous step's
+ * rebuild: with two position buffers, consecutive steps' rebuilds can run
+ * concurrently.  HQ_E_INVALID for a NULL pointer.  Capturable. */
+hq_status hq_rigid_motion(hq_handle h, const double *positions, double *out, const double *rot,
+                          const double *trans, const double *centers, hq_stream stream);
+
 /* Sizes (Section 1: Q~ of body j has 3n_j - 6 rows), phase and tile counts,
  * conditioning of the per-node factorisations (Section 3) and device flags.
  * Synchronises the handle's stream (work queued on other streams must be

@@ -288,6 +288,18 @@ class Handle:
         _check(_lib.load().hq_rigid_update(self._h(), _ptr(positions), _ptr(rot), _ptr(trans), _stream(stream)),
                "hq_rigid_update")
 
+    def rigid_motion(self, positions, out, rot, trans, centers, stream=None):
+        """hq_rigid_motion: out = Rot_j (positions - c_j) + c_j + t_j per body
+        (out may be positions); positions and out (N, 3), rot m x 9, trans
+        and centers m x 3, float64 on the device."""
+        _check_f64(positions, "positions", 3 * self.N, (self.N, 3))
+        _check_f64(out, "out", 3 * self.N, (self.N, 3))
+        _check_f64(rot, "rot", 9 * self.m)
+        _check_f64(trans, "trans", 3 * self.m)
+        _check_f64(centers, "centers", 3 * self.m)
+        _check(_lib.load().hq_rigid_motion(self._h(), _ptr(positions), _ptr(out), _ptr(rot), _ptr(trans),
+                                           _ptr(centers), _stream(stream)), "hq_rigid_motion")
+
     # -- explicit Q~ --------------------------------------------------------
     def explicit(self, body=0, stream=None):
         """Dense Q~ of one body: (3n-6) x 3n float64 on the device."""

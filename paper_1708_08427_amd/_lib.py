@@ -70,6 +70,7 @@ SIGNATURES = [
     ("hq_explicit_blocks", c_i32, [c_vp, c_i64, c_i32, c_vp, P_i64, P_i64, P_i64, P_i32, P_i32, c_vp]),
     ("hq_sorted_beads", c_i32, [c_vp, c_i64, P_i64]),
     ("hq_rigid_update", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    ("hq_rigid_motion", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     ("hq_query", c_i32, [c_vp, ctypes.POINTER(Info)]),
     ("hq_body_info", c_i32, [c_vp, P_i32, P_f64]),
     ("hq_node_data", c_i32, [c_vp, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_f64, P_f64, P_f64, P_i32, P_i32]),

@@ -1076,6 +1076,17 @@ hq_status hq_rigid_update(hq_handle h, double *positions, const double *rot, con
     return rigid_update(*P, positions, rot, trans, reinterpret_cast<hipStream_t>(stream));
 }
 
+hq_status hq_rigid_motion(hq_handle h, const double *positions, double *out, const double *rot, const double *trans,
+                          const double *centers, hq_stream stream) {
+    Plan *P = get_plan(h);
+    if (!P) return HQ_E_INVALID;
+    if (!positions || !out || !rot || !trans || !centers) {
+        set_error("NULL argument");
+        return HQ_E_INVALID;
+    }
+    return rigid_motion(*P, positions, out, rot, trans, centers, reinterpret_cast<hipStream_t>(stream));
+}
+
 hq_status hq_query(hq_handle h, hq_info *info) {
     Plan *P = get_plan(h);
     if (!P) return HQ_E_INVALID;

@@ -1940,18 +1940,20 @@ __global__ void k_tile_copy(int64_t NI, const int32_t *__restrict__ cnt, const i
 }
 
 // Rigid motion: r <- Rot (r - c) + c + t per body.
-__global__ void __launch_bounds__(kThreads) k_rigid(const int32_t *__restrict__ chunks, double *pos,
-                                                    const double *__restrict__ rot, const double *__restrict__ trans,
-                                                    const double *__restrict__ bcen) {
+// pin and pout may be the same buffer: each thread reads a bead's position
+// before it writes it.
+__global__ void __launch_bounds__(kThreads) k_rigid(const int32_t *__restrict__ chunks, const double *pin,
+                                                    double *pout, const double *__restrict__ rot,
+                                                    const double *__restrict__ trans, const double *__restrict__ cen) {
     const int body = chunks[3 * blockIdx.x], b0 = chunks[3 * blockIdx.x + 1], b1 = chunks[3 * blockIdx.x + 2];
     double R[9], c[3], t[3];
     for (int i = 0; i < 9; ++i) R[i] = rot[9 * body + i];
-    for (int d = 0; d < 3; ++d) { c[d] = bcen[3 * body + d]; t[d] = trans[3 * body + d]; }
+    for (int d = 0; d < 3; ++d) { c[d] = cen[3 * body + d]; t[d] = trans[3 * body + d]; }
     for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
         double x[3];
-        for (int d = 0; d < 3; ++d) x[d] = pos[3 * (int64_t)i + d] - c[d];
+        for (int d = 0; d < 3; ++d) x[d] = pin[3 * (int64_t)i + d] - c[d];
         for (int d = 0; d < 3; ++d)
-            pos[3 * (int64_t)i + d] = R[3 * d] * x[0] + R[3 * d + 1] * x[1] + R[3 * d + 2] * x[2] + c[d] + t[d];
+            pout[3 * (int64_t)i + d] = R[3 * d] * x[0] + R[3 * d + 1] * x[1] + R[3 * d + 2] * x[2] + c[d] + t[d];
     }
 }
 
@@ -2264,7 +2266,14 @@ hq_status rotate_vectors(Plan &P, const double *rot, const void *in, void *out, 
 }
 
 hq_status rigid_update(Plan &P, double *pos, const double *rot, const double *trans, hipStream_t s) {
-    hipLaunchKernelGGL(k_rigid, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, rot, trans, P.d_cen);
+    hipLaunchKernelGGL(k_rigid, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pos, pos, rot, trans, P.d_cen);
+    HQ_HIP(hipGetLastError());
+    return HQ_OK;
+}
+
+hq_status rigid_motion(Plan &P, const double *pin, double *pout, const double *rot, const double *trans,
+                       const double *cen, hipStream_t s) {
+    hipLaunchKernelGGL(k_rigid, dim3(P.nchunks), dim3(kThreads), 0, s, P.d_chunks, pin, pout, rot, trans, cen);
     HQ_HIP(hipGetLastError());
     return HQ_OK;
 }

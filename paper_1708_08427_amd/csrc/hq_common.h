@@ -312,6 +312,8 @@ int64_t scan_blocks_needed(int64_t n);
 size_t krylov_bytes(int64_t rows, int64_t nrhs, size_t elem);
 int lanes_per_tile(int64_t nrhs);
 hq_status rigid_update(Plan &P, double *pos, const double *rot, const double *trans, hipStream_t s);
+hq_status rigid_motion(Plan &P, const double *pin, double *pout, const double *rot, const double *trans,
+                       const double *cen, hipStream_t s);
 // in or out times blockdiag(Rot_j^T) (transpose = 1) or blockdiag(Rot_j) per body; in may equal out
 hq_status rotate_vectors(Plan &P, const double *rot, const void *in, void *out, int64_t nrhs, int prec, int layout,
                          int transpose, hipStream_t s);

@@ -66,6 +66,7 @@ def test_null_arguments_rejected(lib):
     assert lib.hq_build(ctypes.c_void_p(1), None, 1, None, None, ctypes.byref(h)) == 1
     assert lib.hq_apply(None, None, None, 0, 1, 0, None) == 1
     assert lib.hq_query(None, None) == 1
+    assert lib.hq_rigid_motion(None, None, None, None, None, None, None) == 1
     lib.hq_destroy(None)
 
 

@@ -205,6 +205,115 @@ def test_two_handle_pipeline_matches_sequence(hq):
             assert hx.query()["device_flags"] == 0
 
 
+def test_rigid_motion_matches_numpy(hq):
+    """hq_rigid_motion about given centres, into another buffer and in place,
+    against numpy; the input buffer is left untouched."""
+    w, rot, trans, _ = _workload()
+    pos = torch.from_numpy(w.pos).cuda()
+    h = hq.build(pos, w.offsets)
+    rng = np.random.default_rng(5)
+    cen = rng.uniform(0.0, 100.0, (w.m, 3))
+    rot_d = torch.from_numpy(rot[0].reshape(w.m, 9)).cuda()
+    tr_d = torch.from_numpy(trans[0]).cuda()
+    cen_d = torch.from_numpy(cen).cuda()
+    out = torch.empty_like(pos)
+    h.rigid_motion(pos, out, rot_d, tr_d, cen_d)
+    torch.cuda.synchronize()
+    assert np.array_equal(pos.cpu().numpy(), w.pos)
+    got = out.cpu().numpy()
+    for j in range(w.m):
+        p = w.pos[w.offsets[j]:w.offsets[j + 1]]
+        want = (p - cen[j]) @ rot[0, j].T + cen[j] + trans[0, j]
+        assert np.abs(got[w.offsets[j]:w.offsets[j + 1]] - want).max() < 1e-9
+    h.rigid_motion(pos, pos, rot_d, tr_d, cen_d)
+    assert torch.equal(pos, out)
+    with pytest.raises(ValueError):
+        h.rigid_motion(pos, out, rot_d, tr_d, cen_d[:-1])
+
+
+def test_two_position_buffers_equal_one_handle(hq):
+    """Steps on two handles and two position buffers, step i moving buffer
+    (i - 1) % 2 into buffer i % 2 about tracked centroids, so that a step
+    waits only for the previous step's motion (consecutive rebuilds run
+    concurrently): the positions and products of the one-handle sequence in
+    place, bit for bit, eagerly and replayed from a graph captured across
+    both streams."""
+    w, rot, trans, f = _workload()
+    K = 4
+    rot_d = torch.from_numpy(rot.reshape(K, w.m, 9)).cuda()
+    tr_d = torch.from_numpy(trans).cuda()
+    sizes = np.diff(np.asarray(w.offsets))
+    c0 = np.add.reduceat(w.pos, np.asarray(w.offsets[:-1]), axis=0) / sizes[:, None]
+    cen = c0[None] + np.concatenate([np.zeros((1, w.m, 3)), np.cumsum(trans, axis=0)[:-1]], axis=0)
+    cen_d = torch.from_numpy(np.ascontiguousarray(cen)).cuda()
+    f32 = torch.from_numpy(f).float().cuda()
+    s0, s1 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s0):
+        pos = torch.from_numpy(w.pos).cuda()
+        h = hq.build(pos, w.offsets, tile_units=16, store=2, stream=s0)
+        tmp = torch.empty((w.rows, 32), dtype=torch.float32, device="cuda")
+        out = torch.empty((3 * w.N, 32), dtype=torch.float32, device="cuda")
+        for i in range(K):
+            h.rigid_motion(pos, pos, rot_d[i], tr_d[i], cen_d[i], stream=s0)
+            h.rebuild(pos, stream=s0)
+            h.apply(f32, out=tmp, stream=s0)
+            h.apply(tmp, transpose=True, out=out, stream=s0)
+        torch.cuda.synchronize()
+        want_pos, want_out = pos.cpu().numpy(), out.cpu().numpy()
+
+        posb = [torch.from_numpy(w.pos).cuda() for _ in range(2)]
+        hs = [hq.build(posb[0], w.offsets, tile_units=16, store=2, stream=s0) for _ in range(2)]
+        for hx in hs:
+            hx.reserve(32, torch.float32)
+        ss = [s0, s1]
+        tmps = [torch.empty_like(tmp) for _ in range(2)]
+        outs = [torch.empty_like(out) for _ in range(2)]
+        events = []
+
+        def event(s):
+            e = torch.cuda.Event()
+            e.record(s)
+            events.append(e)
+            return e
+
+        def steps():
+            s1.wait_event(event(s0))
+            moved = None
+            for i in range(K):
+                x = i % 2
+                if moved is not None:
+                    ss[x].wait_event(moved)
+                hs[x].rigid_motion(posb[(i - 1) % 2], posb[x], rot_d[i], tr_d[i], cen_d[i], stream=ss[x])
+                moved = event(ss[x])
+                hs[x].rebuild(posb[x], stream=ss[x])
+                hs[x].apply(f32, out=tmps[x], stream=ss[x])
+                hs[x].apply(tmps[x], transpose=True, out=outs[x], stream=ss[x])
+            s0.wait_event(event(s1))
+
+        torch.cuda.synchronize()
+        steps()
+        torch.cuda.synchronize()
+        assert np.array_equal(posb[(K - 1) % 2].cpu().numpy(), want_pos)
+        assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out)
+
+        hq.capture_begin(s0)
+        steps()
+        g = hq.capture_end(s0)
+        for rep in range(3):
+            posb[1].copy_(torch.from_numpy(w.pos).cuda())
+            posb[0].zero_()
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            g.launch(s0)
+            torch.cuda.synchronize()
+            assert np.array_equal(posb[(K - 1) % 2].cpu().numpy(), want_pos), rep
+            assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out), rep
+        g.destroy()
+        for hx in hs:
+            assert hx.query()["device_flags"] == 0
+
+
 def test_first_phase_grid_cap_matches_uncapped(hq):
     """A capped first-phase grid (one wave per compute unit, grid-strided
     over more run pairs than it has waves) gives the uncapped sweeps' results
