@@ -231,13 +231,14 @@ def test_rigid_motion_matches_numpy(hq):
         h.rigid_motion(pos, out, rot_d, tr_d, cen_d[:-1])
 
 
-def test_two_position_buffers_equal_one_handle(hq):
-    """Steps on two handles and two position buffers, step i moving buffer
-    (i - 1) % 2 into buffer i % 2 about tracked centroids, so that a step
+@pytest.mark.parametrize("P", [2, 3])
+def test_position_buffers_equal_one_handle(hq, P):
+    """Steps on P handles and P position buffers, step i moving buffer
+    (i - 1) % P into buffer i % P about tracked centroids, so that a step
     waits only for the previous step's motion (consecutive rebuilds run
     concurrently): the positions and products of the one-handle sequence in
     place, bit for bit, eagerly and replayed from a graph captured across
-    both streams."""
+    the streams."""
     w, rot, trans, f = _workload()
     K = 4
     rot_d = torch.from_numpy(rot.reshape(K, w.m, 9)).cuda()
@@ -261,13 +262,13 @@ def test_two_position_buffers_equal_one_handle(hq):
         torch.cuda.synchronize()
         want_pos, want_out = pos.cpu().numpy(), out.cpu().numpy()
 
-        posb = [torch.from_numpy(w.pos).cuda() for _ in range(2)]
-        hs = [hq.build(posb[0], w.offsets, tile_units=16, store=2, stream=s0) for _ in range(2)]
+        posb = [torch.from_numpy(w.pos).cuda() for _ in range(P)]
+        hs = [hq.build(posb[0], w.offsets, tile_units=16, store=2, stream=s0) for _ in range(P)]
         for hx in hs:
             hx.reserve(32, torch.float32)
-        ss = [s0, s1]
-        tmps = [torch.empty_like(tmp) for _ in range(2)]
-        outs = [torch.empty_like(out) for _ in range(2)]
+        ss = [s0, s1] + [torch.cuda.Stream() for _ in range(2, P)]
+        tmps = [torch.empty_like(tmp) for _ in range(P)]
+        outs = [torch.empty_like(out) for _ in range(P)]
         events = []
 
         def event(s):
@@ -277,38 +278,42 @@ def test_two_position_buffers_equal_one_handle(hq):
             return e
 
         def steps():
-            s1.wait_event(event(s0))
+            fork = event(s0)
+            for s in ss[1:]:
+                s.wait_event(fork)
             moved = None
             for i in range(K):
-                x = i % 2
+                x = i % P
                 if moved is not None:
                     ss[x].wait_event(moved)
-                hs[x].rigid_motion(posb[(i - 1) % 2], posb[x], rot_d[i], tr_d[i], cen_d[i], stream=ss[x])
+                hs[x].rigid_motion(posb[(i - 1) % P], posb[x], rot_d[i], tr_d[i], cen_d[i], stream=ss[x])
                 moved = event(ss[x])
                 hs[x].rebuild(posb[x], stream=ss[x])
                 hs[x].apply(f32, out=tmps[x], stream=ss[x])
                 hs[x].apply(tmps[x], transpose=True, out=outs[x], stream=ss[x])
-            s0.wait_event(event(s1))
+            for s in ss[1:]:
+                s0.wait_event(event(s))
 
         torch.cuda.synchronize()
         steps()
         torch.cuda.synchronize()
-        assert np.array_equal(posb[(K - 1) % 2].cpu().numpy(), want_pos)
-        assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out)
+        assert np.array_equal(posb[(K - 1) % P].cpu().numpy(), want_pos)
+        assert np.array_equal(outs[(K - 1) % P].cpu().numpy(), want_out)
 
         hq.capture_begin(s0)
         steps()
         g = hq.capture_end(s0)
         for rep in range(3):
-            posb[1].copy_(torch.from_numpy(w.pos).cuda())
-            posb[0].zero_()
+            for b in posb:
+                b.zero_()
+            posb[P - 1].copy_(torch.from_numpy(w.pos).cuda())
             for o in outs:
                 o.zero_()
             torch.cuda.synchronize()
             g.launch(s0)
             torch.cuda.synchronize()
-            assert np.array_equal(posb[(K - 1) % 2].cpu().numpy(), want_pos), rep
-            assert np.array_equal(outs[(K - 1) % 2].cpu().numpy(), want_out), rep
+            assert np.array_equal(posb[(K - 1) % P].cpu().numpy(), want_pos), rep
+            assert np.array_equal(outs[(K - 1) % P].cpu().numpy(), want_out), rep
         g.destroy()
         for hx in hs:
             assert hx.query()["device_flags"] == 0
