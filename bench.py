@@ -714,9 +714,64 @@ def main():
         nbytes64 = algorithmic_bytes(h64, R, 8)
         assert h64.query()["device_flags"] == 0
         h64.destroy()
-        del f64, tmp64, out64
+        # the FP64 step pipelined like the FP32 one, the paper's precision
+        # throughout: its own handles, vectors and position buffers on the
+        # same streams, from the first positions with the same motions
+        k64, w64 = min(20, args.steps), min(5, args.warmup)
+        posb64 = [pos0.clone() for _ in range(npipe)]
+        hs64, tmps64, outs64 = [], [], []
+        for _ in range(npipe):
+            hs64.append(hq.build(posb64[0], wl.offsets, store=1, stream=stream, **opts))
+            hs64[-1].reserve(R, torch.float64)
+            tmps64.append(torch.empty_like(tmp64))
+            outs64.append(torch.empty_like(out64))
+        torch.cuda.synchronize()
+
+        def steps64(i0, i1):
+            fork = event(stream)
+            for s_ in ss[1:]:
+                s_.wait_event(fork)
+            moved = None
+            for i in range(i0, i1):
+                x = i % npipe
+                hx, sx = hs64[x], ss[x]
+                if moved is not None and npipe > 1:
+                    sx.wait_event(moved)
+                hx.rigid_motion(posb64[(i - 1) % npipe], posb64[x], rot_d[i], trans_d[i], cen_d[i], stream=sx)
+                moved = event(sx)
+                hx.rebuild(posb64[x], stream=sx)
+                hx.apply(f64, out=tmps64[x], stream=sx, layout=lay)
+                hx.apply(tmps64[x], transpose=True, out=outs64[x], stream=sx, layout=lay)
+            for s_ in ss[1:]:
+                stream.wait_event(event(s_))
+
+        hq.capture_begin(stream)
+        steps64(0, w64)
+        g64_warm = hq.capture_end(stream)
+        hq.capture_begin(stream)
+        steps64(w64, w64 + k64)
+        g64_timed = hq.capture_end(stream)
+        g64_warm.launch(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g64_timed.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_step64p = e0.elapsed_time(e1) / k64
+        for hx in hs64:
+            if hx.query()["device_flags"] != 0:
+                raise RuntimeError(f"device flags raised (FP64 pipeline): {hx.query()}")
+            hx.destroy()
+        g64_warm.destroy()
+        g64_timed.destroy()
+        del f64, tmp64, out64, tmps64, outs64, posb64
         fp64 = {"up_ms": t_up64, "down_ms": t_dn64, "rebuild_ms": t_rb64, "step_ms": t_step64,
                 "bead_vectors_per_s": N * R / (t_step64 * 1e-3),
+                "pipelined": {"step_ms": t_step64p, "bead_vectors_per_s": N * R / (t_step64p * 1e-3),
+                              "steps": k64, "warmup": w64,
+                              "what": f"the FP64 BD step (FP64 rebuild, FP64 records and vectors) on {npipe} "
+                                      "handles, streams and position buffers, hipGraph, as the FP32 step"},
                 "apply_only_bead_vectors_per_s": N * R / ((t_up64 + t_dn64) * 1e-3),
                 "roofline": {"bound": "hbm", "kernel": sweep_kernel(R, lay, "double"), "bytes": int(pb64[1]),
                              "ms": t_p1_64, "achieved": pb64[1] / (t_p1_64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
@@ -724,9 +779,10 @@ def main():
                              "whole_sweep_up": {"bytes": int(nbytes64), "ms": t_up64,
                                                 "frac": nbytes64 / (t_up64 * 1e-3) / 1e9 / HBM_PEAK_GBS}},
                 "what": "FP64 transforms and vectors on the same workload (final positions): rebuild + Q~f + "
-                        "Q~^T(Q~f) per step, eager launches on one stream, no pipelining"}
+                        "Q~^T(Q~f) per step, eager launches on one stream (step_ms), and the pipelined graph "
+                        "of whole steps (pipelined)"}
         log(f"sweeps: up {t_up:.3f} ms, down {t_dn:.3f} ms, rebuild {t_rb:.3f} ms; FP64 up {t_up64:.3f} "
-            f"down {t_dn64:.3f} step {t_step64:.3f} ms")
+            f"down {t_dn64:.3f} step {t_step64:.3f} ms (pipelined {t_step64p:.3f} ms)")
         nbytes = algorithmic_bytes(h, R)
         # the dominant kernel: the first tile phase's upward launch, timed with
         # HIP events around that launch on the stream it runs on
