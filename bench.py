@@ -70,7 +70,7 @@ def cpu_model():
 
 
 def host_workers():
-    """Host threads this process may use (at most 16, the GPU machine's share)."""
+    """Host threads this process may use (its CPU affinity, at most 16)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
