@@ -953,6 +953,58 @@ __device__ __forceinline__ void bstc(T v, rsrc_t r, uint32_t vo, uint32_t so) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
 }
 
+// Three or six consecutive values at byte offset vo (kOOB: switched off), for
+// the lane kernels' single right-hand side: with R = 1 a bead's triple, a
+// node's residue rows and an exchange entry are contiguous in either layout,
+// so one wide access replaces one per value (each lane of the lane kernels
+// touches its own lines, and the number of accesses bounds them).  Offsets
+// stay in the vector offset, as for every store wider than 64 bits.
+template <typename T>
+__device__ __forceinline__ void bld3c(rsrc_t r, uint32_t vo, T (&m)[3]) {
+    if constexpr (sizeof(T) == 4) {
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, vo, 0, 0);
+        m[0] = __uint_as_float(a.x);
+        m[1] = __uint_as_float(a.y);
+        m[2] = __uint_as_float(a.z);
+    } else {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, vo + 16, 0, 0);
+        m[0] = __builtin_bit_cast(double, u32x2{a.x, a.y});
+        m[1] = __builtin_bit_cast(double, u32x2{a.z, a.w});
+        m[2] = __builtin_bit_cast(double, b);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bst3c(T m0, T m1, T m2, rsrc_t r, uint32_t vo) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(m0), __float_as_uint(m1), __float_as_uint(m2)}, r,
+                                              vo, 0, 0);
+    } else {
+        const u32x2 a = __builtin_bit_cast(u32x2, m0), b = __builtin_bit_cast(u32x2, m1);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, vo, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, m2), r, vo + 16, 0, 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bld6c(rsrc_t r, uint32_t vo, T (&m)[6]) {
+    T a[3], b[3];
+    bld3c<T>(r, vo, a);
+    bld3c<T>(r, vo + 3 * (uint32_t)sizeof(T), b);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m[k] = a[k];
+        m[3 + k] = b[k];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bst6c(const T (&m)[6], rsrc_t r, uint32_t vo) {
+    bst3c<T>(m[0], m[1], m[2], r, vo);
+    bst3c<T>(m[3], m[4], m[5], r, vo + 3 * (uint32_t)sizeof(T));
+}
+
 struct LaneLk {
     int xref, yref, off, meta, slots;
 };
@@ -1055,6 +1107,9 @@ __global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phas
     const int sink = C.nslot;
     const rsrc_t rr = make_rsrc(rec, rec_bytes), rv = make_rsrc(v, C.in_bytes), ro = make_rsrc(out, C.out_bytes),
                  rx = make_rsrc(xch, C.xch_bytes);
+    // one right-hand side: triples, residue rows and exchange entries are
+    // contiguous (one wide access each)
+    const bool contig = LPT == 1 && C.R == 1;
     const int tb = phase_tab[2], te = phase_tab[3];
     const int items = ((te - tb + TPW - 1) / TPW) * C.nchunks;
     int bad = 0;
@@ -1068,10 +1123,15 @@ __global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phas
         auto in_of = [&](int i, const LaneLk &l, T (&a)[3], T (&b)[3]) {
             const bool live = i < len && act;
             const bool xb = live && l.xref >= 0 && l.xref < C.N, yb = live && l.yref >= 0 && l.yref < C.N;
+            if (contig) {
+                bld3c<T>(rv, lane_vo<T>(xb, 3 * (int64_t)l.xref, 0, r, C), a);
+                bld3c<T>(rv, lane_vo<T>(yb, 3 * (int64_t)l.yref, 0, r, C), b);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                a[k] = bldc<T>(rv, lane_vo<T>(xb, 3 * (int64_t)l.xref, k, r, C), 0);
-                b[k] = bldc<T>(rv, lane_vo<T>(yb, 3 * (int64_t)l.yref, k, r, C), 0);
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = bldc<T>(rv, lane_vo<T>(xb, 3 * (int64_t)l.xref, k, r, C), 0);
+                    b[k] = bldc<T>(rv, lane_vo<T>(yb, 3 * (int64_t)l.yref, k, r, C), 0);
+                }
             }
         };
         LaneLk lq[RD];
@@ -1131,16 +1191,22 @@ __global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phas
                              n.xref >= C.N || n.yref >= C.N))
                     bad |= kFlagBounds;
                 const bool en = live && act && rok;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    bstc<T>(t9[3 + k], ro, lane_vo<T>(en && any, n.off, k, r, C), 0);
-                    bstc<T>(t9[6 + k], ro, lane_vo<T>(en && both, (int64_t)n.off + 3, k, r, C), 0);
-                }
                 const bool xen = live && act && troot && xok;
                 const uint32_t xb0 = xen ? (uint32_t)(xidx<false>(slot, 0, r, C) * (int64_t)sizeof(T)) : kOOB;
-                const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+                if (contig) {
+                    bst3c<T>(t9[3], t9[4], t9[5], ro, lane_vo<T>(en && any, n.off, 0, r, C));
+                    bst3c<T>(t9[6], t9[7], t9[8], ro, lane_vo<T>(en && both, (int64_t)n.off + 3, 0, r, C));
+                    bst6c<T>(mp, rx, xb0);
+                } else {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) bstc<T>(mp[k], rx, xb0 + (xen ? k * xstep : 0), 0);
+                    for (int k = 0; k < 3; ++k) {
+                        bstc<T>(t9[3 + k], ro, lane_vo<T>(en && any, n.off, k, r, C), 0);
+                        bstc<T>(t9[6 + k], ro, lane_vo<T>(en && both, (int64_t)n.off + 3, k, r, C), 0);
+                    }
+                    const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) bstc<T>(mp[k], rx, xb0 + (xen ? k * xstep : 0), 0);
+                }
                 lane_put6<T>(lds, (live && !troot) ? min((n.slots >> 16) & 0xff, sink) : sink, lane, mp);
             }
         }
@@ -1163,6 +1229,7 @@ __global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ ph
     const int sink = C.nslot;
     const rsrc_t rr = make_rsrc(rec, rec_bytes), rw = make_rsrc(w, C.in_bytes), ro = make_rsrc(out, C.out_bytes),
                  rx = make_rsrc(xch, C.xch_bytes);
+    const bool contig = LPT == 1 && C.R == 1;  // as in k_up_lane
     const int tb = phase_tab[2], te = phase_tab[3];
     const int items = ((te - tb + TPW - 1) / TPW) * C.nchunks;
     int bad = 0;
@@ -1183,15 +1250,27 @@ __global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ ph
             const int slot = l.meta >> kMetaSlotShift;
             const bool xin = live && (l.meta & kMetaTileRoot) && (!(l.meta & kMetaBodyRoot) || C.root_in) &&
                              slot < C.xch_cap;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                a[k] = bldc<T>(rw, lane_vo<T>(live && rok && dim >= 3, l.off, k, r, C), 0);
-                a[3 + k] = bldc<T>(rw, lane_vo<T>(live && rok && dim == 6, (int64_t)l.off + 3, k, r, C), 0);
-            }
             const uint32_t xb0 = xin ? (uint32_t)(xidx<false>(slot, 0, r, C) * (int64_t)sizeof(T)) : kOOB;
-            const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+            if (contig) {
+                T a0[3], a1[3];
+                bld3c<T>(rw, lane_vo<T>(live && rok && dim >= 3, l.off, 0, r, C), a0);
+                bld3c<T>(rw, lane_vo<T>(live && rok && dim == 6, (int64_t)l.off + 3, 0, r, C), a1);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) lv[k] = bldc<T>(rx, xb0 + (xin ? k * xstep : 0), 0);
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = a0[k];
+                    a[3 + k] = a1[k];
+                }
+                bld6c<T>(rx, xb0, lv);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = bldc<T>(rw, lane_vo<T>(live && rok && dim >= 3, l.off, k, r, C), 0);
+                    a[3 + k] = bldc<T>(rw, lane_vo<T>(live && rok && dim == 6, (int64_t)l.off + 3, k, r, C), 0);
+                }
+                const uint32_t xstep = (uint32_t)(C.R * sizeof(T));
+#pragma unroll
+                for (int k = 0; k < 6; ++k) lv[k] = bldc<T>(rx, xb0 + (xin ? k * xstep : 0), 0);
+            }
         };
         LaneLk lq[RD];
         T gq[RD][26], ia[RD][6], il[RD][6];
@@ -1245,10 +1324,15 @@ __global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ ph
                     bad |= kFlagBounds;
                 const bool en = live && act;
                 const bool xb = en && n.xref >= 0 && n.xref < C.N, yb = en && n.yref >= 0 && n.yref < C.N;
+                if (contig) {
+                    bst3c<T>(Lx[0], Lx[1], Lx[2], ro, lane_vo<T>(xb, 3 * (int64_t)n.xref, 0, r, C));
+                    bst3c<T>(Ly[0], Ly[1], Ly[2], ro, lane_vo<T>(yb, 3 * (int64_t)n.yref, 0, r, C));
+                } else {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    bstc<T>(Lx[k], ro, lane_vo<T>(xb, 3 * (int64_t)n.xref, k, r, C), 0);
-                    bstc<T>(Ly[k], ro, lane_vo<T>(yb, 3 * (int64_t)n.yref, k, r, C), 0);
+                    for (int k = 0; k < 3; ++k) {
+                        bstc<T>(Lx[k], ro, lane_vo<T>(xb, 3 * (int64_t)n.xref, k, r, C), 0);
+                        bstc<T>(Ly[k], ro, lane_vo<T>(yb, 3 * (int64_t)n.yref, k, r, C), 0);
+                    }
                 }
                 lane_put6<T>(lds, (live && xst) ? min(n.slots & 0xff, sink) : sink, lane, Lx);
                 lane_put6<T>(lds, (live && yst) ? min((n.slots >> 8) & 0xff, sink) : sink, lane, Ly);
