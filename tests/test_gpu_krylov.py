@@ -5,7 +5,8 @@ basis (oracle.bd).
 
 * FP64, three bodies, 1 to 40 right-hand sides (narrow and wide sweeps), both
   layouts: V and g <= 1e-9 relative, with CG run to a 1e-12 residual.
-* FP32: <= 1e-4 relative.
+* FP32, 1 to 8 right-hand sides, both layouts (the 16-byte and the
+  one-element CG vector passes): <= 1e-4 relative.
 * A D that is not positive definite is reported as HQ_E_INVALID; a failing
   callback's exception reaches the caller.
 """
@@ -77,15 +78,23 @@ def test_constrained_solve_fp64(hq, R, layout):
     assert h.query()["device_flags"] == 0
 
 
-def test_constrained_solve_fp32(hq):
-    w, D, F = problem(52, [20, 70, 200], 8)
+# 855 constraint rows: rows x R is a whole number of 16-byte units for R = 8
+# and R = 4 (the 16-byte CG passes), not for R = 1 and R = 6 (the one-element
+# passes)
+@pytest.mark.parametrize("R,layout", [(8, "rows"), (1, "rows"), (6, "triples"), (4, "triples")])
+def test_constrained_solve_fp32(hq, R, layout):
+    w, D, F = problem(52, [20, 70, 201], R)
+    assert w.rows == 855
     V_o, g_o = bd.constrained_solve(w.pos, w.offsets, D, F)
     h = hq.build(torch.from_numpy(w.pos).cuda(), w.offsets)
     Dd = torch.from_numpy(D).float().cuda()
-    V, g, info = hq.constrained_solve(h, dense_dapply(Dd, "rows"), torch.from_numpy(F).float().cuda(), rtol=1e-6)
+    V, g, info = hq.constrained_solve(h, dense_dapply(Dd, layout), torch.from_numpy(to_layout(F, layout)).float().cuda(),
+                                      layout=layout, rtol=1e-6)
+    V = from_layout(V.cpu().numpy(), layout)
+    g = from_layout(g.cpu().numpy(), layout)
     assert info["max_rel_residual"] <= 1e-6
-    assert np.abs(V.cpu().numpy() - V_o).max() <= 1e-4 * np.abs(V_o).max()
-    assert np.abs(g.cpu().numpy() - g_o).max() <= 1e-4 * np.abs(g_o).max()
+    assert np.abs(V - V_o).max() <= 1e-4 * np.abs(V_o).max()
+    assert np.abs(g - g_o).max() <= 1e-4 * np.abs(g_o).max()
 
 
 def test_constrained_solve_errors(hq):
