@@ -167,7 +167,7 @@ def stream_ceiling(hq, torch, read_bytes, write_bytes, stream, reps=10):
     sink = torch.zeros(4, dtype=torch.int32, device="cuda")
     sp = ctypes.c_void_p(stream.cuda_stream)
     best = None
-    for blocks in (1024, 2048, 4096, 8192):
+    for blocks in (256, 512, 1024, 2048, 4096, 8192):
         def run():
             st = lib.hq_stream_ceiling(ctypes.c_void_p(src.data_ptr()), rb, ctypes.c_void_p(dst.data_ptr()), wb,
                                        blocks, ctypes.c_void_p(sink.data_ptr()), sp)
@@ -189,7 +189,7 @@ def stream_ceiling(hq, torch, read_bytes, write_bytes, stream, reps=10):
     del src, dst
     best["frac"] = best["achieved"] / HBM_PEAK_GBS
     best["what"] = ("hq_stream_ceiling: one launch reading and writing the dominant launch's HBM traffic mix "
-                    "(non-temporal 16-byte accesses, 256 threads per block, best of 1024-8192 blocks)")
+                    "(non-temporal 16-byte accesses, 256 threads per block, best of 256-8192 blocks)")
     return best
 
 
@@ -330,11 +330,17 @@ def config_leg(hq, torch, W, name, stream, reps=10, log=print):
     v, w = wl.draw_vectors()
     log(f"leg {name}: {wl.name} N={wl.N} m={wl.m} R={R}")
     pos = torch.from_numpy(wl.pos).to(dev)
+    # the launch configuration the autotuner picks for this workload's FP32
+    # sweeps (these legs time sweeps, not rebuilds)
+    t0 = time.perf_counter()
+    tuned = hq.autotune(pos, wl.offsets, R, torch.float32, include_rebuild=False, stream=stream)
+    opts = {k: tuned[k] for k in ("tile_units", "run_nodes", "waves_per_cu", "later_tile_units", "leaf_size")}
+    log(f"leg {name}: autotune {1e3 * (time.perf_counter() - t0):.0f} ms: {opts}")
     # C5 also generates its explicit block-sparse Q~, which needs the FP64
     # transforms
-    h = hq.build(pos, wl.offsets, store=3 if (fp64 or name == "C5") else 2, stream=stream)
+    h = hq.build(pos, wl.offsets, store=3 if (fp64 or name == "C5") else 2, stream=stream, **opts)
     res = {"workload": wl.name, "beads": wl.N, "bodies": wl.m, "nrhs": R, "rows": wl.rows,
-           "tiles": h.query()["tiles"], "phases": h.query()["phases"]}
+           "tiles": h.query()["tiles"], "phases": h.query()["phases"], "autotuned": opts}
     precs = [("fp32", torch.float32, 4)] + ([("fp64", torch.float64, 8)] if fp64 else [])
     outs = {}
     for tag, dt, elem in precs:
