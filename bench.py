@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bead-vectors/s for batched Q̃v+Q̃ᵀv; % HBM peak; FP32 err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
-PROBE_SWEEPS = 3  # must match paper_1708_08427_amd.traffic
+PROBE_SWEEPS = 3  # must match traffic.PROBE_SWEEPS
 TRAFFIC_GLOB = "traffic_up_sweep_bd_m4096_R32*.json"  # one counter summary per launch configuration
 
 
@@ -307,25 +307,87 @@ def first_phase_ms(torch, h, v, out, stream, reps, transpose=False):
     return float(np.median(ms))
 
 
+def leg_workload(W, name):
+    """(workload, right-hand sides, FP64 timed too) of a configuration leg."""
+    if name == "C2":
+        return W.ellipsoid_n65536(), 16, True
+    if name == "C3":
+        return W.batched_m1000(), 1, False
+    return W.large_clustered(), 1, False
+
+
+def leg_options_tag(opts, R):
+    """The configuration a leg's first-phase launch depends on: the tile size,
+    and the run length for the wide sweeps (8 or more right-hand sides); the
+    lane sweeps below 8 take one tile per lane group whatever the run length."""
+    e = effective(opts)
+    keys = ("tile_units", "run_nodes") if R >= 8 else ("tile_units",)
+    return ",".join([f"{k}={e[k]}" for k in keys] + ["layout=rows"])
+
+
+def leg_traffic(wl, opts, R):
+    """HBM bytes of one first-phase upward launch of a leg from its committed
+    counter summary (traffic_up_sweep_<workload>.json), if taken on the
+    current sweep sources in the same configuration (else None and why)."""
+    from traffic import sweep_source_hash
+    path = os.path.join(ROOT, "profiles", f"traffic_up_sweep_{wl.name}.json")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as fh:
+        prof = json.load(fh)
+    if prof.get("source_sha256") != sweep_source_hash():
+        return None, "sweep sources changed since the counters were taken"
+    tag = leg_options_tag(opts, R)
+    if prof.get("options") != tag:
+        return None, f"leg runs {tag}; counters taken with {prof.get('options')}"
+    return prof["up_phase1"]["hbm_bytes"], prof["command"]
+
+
+def probe_leg(hq, torch, W, name, args):
+    """The counter run of a leg: the 512 MiB copy, then PROBE_SWEEPS upward and
+    downward FP32 sweeps of the leg's workload (rows layout) in the launch
+    configuration given on the command line."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    wl, R, _ = leg_workload(W, name)
+    v, w = wl.draw_vectors()
+    pos = torch.from_numpy(wl.pos).to(dev)
+    opts = fixed_options(args)
+    h = hq.build(pos, wl.offsets, store=2, **opts)
+    vd = torch.from_numpy(v).float().to(dev)
+    wd = torch.from_numpy(w).float().to(dev)
+    up = torch.empty((wl.rows, R), dtype=torch.float32, device=dev)
+    dn = torch.empty((3 * wl.N, R), dtype=torch.float32, device=dev)
+    for _ in range(PROBE_SWEEPS):
+        h.apply(vd, out=up)
+    for _ in range(PROBE_SWEEPS):
+        h.apply(wd, transpose=True, out=dn)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "workload": wl.name, "algorithmic_bytes": algorithmic_bytes(h, R),
+                      "first_phase_bytes": phase_bytes(h, R)[1], "phases": h.query()["phases"],
+                      "options": leg_options_tag(opts, R)}), flush=True)
+
+
 def config_leg(hq, torch, W, name, stream, reps=10, log=print):
     """One of the other target configurations, timed like the sweeps of the
     BD step: FP32 Q~v and Q~^T w (and FP64 where the configuration asks for
     it), algorithmic bytes and fraction of the HBM peak per direction, the
-    first tile phase's launch, the FP32 error against the FP64 oracle and the
-    leak.  Inputs are N(0,1) in the rows layout."""
+    first tile phase's launch (with its measured HBM bytes where a counter
+    summary of the same configuration is committed), the FP32 error against
+    the FP64 oracle and the leak.  Inputs are N(0,1) in the rows layout."""
     from oracle import dense, hier
     dev = torch.device("cuda:0")
     flush = None
-    if name == "C2":
-        wl, R, fp64 = W.ellipsoid_n65536(), 16, True
-        # the whole working set fits the 256 MB Infinity Cache: time it after a
+    wl, R, fp64 = leg_workload(W, name)
+    if name in ("C2", "C3"):
+        # the working set fits the 256 MB Infinity Cache: time it after a
         # 1 GiB write evicts it, as well as warm
         fbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         flush = lambda: fbuf.fill_(1.0)
-    elif name == "C3":
-        wl, R, fp64 = W.batched_m1000(), 1, False
-    else:
-        wl, R, fp64 = W.large_clustered(), 1, False
     assert wl.nrhs == R
     v, w = wl.draw_vectors()
     log(f"leg {name}: {wl.name} N={wl.N} m={wl.m} R={R}")
@@ -362,6 +424,10 @@ def config_leg(hq, torch, W, name, stream, reps=10, log=print):
                "first_phase": {"kernel": sweep_kernel(R, "rows", "float" if elem == 4 else "double"),
                                "ms": t_p1, "bytes": int(pb[1]),
                                "frac": pb[1] / (t_p1 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+        if tag == "fp32":
+            tb, tsrc = leg_traffic(wl, opts, R)
+            leg["first_phase"]["traffic"] = tb
+            leg["first_phase"]["traffic_source"] = tsrc
         if flush is not None:
             c_up = timed_ms(torch, stream, lambda: h.apply(vd, out=up, stream=stream), reps, before=flush)
             c_dn = timed_ms(torch, stream, lambda: h.apply(wd, transpose=True, out=dn, stream=stream), reps,
@@ -457,6 +523,8 @@ def main():
                     help="only build, copy 512 MiB once and run 3 sweeps per direction (for rocprofv3 --pmc)")
     ap.add_argument("--no-legs", action="store_true", help="skip the other configurations (C2, C3, C5)")
     ap.add_argument("--legs-only", action="store_true", help="only the other configurations (for rocprofv3)")
+    ap.add_argument("--probe-leg", choices=("C2", "C3", "C5"),
+                    help="the counter run of one configuration leg (launch options from the command line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bodies of this workload "
@@ -471,6 +539,9 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.probe_leg:
+        probe_leg(hq, torch, W, args.probe_leg, args)
+        return
     if args.legs_only:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):

@@ -934,6 +934,16 @@ __device__ __forceinline__ void bst<double>(double v, rsrc_t r, uint32_t vo, uin
 // tile, and only the tile root touches the exchange buffer.
 // ---------------------------------------------------------------------------
 constexpr int kLaneRing = 5;  // ring slots: links 4 nodes ahead, the rest 2
+// How far ahead a lane loads a record's reflectors.  FP32: with the links,
+// 4 nodes ahead, so the record's one 128-byte line is fetched once (loaded 2
+// nodes after its links, the line had often left L2 on large batches, where
+// each lane keeps several records in flight, and came from HBM twice).  FP64
+// records span two lines, and two more nodes of FP64 reflectors would not
+// fit the register budget: 2 nodes ahead.
+template <typename T>
+constexpr int lane_g_ahead() {
+    return sizeof(T) == 4 ? 4 : 2;
+}
 
 // Buffer accesses of the lane kernels with the default cache policy: a lane
 // touches parts of a line in several instructions (a record in eight loads, a
@@ -1100,7 +1110,7 @@ __global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phas
                                                 T *__restrict__ xch, Ctx C, int32_t *err) {
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
-    constexpr int TPW = 64 / LPT, RD = kLaneRing;
+    constexpr int TPW = 64 / LPT, RD = kLaneRing, kLaneGAhead = lane_g_ahead<T>();
     constexpr uint32_t RB = kRecWords * sizeof(T);
     const int lane = threadIdx.x;
     const int tslot = lane / LPT, rl = lane % LPT;
@@ -1137,18 +1147,18 @@ __global__ void __launch_bounds__(64) k_up_lane(const int32_t *__restrict__ phas
         LaneLk lq[RD];
         T gq[RD][26], ia[RD][3], ib[RD][3];
 #pragma unroll
-        for (int u = 0; u < RD - 1; ++u) lane_links<T>(rr, bo(u), lq[u]);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            lane_g<T>(rr, bo(u), gq[u]);
-            in_of(u, lq[u], ia[u], ib[u]);
+        for (int u = 0; u < RD - 1; ++u) {
+            lane_links<T>(rr, bo(u), lq[u]);
+            if (u < kLaneGAhead) lane_g<T>(rr, bo(u), gq[u]);
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) in_of(u, lq[u], ia[u], ib[u]);
         for (int i0 = 0; i0 < lmax; i0 += RD) {
 #pragma unroll
             for (int u = 0; u < RD; ++u) {
                 const int i = i0 + u;
                 lane_links<T>(rr, bo(i + 4), lq[(u + 4) % RD]);
-                lane_g<T>(rr, bo(i + 2), gq[(u + 2) % RD]);
+                lane_g<T>(rr, bo(i + kLaneGAhead), gq[(u + kLaneGAhead) % RD]);
                 in_of(i + 2, lq[(u + 2) % RD], ia[(u + 2) % RD], ib[(u + 2) % RD]);
                 // node i (Eqs. 4.2-4.3)
                 const LaneLk &n = lq[u];
@@ -1222,7 +1232,7 @@ __global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ ph
                                                   const T *__restrict__ xch, Ctx C, int32_t *err) {
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
-    constexpr int TPW = 64 / LPT, RD = kLaneRing;
+    constexpr int TPW = 64 / LPT, RD = kLaneRing, kLaneGAhead = lane_g_ahead<T>();
     constexpr uint32_t RB = kRecWords * sizeof(T);
     const int lane = threadIdx.x;
     const int tslot = lane / LPT, rl = lane % LPT;
@@ -1275,18 +1285,18 @@ __global__ void __launch_bounds__(64) k_down_lane(const int32_t *__restrict__ ph
         LaneLk lq[RD];
         T gq[RD][26], ia[RD][6], il[RD][6];
 #pragma unroll
-        for (int u = 0; u < RD - 1; ++u) lane_links<T>(rr, bo(u), lq[u]);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            lane_g<T>(rr, bo(u), gq[u]);
-            in_of(u, lq[u], ia[u], il[u]);
+        for (int u = 0; u < RD - 1; ++u) {
+            lane_links<T>(rr, bo(u), lq[u]);
+            if (u < kLaneGAhead) lane_g<T>(rr, bo(u), gq[u]);
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) in_of(u, lq[u], ia[u], il[u]);
         for (int j0 = 0; j0 < lmax; j0 += RD) {
 #pragma unroll
             for (int u = 0; u < RD; ++u) {
                 const int j = j0 + u;
                 lane_links<T>(rr, bo(j + 4), lq[(u + 4) % RD]);
-                lane_g<T>(rr, bo(j + 2), gq[(u + 2) % RD]);
+                lane_g<T>(rr, bo(j + kLaneGAhead), gq[(u + kLaneGAhead) % RD]);
                 in_of(j + 2, lq[(u + 2) % RD], ia[(u + 2) % RD], il[(u + 2) % RD]);
                 // node j (Algorithm 3)
                 const LaneLk &n = lq[u];

@@ -1,14 +1,16 @@
 """HBM traffic of the sweeps from hardware counters.
 
-Two rocprofv3 counter runs of ``bench.py --probe`` (one with FETCH_SIZE, one
-with WRITE_SIZE; both in KiB per dispatch) are turned into the bytes one
-upward and one downward FP32 sweep move to and from HBM, in total and for
-the launch of the first tile phase (the dominant kernel).  Each counter is
-scaled by what it reads for the probe's device copy of 512 MiB (bytes it
+Two rocprofv3 counter runs of ``bench.py --probe`` (or ``--probe-leg C2|C3|C5``;
+one with FETCH_SIZE, one with WRITE_SIZE; both in KiB per dispatch) are turned
+into the bytes one upward and one downward FP32 sweep move to and from HBM, in
+total and for the launch of the first tile phase (the dominant kernel: the
+wide sweep at 8 or more right-hand sides, the lane sweep below).  Each counter
+is scaled by what it reads for the probe's device copy of 512 MiB (bytes it
 must read and write), and the summary records a hash of the sweep sources so
 that a reader can tell whether it still describes the current kernels.
 
-    python traffic.py FETCH_DIR WRITE_DIR OUT.json --command "..."
+    python traffic.py FETCH_DIR WRITE_DIR OUT.json --command "..." --options "..."
+        [--first-up k_up_lane --first-down k_down_lane --workload NAME]
 """
 from __future__ import annotations
 
@@ -18,6 +20,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1708_08427_amd")
 COPY_BYTES = 128 * 1024 * 1024 * 4  # the probe's float32 copy
@@ -62,14 +65,20 @@ def first_phase(rows, kernel):
     return name, sum(groups[name]) / len(groups[name])
 
 
-def summarise(rows):
+def is_sweep(name, direction):
+    """A launch of one of the sweep kernels of a direction ("up" or "down"):
+    wide, lane-group, node-parallel or narrow, any tile phase."""
+    return re.search(rf"hq::(\(anonymous namespace\)::)?k_{direction}(_wide|_lane|_np)?[<(]", name) is not None
+
+
+def summarise(rows, first_up="k_up_wide", first_down="k_down_wide"):
     copies = [r for r in rows if "copy" in r["name"].lower() and "hq::" not in r["name"]]
     if not copies:
         raise ValueError("the probe's copy kernel is missing")
     copy_kib = max(r["value"] for r in copies)
-    up = sum(r["value"] for r in rows if "k_up_wide" in r["name"]) / PROBE_SWEEPS
-    down = sum(r["value"] for r in rows if "k_down_wide" in r["name"]) / PROBE_SWEEPS
-    return copy_kib, up, down, first_phase(rows, "k_up_wide"), first_phase(rows, "k_down_wide")
+    up = sum(r["value"] for r in rows if is_sweep(r["name"], "up")) / PROBE_SWEEPS
+    down = sum(r["value"] for r in rows if is_sweep(r["name"], "down")) / PROBE_SWEEPS
+    return copy_kib, up, down, first_phase(rows, first_up), first_phase(rows, first_down)
 
 
 def main():
@@ -79,13 +88,17 @@ def main():
     ap.add_argument("out")
     ap.add_argument("--command", required=True)
     ap.add_argument("--options", required=True, help="launch configuration of the probe (its 'options' field)")
+    ap.add_argument("--first-up", default="k_up_wide", help="kernel of the first phase's upward launch")
+    ap.add_argument("--first-down", default="k_down_wide", help="kernel of the first phase's downward launch")
+    ap.add_argument("--workload", default="bd_m4096_lognormal500_R32")
     a = ap.parse_args()
-    cf, uf, df, (n_up, u1f), (n_dn, d1f) = summarise(_read(a.fetch_dir, "FETCH_SIZE"))
-    cw, uw, dw, (_, u1w), (_, d1w) = summarise(_read(a.write_dir, "WRITE_SIZE"))
+    cf, uf, df, (n_up, u1f), (n_dn, d1f) = summarise(_read(a.fetch_dir, "FETCH_SIZE"), a.first_up, a.first_down)
+    cw, uw, dw, (_, u1w), (_, d1w) = summarise(_read(a.write_dir, "WRITE_SIZE"), a.first_up, a.first_down)
     ff = COPY_BYTES / (cf * 1024.0)
     fw = COPY_BYTES / (cw * 1024.0)
     res = {
         "command": a.command,
+        "workload": a.workload,
         "source_sha256": sweep_source_hash(),
         "options": a.options,
         "copy": {"bytes_each_way": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
