@@ -926,14 +926,15 @@ __device__ __forceinline__ void bst<double>(double v, rsrc_t r, uint32_t vo, uin
 // not the node needs it, with an out-of-range offset where it does not, so
 // that the compiler's wait counts are exact and no node waits for the stores
 // of the nodes before it.  Three streams run ahead of the node being
-// computed: its link words four nodes ahead, then (with two nodes of slack
-// for the links to arrive) its reflectors and the vectors the links address
-// two nodes ahead.  Pending results sit in the fixed LDS slots the links name
+// computed: its link words four nodes ahead (in FP32 with its reflectors),
+// then (with two nodes of slack for the links to arrive) the vectors the
+// links address, and in FP64 the reflectors, two nodes ahead.  Pending
+// results sit in the fixed LDS slots the links name
 // (as in the wide sweeps), plus one sink slot for the writes of absent
 // values.  In the first phase every child is a bead or a node of the same
 // tile, and only the tile root touches the exchange buffer.
 // ---------------------------------------------------------------------------
-constexpr int kLaneRing = 5;  // ring slots: links 4 nodes ahead, the rest 2
+constexpr int kLaneRing = 5;  // ring slots: links 4 nodes ahead, inputs 2
 // How far ahead a lane loads a record's reflectors.  FP32: with the links,
 // 4 nodes ahead, so the record's one 128-byte line is fetched once (loaded 2
 // nodes after its links, the line had often left L2 on large batches, where
